@@ -1,0 +1,164 @@
+"""ctypes binding of the CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` use it; the product package never imports it.
+
+Matrices are passed as numpy arrays of shape (4, n) in the element order
+11, 21, 12, 22 (the record layout of section 8 of arXiv:2005.07403); complex
+input is a complex array and is split into the SoA real/imaginary trains of
+section 3 before the call.  Results come back in the same shape.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+REF, MIRROR = 0, 1
+POLICY = {"ref": REF, "mirror": MIRROR}
+BACKSCALE = {"none": 0, "safe": 1, "all": 2}
+TRACE_FIELDS = ["s", "c", "r", "r11", "r12", "r22", "mt", "ca", "x", "y", "t2",
+                "tphi", "sec2phi", "cphi", "tpsi", "sec2psi", "cpsi", "smax",
+                "smin", "n1", "n2", "rescued"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} missing: run python oracle/build.py")
+        _lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        for name in ("oracle_dsvd2", "oracle_zsvd2"):
+            f = getattr(_lib, name)
+            f.argtypes = [ctypes.c_size_t, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+            f.restype = ctypes.c_int
+        for name in ("oracle_ssvd2", "oracle_csvd2"):
+            f = getattr(_lib, name)
+            f.argtypes = [ctypes.c_size_t, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          P, ctypes.c_int]
+            f.restype = ctypes.c_int
+        _lib.oracle_trace_d.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
+        _lib.oracle_trace_s.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        for name in ("oracle_metrics_d", "oracle_metrics_s"):
+            f = getattr(_lib, name)
+            f.argtypes = [ctypes.c_size_t, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
+            f.restype = ctypes.c_int
+    return _lib
+
+
+def _ptrs(arrays):
+    arr = (ctypes.c_void_p * len(arrays))(*[a.ctypes.data for a in arrays])
+    return arr
+
+
+def split(A: np.ndarray, real_dtype) -> list:
+    """(4, n) real or complex -> list of contiguous SoA trains."""
+    if np.iscomplexobj(A):
+        out = []
+        for e in range(4):
+            out.append(np.ascontiguousarray(A[e].real, dtype=real_dtype))
+            out.append(np.ascontiguousarray(A[e].imag, dtype=real_dtype))
+        return out
+    return [np.ascontiguousarray(A[e], dtype=real_dtype) for e in range(4)]
+
+
+def join(trains: list, cplx: bool) -> np.ndarray:
+    """SoA trains -> (4, n) array (complex when cplx)."""
+    if cplx:
+        return np.stack([_cx(trains[2 * e], trains[2 * e + 1]) for e in range(4)])
+    return np.stack(trains[:4])
+
+
+def _cx(re, im):
+    out = np.empty(re.shape, dtype=np.complex128 if re.dtype == np.float64 else np.complex64)
+    out.real = re
+    out.imag = im
+    return out
+
+
+def svd2(A: np.ndarray, dtype=np.float64, policy: str = "mirror", backscale: str = "none",
+         rescue: bool = False, nthreads: int = 0, cplx: bool | None = None) -> dict:
+    """Run the oracle over a batch.
+
+    A: (4, n) array (real or complex), element order 11, 21, 12, 22.
+    dtype: np.float64 or np.float32 (the arithmetic precision).
+    Returns dict(U=(4,n), V=(4,n), smax, smin, s, flagged, trains=list of output arrays).
+    """
+    if cplx is None:
+        cplx = bool(np.iscomplexobj(A))
+    dtype = np.dtype(dtype)
+    if cplx and not np.iscomplexobj(A):
+        A = A.astype(np.complex128 if dtype == np.float64 else np.complex64)
+    n = A.shape[1]
+    ins = split(A, dtype)
+    nout = 19 if cplx else 11
+    outs = [np.empty(n, dtype=dtype) for _ in range(nout)]
+    L = lib()
+    flagged = np.zeros(n, dtype=np.uint8)
+    pin, pout = _ptrs(ins), _ptrs(outs)
+    pol = POLICY[policy]
+    bs = BACKSCALE[backscale]
+    if dtype == np.float64:
+        f = L.oracle_zsvd2 if cplx else L.oracle_dsvd2
+        f(n, pin, pout, pol, bs, nthreads)
+    elif dtype == np.float32:
+        f = L.oracle_csvd2 if cplx else L.oracle_ssvd2
+        f(n, pin, pout, pol, bs, int(rescue), flagged.ctypes.data, nthreads)
+    else:
+        raise ValueError(dtype)
+    k = 16 if cplx else 8
+    return dict(U=join(outs[0:k // 2], cplx), V=join(outs[k // 2:k], cplx),
+                smax=outs[k], smin=outs[k + 1], s=outs[k + 2], flagged=flagged,
+                trains=outs, inputs=ins)
+
+
+def run_trains(ins: list, cplx: bool, dtype, policy="mirror", backscale="none",
+               rescue=False, nthreads=0) -> tuple:
+    """Same as svd2 but on SoA trains directly; returns (outs, flagged)."""
+    dtype = np.dtype(dtype)
+    n = ins[0].shape[0]
+    nout = 19 if cplx else 11
+    outs = [np.empty(n, dtype=dtype) for _ in range(nout)]
+    flagged = np.zeros(n, dtype=np.uint8)
+    L = lib()
+    pin, pout = _ptrs(ins), _ptrs(outs)
+    if dtype == np.float64:
+        (L.oracle_zsvd2 if cplx else L.oracle_dsvd2)(n, pin, pout, POLICY[policy],
+                                                    BACKSCALE[backscale], nthreads)
+    else:
+        (L.oracle_csvd2 if cplx else L.oracle_ssvd2)(n, pin, pout, POLICY[policy],
+                                                    BACKSCALE[backscale], int(rescue),
+                                                    flagged.ctypes.data, nthreads)
+    return outs, flagged
+
+
+def trace(a, cplx: bool, dtype=np.float64, policy="mirror", rescue=False) -> dict:
+    """Intermediates of one matrix.  a: 4 (real) or 8 (complex) components in
+    the order a11[r,i], a21[r,i], a12[r,i], a22[r,i]."""
+    dtype = np.dtype(dtype)
+    a = np.ascontiguousarray(a, dtype=dtype)
+    tr = np.zeros(len(TRACE_FIELDS), dtype=np.float64)
+    L = lib()
+    if dtype == np.float64:
+        L.oracle_trace_d(a.ctypes.data, int(cplx), POLICY[policy], tr.ctypes.data)
+    else:
+        L.oracle_trace_s(a.ctypes.data, int(cplx), POLICY[policy], int(rescue), tr.ctypes.data)
+    return dict(zip(TRACE_FIELDS, tr.tolist()))
+
+
+def metrics(ins: list, outs: list, cplx: bool, nthreads: int = 0) -> dict:
+    """kappa, rho, delta, eta of eqs. (32)-(35) per lane, in binary128."""
+    n = ins[0].shape[0]
+    res = {k: np.empty(n, dtype=np.float64) for k in ("kappa", "rho", "delta", "eta")}
+    L = lib()
+    f = L.oracle_metrics_d if ins[0].dtype == np.float64 else L.oracle_metrics_s
+    f(n, int(cplx), _ptrs(ins), _ptrs(outs), res["kappa"].ctypes.data, res["rho"].ctypes.data,
+      res["delta"].ctypes.data, res["eta"].ctypes.data, nthreads)
+    return res

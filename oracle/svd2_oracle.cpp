@@ -1,0 +1,609 @@
+/*
+ * svd2_oracle.cpp -- plain per-matrix CPU oracle of the batched 2x2 SVD.
+ *
+ * TEST INFRASTRUCTURE ONLY (see svd2_oracle.h).  Built with
+ * -O2 -ffp-contract=off -fno-fast-math so that every +, -, *, /, sqrt and fma
+ * below is one correctly rounded IEEE-754 operation, in the written order.
+ *
+ * The algorithm is the one of section 2 of arXiv:2005.07403, with the
+ * operation order of its vectorised description (sections 5-7, Figs. 3-10,
+ * and the expansion of eq. (29) in section 2.3).  Each matrix is processed on
+ * its own; there is no blocking, fusion or reordering.
+ */
+#include "svd2_oracle.h"
+
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <omp.h>
+#include <quadmath.h>
+#include <type_traits>
+#include <utility>
+
+namespace {
+
+/* ---------------------------------------------------------------------------
+ * Constants per element type.
+ *   h   : two less than the largest finite binary exponent (section 2.1)
+ *   big : the finite upper bound on s in eq. (2)
+ *   tm  : the smallest positive subnormal (eq. (1))
+ *   f   : sqrt(MAX) rounded to T, the clamp of tan 2phi in eq. (14)
+ * ------------------------------------------------------------------------- */
+template <class T> struct Lim;
+template <> struct Lim<double> {
+  static constexpr int h = DBL_MAX_EXP - 3; /* 1021 */
+  static double big() { return DBL_MAX; }
+  static double tm() { return DBL_TRUE_MIN; }
+  static double f() { return 0x1.fffffffffffffp+511; }
+};
+template <> struct Lim<float> {
+  static constexpr int h = FLT_MAX_EXP - 3; /* 125 */
+  static float big() { return FLT_MAX; }
+  static float tm() { return FLT_TRUE_MIN; }
+  static float f() { return 0x1.fffffep+63f; }
+};
+
+/* "Relaxed" min/max of section 2: the minimum (maximum) of two non-NaN
+ * arguments, or the second argument when the first is a NaN. */
+template <class T> inline T rmin(T a, T b) { return (a < b) ? a : b; }
+template <class T> inline T rmax(T a, T b) { return (a > b) ? a : b; }
+
+template <class T> inline T fmaT(T a, T b, T c) { return std::fma(a, b, c); }
+template <class T> inline T sqrtT(T a) { return std::sqrt(a); }
+
+/* hypot, two readings (the paper only demands hypot(a,b)=0 <=> a=b=0).
+ * MIRROR: the per-lane fallback of section 5 (Fig. 4 discussion):
+ *   a' = max|.|, b' = min|.|, q = b'/max(a', TRUE_MIN), c = a' sqrt(fma(q,q,1)).
+ * REF: sqrt(a^2+b^2) evaluated in binary128 and rounded once to T. */
+template <class T> T hypot_mirror(T a, T b) {
+  T aa = std::fabs(a), bb = std::fabs(b);
+  T hi = rmax(aa, bb), lo = rmin(aa, bb);
+  T q = lo / rmax(hi, Lim<T>::tm());
+  return hi * sqrtT(fmaT(q, q, T(1)));
+}
+template <class T> T hypot_ref(T a, T b) {
+  __float128 qa = a, qb = b;
+  return (T)sqrtq(qa * qa + qb * qb);
+}
+/* invsqrt(x) = 1/sqrt(x) (section 2, eq. (7)); MIRROR takes the first remedy
+ * of section 6 (divide one by the secant), REF rounds 1/sqrt once. */
+template <class T> T invsqrt_mirror(T x) { return T(1) / sqrtT(x); }
+template <class T> T invsqrt_ref(T x) { return (T)(1 / sqrtq((__float128)x)); }
+
+template <class T> struct Prim {
+  int policy;
+  T hyp(T a, T b) const { return policy == ORACLE_REF ? hypot_ref(a, b) : hypot_mirror(a, b); }
+  T isq(T x) const { return policy == ORACLE_REF ? invsqrt_ref(x) : invsqrt_mirror(x); }
+};
+
+/* exp2 of section 2.1: floor(lg|a|) for finite non-zero a (the true exponent,
+ * also for subnormals), -inf for zero.  Returned as E = h - exp2(a), so a zero
+ * component gives +inf. */
+template <class T> T scale_exponent(T a) {
+  if (a == T(0)) return (T)INFINITY;
+  return (T)(Lim<T>::h - std::ilogb(a));
+}
+/* SCALEF(a, s) = a 2^s, correctly rounded.  s is an integer-valued T, or BIG
+ * (then every component is zero and the zero is returned unchanged). */
+template <class T> T scalef(T a, T s) {
+  if (s == Lim<T>::big()) return a;
+  return std::ldexp(a, (int)s);
+}
+
+template <class T> struct Cx { T re, im; };
+
+/* eq. (5): c = a * b with one fma per component. */
+template <class T> Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {fmaT(a.re, b.re, -(a.im * b.im)), fmaT(a.re, b.im, a.im * b.re)};
+}
+/* conj(a) * b, eq. (5) with the conjugation folded into the signs (Fig. 7):
+ * re = fma(Re a, Re b, Im a Im b), im = fma(Re a, Im b, -(Im a Re b)). */
+template <class T> Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+  return {fmaT(a.re, b.re, a.im * b.im), fmaT(a.re, b.im, -(a.im * b.re))};
+}
+/* eq. (1): e^{i arg z} from z and |z|, without complex operations:
+ * cos = copysign(min(|Re z|/|z|, 1), Re z), sin = Im z / max(|z|, TRUE_MIN). */
+template <class T> Cx<T> phase(Cx<T> z, T absz) {
+  return {std::copysign(rmin(std::fabs(z.re) / absz, T(1)), z.re),
+          z.im / rmax(absz, Lim<T>::tm())};
+}
+
+/* Output of one matrix, in the element order of the header. */
+template <class T> struct Res {
+  Cx<T> u[2][2], v[2][2];
+  T smax, smin, s;
+};
+
+/* Intermediates kept for the trace entry point and for the FP64 rescue. */
+template <class T> struct Mid {
+  T s; bool c, r;
+  Cx<T> ah[2][2];     /* scaled input A^ = 2^s A, original positions */
+  Cx<T> d1, d2;       /* diagonal of D (conjugates of D*), eq. (4)   */
+  bool neg1, neg2;    /* real case: sign bits of a''_11, a''_21      */
+  T r11, r12, r22, mt, ca;
+  Cx<T> e12;          /* e^{i arg r'_12}; D~_22 = conj(e12), eq. (8)  */
+  bool negt;          /* real case: sign bit of r'_12                */
+  Cx<T> dh;           /* e^{i arg r'_22} = D^_22, eq. (9)            */
+  bool negh;          /* real case: sign bit of r'_22                */
+  T n1, n2;
+  T x, y, t2, tphi, sec2phi, cphi, tpsi, sec2psi, cpsi;
+};
+
+/* ---------------------------------------------------------------------------
+ * Section 2.3, eqs. (13)-(17) with the operation order of Fig. 10: the SVD of
+ * the non-negative upper-triangular R = [[r11, r12], [0, r22]].
+ * ------------------------------------------------------------------------- */
+template <class T> void triangular_svd(const Prim<T> &P, Mid<T> &m, T &smax, T &smin) {
+  const T one = T(1), zero = T(0);
+  m.x = rmax(m.r12 / m.r11, zero);                              /* eq. (13) */
+  m.y = rmax(m.r22 / m.r11, zero);
+  T lo = rmin(m.x, m.y), hi = rmax(m.x, m.y);
+  T num = std::ldexp(lo, 1) * hi;                               /* (2 min) max */
+  T den = fmaT(m.x - m.y, m.x + m.y, one);
+  m.t2 = -rmin(rmax(num / den, zero), Lim<T>::f());             /* eq. (14), sign forced */
+  m.tphi = m.t2 / (one + sqrtT(fmaT(m.t2, m.t2, one)));         /* eq. (15) */
+  m.sec2phi = fmaT(m.tphi, m.tphi, one);
+  m.cphi = P.isq(m.sec2phi);
+  m.tpsi = fmaT(m.y, m.tphi, -m.x);                             /* eq. (16) */
+  m.sec2psi = fmaT(m.tpsi, m.tpsi, one);
+  m.cpsi = P.isq(m.sec2psi);
+  T k = m.cphi * m.cpsi;                                        /* eq. (17) */
+  smax = (k * m.sec2psi) * m.r11;
+  smin = (k * m.sec2phi) * m.r22;
+}
+
+/* Section 2.1, eq. (2), Fig. 3: s and A^ = 2^s A over ncomp components. */
+template <class T> T scaling(const T *a, int ncomp, T *ah) {
+  T s = Lim<T>::big();
+  for (int i = 0; i < ncomp; ++i) s = rmin(s, scale_exponent(a[i]));
+  for (int i = 0; i < ncomp; ++i) ah[i] = scalef(a[i], s);
+  return s;
+}
+
+/* ---------------------------------------------------------------------------
+ * Complex case, one matrix.  a[8] = a11r,a11i,a21r,a21i,a12r,a12i,a22r,a22i.
+ * ------------------------------------------------------------------------- */
+template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T> &m) {
+  const T one = T(1);
+  /* scaling, eq. (2) */
+  T ahv[8];
+  m.s = scaling(a, 8, ahv);
+  Cx<T> A[2][2] = {{{ahv[0], ahv[1]}, {ahv[4], ahv[5]}},
+                   {{ahv[2], ahv[3]}, {ahv[6], ahv[7]}}}; /* A[i][j] = a^_{i+1,j+1} */
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) m.ah[i][j] = A[i][j];
+  /* |a^_ij| by eq. (1) and the column norms of eq. (3), Fig. 4 */
+  T mag[2][2];
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) mag[i][j] = P.hyp(A[i][j].re, A[i][j].im);
+  T nrm[2] = {P.hyp(mag[0][0], mag[1][0]), P.hyp(mag[0][1], mag[1][1])};
+  /* column pivoting P_c (section 2.2, Fig. 5): swap iff ||a^_1|| < ||a^_2|| */
+  m.c = nrm[0] < nrm[1];
+  if (m.c) {
+    for (int i = 0; i < 2; ++i) { std::swap(A[i][0], A[i][1]); std::swap(mag[i][0], mag[i][1]); }
+    std::swap(nrm[0], nrm[1]);
+  }
+  m.n1 = nrm[0]; m.n2 = nrm[1];
+  /* row sorting P_r* (Fig. 6): swap iff |a'_11| < |a'_21| */
+  m.r = mag[0][0] < mag[1][0];
+  if (m.r) {
+    for (int j = 0; j < 2; ++j) { std::swap(A[0][j], A[1][j]); std::swap(mag[0][j], mag[1][j]); }
+  }
+  /* D*, eq. (4), Fig. 7: a'''_i1 = |a''_i1|, a'''_i2 = conj(d_i) a''_i2 */
+  m.d1 = phase(A[0][0], mag[0][0]);
+  m.d2 = phase(A[1][0], mag[1][0]);
+  T a311 = mag[0][0], a321 = mag[1][0];
+  Cx<T> a312 = cmulc(m.d1, A[0][1]);
+  Cx<T> a322 = cmulc(m.d2, A[1][1]);
+  /* Givens QR, eqs. (6)-(7), Fig. 8.  mt = -tan(alpha) >= 0. */
+  m.r11 = nrm[0];
+  m.mt = rmax(a321 / a311, T(0));
+  m.ca = P.isq(fmaT(m.mt, m.mt, one));
+  Cx<T> r12p = {m.ca * fmaT(m.mt, a322.re, a312.re), m.ca * fmaT(m.mt, a322.im, a312.im)};
+  Cx<T> r22pp = {m.ca * fmaT(-m.mt, a312.re, a322.re), m.ca * fmaT(-m.mt, a312.im, a322.im)};
+  /* D~, eq. (8), Fig. 9: r12 = |r'_12|, r'_22 = r''_22 conj(e^{i arg r'_12}) */
+  m.r12 = P.hyp(r12p.re, r12p.im);
+  m.e12 = phase(r12p, m.r12);
+  Cx<T> r22p = {fmaT(r22pp.re, m.e12.re, r22pp.im * m.e12.im),
+                fmaT(r22pp.im, m.e12.re, -(r22pp.re * m.e12.im))};
+  /* D^, eq. (9), Fig. 9: r22 = |r'_22| */
+  m.r22 = P.hyp(r22p.re, r22p.im);
+  m.dh = phase(r22p, m.r22);
+  /* triangular SVD, eqs. (13)-(17) */
+  triangular_svd(P, m, o.smax, o.smin);
+  /* assembly of U and V, eq. (29) and its expansion (section 2.3).
+   * C = cos(alpha) cos(phi), t = -tan(alpha) tan(phi), tan(alpha) = -mt. */
+  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
+  Cx<T> w11 = {fmaT(m.dh.re, t, one), m.dh.im * t};
+  Cx<T> w21 = {fmaT(m.dh.re, m.tphi, ta), m.dh.im * m.tphi};
+  Cx<T> w12 = {fmaT(m.dh.re, ta, m.tphi), m.dh.im * ta};
+  Cx<T> w22 = {fmaT(m.mt, m.tphi, m.dh.re), m.dh.im};
+  Cx<T> p11 = cmul(m.d1, w11), p21 = cmul(m.d2, w21), p12 = cmul(m.d1, w12), p22 = cmul(m.d2, w22);
+  Cx<T> U[2][2] = {{{C * p11.re, C * p11.im}, {C * p12.re, C * p12.im}},
+                   {{-(C * p21.re), -(C * p21.im)}, {C * p22.re, C * p22.im}}};
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); } /* P_r */
+  /* V = cos(psi) P_c [[1, tan psi], [-d~ tan psi, d~]], d~ = conj(e12) */
+  T ct = m.cpsi * m.tpsi;
+  Cx<T> V[2][2] = {{{m.cpsi, T(0)}, {ct, T(0)}},
+                   {{-(ct * m.e12.re), ct * m.e12.im}, {m.cpsi * m.e12.re, -(m.cpsi * m.e12.im)}}};
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); } /* P_c */
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) { o.u[i][j] = U[i][j]; o.v[i][j] = V[i][j]; }
+  o.s = m.s;
+}
+
+/* ---------------------------------------------------------------------------
+ * Real case, one matrix.  a[4] = a11, a21, a12, a22.  D*, D~ and D^ of
+ * eq. (10) are sign flips (the sign bit of the pivot, -0 counting as
+ * negative), applied as negations.
+ * ------------------------------------------------------------------------- */
+template <class T> void dsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T> &m) {
+  const T one = T(1);
+  T ahv[4];
+  m.s = scaling(a, 4, ahv);
+  T A[2][2] = {{ahv[0], ahv[2]}, {ahv[1], ahv[3]}};
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) m.ah[i][j] = {A[i][j], T(0)};
+  T mag[2][2];
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) mag[i][j] = std::fabs(A[i][j]);
+  T nrm[2] = {P.hyp(mag[0][0], mag[1][0]), P.hyp(mag[0][1], mag[1][1])};
+  m.c = nrm[0] < nrm[1];
+  if (m.c) {
+    for (int i = 0; i < 2; ++i) { std::swap(A[i][0], A[i][1]); std::swap(mag[i][0], mag[i][1]); }
+    std::swap(nrm[0], nrm[1]);
+  }
+  m.n1 = nrm[0]; m.n2 = nrm[1];
+  m.r = mag[0][0] < mag[1][0];
+  if (m.r) {
+    for (int j = 0; j < 2; ++j) { std::swap(A[0][j], A[1][j]); std::swap(mag[0][j], mag[1][j]); }
+  }
+  m.neg1 = std::signbit(A[0][0]);
+  m.neg2 = std::signbit(A[1][0]);
+  m.d1 = {m.neg1 ? -one : one, T(0)};
+  m.d2 = {m.neg2 ? -one : one, T(0)};
+  T a311 = mag[0][0], a321 = mag[1][0];
+  T a312 = m.neg1 ? -A[0][1] : A[0][1];
+  T a322 = m.neg2 ? -A[1][1] : A[1][1];
+  m.r11 = nrm[0];
+  m.mt = rmax(a321 / a311, T(0));
+  m.ca = P.isq(fmaT(m.mt, m.mt, one));
+  T r12p = m.ca * fmaT(m.mt, a322, a312);
+  T r22pp = m.ca * fmaT(-m.mt, a312, a322);
+  m.negt = std::signbit(r12p);
+  m.e12 = {m.negt ? -one : one, T(0)};
+  m.r12 = std::fabs(r12p);
+  T r22p = m.negt ? -r22pp : r22pp;
+  m.negh = std::signbit(r22p);
+  m.dh = {m.negh ? -one : one, T(0)};
+  m.r22 = std::fabs(r22p);
+  triangular_svd(P, m, o.smax, o.smin);
+  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
+  T dh = m.dh.re;
+  T w11 = fmaT(dh, t, one), w21 = fmaT(dh, m.tphi, ta), w12 = fmaT(dh, ta, m.tphi),
+    w22 = fmaT(m.mt, m.tphi, dh);
+  T U[2][2] = {{C * (m.neg1 ? -w11 : w11), C * (m.neg1 ? -w12 : w12)},
+               {-(C * (m.neg2 ? -w21 : w21)), C * (m.neg2 ? -w22 : w22)}};
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); }
+  T ct = m.cpsi * m.tpsi;
+  T V[2][2] = {{m.cpsi, ct}, {m.negt ? ct : -ct, m.negt ? -m.cpsi : m.cpsi}};
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); }
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+    o.u[i][j] = {U[i][j], T(0)};
+    o.v[i][j] = {V[i][j], T(0)};
+  }
+  o.s = m.s;
+}
+
+/* ---------------------------------------------------------------------------
+ * Backscaling, eq. (28) and Fig. 1.
+ * ------------------------------------------------------------------------- */
+template <class T> void backscale(Res<T> &o, int mode) {
+  if (mode == ORACLE_BS_NONE) return;
+  T smax = o.smax, smin = o.smin; /* zero matrix (s = BIG): sigma' = 0 already */
+  if (o.s != Lim<T>::big()) {
+    T ns = -o.s; /* negation by the sign bit, as in Fig. 1 */
+    smax = scalef(o.smax, ns);
+    smin = scalef(o.smin, ns);
+  }
+  if (mode == ORACLE_BS_SAFE) {
+    bool exact = std::isfinite(smax) && std::isfinite(smin) &&
+                 scalef(smax, o.s) == o.smax && scalef(smin, o.s) == o.smin;
+    if (!exact) return;
+  }
+  o.smax = smax; o.smin = smin; o.s = -T(0);
+}
+
+/* ---------------------------------------------------------------------------
+ * FP64 rescue of a near-degenerate FP32 lane.
+ *
+ * In FP32 the (2,2) entry of R'' in eq. (6) is a difference that cancels when
+ * A is nearly singular, so sigma'_min loses relative accuracy.  Its magnitude
+ * is fixed by det: r11 r'_22 = det(R') = det(Q*) det(D*) det(P_r*) det(A^)
+ * det(P_c) det(D~) with det(Q*) = 1, each swap contributing -1, and
+ * det(D*) = conj(d1 d2), det(D~) = conj(e12).  Products of two FP32 numbers
+ * are exact in FP64, so det(A^) is formed in FP64 with a compensated sum, r'_22
+ * is recomputed from it, and eqs. (9), (13)-(17) and (29) are evaluated in
+ * FP64 from the FP32 pivots, phases and rotation alpha.  The result is
+ * rounded to FP32.
+ * ------------------------------------------------------------------------- */
+inline void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+/* a + b + c + d, accumulated with error-free transformations (cascaded
+ * TwoSum with the rounding errors summed separately). */
+inline double sum4(double a, double b, double c, double d) {
+  double s, e, acc;
+  two_sum(a, b, s, acc);
+  two_sum(s, c, s, e); acc += e;
+  two_sum(s, d, s, e); acc += e;
+  return s + acc;
+}
+
+template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
+  Prim<double> P{ORACLE_MIRROR};
+  const double one = 1.0;
+  Cx<double> a[2][2];
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) a[i][j] = {(double)m.ah[i][j].re, (double)m.ah[i][j].im};
+  Cx<double> det;
+  if (CPLX) {
+    det.re = sum4(a[0][0].re * a[1][1].re, -(a[0][0].im * a[1][1].im),
+                  -(a[0][1].re * a[1][0].re), a[0][1].im * a[1][0].im);
+    det.im = sum4(a[0][0].re * a[1][1].im, a[0][0].im * a[1][1].re,
+                  -(a[0][1].re * a[1][0].im), -(a[0][1].im * a[1][0].re));
+  } else {
+    det.re = a[0][0].re * a[1][1].re - a[0][1].re * a[1][0].re;
+    det.im = 0.0;
+  }
+  double sgn = (m.c != m.r) ? -one : one;
+  Mid<double> w{};
+  w.r11 = m.r11; w.r12 = m.r12; w.mt = m.mt; w.ca = m.ca;
+  double r22p_re, r22p_im;
+  if (CPLX) {
+    Cx<double> d1 = {m.d1.re, m.d1.im}, d2 = {m.d2.re, m.d2.im}, e = {m.e12.re, m.e12.im};
+    Cx<double> ph = cmul(cmul(d1, d2), e);  /* d1 d2 e12; det(D*)det(D~) = conj of it */
+    Cx<double> q = cmulc(ph, det);          /* conj(d1 d2 e12) det(A^) */
+    r22p_re = sgn * (q.re / w.r11);
+    r22p_im = sgn * (q.im / w.r11);
+    w.r22 = P.hyp(r22p_re, r22p_im);
+    w.dh = phase(Cx<double>{r22p_re, r22p_im}, w.r22);
+  } else {
+    if (m.neg1 != m.neg2) sgn = -sgn;
+    if (m.negt) sgn = -sgn;
+    r22p_re = sgn * (det.re / w.r11);
+    w.negh = std::signbit(r22p_re);
+    w.r22 = std::fabs(r22p_re);
+    w.dh = {w.negh ? -one : one, 0.0};
+  }
+  double smax, smin;
+  triangular_svd(P, w, smax, smin);
+  double C = w.ca * w.cphi, ta = -w.mt, t = w.mt * w.tphi;
+  Cx<double> U[2][2], V[2][2];
+  double ct = w.cpsi * w.tpsi;
+  if (CPLX) {
+    Cx<double> d1 = {m.d1.re, m.d1.im}, d2 = {m.d2.re, m.d2.im}, e = {m.e12.re, m.e12.im};
+    Cx<double> w11 = {fmaT(w.dh.re, t, one), w.dh.im * t};
+    Cx<double> w21 = {fmaT(w.dh.re, w.tphi, ta), w.dh.im * w.tphi};
+    Cx<double> w12 = {fmaT(w.dh.re, ta, w.tphi), w.dh.im * ta};
+    Cx<double> w22 = {fmaT(w.mt, w.tphi, w.dh.re), w.dh.im};
+    Cx<double> p11 = cmul(d1, w11), p21 = cmul(d2, w21), p12 = cmul(d1, w12), p22 = cmul(d2, w22);
+    U[0][0] = {C * p11.re, C * p11.im}; U[0][1] = {C * p12.re, C * p12.im};
+    U[1][0] = {-(C * p21.re), -(C * p21.im)}; U[1][1] = {C * p22.re, C * p22.im};
+    V[0][0] = {w.cpsi, 0.0}; V[0][1] = {ct, 0.0};
+    V[1][0] = {-(ct * e.re), ct * e.im}; V[1][1] = {w.cpsi * e.re, -(w.cpsi * e.im)};
+  } else {
+    double dh = w.dh.re;
+    double w11 = fmaT(dh, t, one), w21 = fmaT(dh, w.tphi, ta), w12 = fmaT(dh, ta, w.tphi),
+           w22 = fmaT(w.mt, w.tphi, dh);
+    U[0][0] = {C * (m.neg1 ? -w11 : w11), 0.0}; U[0][1] = {C * (m.neg1 ? -w12 : w12), 0.0};
+    U[1][0] = {-(C * (m.neg2 ? -w21 : w21)), 0.0}; U[1][1] = {C * (m.neg2 ? -w22 : w22), 0.0};
+    V[0][0] = {w.cpsi, 0.0}; V[0][1] = {ct, 0.0};
+    V[1][0] = {m.negt ? ct : -ct, 0.0}; V[1][1] = {m.negt ? -w.cpsi : w.cpsi, 0.0};
+  }
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); }
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); }
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+    o.u[i][j] = {(float)U[i][j].re, (float)U[i][j].im};
+    o.v[i][j] = {(float)V[i][j].re, (float)V[i][j].im};
+  }
+  o.smax = (float)smax;
+  o.smin = (float)smin;
+}
+
+/* Lane flag for the rescue: smin' < 2^-20 smax' (a zero matrix is not flagged). */
+inline bool near_degenerate(float smax, float smin) { return smin < std::ldexp(smax, -20); }
+
+/* ---------------------------------------------------------------------------
+ * Batched drivers: the loop over matrices (Fig. 2 with a lane width of one).
+ * ------------------------------------------------------------------------- */
+template <class T, bool CPLX>
+void run_one(const Prim<T> &P, const T *const *in, size_t k, Res<T> &o, Mid<T> &m) {
+  if (CPLX) {
+    T a[8];
+    for (int i = 0; i < 8; ++i) a[i] = in[i][k];
+    zsvd2_one(P, a, o, m);
+  } else {
+    T a[4];
+    for (int i = 0; i < 4; ++i) a[i] = in[i][k];
+    dsvd2_one(P, a, o, m);
+  }
+}
+
+template <class T, bool CPLX>
+void store(const Res<T> &o, T *const *out, size_t k) {
+  /* element order 11, 21, 12, 22 */
+  const int ii[4] = {0, 1, 0, 1}, jj[4] = {0, 0, 1, 1};
+  if (CPLX) {
+    for (int e = 0; e < 4; ++e) {
+      out[2 * e][k] = o.u[ii[e]][jj[e]].re; out[2 * e + 1][k] = o.u[ii[e]][jj[e]].im;
+      out[8 + 2 * e][k] = o.v[ii[e]][jj[e]].re; out[8 + 2 * e + 1][k] = o.v[ii[e]][jj[e]].im;
+    }
+    out[16][k] = o.smax; out[17][k] = o.smin; out[18][k] = o.s;
+  } else {
+    for (int e = 0; e < 4; ++e) {
+      out[e][k] = o.u[ii[e]][jj[e]].re;
+      out[4 + e][k] = o.v[ii[e]][jj[e]].re;
+    }
+    out[8][k] = o.smax; out[9][k] = o.smin; out[10][k] = o.s;
+  }
+}
+
+template <class T, bool CPLX>
+void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int rescue,
+           uint8_t *flagged, int nthreads) {
+  Prim<T> P{policy};
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (long long kk = 0; kk < (long long)n; ++kk) {
+    size_t k = (size_t)kk;
+    Res<T> o;
+    Mid<T> m{};
+    run_one<T, CPLX>(P, in, k, o, m);
+    bool fl = false;
+    if constexpr (std::is_same<T, float>::value) {
+      if (rescue && near_degenerate(o.smax, o.smin)) {
+        rescue_fp64<CPLX>(m, o);
+        fl = true;
+      }
+    }
+    if (flagged) flagged[k] = fl ? 1 : 0;
+    backscale(o, bs);
+    store<T, CPLX>(o, out, k);
+  }
+}
+
+template <class T> void fill_trace(const Mid<T> &m, const Res<T> &o, double *tr) {
+  double v[ORACLE_TRACE_LEN] = {(double)m.s, (double)m.c, (double)m.r, (double)m.r11,
+      (double)m.r12, (double)m.r22, (double)m.mt, (double)m.ca, (double)m.x, (double)m.y,
+      (double)m.t2, (double)m.tphi, (double)m.sec2phi, (double)m.cphi, (double)m.tpsi,
+      (double)m.sec2psi, (double)m.cpsi, (double)o.smax, (double)o.smin, (double)m.n1,
+      (double)m.n2, 0.0};
+  std::memcpy(tr, v, sizeof v);
+}
+
+/* ---------------------------------------------------------------------------
+ * Metrics of section 8 in binary128.
+ * ------------------------------------------------------------------------- */
+struct Q { __float128 re, im; };
+inline Q qmul(Q a, Q b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline Q qconj(Q a) { return {a.re, -a.im}; }
+inline __float128 qabs2(Q a) { return a.re * a.re + a.im * a.im; }
+
+template <class T>
+void metrics_one(int cplx, const T *const *in, const T *const *out, size_t k,
+                 double &kappa, double &rho, double &delta, double &eta) {
+  Q A[2][2], U[2][2], V[2][2];
+  const int ii[4] = {0, 1, 0, 1}, jj[4] = {0, 0, 1, 1};
+  for (int e = 0; e < 4; ++e) {
+    if (cplx) {
+      A[ii[e]][jj[e]] = {(__float128)in[2 * e][k], (__float128)in[2 * e + 1][k]};
+      U[ii[e]][jj[e]] = {(__float128)out[2 * e][k], (__float128)out[2 * e + 1][k]};
+      V[ii[e]][jj[e]] = {(__float128)out[8 + 2 * e][k], (__float128)out[8 + 2 * e + 1][k]};
+    } else {
+      A[ii[e]][jj[e]] = {(__float128)in[e][k], 0};
+      U[ii[e]][jj[e]] = {(__float128)out[e][k], 0};
+      V[ii[e]][jj[e]] = {(__float128)out[4 + e][k], 0};
+    }
+  }
+  int base = cplx ? 16 : 8;
+  T smax = out[base][k], smin = out[base + 1][k], s = out[base + 2][k];
+  __float128 sig[2];
+  if (s == Lim<T>::big()) { sig[0] = smax; sig[1] = smin; }
+  else { sig[0] = ldexpq((__float128)smax, -(int)s); sig[1] = ldexpq((__float128)smin, -(int)s); }
+  /* eq. (32): kappa = fmin(smax/smin, inf) */
+  __float128 kq = sig[0] / sig[1];
+  kappa = (kq != kq) ? INFINITY : (double)kq;
+  /* eq. (33): ||U Sigma V* - A||_F / ||A||_F, NaN (zero A) -> 0 */
+  __float128 num = 0, den = 0;
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+    Q acc = {0, 0};
+    for (int l = 0; l < 2; ++l) {
+      Q t = qmul(U[i][l], qconj(V[j][l]));
+      acc.re += sig[l] * t.re; acc.im += sig[l] * t.im;
+    }
+    Q d = {acc.re - A[i][j].re, acc.im - A[i][j].im};
+    num += qabs2(d);
+    den += qabs2(A[i][j]);
+  }
+  __float128 rq = sqrtq(num) / sqrtq(den);
+  rho = (rq != rq) ? 0.0 : (double)rq;
+  /* eqs. (34)-(35): ||X* X - I||_F */
+  auto orth = [](Q X[2][2]) {
+    __float128 acc = 0;
+    for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+      Q g = {0, 0};
+      for (int l = 0; l < 2; ++l) {
+        Q t = qmul(qconj(X[l][i]), X[l][j]);
+        g.re += t.re; g.im += t.im;
+      }
+      if (i == j) g.re -= 1;
+      acc += qabs2(g);
+    }
+    return (double)sqrtq(acc);
+  };
+  delta = orth(U);
+  eta = orth(V);
+}
+
+template <class T>
+void metrics(size_t n, int cplx, const T *const *in, const T *const *out, double *kappa,
+             double *rho, double *delta, double *eta, int nthreads) {
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (long long kk = 0; kk < (long long)n; ++kk)
+    metrics_one<T>(cplx, in, out, (size_t)kk, kappa[kk], rho[kk], delta[kk], eta[kk]);
+}
+
+} /* namespace */
+
+extern "C" {
+
+int oracle_dsvd2(size_t n, const double *const *in, double *const *out, int policy,
+                 int backscale_mode, int nthreads) {
+  batch<double, false>(n, in, out, policy, backscale_mode, 0, nullptr, nthreads);
+  return 0;
+}
+int oracle_zsvd2(size_t n, const double *const *in, double *const *out, int policy,
+                 int backscale_mode, int nthreads) {
+  batch<double, true>(n, in, out, policy, backscale_mode, 0, nullptr, nthreads);
+  return 0;
+}
+int oracle_ssvd2(size_t n, const float *const *in, float *const *out, int policy,
+                 int backscale_mode, int rescue, uint8_t *flagged, int nthreads) {
+  batch<float, false>(n, in, out, policy, backscale_mode, rescue, flagged, nthreads);
+  return 0;
+}
+int oracle_csvd2(size_t n, const float *const *in, float *const *out, int policy,
+                 int backscale_mode, int rescue, uint8_t *flagged, int nthreads) {
+  batch<float, true>(n, in, out, policy, backscale_mode, rescue, flagged, nthreads);
+  return 0;
+}
+
+int oracle_trace_d(const double *a, int cplx, int policy, double *trace) {
+  Prim<double> P{policy};
+  Res<double> o; Mid<double> m{};
+  if (cplx) zsvd2_one(P, a, o, m); else dsvd2_one(P, a, o, m);
+  fill_trace(m, o, trace);
+  return 0;
+}
+int oracle_trace_s(const float *a, int cplx, int policy, int rescue, double *trace) {
+  Prim<float> P{policy};
+  Res<float> o; Mid<float> m{};
+  if (cplx) zsvd2_one(P, a, o, m); else dsvd2_one(P, a, o, m);
+  fill_trace(m, o, trace);
+  if (rescue && near_degenerate(o.smax, o.smin)) {
+    if (cplx) rescue_fp64<true>(m, o); else rescue_fp64<false>(m, o);
+    trace[17] = o.smax; trace[18] = o.smin; trace[21] = 1.0;
+  }
+  return 0;
+}
+
+int oracle_metrics_d(size_t n, int cplx, const double *const *in, const double *const *out,
+                     double *kappa, double *rho, double *delta, double *eta, int nthreads) {
+  metrics<double>(n, cplx, in, out, kappa, rho, delta, eta, nthreads);
+  return 0;
+}
+int oracle_metrics_s(size_t n, int cplx, const float *const *in, const float *const *out,
+                     double *kappa, double *rho, double *delta, double *eta, int nthreads) {
+  metrics<float>(n, cplx, in, out, kappa, rho, delta, eta, nthreads);
+  return 0;
+}
+
+} /* extern "C" */

@@ -1,0 +1,85 @@
+/*
+ * svd2_oracle.h -- plain, slow CPU oracle for the batched 2x2 SVD.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no source with the GPU path.
+ *
+ * Source: V. Novakovic, "Batched computation of the singular value
+ * decompositions of order two by the AVX-512 vectorization" (arXiv:2005.07403).
+ * Every step is written per matrix, in the paper's order (section 2 for the
+ * mathematics, sections 5-7 for the operation order), with correctly rounded
+ * IEEE-754 basic operations (+, -, *, /, sqrt, fma, ldexp).
+ *
+ * Data layout (section 3): structure of arrays, one array per matrix element
+ * and per real/imaginary part, in the record order of section 8:
+ *   real:    a11, a21, a12, a22
+ *   complex: a11r, a11i, a21r, a21i, a12r, a12i, a22r, a22i
+ * Outputs, in the same element order:
+ *   real:    u11,u21,u12,u22, v11,v21,v12,v22, smax, smin, s        (11 arrays)
+ *   complex: u11r,u11i,...,u22i, v11r,...,v22i, smax, smin, s      (19 arrays)
+ * smax/smin are the scaled singular values sigma' of eq. (12) and s is the
+ * exponent of eq. (2), stored in the element type (BIG for a zero matrix, -0
+ * after a backscale as in Fig. 1).
+ */
+#ifndef SVD2_ORACLE_H
+#define SVD2_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hypot / invsqrt policy (the paper fixes only their contract, section 2) */
+enum { ORACLE_REF = 0,    /* hypot and 1/sqrt correctly rounded via __float128 */
+       ORACLE_MIRROR = 1  /* hypot = the division-based fallback of section 5,
+                             invsqrt = 1/sqrt(x): two correctly rounded ops    */ };
+
+/* backscale mode of eq. (28) */
+enum { ORACLE_BS_NONE = 0, /* write sigma' and s (the paper's default)          */
+       ORACLE_BS_SAFE = 1, /* per lane, only if 2^-s sigma' is exact and finite */
+       ORACLE_BS_ALL = 2   /* Fig. 1: unconditional                             */ };
+
+/* Batched SVD over n matrices.  in/out are arrays of host pointers as above.
+ * rescue (float only): 0 = plain FP32 algorithm; 1 = recompute R's (2,2)
+ * entry from det(A^) in FP64 on lanes with smin' < 2^-20 smax', then run the
+ * triangular SVD and the assembly of U, V in FP64 for those lanes.
+ * flagged (optional, may be NULL): per-lane 0/1 marks of rescued lanes.
+ * nthreads <= 0: use the OpenMP default.  Returns 0. */
+int oracle_dsvd2(size_t n, const double *const *in, double *const *out,
+                 int policy, int backscale, int nthreads);
+int oracle_zsvd2(size_t n, const double *const *in, double *const *out,
+                 int policy, int backscale, int nthreads);
+int oracle_ssvd2(size_t n, const float *const *in, float *const *out,
+                 int policy, int backscale, int rescue, uint8_t *flagged,
+                 int nthreads);
+int oracle_csvd2(size_t n, const float *const *in, float *const *out,
+                 int policy, int backscale, int rescue, uint8_t *flagged,
+                 int nthreads);
+
+/* Intermediates of one matrix, for the invariant tests of Theorem 1.
+ * Layout of trace[ORACLE_TRACE_LEN] (doubles, float results widened):
+ *  0 s      1 c(col swap)  2 r(row swap)  3 r11   4 r12   5 r22
+ *  6 mt(=-tan alpha)      7 cos alpha     8 x     9 y    10 tan 2phi
+ * 11 tan phi 12 sec^2 phi 13 cos phi     14 tan psi 15 sec^2 psi 16 cos psi
+ * 17 smax'  18 smin'  19 n1 (first column norm after pivoting) 20 n2
+ * 21 rescued (float only) */
+#define ORACLE_TRACE_LEN 22
+int oracle_trace_d(const double *a, int cplx, int policy, double *trace);
+int oracle_trace_s(const float *a, int cplx, int policy, int rescue, double *trace);
+
+/* Error metrics of section 8, eqs. (32)-(35), per lane, in __float128.
+ * sigma = 2^-s sigma' is formed exactly in quad precision.
+ * Results (rounded to double): kappa, rho, delta, eta (arrays of n). */
+int oracle_metrics_d(size_t n, int cplx, const double *const *in,
+                     const double *const *out, double *kappa, double *rho,
+                     double *delta, double *eta, int nthreads);
+int oracle_metrics_s(size_t n, int cplx, const float *const *in,
+                     const float *const *out, double *kappa, double *rho,
+                     double *delta, double *eta, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
