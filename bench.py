@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched 2x2 SVD on one MI355X.
+
+Headline (one JSON line on stdout): complex FP64 batched SVD, n = 2^24 matrices
+whose real and imaginary parts are +-m 2^e (m ~ U[1,2), e ~ U{-1000..1000})
+with 1 % special lanes, in SoA layout resident in HBM.  One step = one
+zsvd2_batch call over the whole batch.  value = SVDs per second.
+
+The same line carries the other forms of the metric (real FP64, real and
+complex FP32 with the FP64 rescue, at n = 2^24; the Kogbetliantz solver when
+built), the roofline of the dominant kernel measured with HIP events on the
+launch stream, and the CPU oracle timed on this host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2×2 SVDs/s at n=2^24 (FP64, FP32) + % HBM roofline; Kogbetliantz sweeps/s"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per SVD: SoA inputs read once + U, V, smax, smin, s written once
+BYTES_PER_SVD = {"d": 120, "z": 216, "s": 60, "c": 108}
+# launch shape (threads per block, matrices per lane) used by the benchmark
+DEFAULT_LAUNCH = {"d": (256, 2), "z": (256, 1), "s": (256, 2), "c": (256, 2)}
+KERNEL_SOURCES = ["paper_2005_07403_amd/csrc/svd2_batch.hip", "paper_2005_07403_amd/csrc/svd2_lane.hpp"]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_inputs(variant: str, n: int, seed_off: int = 1):
+    from workloads import SEED_BASE, scaled_law, to_trains
+    cplx = variant in ("z", "c")
+    dtype = np.float64 if variant in ("d", "z") else np.float32
+    A = scaled_law(n, SEED_BASE + seed_off, cplx, dtype=dtype)
+    return to_trains(A, dtype)
+
+
+def time_variant(variant: str, trains_np, steps: int, warmup: int, flags: int):
+    """Time `steps` batched calls on inputs resident in HBM.  Returns a dict
+    with the wall-clock time of the timed region and the per-launch kernel
+    time from HIP events recorded on the launch stream."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    S.svd2_set_launch(*DEFAULT_LAUNCH[variant])
+    dev = [torch.from_numpy(t).cuda() for t in trains_np]
+    n = dev[0].numel()
+    nout = 19 if len(dev) == 8 else 11
+    out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(nout)]
+    ws = None
+    wsb = S.svd2_workspace_bytes(n, flags) if dev[0].dtype == torch.float32 else 0
+    if wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.svd2(dev, flags=flags, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        S.svd2(dev, flags=flags, out=out, ws=ws)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms = [a.elapsed_time(b) for a, b in ev]
+    del dev, out, ws
+    torch.cuda.empty_cache()
+    return dict(n=n, wall_s=t1 - t0, kernel_ms=kms)
+
+
+def cpu_baseline(variant: str, trains_np, budget_s: float = 12.0):
+    """The oracle (MIRROR policy, OpenMP over matrices) on this host."""
+    import oracle.oracle as O
+    cplx = len(trains_np) == 8
+    dtype = trains_np[0].dtype
+    nthreads = os.cpu_count() or 1
+    try:
+        nthreads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    n = trains_np[0].shape[0]
+    reps, t_total = 0, 0.0
+    while t_total < budget_s and reps < 50:
+        t0 = time.perf_counter()
+        O.run_trains(trains_np, cplx, dtype, policy="mirror", rescue=(dtype == np.float32),
+                     nthreads=nthreads)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return dict(value=reps * n / t_total, unit="SVDs/s", cores=nthreads, kind="oracle",
+                sample=f"{reps} pass(es) over the same {n}-matrix batch "
+                       f"({'complex' if cplx else 'real'} {dtype.name}), {t_total:.1f} s")
+
+
+def read_traffic(kernel_key: str):
+    """HBM bytes per dispatch from the committed rocprofv3 --pmc summary, or
+    None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_dispatch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != source_hash():
+        return None
+    return float(b.group(1))
+
+
+def summarize(variant, r, flags_desc=""):
+    n = r["n"]
+    kms = float(np.mean(r["kernel_ms"]))
+    wall_ms = r["wall_s"] * 1e3 / len(r["kernel_ms"])
+    gbs = BYTES_PER_SVD[variant] * n / (kms * 1e-3) / 1e9
+    return dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
+                kernel_ms_min=float(np.min(r["kernel_ms"])), algorithmic_GBs=gbs,
+                hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=BYTES_PER_SVD[variant],
+                flags=flags_desc)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", choices=["d", "z", "s", "c"], default=None,
+                    help="time one variant only (for profiling runs)")
+    ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the batched SVD shards trivially by contiguous chunks; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    S.lib()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB done")
+        return
+
+    variants = [args.only] if args.only else ["z", "d", "s", "c"]
+    flags = {"d": 0, "z": 0, "s": S.SVD2_RESCUE_FP64, "c": S.SVD2_RESCUE_FP64}
+    flag_desc = {"d": "", "z": "", "s": "RESCUE_FP64", "c": "RESCUE_FP64"}
+    results, inputs_z = {}, None
+    for v in variants:
+        log(f"[bench] generating {v} inputs n={args.n}")
+        tr = make_inputs(v, args.n)
+        log(f"[bench] timing {v}: warmup {args.warmup}, steps {args.steps}")
+        r = time_variant(v, tr, args.steps, args.warmup, flags[v])
+        results[v] = summarize(v, r, flag_desc[v])
+        log(f"[bench] {v}: {json.dumps(results[v])}")
+        if v == "z":
+            inputs_z = tr
+        else:
+            del tr
+
+    head = "z" if "z" in results else variants[0]
+    h = results[head]
+    steps = args.steps
+    cpu = None
+    if not args.no_cpu_baseline and inputs_z is not None:
+        log("[bench] CPU baseline (oracle) ...")
+        cpu = cpu_baseline("z", inputs_z)
+        log(f"[bench] cpu: {json.dumps(cpu)}")
+    traffic = read_traffic(f"svd2_{head}")
+    dtype_name = {"d": "f64", "z": "f64", "s": "f32", "c": "f32"}[head]
+    line = {
+        "metric": METRIC,
+        "value": h["svds_per_s"],
+        "unit": "SVDs/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic (seeded +-m 2^e law with 1% special lanes; stands in for the "
+                "paper's private random-bit file)",
+        "config": {"workload": {"z": "complex FP64 batched 2x2 SVD",
+                                "d": "real FP64 batched 2x2 SVD",
+                                "s": "real FP32 batched 2x2 SVD + FP64 rescue",
+                                "c": "complex FP32 batched 2x2 SVD + FP64 rescue"}[head],
+                   "n": h["n"], "layout": "SoA", "exponents": "e in [-1000,1000]" if head in "dz"
+                   else "e in [-120,120]", "special_lanes": 0.01,
+                   "launch": list(DEFAULT_LAUNCH[head])},
+        "roofline": {"bound": "hbm", "achieved": h["algorithmic_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": h["hbm_frac"],
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "variants": results,
+        "kernel_source_sha": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * svd2.h -- C ABI of libsvd2: batched SVDs of order two on MI355X (gfx950).
+ *
+ * Method: V. Novakovic, "Batched computation of the singular value
+ * decompositions of order two by the AVX-512 vectorization",
+ * arXiv:2005.07403.  For each k < n the library computes A = U Sigma V* of a
+ * real or complex 2x2 matrix A (section 1), as
+ *   exact power-of-two scaling A^ = 2^s A            (section 2.1, eq. (2)),
+ *   URV factorisation R = U+* A^ V+                  (section 2.2, eqs. (3)-(11)),
+ *   SVD of the non-negative upper-triangular R       (section 2.3, eqs. (12)-(17)),
+ *   assembly of U and V                              (eqs. (28)-(29)).
+ * One GPU lane computes one matrix; there is no branching on data except the
+ * optional FP64 rescue of near-degenerate FP32 lanes.
+ *
+ * Data layout (section 3): structure of arrays.  Every matrix element (and,
+ * for complex data, its real and imaginary part) is its own contiguous array
+ * of n elements; element k of every array belongs to matrix k.  Argument
+ * order follows the record layout of section 8: 11, 21, 12, 22.
+ *
+ * Outputs: U, V in the same layout; smax, smin = the scaled singular values
+ * sigma'_max >= sigma'_min >= 0 of eq. (12) (Theorem 1: always finite); s = the
+ * exponent of eq. (2) stored in the element type: Sigma = 2^-s Sigma'.
+ * s is the largest finite value of the type for a zero matrix, and -0 after a
+ * backscale.  By default sigma' and s are returned unscaled, as the paper
+ * recommends (eq. (28) and Fig. 1); see the SVD2_BACKSCALE_* flags.
+ *
+ * Conventions, for every entry point:
+ *  - All array pointers are DEVICE pointers (hipMalloc / torch allocations)
+ *    owned by the caller; the library keeps no reference after the call and
+ *    allocates nothing.  The argument struct is read on the host during the
+ *    call only.
+ *  - Work is enqueued on `stream` and the call returns without waiting;
+ *    results are valid once the stream has been synchronised.
+ *  - Arguments are validated before any HIP call; on an argument error
+ *    nothing is launched.  n == 0 is a no-op returning SVD2_OK.
+ *  - Pointers must be aligned to the element size; 16-byte alignment of every
+ *    array enables the wide-load path (hipMalloc gives 256 bytes).
+ *  - No output may overlap an input or another output (SVD2_ERR_ALIAS).
+ *  - Inputs must be finite (section 1).  A lane with a non-finite input gets
+ *    unspecified outputs; no other lane is affected and no error is raised.
+ */
+#ifndef SVD2_H
+#define SVD2_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SVD2_OK = 0,
+  SVD2_ERR_NULL = 1,     /* a required pointer is NULL                       */
+  SVD2_ERR_ALIGN = 2,    /* a pointer is not aligned to its element size     */
+  SVD2_ERR_ALIAS = 3,    /* an output overlaps an input or another output    */
+  SVD2_ERR_FLAGS = 4,    /* unknown or contradictory flag bits               */
+  SVD2_ERR_HIP = 5,      /* a HIP call failed; see svd2_last_hip_error()     */
+  SVD2_ERR_SIZE = 6,     /* n or a workspace size is out of range            */
+  SVD2_NOT_CONVERGED = 7 /* Kogbetliantz: max_sweeps reached                 */
+} svd2_status;
+
+enum {
+  /* backscale of eq. (28); at most one of these may be set */
+  SVD2_BACKSCALE_NONE = 0,  /* default: write sigma' and s                          */
+  SVD2_BACKSCALE_SAFE = 1,  /* per lane, only where 2^-s sigma' is exact and finite;
+                               such lanes get Sigma and s = -0                       */
+  SVD2_BACKSCALE_ALL = 2,   /* Fig. 1: unconditional (may overflow or underflow)     */
+  /* FP32 entry points only: FP64 rescue of lanes with sigma'_min < 2^-20 sigma'_max.
+     On such lanes the (2,2) entry of R is recomputed from det(A^) in FP64 (exact
+     products, compensated sum), and eqs. (9), (13)-(17), (29) run in FP64. */
+  SVD2_RESCUE_FP64 = 4,     /* rescue inside the main kernel (divergent, no queue)  */
+  SVD2_RESCUE_QUEUE = 8     /* with RESCUE_FP64: flagged lanes are compacted into a
+                               queue (one atomic per wavefront) and redone by a
+                               second kernel; needs a workspace                     */
+};
+
+/* Real FP64: a_ij in, u_ij, v_ij, smax, smin, s out (all length n). */
+typedef struct {
+  const double *a11, *a21, *a12, *a22;
+  double *u11, *u21, *u12, *u22;
+  double *v11, *v21, *v12, *v22;
+  double *smax, *smin, *s;
+} dsvd2_args;
+
+/* Complex FP64: real and imaginary parts as separate arrays (section 3). */
+typedef struct {
+  const double *a11r, *a11i, *a21r, *a21i, *a12r, *a12i, *a22r, *a22i;
+  double *u11r, *u11i, *u21r, *u21i, *u12r, *u12i, *u22r, *u22i;
+  double *v11r, *v11i, *v21r, *v21i, *v12r, *v12i, *v22r, *v22i;
+  double *smax, *smin, *s;
+} zsvd2_args;
+
+/* Real FP32.  nrescued: optional device counter; when not NULL the number of
+   rescued lanes is ADDED to it (the caller zeroes it). */
+typedef struct {
+  const float *a11, *a21, *a12, *a22;
+  float *u11, *u21, *u12, *u22;
+  float *v11, *v21, *v12, *v22;
+  float *smax, *smin, *s;
+  uint32_t *nrescued;
+} ssvd2_args;
+
+/* Complex FP32. */
+typedef struct {
+  const float *a11r, *a11i, *a21r, *a21i, *a12r, *a12i, *a22r, *a22i;
+  float *u11r, *u11i, *u21r, *u21i, *u12r, *u12i, *u22r, *u22i;
+  float *v11r, *v11i, *v21r, *v21i, *v12r, *v12i, *v22r, *v22i;
+  float *smax, *smin, *s;
+  uint32_t *nrescued;
+} csvd2_args;
+
+/* Batched SVDs of n matrices (sections 2-7).  flags: SVD2_BACKSCALE_*.
+   Errors: SVD2_ERR_NULL/ALIGN/ALIAS/FLAGS before launch, SVD2_ERR_HIP if the
+   launch fails. */
+svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream);
+svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream_t stream);
+
+/* FP32 form (the paper notes the method carries over to single precision,
+   section 1; the tan 2phi clamp becomes sqrt(FLT_MAX), section 7).
+   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE].
+   ws / ws_bytes: device workspace, at least svd2_workspace_bytes(n, flags)
+   bytes (may be NULL/0 when that is 0).  With RESCUE_QUEUE, n must be below
+   2^32 (SVD2_ERR_SIZE otherwise).  Calls sharing one workspace must not
+   overlap in time. */
+svd2_status ssvd2_batch(size_t n, const ssvd2_args *p, unsigned flags, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* Workspace needed by the FP32 entry points: 0 unless SVD2_RESCUE_QUEUE. */
+size_t svd2_workspace_bytes(size_t n, unsigned flags);
+
+/* Launch shape of the batched kernels (all dtypes).  block: threads per
+   workgroup, a multiple of 64 in [64, 1024]; per_thread: matrices per lane,
+   1 or 2 (2 uses 16-byte loads and stores).  Takes effect for later calls
+   from any thread.  Returns SVD2_ERR_SIZE for values out of range. */
+svd2_status svd2_set_launch(int block, int per_thread);
+void svd2_get_launch(int *block, int *per_thread);
+
+/* Text of a status code, and the last hipError_t seen by this thread. */
+const char *svd2_status_string(svd2_status st);
+int svd2_last_hip_error(void);
+
+/* Conformance probe of the device primitives the kernels use (correct
+   rounding of /, sqrt, fma, ldexp; frexp exponents of subnormals; NaN
+   handling of fmin/fmax), for tests.  op: 0 div, 1 sqrt, 2 fma, 3 ldexp(x,
+   (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y).
+   x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
+svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y,
+                           const double *z, double *out, hipStream_t stream);
+svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
+                           const float *z, float *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVD2_H */

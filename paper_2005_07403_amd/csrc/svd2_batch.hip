@@ -1,0 +1,413 @@
+// svd2_batch.hip -- batched 2x2 SVD kernels for gfx950 and the C ABI of
+// include/svd2.h.
+//
+// Mapping (section 3 layout, section 4 pipeline): lane k of the grid computes
+// matrix k (or matrices 2k, 2k+1 with 16-byte accesses).  Every input array
+// is read once and every output array written once, coalesced, with
+// non-temporal stores; nothing is staged in LDS because nothing is reused.
+// The work is HBM-bound (120 B per real FP64 SVD against ~300 VALU
+// instructions), so the kernels keep many loads in flight rather than
+// shortening the arithmetic, which must stay bit-for-bit the paper's.
+#include "svd2.h"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <stdint.h>
+
+#include "svd2_lane.hpp"
+
+using namespace svd2;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+std::atomic<int> g_block{256};
+std::atomic<int> g_per_thread{1};
+
+template <class T, int NIN, int NOUT> struct KArgs {
+  const T *in[NIN];
+  T *out[NOUT];
+};
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <class T> struct Vec2;
+template <> struct Vec2<double> { typedef d2v type; };
+template <> struct Vec2<float> { typedef f2v type; };
+
+template <class T> __device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
+// ---------------------------------------------------------------------------
+// loads / stores of PT consecutive matrices per lane
+// ---------------------------------------------------------------------------
+template <class T, int N, int PT>
+__device__ __forceinline__ void load_lanes(const T *const (&in)[N], size_t k, int cnt, T (&x)[PT][N]) {
+  if (PT == 2 && cnt == 2) {
+    typedef typename Vec2<T>::type V;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      V v = *reinterpret_cast<const V *>(in[i] + k);
+      x[0][i] = v.x;
+      x[PT - 1][i] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PT; ++j)
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[j][i] = (j < cnt) ? in[i][k + j] : T(0);
+  }
+}
+
+template <class T, int N, int PT>
+__device__ __forceinline__ void store_lanes(T *const (&out)[N], size_t k, int cnt, const T (&y)[PT][N]) {
+  if (PT == 2 && cnt == 2) {
+    typedef typename Vec2<T>::type V;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      V v;
+      v.x = y[0][i];
+      v.y = y[PT - 1][i];
+      st_nt(reinterpret_cast<V *>(out[i] + k), v);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PT; ++j)
+      if (j < cnt) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) st_nt(out[i] + k + j, y[j][i]);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one matrix: inputs x[NIN] -> outputs y[NOUT]; returns the rescue flag
+// RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int RESCUE>
+__device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
+  bool flagged = false;
+  if constexpr (!CPLX) {
+    RealRes<T> o;
+    real_lane<T>(x[0], x[1], x[2], x[3], o);
+    if constexpr (RESCUE != 0) {
+      flagged = near_degenerate(o.smax, o.smin);
+      if constexpr (RESCUE == 1) {
+        if (flagged) real_rescue(o);
+      }
+    }
+    y[0] = o.u11; y[1] = o.u21; y[2] = o.u12; y[3] = o.u22;
+    y[4] = o.v11; y[5] = o.v21; y[6] = o.v12; y[7] = o.v22;
+    T smax = o.smax, smin = o.smin;
+    T sv = backscale<T>(bs, o.s, smax, smin);
+    y[8] = smax; y[9] = smin; y[10] = sv;
+  } else {
+    CplxRes<T> o;
+    cplx_lane<T>(x, o);
+    if constexpr (RESCUE != 0) {
+      flagged = near_degenerate(o.smax, o.smin);
+      if constexpr (RESCUE == 1) {
+        if (flagged) cplx_rescue(o);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      y[2 * e] = o.u[e].re; y[2 * e + 1] = o.u[e].im;
+      y[8 + 2 * e] = o.v[e].re; y[8 + 2 * e + 1] = o.v[e].im;
+    }
+    T smax = o.smax, smin = o.smin;
+    T sv = backscale<T>(bs, o.s, smax, smin);
+    y[16] = smax; y[17] = smin; y[18] = sv;
+  }
+  return flagged;
+}
+
+__device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// ---------------------------------------------------------------------------
+// Main batched kernel.  RESCUE: 0 plain, 1 in-place FP64 rescue, 2 queue the
+// flagged lanes for svd2_rescue_kernel.
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int PT, int RESCUE>
+__global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
+                                                   int bs, uint32_t *nresc, uint32_t *queue,
+                                                   uint32_t *qcount) {
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  size_t k = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  int cnt = (k < n) ? (int)((n - k < (size_t)PT) ? (n - k) : PT) : 0;
+  T x[PT][NIN], y[PT][NOUT];
+  bool fl[PT];
+  if (cnt > 0) load_lanes<T, NIN, PT>(a.in, k, cnt, x);
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    fl[j] = false;
+    if (j < cnt) fl[j] = one_matrix<T, CPLX, RESCUE>(x[j], y[j], bs);
+  }
+  if (cnt > 0) store_lanes<T, NOUT, PT>(a.out, k, cnt, y);
+  if constexpr (RESCUE != 0) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      uint64_t m = __ballot(fl[j]);
+      if (m == 0) continue;
+      unsigned total = (unsigned)__popcll(m);
+      unsigned lane = __lane_id();
+      unsigned first = (unsigned)__ffsll((unsigned long long)m) - 1;
+      if (nresc && lane == first) atomicAdd(nresc, total);
+      if constexpr (RESCUE == 2) {
+        unsigned base = 0;
+        if (lane == first) base = atomicAdd(qcount, total);
+        base = __shfl(base, (int)first);
+        if (fl[j]) queue[base + lane_prefix(m)] = (uint32_t)(k + j);
+      }
+    }
+  }
+}
+
+// Second pass for RESCUE == 2: redo each queued lane with the FP64 tail.  The
+// grid is fixed; every lane loops until the device-side count is exhausted.
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
+                                                          int bs, const uint32_t *queue,
+                                                          const uint32_t *qcount) {
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  uint32_t total = *qcount;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    size_t k = queue[i];
+    T x[NIN], y[NOUT];
+#pragma unroll
+    for (int e = 0; e < NIN; ++e) x[e] = a.in[e][k];
+    one_matrix<T, CPLX, 1>(x, y, bs);
+#pragma unroll
+    for (int e = 0; e < NOUT; ++e) st_nt(a.out[e] + k, y[e]);
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t *p) { *p = 0u; }
+
+// ---------------------------------------------------------------------------
+// primitive probe
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void probe_kernel(int op, size_t n, const T *x, const T *y,
+                                                    const T *z, T *out) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T r;
+  switch (op) {
+    case 0: r = x[i] / y[i]; break;
+    case 1: r = vsqrt(x[i]); break;
+    case 2: r = vfma(x[i], y[i], z[i]); break;
+    case 3: r = vldexp(x[i], (int)y[i]); break;
+    case 4: r = (T)vfrexp_exp(x[i]); break;
+    case 5: r = vmin(x[i], y[i]); break;
+    default: r = vmax(x[i], y[i]); break;
+  }
+  out[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// host-side validation
+// ---------------------------------------------------------------------------
+struct Span {
+  uintptr_t lo, hi;
+};
+
+template <class T>
+svd2_status check_ptrs(size_t n, const T *const *in, int nin, T *const *out, int nout) {
+  for (int i = 0; i < nin; ++i)
+    if (!in[i]) return SVD2_ERR_NULL;
+  for (int i = 0; i < nout; ++i)
+    if (!out[i]) return SVD2_ERR_NULL;
+  for (int i = 0; i < nin; ++i)
+    if ((uintptr_t)in[i] % sizeof(T)) return SVD2_ERR_ALIGN;
+  for (int i = 0; i < nout; ++i)
+    if ((uintptr_t)out[i] % sizeof(T)) return SVD2_ERR_ALIGN;
+  if (n > SIZE_MAX / sizeof(T)) return SVD2_ERR_SIZE;
+  const size_t bytes = n * sizeof(T);
+  Span sp[27 + 8];
+  int m = 0;
+  for (int i = 0; i < nout; ++i) sp[m++] = {(uintptr_t)out[i], (uintptr_t)out[i] + bytes};
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j)
+      if (sp[i].lo < sp[j].hi && sp[j].lo < sp[i].hi) return SVD2_ERR_ALIAS;
+  for (int i = 0; i < nin; ++i) {
+    Span s = {(uintptr_t)in[i], (uintptr_t)in[i] + bytes};
+    for (int j = 0; j < m; ++j)
+      if (s.lo < sp[j].hi && sp[j].lo < s.hi) return SVD2_ERR_ALIAS;
+  }
+  return SVD2_OK;
+}
+
+template <class T, int NIN, int NOUT>
+bool all_aligned16(const KArgs<T, NIN, NOUT> &a) {
+  for (int i = 0; i < NIN; ++i)
+    if ((uintptr_t)a.in[i] % 16) return false;
+  for (int i = 0; i < NOUT; ++i)
+    if ((uintptr_t)a.out[i] % 16) return false;
+  return true;
+}
+
+svd2_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return SVD2_OK;
+  g_last_hip = (int)e;
+  return SVD2_ERR_HIP;
+}
+
+template <class T, bool CPLX, int RESCUE>
+svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
+                   uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
+  int block = g_block.load(), pt = g_per_thread.load();
+  if (pt == 2 && !all_aligned16(a)) pt = 1;
+  size_t lanes = (n + pt - 1) / pt;
+  size_t grid = (lanes + block - 1) / block;
+  if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
+  if (pt == 2)
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE>), dim3((unsigned)grid), dim3(block), 0, st,
+                       n, a, bs, nresc, queue, qcount);
+  else
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE>), dim3((unsigned)grid), dim3(block), 0, st,
+                       n, a, bs, nresc, queue, qcount);
+  return hip_status(hipGetLastError());
+}
+
+bool bad_bs_flags(unsigned flags) { return (flags & 3u) == 3u; }
+
+template <class T, bool CPLX>
+svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, unsigned flags,
+                     uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
+  int bs = (int)(flags & 3u);
+  bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE;
+  if (!resc) return launch<T, CPLX, 0>(n, a, bs, nullptr, nullptr, nullptr, st);
+  if (!queue) return launch<T, CPLX, 1>(n, a, bs, nresc, nullptr, nullptr, st);
+  if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
+  if (!ws) return SVD2_ERR_NULL;
+  if (ws_bytes < svd2_workspace_bytes(n, flags)) return SVD2_ERR_SIZE;
+  if ((uintptr_t)ws % 4) return SVD2_ERR_ALIGN;
+  uint32_t *qcount = (uint32_t *)ws;
+  uint32_t *q = qcount + 64;  // keep the queue 256-byte aligned
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, qcount);
+  svd2_status s0 = hip_status(hipGetLastError());
+  if (s0 != SVD2_OK) return s0;
+  svd2_status s1 = launch<T, CPLX, 2>(n, a, bs, nresc, q, qcount, st);
+  if (s1 != SVD2_OK) return s1;
+  hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
+  return hip_status(hipGetLastError());
+}
+
+template <class T>
+svd2_status probe(int op, size_t n, const T *x, const T *y, const T *z, T *out,
+                         hipStream_t stream) {
+  if (op < 0 || op > 6) return SVD2_ERR_FLAGS;
+  if (!x || !out || (!y && op != 1 && op != 4) || (!z && op == 2)) return SVD2_ERR_NULL;
+  if (n == 0) return SVD2_OK;
+  size_t grid = (n + 255) / 256;
+  if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
+  hipLaunchKernelGGL((probe_kernel<T>), dim3((unsigned)grid), dim3(256), 0, stream, op, n, x, y, z,
+                     out);
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (flags & ~3u || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<double, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
+                            {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
+                             p->smax, p->smin, p->s}};
+  svd2_status st = check_ptrs<double>(n, a.in, 4, a.out, 11);
+  if (st != SVD2_OK || n == 0) return st;
+  return launch<double, false, 0>(n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+}
+
+svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (flags & ~3u || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<double, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
+                            {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
+                             p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
+                             p->smax, p->smin, p->s}};
+  svd2_status st = check_ptrs<double>(n, a.in, 8, a.out, 19);
+  if (st != SVD2_OK || n == 0) return st;
+  return launch<double, true, 0>(n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+}
+
+static bool bad_fp32_flags(unsigned flags) {
+  if (flags & ~15u || bad_bs_flags(flags)) return true;
+  if ((flags & SVD2_RESCUE_QUEUE) && !(flags & SVD2_RESCUE_FP64)) return true;
+  return false;
+}
+
+svd2_status ssvd2_batch(size_t n, const ssvd2_args *p, unsigned flags, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (bad_fp32_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<float, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
+                           {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
+                            p->smax, p->smin, p->s}};
+  svd2_status st = check_ptrs<float>(n, a.in, 4, a.out, 11);
+  if (st != SVD2_OK || n == 0) return st;
+  return run_fp32<float, false>(n, a, flags, p->nrescued, ws, ws_bytes, stream);
+}
+
+svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (bad_fp32_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<float, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
+                           {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
+                            p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
+                            p->smax, p->smin, p->s}};
+  svd2_status st = check_ptrs<float>(n, a.in, 8, a.out, 19);
+  if (st != SVD2_OK || n == 0) return st;
+  return run_fp32<float, true>(n, a, flags, p->nrescued, ws, ws_bytes, stream);
+}
+
+size_t svd2_workspace_bytes(size_t n, unsigned flags) {
+  if (!(flags & SVD2_RESCUE_QUEUE)) return 0;
+  return 256 + n * sizeof(uint32_t);
+}
+
+svd2_status svd2_set_launch(int block, int per_thread) {
+  if (block < 64 || block > 256 || block % 64) return SVD2_ERR_SIZE;
+  if (per_thread != 1 && per_thread != 2) return SVD2_ERR_SIZE;
+  g_block.store(block);
+  g_per_thread.store(per_thread);
+  return SVD2_OK;
+}
+
+void svd2_get_launch(int *block, int *per_thread) {
+  if (block) *block = g_block.load();
+  if (per_thread) *per_thread = g_per_thread.load();
+}
+
+const char *svd2_status_string(svd2_status st) {
+  switch (st) {
+    case SVD2_OK: return "ok";
+    case SVD2_ERR_NULL: return "null pointer";
+    case SVD2_ERR_ALIGN: return "misaligned pointer";
+    case SVD2_ERR_ALIAS: return "output overlaps an input or another output";
+    case SVD2_ERR_FLAGS: return "invalid flags";
+    case SVD2_ERR_HIP: return "HIP error";
+    case SVD2_ERR_SIZE: return "size out of range";
+    case SVD2_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+int svd2_last_hip_error(void) { return g_last_hip; }
+
+svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y, const double *z,
+                           double *out, hipStream_t stream) {
+  return probe<double>(op, n, x, y, z, out, stream);
+}
+svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y, const float *z,
+                           float *out, hipStream_t stream) {
+  return probe<float>(op, n, x, y, z, out, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,370 @@
+// svd2_lane.hpp -- per-lane pipeline of the 2x2 SVD for gfx950.
+//
+// One lane computes one matrix, branch-free (section 4), with the operation
+// order of sections 5-7 (Figs. 3-10) and the expansion of eq. (29).  Every
+// arithmetic operation is a single correctly rounded IEEE-754 operation:
+// hipcc lowers '/' and sqrt to correctly rounded sequences (checked bitwise by
+// the primitive probe), fma is the hardware fused multiply-add, and the file
+// is compiled with -ffp-contract=off.
+//
+// Readings of points the paper leaves open (shared with the documentation):
+//  * hypot(a, b) is the division-based fallback of section 5:
+//      a' = max(|a|,|b|), b' = min(|a|,|b|), q = b'/max(a', TRUE_MIN),
+//      hypot = a' sqrt(fma(q, q, 1)).
+//  * invsqrt(x) = 1/sqrt(x), the first remedy named in section 6.
+//  * The relaxed min/max of section 2 (NaN first argument -> second argument)
+//    are the hardware v_min/v_max: at every use the first argument is a
+//    non-negative number or a quiet NaN from 0/0 and the second is a positive
+//    constant or a non-negative number, so the IEEE minNum/maxNum result is
+//    the relaxed one.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svd2 {
+
+template <class T> struct Fmt;
+template <> struct Fmt<double> {
+  static constexpr int h = 1021;                        // DBL_MAX_EXP - 3
+  static constexpr double big = 0x1.fffffffffffffp+1023; // DBL_MAX
+  static constexpr double tm = 0x1p-1074;                // DBL_TRUE_MIN
+  static constexpr double f = 0x1.fffffffffffffp+511;    // sqrt(DBL_MAX), Fig. 10
+};
+template <> struct Fmt<float> {
+  static constexpr int h = 125;                          // FLT_MAX_EXP - 3
+  static constexpr float big = 0x1.fffffep+127f;         // FLT_MAX
+  static constexpr float tm = 0x1p-149f;                 // FLT_TRUE_MIN
+  static constexpr float f = 0x1.fffffep+63f;            // sqrt(FLT_MAX) rounded down
+};
+
+// ---------------------------------------------------------------------------
+// primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double vsqrt(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ float vsqrt(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double vabs(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float vabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double vcopysign(double a, double b) { return __builtin_copysign(a, b); }
+__device__ __forceinline__ float vcopysign(float a, float b) { return __builtin_copysignf(a, b); }
+// frexp exponent: x = m 2^e, m in [0.5, 1); the true exponent also for subnormals
+__device__ __forceinline__ int vfrexp_exp(double a) { return __builtin_amdgcn_frexp_exp(a); }
+__device__ __forceinline__ int vfrexp_exp(float a) { return __builtin_amdgcn_frexp_expf(a); }
+__device__ __forceinline__ double vldexp(double a, int e) { return __builtin_amdgcn_ldexp(a, e); }
+__device__ __forceinline__ float vldexp(float a, int e) { return __builtin_amdgcn_ldexpf(a, e); }
+__device__ __forceinline__ bool vsignbit(double a) { return __builtin_signbit(a); }
+__device__ __forceinline__ bool vsignbit(float a) { return __builtin_signbit(a); }
+// negate when the flag is set (an XOR of the sign bit)
+template <class T> __device__ __forceinline__ T flip(bool neg, T a) { return neg ? -a : a; }
+
+template <class T> __device__ __forceinline__ T hyp(T a, T b) {
+  T x = vabs(a), y = vabs(b);
+  T hi = vmax(x, y), lo = vmin(x, y);
+  T q = lo / vmax(hi, Fmt<T>::tm);
+  return hi * vsqrt(vfma(q, q, T(1)));
+}
+template <class T> __device__ __forceinline__ T rsq(T x) { return T(1) / vsqrt(x); }
+
+template <class T> struct Cx { T re, im; };
+
+// eq. (5)
+template <class T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {vfma(a.re, b.re, -(a.im * b.im)), vfma(a.re, b.im, a.im * b.re)};
+}
+// conj(a) b, eq. (5) with the conjugation in the signs (Fig. 7)
+template <class T> __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+  return {vfma(a.re, b.re, a.im * b.im), vfma(a.re, b.im, -(a.im * b.re))};
+}
+// eq. (1): e^{i arg z} from z and |z|
+template <class T> __device__ __forceinline__ Cx<T> phase(Cx<T> z, T az) {
+  return {vcopysign(vmin(vabs(z.re) / az, T(1)), z.re), z.im / vmax(az, Fmt<T>::tm)};
+}
+
+// ---------------------------------------------------------------------------
+// Section 2.1, eq. (2), Fig. 3.  s = min over components of h - exp2(x), with
+// zero components ignored; all-zero -> s = BIG.  Kept as an int (sentinel
+// INT_MAX for BIG); ldexp(0, INT_MAX) = 0, so the scaling needs no branch.
+// ---------------------------------------------------------------------------
+constexpr int kSBig = 0x7fffffff;
+template <class T> __device__ __forceinline__ int scale_exp(T x) {
+  return (x == T(0)) ? kSBig : (Fmt<T>::h + 1 - vfrexp_exp(x));
+}
+template <class T> __device__ __forceinline__ T s_value(int s) {
+  return (s == kSBig) ? Fmt<T>::big : (T)s;
+}
+
+// ---------------------------------------------------------------------------
+// Section 2.3, eqs. (13)-(17), Fig. 10.
+// ---------------------------------------------------------------------------
+template <class T> struct Tri {
+  T tphi, cphi, tpsi, cpsi, smax, smin;
+};
+template <class T> __device__ __forceinline__ Tri<T> tri_svd(T r11, T r12, T r22) {
+  const T one = T(1), zero = T(0);
+  T x = vmax(r12 / r11, zero);
+  T y = vmax(r22 / r11, zero);
+  T lo = vmin(x, y), hi = vmax(x, y);
+  T num = (lo * T(2)) * hi;
+  T den = vfma(x - y, x + y, one);
+  T t2 = -vmin(vmax(num / den, zero), Fmt<T>::f);
+  Tri<T> o;
+  o.tphi = t2 / (one + vsqrt(vfma(t2, t2, one)));
+  T sec2phi = vfma(o.tphi, o.tphi, one);
+  o.cphi = rsq(sec2phi);
+  o.tpsi = vfma(y, o.tphi, -x);
+  T sec2psi = vfma(o.tpsi, o.tpsi, one);
+  o.cpsi = rsq(sec2psi);
+  T k = o.cphi * o.cpsi;
+  o.smax = (k * sec2psi) * r11;
+  o.smin = (k * sec2phi) * r22;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Real case.  D*, D~, D^ of eq. (10) are sign bits (-0 counts as negative).
+// ---------------------------------------------------------------------------
+template <class T> struct RealRes {
+  T u11, u21, u12, u22, v11, v21, v12, v22, smax, smin;
+  int s;
+  // kept for the FP64 rescue of FP32 lanes
+  T ah11, ah21, ah12, ah22, r11, r12, mt, ca;
+  bool c, r, neg1, neg2, negt;
+};
+
+// eq. (29) expansion and the final row permutations, real case.
+template <class T, class W>
+__device__ __forceinline__ void real_assemble(const Tri<W> &t, W mt, W ca, bool negh, bool neg1,
+                                              bool neg2, bool negt, bool c, bool r, T *u, T *v) {
+  const W one = W(1);
+  W C = ca * t.cphi, ta = -mt, tt = mt * t.tphi;
+  W dh = negh ? -one : one;
+  W w11 = vfma(dh, tt, one), w21 = vfma(dh, t.tphi, ta), w12 = vfma(dh, ta, t.tphi),
+    w22 = vfma(mt, t.tphi, dh);
+  W U11 = C * flip(neg1, w11), U12 = C * flip(neg1, w12);
+  W U21 = -(C * flip(neg2, w21)), U22 = C * flip(neg2, w22);
+  W ct = t.cpsi * t.tpsi;
+  W V11 = t.cpsi, V12 = ct, V21 = negt ? ct : -ct, V22 = flip(negt, t.cpsi);
+  // P_r on the rows of U, P_c on the rows of V; element order 11, 21, 12, 22
+  u[0] = (T)(r ? U21 : U11); u[1] = (T)(r ? U11 : U21);
+  u[2] = (T)(r ? U22 : U12); u[3] = (T)(r ? U12 : U22);
+  v[0] = (T)(c ? V21 : V11); v[1] = (T)(c ? V11 : V21);
+  v[2] = (T)(c ? V22 : V12); v[3] = (T)(c ? V12 : V22);
+}
+
+template <class T>
+__device__ __forceinline__ void real_lane(T a11, T a21, T a12, T a22, RealRes<T> &o) {
+  const T one = T(1);
+  // scaling (eq. (2), Fig. 3)
+  int s = min(min(scale_exp(a11), scale_exp(a21)), min(scale_exp(a12), scale_exp(a22)));
+  T b11 = vldexp(a11, s), b21 = vldexp(a21, s), b12 = vldexp(a12, s), b22 = vldexp(a22, s);
+  o.s = s;
+  o.ah11 = b11; o.ah21 = b21; o.ah12 = b12; o.ah22 = b22;
+  // column norms (eq. (3), Fig. 4)
+  T n1 = hyp(b11, b21), n2 = hyp(b12, b22);
+  // column pivoting (Fig. 5)
+  bool c = n1 < n2;
+  T p11 = c ? b12 : b11, p21 = c ? b22 : b21, p12 = c ? b11 : b12, p22 = c ? b21 : b22;
+  T r11 = c ? n2 : n1;
+  // row sorting (Fig. 6)
+  bool r = vabs(p11) < vabs(p21);
+  T q11 = r ? p21 : p11, q21 = r ? p11 : p21, q12 = r ? p22 : p12, q22 = r ? p12 : p22;
+  // D* (eq. (10), Fig. 7)
+  bool neg1 = vsignbit(q11), neg2 = vsignbit(q21);
+  T a311 = vabs(q11), a321 = vabs(q21);
+  T a312 = flip(neg1, q12), a322 = flip(neg2, q22);
+  // QR (eqs. (6)-(7), Fig. 8)
+  T mt = vmax(a321 / a311, T(0));
+  T ca = rsq(vfma(mt, mt, one));
+  T r12p = ca * vfma(mt, a322, a312);
+  T r22pp = ca * vfma(-mt, a312, a322);
+  // D~, D^ (eq. (10), Fig. 9)
+  bool negt = vsignbit(r12p);
+  T r12 = vabs(r12p);
+  T r22p = flip(negt, r22pp);
+  bool negh = vsignbit(r22p);
+  T r22 = vabs(r22p);
+  Tri<T> t = tri_svd(r11, r12, r22);
+  T u[4], v[4];
+  real_assemble<T, T>(t, mt, ca, negh, neg1, neg2, negt, c, r, u, v);
+  o.u11 = u[0]; o.u21 = u[1]; o.u12 = u[2]; o.u22 = u[3];
+  o.v11 = v[0]; o.v21 = v[1]; o.v12 = v[2]; o.v22 = v[3];
+  o.smax = t.smax; o.smin = t.smin;
+  o.r11 = r11; o.r12 = r12; o.mt = mt; o.ca = ca;
+  o.c = c; o.r = r; o.neg1 = neg1; o.neg2 = neg2; o.negt = negt;
+}
+
+// ---------------------------------------------------------------------------
+// Complex case.
+// ---------------------------------------------------------------------------
+template <class T> struct CplxRes {
+  Cx<T> u[4], v[4];  // element order 11, 21, 12, 22
+  T smax, smin;
+  int s;
+  Cx<T> ah[4];       // A^ in element order 11, 21, 12, 22 (for the rescue)
+  Cx<T> d1, d2, e12;
+  T r11, r12, mt, ca;
+  bool c, r;
+};
+
+template <class T, class W>
+__device__ __forceinline__ void cplx_assemble(const Tri<W> &t, W mt, W ca, Cx<W> dh, Cx<W> d1,
+                                              Cx<W> d2, Cx<W> e12, bool c, bool r, Cx<T> *u,
+                                              Cx<T> *v) {
+  const W one = W(1);
+  W C = ca * t.cphi, ta = -mt, tt = mt * t.tphi;
+  Cx<W> w11 = {vfma(dh.re, tt, one), dh.im * tt};
+  Cx<W> w21 = {vfma(dh.re, t.tphi, ta), dh.im * t.tphi};
+  Cx<W> w12 = {vfma(dh.re, ta, t.tphi), dh.im * ta};
+  Cx<W> w22 = {vfma(mt, t.tphi, dh.re), dh.im};
+  Cx<W> p11 = cmul(d1, w11), p21 = cmul(d2, w21), p12 = cmul(d1, w12), p22 = cmul(d2, w22);
+  Cx<W> U11 = {C * p11.re, C * p11.im}, U12 = {C * p12.re, C * p12.im};
+  Cx<W> U21 = {-(C * p21.re), -(C * p21.im)}, U22 = {C * p22.re, C * p22.im};
+  W ct = t.cpsi * t.tpsi;
+  Cx<W> V11 = {t.cpsi, W(0)}, V12 = {ct, W(0)};
+  Cx<W> V21 = {-(ct * e12.re), ct * e12.im}, V22 = {t.cpsi * e12.re, -(t.cpsi * e12.im)};
+  auto pick = [](bool sw, Cx<W> a, Cx<W> b) { return sw ? b : a; };
+  auto cvt = [](Cx<W> a) { return Cx<T>{(T)a.re, (T)a.im}; };
+  u[0] = cvt(pick(r, U11, U21)); u[1] = cvt(pick(r, U21, U11));
+  u[2] = cvt(pick(r, U12, U22)); u[3] = cvt(pick(r, U22, U12));
+  v[0] = cvt(pick(c, V11, V21)); v[1] = cvt(pick(c, V21, V11));
+  v[2] = cvt(pick(c, V12, V22)); v[3] = cvt(pick(c, V22, V12));
+}
+
+// a[8] = a11r, a11i, a21r, a21i, a12r, a12i, a22r, a22i
+template <class T>
+__device__ __forceinline__ void cplx_lane(const T *a, CplxRes<T> &o) {
+  const T one = T(1);
+  int s = scale_exp(a[0]);
+#pragma unroll
+  for (int i = 1; i < 8; ++i) s = min(s, scale_exp(a[i]));
+  o.s = s;
+  Cx<T> b11 = {vldexp(a[0], s), vldexp(a[1], s)}, b21 = {vldexp(a[2], s), vldexp(a[3], s)};
+  Cx<T> b12 = {vldexp(a[4], s), vldexp(a[5], s)}, b22 = {vldexp(a[6], s), vldexp(a[7], s)};
+  o.ah[0] = b11; o.ah[1] = b21; o.ah[2] = b12; o.ah[3] = b22;
+  // |a^_ij| (eq. (1)) and column norms (eq. (3), Fig. 4)
+  T m11 = hyp(b11.re, b11.im), m21 = hyp(b21.re, b21.im);
+  T m12 = hyp(b12.re, b12.im), m22 = hyp(b22.re, b22.im);
+  T n1 = hyp(m11, m21), n2 = hyp(m12, m22);
+  // column pivoting (Fig. 5)
+  bool c = n1 < n2;
+  auto pick = [](bool sw, Cx<T> x, Cx<T> y) { return sw ? y : x; };
+  Cx<T> p11 = pick(c, b11, b12), p21 = pick(c, b21, b22);
+  Cx<T> p12 = pick(c, b12, b11), p22 = pick(c, b22, b21);
+  T g11 = c ? m12 : m11, g21 = c ? m22 : m21;
+  T r11 = c ? n2 : n1;
+  // row sorting (Fig. 6)
+  bool r = g11 < g21;
+  Cx<T> q11 = pick(r, p11, p21), q21 = pick(r, p21, p11);
+  Cx<T> q12 = pick(r, p12, p22), q22 = pick(r, p22, p12);
+  T h11 = r ? g21 : g11, h21 = r ? g11 : g21;
+  // D* (eq. (4), Fig. 7)
+  Cx<T> d1 = phase(q11, h11), d2 = phase(q21, h21);
+  Cx<T> a312 = cmulc(d1, q12), a322 = cmulc(d2, q22);
+  // QR (eqs. (6)-(7), Fig. 8); a'''_11 = h11, a'''_21 = h21
+  T mt = vmax(h21 / h11, T(0));
+  T ca = rsq(vfma(mt, mt, one));
+  Cx<T> r12p = {ca * vfma(mt, a322.re, a312.re), ca * vfma(mt, a322.im, a312.im)};
+  Cx<T> r22pp = {ca * vfma(-mt, a312.re, a322.re), ca * vfma(-mt, a312.im, a322.im)};
+  // D~ (eq. (8), Fig. 9)
+  T r12 = hyp(r12p.re, r12p.im);
+  Cx<T> e12 = phase(r12p, r12);
+  Cx<T> r22p = {vfma(r22pp.re, e12.re, r22pp.im * e12.im),
+                vfma(r22pp.im, e12.re, -(r22pp.re * e12.im))};
+  // D^ (eq. (9), Fig. 9)
+  T r22 = hyp(r22p.re, r22p.im);
+  Cx<T> dh = phase(r22p, r22);
+  Tri<T> t = tri_svd(r11, r12, r22);
+  cplx_assemble<T, T>(t, mt, ca, dh, d1, d2, e12, c, r, o.u, o.v);
+  o.smax = t.smax; o.smin = t.smin;
+  o.d1 = d1; o.d2 = d2; o.e12 = e12;
+  o.r11 = r11; o.r12 = r12; o.mt = mt; o.ca = ca;
+  o.c = c; o.r = r;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 rescue of a near-degenerate FP32 lane (flag: smin' < 2^-20 smax').
+// r11 r'_22 = det(R') = det(Q*) det(D*) det(P_r*) det(A^) det(P_c) det(D~),
+// det(Q*) = 1, each swap -1, det(D*) = conj(d1 d2), det(D~) = conj(e12).
+// FP32 products are exact in FP64; det(A^) is summed with TwoSum.  Then
+// eqs. (9), (13)-(17), (29) run in FP64 and the results are rounded to FP32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ double sum4(double a, double b, double c, double d) {
+  double s, e, acc;
+  two_sum(a, b, s, acc);
+  two_sum(s, c, s, e);
+  acc += e;
+  two_sum(s, d, s, e);
+  acc += e;
+  return s + acc;
+}
+
+__device__ __forceinline__ bool near_degenerate(float smax, float smin) {
+  return smin < vldexp(smax, -20);
+}
+
+__device__ __forceinline__ void real_rescue(RealRes<float> &o) {
+  double det = (double)o.ah11 * (double)o.ah22 - (double)o.ah12 * (double)o.ah21;
+  bool neg = (o.c != o.r) != ((o.neg1 != o.neg2) != o.negt);
+  double r11 = o.r11;
+  double r22p = flip(neg, det / r11);
+  bool negh = vsignbit(r22p);
+  double r22 = vabs(r22p);
+  Tri<double> t = tri_svd(r11, (double)o.r12, r22);
+  float u[4], v[4];
+  real_assemble<float, double>(t, (double)o.mt, (double)o.ca, negh, o.neg1, o.neg2, o.negt, o.c,
+                               o.r, u, v);
+  o.u11 = u[0]; o.u21 = u[1]; o.u12 = u[2]; o.u22 = u[3];
+  o.v11 = v[0]; o.v21 = v[1]; o.v12 = v[2]; o.v22 = v[3];
+  o.smax = (float)t.smax;
+  o.smin = (float)t.smin;
+}
+
+__device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
+  Cx<double> a11 = {o.ah[0].re, o.ah[0].im}, a21 = {o.ah[1].re, o.ah[1].im};
+  Cx<double> a12 = {o.ah[2].re, o.ah[2].im}, a22 = {o.ah[3].re, o.ah[3].im};
+  Cx<double> det = {sum4(a11.re * a22.re, -(a11.im * a22.im), -(a12.re * a21.re), a12.im * a21.im),
+                    sum4(a11.re * a22.im, a11.im * a22.re, -(a12.re * a21.im), -(a12.im * a21.re))};
+  double sgn = (o.c != o.r) ? -1.0 : 1.0;
+  Cx<double> d1 = {o.d1.re, o.d1.im}, d2 = {o.d2.re, o.d2.im}, e = {o.e12.re, o.e12.im};
+  Cx<double> ph = cmul(cmul(d1, d2), e);
+  Cx<double> q = cmulc(ph, det);
+  double r11 = o.r11;
+  Cx<double> r22p = {sgn * (q.re / r11), sgn * (q.im / r11)};
+  double r22 = hyp(r22p.re, r22p.im);
+  Cx<double> dh = phase(r22p, r22);
+  Tri<double> t = tri_svd(r11, (double)o.r12, r22);
+  cplx_assemble<float, double>(t, (double)o.mt, (double)o.ca, dh, d1, d2, e, o.c, o.r, o.u, o.v);
+  o.smax = (float)t.smax;
+  o.smin = (float)t.smin;
+}
+
+// ---------------------------------------------------------------------------
+// Backscale (eq. (28), Fig. 1).  mode 1: only where exact and finite.
+// Returns the value to store for s.
+// ---------------------------------------------------------------------------
+template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &smax, T &smin) {
+  T sv = s_value<T>(s);
+  if (mode == 0) return sv;
+  if (s == kSBig) return -T(0);  // zero matrix: sigma' = Sigma = 0
+  T bmax = vldexp(smax, -s), bmin = vldexp(smin, -s);
+  if (mode == 1) {
+    bool ok = __builtin_isfinite(bmax) && __builtin_isfinite(bmin) && vldexp(bmax, s) == smax &&
+              vldexp(bmin, s) == smin;
+    if (!ok) return sv;
+  }
+  smax = bmax;
+  smin = bmin;
+  return -T(0);
+}
+
+}  // namespace svd2

@@ -1,0 +1,200 @@
+"""Python binding of libsvd2 (include/svd2.h): argument marshalling only.
+
+Every step of the batched SVD runs in the HIP kernels of ``libsvd2.so``; this
+module builds the pointer structs, passes the current HIP stream and maps
+status codes to exceptions.  PyTorch is used for device memory and streams
+only.  There is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsvd2.so")
+
+SVD2_OK = 0
+STATUS = {0: "SVD2_OK", 1: "SVD2_ERR_NULL", 2: "SVD2_ERR_ALIGN", 3: "SVD2_ERR_ALIAS",
+          4: "SVD2_ERR_FLAGS", 5: "SVD2_ERR_HIP", 6: "SVD2_ERR_SIZE", 7: "SVD2_NOT_CONVERGED"}
+SVD2_BACKSCALE_NONE = 0
+SVD2_BACKSCALE_SAFE = 1
+SVD2_BACKSCALE_ALL = 2
+SVD2_RESCUE_FP64 = 4
+SVD2_RESCUE_QUEUE = 8
+
+_P = ctypes.c_void_p
+REAL_IN = ["a11", "a21", "a12", "a22"]
+REAL_OUT = ["u11", "u21", "u12", "u22", "v11", "v21", "v12", "v22", "smax", "smin", "s"]
+CPLX_IN = [f"{e}{p}" for e in REAL_IN for p in ("r", "i")]
+CPLX_OUT = [f"{e}{p}" for e in REAL_OUT[:8] for p in ("r", "i")] + ["smax", "smin", "s"]
+
+
+class dsvd2_args(ctypes.Structure):
+    _fields_ = [(k, _P) for k in REAL_IN + REAL_OUT]
+
+
+class zsvd2_args(ctypes.Structure):
+    _fields_ = [(k, _P) for k in CPLX_IN + CPLX_OUT]
+
+
+class ssvd2_args(ctypes.Structure):
+    _fields_ = [(k, _P) for k in REAL_IN + REAL_OUT] + [("nrescued", _P)]
+
+
+class csvd2_args(ctypes.Structure):
+    _fields_ = [(k, _P) for k in CPLX_IN + CPLX_OUT] + [("nrescued", _P)]
+
+
+class Svd2Error(RuntimeError):
+    def __init__(self, fn: str, status: int, hip: int = 0):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}" + (f" (hipError {hip})" if hip else ""))
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_workspace_bytes",
+           "svd2_set_launch", "svd2_get_launch", "svd2_status_string", "svd2_last_hip_error",
+           "svd2_probe_f64", "svd2_probe_f32"]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsvd2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "python paper_2005_07403_amd/build.py (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        sz, ui, i = ctypes.c_size_t, ctypes.c_uint, ctypes.c_int
+        L.dsvd2_batch.argtypes = [sz, ctypes.POINTER(dsvd2_args), ui, _P]
+        L.zsvd2_batch.argtypes = [sz, ctypes.POINTER(zsvd2_args), ui, _P]
+        L.ssvd2_batch.argtypes = [sz, ctypes.POINTER(ssvd2_args), ui, _P, sz, _P]
+        L.csvd2_batch.argtypes = [sz, ctypes.POINTER(csvd2_args), ui, _P, sz, _P]
+        for f in ("dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch"):
+            getattr(L, f).restype = i
+        L.svd2_workspace_bytes.argtypes = [sz, ui]
+        L.svd2_workspace_bytes.restype = sz
+        L.svd2_set_launch.argtypes = [i, i]
+        L.svd2_set_launch.restype = i
+        L.svd2_get_launch.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.svd2_get_launch.restype = None
+        L.svd2_status_string.argtypes = [i]
+        L.svd2_status_string.restype = ctypes.c_char_p
+        L.svd2_last_hip_error.argtypes = []
+        L.svd2_last_hip_error.restype = i
+        L.svd2_probe_f64.argtypes = [i, sz, _P, _P, _P, _P, _P]
+        L.svd2_probe_f32.argtypes = [i, sz, _P, _P, _P, _P, _P]
+        L.svd2_probe_f64.restype = i
+        L.svd2_probe_f32.restype = i
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, st: int) -> None:
+    if st != SVD2_OK:
+        raise Svd2Error(fn, st, lib().svd2_last_hip_error() if st == 5 else 0)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def _fill(struct_cls, names, ptrs, extra=None):
+    a = struct_cls()
+    for k, p in zip(names, ptrs):
+        setattr(a, k, p)
+    if extra:
+        for k, p in extra.items():
+            setattr(a, k, p)
+    return a
+
+
+# ---------------------------------------------------------------------------
+# raw entry points (pointers as ints), same names as the C ABI
+# ---------------------------------------------------------------------------
+
+def dsvd2_batch(n: int, ins, outs, flags: int = 0, stream=None) -> None:
+    a = _fill(dsvd2_args, REAL_IN + REAL_OUT, list(ins) + list(outs))
+    _check("dsvd2_batch", lib().dsvd2_batch(n, ctypes.byref(a), flags, _stream(stream)))
+
+
+def zsvd2_batch(n: int, ins, outs, flags: int = 0, stream=None) -> None:
+    a = _fill(zsvd2_args, CPLX_IN + CPLX_OUT, list(ins) + list(outs))
+    _check("zsvd2_batch", lib().zsvd2_batch(n, ctypes.byref(a), flags, _stream(stream)))
+
+
+def ssvd2_batch(n: int, ins, outs, flags: int = 0, ws: int = 0, ws_bytes: int = 0,
+                nrescued: int = 0, stream=None) -> None:
+    a = _fill(ssvd2_args, REAL_IN + REAL_OUT, list(ins) + list(outs), {"nrescued": nrescued})
+    _check("ssvd2_batch", lib().ssvd2_batch(n, ctypes.byref(a), flags, ws, ws_bytes,
+                                            _stream(stream)))
+
+
+def csvd2_batch(n: int, ins, outs, flags: int = 0, ws: int = 0, ws_bytes: int = 0,
+                nrescued: int = 0, stream=None) -> None:
+    a = _fill(csvd2_args, CPLX_IN + CPLX_OUT, list(ins) + list(outs), {"nrescued": nrescued})
+    _check("csvd2_batch", lib().csvd2_batch(n, ctypes.byref(a), flags, ws, ws_bytes,
+                                            _stream(stream)))
+
+
+def svd2_workspace_bytes(n: int, flags: int) -> int:
+    return int(lib().svd2_workspace_bytes(n, flags))
+
+
+def svd2_set_launch(block: int, per_thread: int) -> None:
+    _check("svd2_set_launch", lib().svd2_set_launch(block, per_thread))
+
+
+def svd2_get_launch() -> tuple:
+    b, p = ctypes.c_int(), ctypes.c_int()
+    lib().svd2_get_launch(ctypes.byref(b), ctypes.byref(p))
+    return b.value, p.value
+
+
+def svd2_probe(op: int, x, y=None, z=None, out=None, stream=None) -> None:
+    """op on device tensors x, y, z -> out (see include/svd2.h)."""
+    import torch
+    fn = lib().svd2_probe_f64 if x.dtype == torch.float64 else lib().svd2_probe_f32
+    ptr = lambda t: 0 if t is None else t.data_ptr()
+    _check("svd2_probe", fn(op, x.numel(), ptr(x), ptr(y), ptr(z), ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# tensor convenience: allocate outputs with torch and call the entry point
+# ---------------------------------------------------------------------------
+
+def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
+    """Batched SVD of SoA trains (list of 4 real or 8 re/im device tensors of
+    one dtype, element order 11, 21, 12, 22).  Returns the list of output
+    trains (11 or 19 tensors: U, V, smax, smin, s) in the order of the C ABI."""
+    import torch
+    trains = list(trains)
+    cplx = len(trains) == 8
+    if len(trains) not in (4, 8):
+        raise ValueError("expected 4 (real) or 8 (complex) trains")
+    dt = trains[0].dtype
+    n = trains[0].numel()
+    for t in trains:
+        if t.dtype != dt or t.numel() != n or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("trains must be contiguous device tensors of one dtype and length")
+    nout = 19 if cplx else 11
+    if out is None:
+        out = [torch.empty(n, dtype=dt, device=trains[0].device) for _ in range(nout)]
+    ins = [t.data_ptr() for t in trains]
+    outs = [t.data_ptr() for t in out]
+    if dt == torch.float64:
+        (zsvd2_batch if cplx else dsvd2_batch)(n, ins, outs, flags, stream)
+    elif dt == torch.float32:
+        wsb = svd2_workspace_bytes(n, flags)
+        if wsb and ws is None:
+            ws = torch.empty(wsb, dtype=torch.uint8, device=trains[0].device)
+        (csvd2_batch if cplx else ssvd2_batch)(
+            n, ins, outs, flags, 0 if ws is None else ws.data_ptr(), wsb,
+            0 if nrescued is None else nrescued.data_ptr(), stream)
+    else:
+        raise TypeError(dt)
+    return out

@@ -1,0 +1,118 @@
+"""C-ABI contract of libsvd2.so on the CPU: the library loads without a GPU,
+exports every symbol include/svd2.h declares, and rejects bad arguments with
+status codes before any HIP call is made (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2005_07403_amd import svd2 as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "svd2.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(\w+)\s*\([^;{]*\)\s*;", txt)) - {"if", "return"})
+
+
+def test_library_exports_every_declared_symbol():
+    L = S.lib()
+    names = _header_functions()
+    assert "dsvd2_batch" in names and "csvd2_batch" in names
+    for name in names:
+        assert hasattr(L, name), name
+    for name in S.EXPORTS:
+        assert name in names, name
+
+
+FAKE = 1 << 40  # host-side fake "device" addresses: never dereferenced
+
+
+def _ptrs(count, base=FAKE, stride=1 << 30):
+    return [base + i * stride for i in range(count)]
+
+
+def _call(fn, n, ins, outs, flags=0, **kw):
+    try:
+        fn(n, ins, outs, flags, stream=0, **kw) if not kw else fn(n, ins, outs, flags, stream=0, **kw)
+    except S.Svd2Error as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("fn,nin,nout", [(S.dsvd2_batch, 4, 11), (S.zsvd2_batch, 8, 19),
+                                         (S.ssvd2_batch, 4, 11), (S.csvd2_batch, 8, 19)])
+def test_argument_errors(fn, nin, nout):
+    ins, outs = _ptrs(nin), _ptrs(nout, base=FAKE + (64 << 30))
+    # n == 0 with valid pointers: no-op, no HIP call
+    assert _call(fn, 0, ins, outs) == 0
+    # NULL pointer
+    bad = list(outs)
+    bad[3] = 0
+    assert _call(fn, 10, ins, bad) == 1
+    # misaligned pointer
+    bad = list(ins)
+    bad[1] += 1
+    assert _call(fn, 10, bad, outs) == 2
+    # output overlapping another output
+    bad = list(outs)
+    bad[2] = bad[1] + 8
+    assert _call(fn, 10, ins, bad) == 3
+    # output overlapping an input
+    bad = list(outs)
+    bad[0] = ins[2]
+    assert _call(fn, 10, ins, bad) == 3
+    # adjacent but disjoint ranges are fine (n = 0 avoids any launch)
+    ok = [FAKE + i * 80 for i in range(nin + nout)]
+    assert _call(fn, 0, ok[:nin], ok[nin:]) == 0
+    # contradictory backscale flags
+    assert _call(fn, 10, ins, outs, flags=3) == 4
+    # unknown flag bits
+    assert _call(fn, 10, ins, outs, flags=1 << 12) == 4
+
+
+def test_fp64_rejects_fp32_flags():
+    ins, outs = _ptrs(4), _ptrs(11, base=FAKE + (64 << 30))
+    assert _call(S.dsvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_FP64) == 4
+
+
+def test_fp32_queue_needs_rescue_and_workspace():
+    ins, outs = _ptrs(4), _ptrs(11, base=FAKE + (64 << 30))
+    assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_QUEUE) == 4
+    # queue without workspace
+    assert _call(S.ssvd2_batch, 10, ins, outs,
+                 flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE) == 1
+    # too-small workspace
+    assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE,
+                 ws=FAKE + (200 << 30), ws_bytes=16) == 6
+
+
+def test_workspace_size_and_launch_shape():
+    assert S.svd2_workspace_bytes(1000, 0) == 0
+    assert S.svd2_workspace_bytes(1000, S.SVD2_RESCUE_FP64) == 0
+    assert S.svd2_workspace_bytes(1000, S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE) >= 4000
+    old = S.svd2_get_launch()
+    with pytest.raises(S.Svd2Error):
+        S.svd2_set_launch(100, 1)
+    with pytest.raises(S.Svd2Error):
+        S.svd2_set_launch(256, 3)
+    S.svd2_set_launch(128, 2)
+    assert S.svd2_get_launch() == (128, 2)
+    S.svd2_set_launch(*old)
+
+
+def test_status_strings():
+    L = S.lib()
+    for code in range(8):
+        assert L.svd2_status_string(code)
+    assert L.svd2_status_string(3) == b"output overlaps an input or another output"
+
+
+def test_binding_raises_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(S, "_lib", None)
+    monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        S.lib()

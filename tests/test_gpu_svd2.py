@@ -1,0 +1,292 @@
+"""GPU parity of the batched 2x2 SVD (HIP path through the C ABI) against the
+CPU oracle, on seeded inputs.  Bar: s exact, sigma' within 4 ulp, U/V within
+4 eps, and rho, delta, eta (eqs. (33)-(35)) at most 16 eps in binary128.  The
+kernels follow the oracle's operation order, so the lanes are expected to be
+bitwise identical; the count is reported and required to be all lanes."""
+import numpy as np
+import pytest
+
+import oracle.oracle as O
+from tests.gpu_util import compare, oracle_outs, run_gpu, same_bits
+from workloads import SEED_BASE, random_bits, scaled_law, to_trains, uniform_real
+
+pytestmark = pytest.mark.gpu
+
+EPS = {np.float64: 2.0 ** -52, np.float32: 2.0 ** -23}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2005_07403_amd import svd2 as S
+    S.lib()
+    yield
+    S.svd2_set_launch(256, 1)
+
+
+def _set_launch(block, pt):
+    from paper_2005_07403_amd import svd2 as S
+    S.svd2_set_launch(block, pt)
+
+
+def _check(A, dtype, flags=0, rescue=False, backscale="none", expect_bitwise=True, metrics=True):
+    cplx = bool(np.iscomplexobj(A))
+    tr = to_trains(A, dtype)
+    from paper_2005_07403_amd import svd2 as S
+    if dtype == np.float32:
+        gpu, nres = run_gpu(tr, flags=flags, nrescued=True)
+    else:
+        gpu, nres = run_gpu(tr, flags=flags), None
+    ora, flagged = oracle_outs(tr, cplx, dtype, rescue=rescue, backscale=backscale)
+    st = compare(gpu, ora, cplx, EPS[dtype])
+    if expect_bitwise:
+        assert st["bitwise_lanes"] == st["lanes"], st
+    if rescue:
+        assert nres == int(flagged.sum()), (nres, int(flagged.sum()))
+    if metrics:
+        met = O.metrics(tr, gpu, cplx)
+        for key in ("rho", "delta", "eta"):
+            assert np.nanmax(met[key]) <= 16 * EPS[dtype], (key, np.nanmax(met[key]) / EPS[dtype])
+    del S
+    return st
+
+
+# ---------------------------------------------------------------------------
+# T0: the device primitives are the IEEE-754 operations the oracle uses
+# ---------------------------------------------------------------------------
+
+def _rand_f64(rng, n):
+    bits = rng.integers(0, 2 ** 63, size=n, dtype=np.int64).view(np.float64)
+    return np.where(np.isfinite(bits), bits, 1.0)
+
+
+def _fraction_round(fr, dtype):
+    """Correctly rounded Fraction -> dtype (ties to even)."""
+    from fractions import Fraction
+    f = np.array(float(fr), dtype=dtype)
+    best = None
+    for c in (np.nextafter(f, -np.inf, dtype=dtype), f, np.nextafter(f, np.inf, dtype=dtype)):
+        if not np.isfinite(c):
+            continue
+        d = abs(Fraction(float(c)) - fr)
+        if best is None or d < best[0] or (d == best[0] and (int(np.array(c).view(
+                np.int64 if dtype == np.float64 else np.int32)) % 2 == 0)):
+            best = (d, c)
+    return best[1]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_primitives_correctly_rounded(dtype):
+    import torch
+    from fractions import Fraction
+    from paper_2005_07403_amd import svd2 as S
+    rng = np.random.default_rng(SEED_BASE + 100)
+    n = 1 << 20
+    if dtype == np.float64:
+        x, y, z = _rand_f64(rng, n), _rand_f64(rng, n), _rand_f64(rng, n)
+        # plus values near 1 and in [1,3] (the invsqrt arguments), and subnormals
+        x[: n // 8] = rng.uniform(1, 3, n // 8)
+        y[n // 8: n // 4] = np.ldexp(rng.integers(1, 2 ** 52, n // 8).astype(np.float64), -1074)
+    else:
+        x = (rng.standard_normal(n) * np.exp2(rng.integers(-140, 120, n))).astype(np.float32)
+        y = (rng.standard_normal(n) * np.exp2(rng.integers(-140, 120, n))).astype(np.float32)
+        z = (rng.standard_normal(n) * np.exp2(rng.integers(-140, 120, n))).astype(np.float32)
+    dt = torch.float64 if dtype == np.float64 else torch.float32
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (x, y, z))
+    out = torch.empty_like(tx)
+
+    def run(op, a=tx, b=ty, c=tz):
+        S.svd2_probe(op, a, b, c, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().copy()
+
+    with np.errstate(all="ignore"):
+        assert np.array_equal(run(0), x / y, equal_nan=True), "division"
+        ax = np.abs(x)
+        tax = torch.from_numpy(ax).cuda()
+        assert np.array_equal(run(1, tax), np.sqrt(ax)), "sqrt"
+        # ldexp with subnormal results, including s = -1, -2 on huge values
+        e = rng.integers(-1200 if dtype == np.float64 else -300, 60, n).astype(dtype)
+        te = torch.from_numpy(e).cuda()
+        assert np.array_equal(run(3, tx, te), np.ldexp(x, e.astype(np.int64)).astype(dtype)), "ldexp"
+        fe = np.frexp(x)[1].astype(dtype)
+        got = run(4)
+        nz = x != 0
+        assert np.array_equal(got[nz], fe[nz]), "frexp exponent"
+    # fma: exact rational reference on a sample
+    got = run(2)
+    idx = rng.choice(n, 4000, replace=False)
+    for i in idx:
+        exact = Fraction(float(x[i])) * Fraction(float(y[i])) + Fraction(float(z[i]))
+        if abs(exact) >= Fraction(float(np.finfo(dtype).max)):
+            continue
+        want = _fraction_round(exact, dtype)
+        assert same_bits(np.array([got[i]], dtype=dtype), np.array([want], dtype=dtype))[0], i
+    # relaxed min/max: a NaN first argument yields the second
+    nan = np.full(8, np.nan, dtype=dtype)
+    two = np.full(8, 2.0, dtype=dtype)
+    tn, tt = torch.from_numpy(nan).cuda(), torch.from_numpy(two).cuda()
+    o8 = torch.empty_like(tn)
+    S.svd2_probe(5, tn, tt, None, o8)
+    torch.cuda.synchronize()
+    assert np.all(o8.cpu().numpy() == 2.0)
+    S.svd2_probe(6, tn, tt, None, o8)
+    torch.cuda.synchronize()
+    assert np.all(o8.cpu().numpy() == 2.0)
+
+
+# ---------------------------------------------------------------------------
+# FP64 parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("block,pt", [(256, 1), (256, 2), (64, 1), (128, 2)])
+def test_real_uniform_65536(block, pt):
+    """Real FP64, n = 65536, entries U[-1, 1] (the small parity workload)."""
+    _set_launch(block, pt)
+    _check(uniform_real(65536, SEED_BASE + 0), np.float64)
+
+
+@pytest.mark.parametrize("pt", [1, 2])
+def test_complex_scaled_law_ragged(pt):
+    """Complex FP64 with the +-m 2^e law and 1 % special lanes, ragged n."""
+    _set_launch(256, pt)
+    A, kinds = scaled_law((1 << 18) + 37, SEED_BASE + 1, True, return_kinds=True)
+    st = _check(A, np.float64)
+    assert (kinds >= 0).sum() > 2000
+    del st
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_random_bits(cplx):
+    """The paper's own input law: random 64-bit patterns, finite only."""
+    _set_launch(256, 2)
+    _check(random_bits(200003, SEED_BASE + 5, cplx), np.float64)
+
+
+@pytest.mark.parametrize("kind", range(6))
+@pytest.mark.parametrize("cplx", [False, True])
+def test_special_lanes_only(kind, cplx):
+    A, kinds = scaled_law(30000, SEED_BASE + 10 + kind, cplx, special_frac=1.0, return_kinds=True)
+    sel = kinds == kind
+    _check(A[:, sel], np.float64)
+
+
+@pytest.mark.parametrize("mode", ["safe", "all"])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_backscale_modes(mode, cplx):
+    from paper_2005_07403_amd import svd2 as S
+    flags = S.SVD2_BACKSCALE_SAFE if mode == "safe" else S.SVD2_BACKSCALE_ALL
+    A = scaled_law(50000, SEED_BASE + 20, cplx)
+    _check(A, np.float64, flags=flags, backscale=mode, metrics=(mode == "safe"))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 255, 257, 1023])
+def test_small_and_ragged_sizes(n):
+    for pt in (1, 2):
+        _set_launch(64, pt)
+        _check(scaled_law(n, SEED_BASE + 30 + n, True), np.float64, metrics=False)
+        _check(scaled_law(n, SEED_BASE + 31 + n, False), np.float64, metrics=False)
+
+
+def test_unaligned_falls_back_and_matches():
+    """Arrays offset by one element (8-byte aligned only) take the scalar
+    path and still match."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    _set_launch(256, 2)
+    n = 10001
+    A = scaled_law(n, SEED_BASE + 40, False)
+    tr = to_trains(A)
+    big = [torch.zeros(n + 1, dtype=torch.float64, device="cuda") for _ in range(4)]
+    ins = []
+    for b, t in zip(big, tr):
+        b[1:] = torch.from_numpy(t).cuda()
+        ins.append(b[1:])
+    outs = [torch.empty(n + 1, dtype=torch.float64, device="cuda")[1:] for _ in range(11)]
+    S.dsvd2_batch(n, [t.data_ptr() for t in ins], [t.data_ptr() for t in outs])
+    torch.cuda.synchronize()
+    gpu = [o.cpu().numpy() for o in outs]
+    ora, _ = oracle_outs(tr, False, np.float64)
+    st = compare(gpu, ora, False, EPS[np.float64])
+    assert st["bitwise_lanes"] == n
+
+
+def test_lane_isolation_nonfinite():
+    """A lane with Inf/NaN input must not disturb the other lanes."""
+    A = scaled_law(4096, SEED_BASE + 41, True)
+    A[0, 5] = np.inf
+    A[2, 77] = complex(np.nan, 1.0)
+    tr = to_trains(A)
+    gpu = run_gpu(tr)
+    ora, _ = oracle_outs(tr, True, np.float64)
+    ok = np.ones(4096, dtype=bool)
+    ok[[5, 77]] = False
+    compare(gpu, ora, True, EPS[np.float64], lanes=ok)
+
+
+@pytest.mark.slow
+def test_complex_full_size_2_24():
+    """The full complex workload: n = 2^24, +-m 2^e, e in [-1000, 1000], 1 %
+    special lanes, in the launch shape the benchmark times.  All lanes are
+    compared with the oracle."""
+    from bench import DEFAULT_LAUNCH
+    _set_launch(*DEFAULT_LAUNCH["z"])
+    A = scaled_law(1 << 24, SEED_BASE + 1, True)
+    st = _check(A, np.float64, metrics=False)
+    assert st["lanes"] == 1 << 24
+
+
+# ---------------------------------------------------------------------------
+# FP32 form and the FP64 rescue
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("mode", ["plain", "inplace", "queue"])
+def test_fp32_modes(cplx, mode):
+    from paper_2005_07403_amd import svd2 as S
+    _set_launch(256, 2)
+    flags = {"plain": 0, "inplace": S.SVD2_RESCUE_FP64,
+             "queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE}[mode]
+    A = scaled_law((1 << 17) + 5, SEED_BASE + 2, cplx, dtype=np.float32)
+    _check(A, np.float32, flags=flags, rescue=(mode != "plain"), metrics=(mode != "plain"))
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fp32_rescue_near_singular(cplx):
+    from paper_2005_07403_amd import svd2 as S
+    rng = np.random.default_rng(SEED_BASE + 50)
+    n = 20000
+    u = rng.standard_normal((2, n)) + (1j * rng.standard_normal((2, n)) if cplx else 0)
+    v = rng.standard_normal((2, n)) + (1j * rng.standard_normal((2, n)) if cplx else 0)
+    A = np.stack([u[0] * np.conj(v[0]), u[1] * np.conj(v[0]), u[0] * np.conj(v[1]),
+                  u[1] * np.conj(v[1])]) + 3e-8 * rng.standard_normal((4, n))
+    A = A.astype(np.complex64 if cplx else np.float32)
+    for flags in (S.SVD2_RESCUE_FP64, S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE):
+        _check(A, np.float32, flags=flags, rescue=True)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fp32_full_size_2_26_sampled(cplx):
+    """The FP32 workload at n = 2^26 with the FP64 rescue; the oracle checks
+    a random sample of 2^20 lanes of the full-size run."""
+    import torch
+    from bench import DEFAULT_LAUNCH
+    from paper_2005_07403_amd import svd2 as S
+    _set_launch(*DEFAULT_LAUNCH["c" if cplx else "s"])
+    n = 1 << 26
+    A = scaled_law(n, SEED_BASE + 2, cplx, dtype=np.float32)
+    tr = to_trains(A)
+    del A
+    dev = [torch.from_numpy(t).cuda() for t in tr]
+    out = S.svd2(dev, flags=S.SVD2_RESCUE_FP64)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(SEED_BASE + 60)
+    idx = np.sort(rng.choice(n, 1 << 20, replace=False))
+    tidx = torch.from_numpy(idx).cuda()
+    gpu = [o[tidx].cpu().numpy() for o in out]
+    sub = [np.ascontiguousarray(t[idx]) for t in tr]
+    ora, _ = oracle_outs(sub, cplx, np.float32, rescue=True)
+    st = compare(gpu, ora, cplx, EPS[np.float32])
+    assert st["bitwise_lanes"] == st["lanes"]
