@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per SVD: SoA inputs read once + U, V, smax, smin, s written once
 BYTES_PER_SVD = {"d": 120, "z": 216, "s": 60, "c": 108}
 # launch shape (threads per block, matrices per lane) used by the benchmark
-DEFAULT_LAUNCH = {"d": (256, 2), "z": (256, 1), "s": (256, 2), "c": (256, 2)}
+DEFAULT_LAUNCH = {"d": (256, 1), "z": (64, 2), "s": (256, 1), "c": (256, 1)}
 KERNEL_SOURCES = ["paper_2005_07403_amd/csrc/svd2_batch.hip", "paper_2005_07403_amd/csrc/svd2_lane.hpp"]
 
 
