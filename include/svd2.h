@@ -153,6 +153,84 @@ svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y,
 svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
                            const float *z, float *out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Kogbetliantz method for the SVD of a square matrix A of even order N
+ * (section 1): each parallel step gathers the pivot blocks
+ * [[a_pp, a_pq], [a_qp, a_qq]] of N/2 disjoint index pairs, computes their
+ * 2x2 SVDs with the batched kernels above (backscaled; FP32 with the FP64
+ * rescue), and updates A <- U^* A V in place: rows p, q by U_k^*, columns
+ * p, q by V_k, with each pivot block set to diag(sigma_p, sigma_q) and exact
+ * zeros.  The paper gives neither the pivot ordering nor the stopping rule;
+ * this library uses:
+ *  - ordering: circle-method round robin, N-1 steps per sweep; at step t,
+ *    pair 0 = (t, N-1), pair k >= 1 = ((t+k) mod (N-1), (t-k) mod (N-1)),
+ *    oriented p < q;
+ *  - placement: if |a_pp| < |a_qq| the singular values and the columns of
+ *    U_k, V_k are swapped (sigma_min goes to (p,p)), keeping the rotations
+ *    near the identity as the iteration converges;
+ *  - stopping: off(A) = sqrt(sum_{i != j} |a_ij|^2) < tol * ||A_0||_F, tested
+ *    before every sweep (one device-to-host copy per sweep).
+ * On return A holds the singular values on its diagonal (unsorted, >= 0).
+ *
+ * Storage: column-major, leading dimension lda >= N (in elements; complex
+ * elements are interleaved re, im).  A must be aligned to its element size.
+ * ws: device workspace of kog_workspace_bytes(N, dtype) bytes, 256-byte
+ * aligned, not overlapping A; calls sharing a workspace must not overlap.
+ * Entry points enqueue on `stream`; *_solve synchronises the stream once per
+ * sweep and returns when done.  Errors are as for the batched calls; a fused
+ * sweep whose grid barrier does not complete within its spin bound aborts all
+ * workgroups and *_solve returns SVD2_ERR_HIP.
+ * flags: 0 = fused (one persistent cooperative kernel per sweep, gather + SVD
+ * and update separated by grid barriers), SVD2_KOG_UNFUSED = per step a
+ * gather kernel, the batched SVD entry point and an update kernel,
+ * SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH = that chain captured once per solve
+ * into a hipGraph and replayed per sweep (solve only).
+ * ------------------------------------------------------------------------- */
+enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2 };
+enum { SVD2_KOG_F64 = 0, SVD2_KOG_C128 = 1, SVD2_KOG_F32 = 2, SVD2_KOG_C64 = 3 };
+
+size_t kog_workspace_bytes(int N, int dtype);
+
+/* one step t (0 <= t < N-1) */
+svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream);
+svd2_status zkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream);
+svd2_status skog_step(int N, float *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream);
+svd2_status ckog_step(int N, float *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream);
+/* one sweep: steps 0 .. N-2 */
+svd2_status dkog_sweep(int N, double *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream);
+svd2_status zkog_sweep(int N, double *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream);
+svd2_status skog_sweep(int N, float *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream);
+svd2_status ckog_sweep(int N, float *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream);
+/* sweeps until converged: SVD2_OK, or SVD2_NOT_CONVERGED after max_sweeps.
+   sweeps, off_rel (host pointers, may be NULL): sweeps done, final off(A)/||A_0||_F */
+svd2_status dkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
+svd2_status zkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
+svd2_status skog_solve(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
+svd2_status ckog_solve(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
+/* off(A)^2 and ||A||_F^2 accumulated in FP64 (host outputs; synchronises) */
+svd2_status dkog_norms(int N, const double *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+svd2_status zkog_norms(int N, const double *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+svd2_status skog_norms(int N, const float *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+/* last hipError_t seen by a Kogbetliantz entry point on this thread */
+int kog_last_hip_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -162,3 +162,72 @@ def metrics(ins: list, outs: list, cplx: bool, nthreads: int = 0) -> dict:
     f(n, int(cplx), _ptrs(ins), _ptrs(outs), res["kappa"].ctypes.data, res["rho"].ctypes.data,
       res["delta"].ctypes.data, res["eta"].ctypes.data, nthreads)
     return res
+
+
+# ---------------------------------------------------------------------------
+# Kogbetliantz oracle
+# ---------------------------------------------------------------------------
+
+def _kog_lib():
+    L = lib()
+    if not getattr(L, "_kog_ready", False):
+        P, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.oracle_kog_pairs.argtypes = [i, i, P]
+        for s in ("d", "z", "s", "c"):
+            getattr(L, f"oracle_kog_step_{s}").argtypes = [i, P, i, i]
+            getattr(L, f"oracle_kog_solve_{s}").argtypes = [i, P, i, d, i, P, P, P]
+            getattr(L, f"oracle_kog_solve_{s}").restype = i
+        L.oracle_kog_norms_d.argtypes = [i, P, i, i, P, P]
+        L.oracle_kog_norms_s.argtypes = [i, P, i, i, P, P]
+        L._kog_ready = True
+    return L
+
+
+def kog_pairs(N: int, t: int) -> np.ndarray:
+    out = np.zeros((N // 2, 2), dtype=np.int32)
+    _kog_lib().oracle_kog_pairs(N, t, out.ctypes.data)
+    return out
+
+
+def _kog_buf(A: np.ndarray):
+    """column-major buffer: real -> float64/float32, complex -> interleaved float64"""
+    assert A.flags.f_contiguous and A.shape[0] == A.shape[1]
+    if np.iscomplexobj(A):
+        flat = A.ravel(order="F")
+        if A.dtype == np.complex128:
+            return flat.view(np.float64), "z"
+        return flat.view(np.float32), "c"
+    return A, ("d" if A.dtype == np.float64 else "s")
+
+
+def kog_step(A: np.ndarray, t: int) -> None:
+    """One step in place (A Fortran-ordered, complex128, float64 or float32)."""
+    buf, s = _kog_buf(A)
+    getattr(_kog_lib(), f"oracle_kog_step_{s}")(A.shape[0], buf.ctypes.data, A.shape[0], t)
+
+
+def kog_norms(A: np.ndarray):
+    L = _kog_lib()
+    off2, tot2 = ctypes.c_double(), ctypes.c_double()
+    buf, s = _kog_buf(A)
+    if s in ("s", "c"):
+        L.oracle_kog_norms_s(A.shape[0], buf.ctypes.data, A.shape[0], int(s == "c"),
+                             ctypes.byref(off2), ctypes.byref(tot2))
+    else:
+        L.oracle_kog_norms_d(A.shape[0], buf.ctypes.data, A.shape[0], int(s == "z"),
+                             ctypes.byref(off2), ctypes.byref(tot2))
+    return off2.value, tot2.value
+
+
+def kog_solve(A: np.ndarray, tol: float = 1e-14, max_sweeps: int = 40) -> dict:
+    """Full solve in place.  Returns status, sweeps, off_rel, history, sigma
+    (the diagonal, sorted in descending order)."""
+    buf, s = _kog_buf(A)
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    hist = np.full(max_sweeps + 1, np.nan)
+    st = getattr(_kog_lib(), f"oracle_kog_solve_{s}")(A.shape[0], buf.ctypes.data, A.shape[0], tol,
+                                                      max_sweeps, ctypes.byref(sw), ctypes.byref(off),
+                                                      hist.ctypes.data)
+    sig = np.sort(np.abs(np.diag(A)).astype(np.float64))[::-1]
+    return dict(status=st, sweeps=sw.value, off_rel=off.value, history=hist[: sw.value + 1],
+                sigma=sig)

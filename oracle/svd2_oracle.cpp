@@ -607,3 +607,198 @@ int oracle_metrics_s(size_t n, int cplx, const float *const *in, const float *co
 }
 
 } /* extern "C" */
+
+/* ===========================================================================
+ * Kogbetliantz method (section 1), plain loops over the whole matrix.
+ * =========================================================================== */
+namespace {
+
+/* circle-method round robin, see the header */
+void kog_pairs(int N, int t, int *pairs) {
+  const int M = N - 1, n = N / 2;
+  pairs[0] = t;
+  pairs[1] = M;
+  for (int k = 1; k < n; ++k) {
+    int a = (t + k) % M, b = ((t - k) % M + M) % M;
+    pairs[2 * k] = a < b ? a : b;
+    pairs[2 * k + 1] = a < b ? b : a;
+  }
+}
+
+template <class T> struct Rot { Cx<T> u[2][2], v[2][2]; T smax, smin; };
+
+/* 2x2 SVD of one pivot block with the batched algorithm above, backscaled. */
+/* 2x2 SVD of one pivot block b = [[b_pp, b_pq], [b_qp, b_qq]] with the
+ * batched algorithm above, backscaled (Fig. 1).  The paper's SVD always puts
+ * sigma_max first (Theorem 1); inside the Kogbetliantz iteration that forces a
+ * rotation by about pi/2 whenever |b_pp| < |b_qq|, and the sweep then keeps
+ * re-sorting the diagonal.  Reading: in that case the columns of U and V and
+ * the two singular values are swapped, so each pivot keeps its larger
+ * singular value where its larger diagonal entry was. */
+template <class T, bool CPLX> Rot<T> pivot_svd(const Cx<T> b[2][2]) {
+  Prim<T> P{ORACLE_MIRROR};
+  Res<T> o; Mid<T> m{};
+  if (CPLX) {
+    T a[8] = {b[0][0].re, b[0][0].im, b[1][0].re, b[1][0].im, b[0][1].re, b[0][1].im,
+              b[1][1].re, b[1][1].im};
+    zsvd2_one(P, a, o, m);
+  } else {
+    T a[4] = {b[0][0].re, b[1][0].re, b[0][1].re, b[1][1].re};
+    dsvd2_one(P, a, o, m);
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (near_degenerate(o.smax, o.smin)) rescue_fp64<CPLX>(m, o);
+  }
+  backscale(o, ORACLE_BS_ALL);
+  Rot<T> r;
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) { r.u[i][j] = o.u[i][j]; r.v[i][j] = o.v[i][j]; }
+  r.smax = o.smax; r.smin = o.smin;
+  bool swap;
+  if (CPLX)
+    swap = b[0][0].re * b[0][0].re + b[0][0].im * b[0][0].im <
+           b[1][1].re * b[1][1].re + b[1][1].im * b[1][1].im;
+  else
+    swap = std::fabs(b[0][0].re) < std::fabs(b[1][1].re);
+  if (swap) {
+    for (int i = 0; i < 2; ++i) { std::swap(r.u[i][0], r.u[i][1]); std::swap(r.v[i][0], r.v[i][1]); }
+    std::swap(r.smax, r.smin);
+  }
+  return r;
+}
+
+template <class T, bool CPLX> struct Mat {
+  T *A; int lda;
+  Cx<T> get(int i, int j) const {
+    size_t o = (size_t)i + (size_t)j * lda;
+    return CPLX ? Cx<T>{A[2 * o], A[2 * o + 1]} : Cx<T>{A[o], T(0)};
+  }
+  void set(int i, int j, Cx<T> v) {
+    size_t o = (size_t)i + (size_t)j * lda;
+    if (CPLX) { A[2 * o] = v.re; A[2 * o + 1] = v.im; } else A[o] = v.re;
+  }
+};
+
+template <class T> Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+
+template <class T, bool CPLX> void kog_step(int N, T *A, int lda, int t) {
+  const int n = N / 2;
+  Mat<T, CPLX> M{A, lda};
+  int *pr = new int[2 * n];
+  kog_pairs(N, t, pr);
+  Rot<T> *R = new Rot<T>[n];
+  for (int k = 0; k < n; ++k) {
+    int p = pr[2 * k], q = pr[2 * k + 1];
+    Cx<T> b[2][2] = {{M.get(p, p), M.get(p, q)}, {M.get(q, p), M.get(q, q)}};
+    R[k] = pivot_svd<T, CPLX>(b);
+  }
+  /* rows: [a_p.; a_q.] <- U_k^* [a_p.; a_q.] */
+  for (int k = 0; k < n; ++k) {
+    int p = pr[2 * k], q = pr[2 * k + 1];
+    const Rot<T> &r = R[k];
+    for (int j = 0; j < N; ++j) {
+      Cx<T> b1 = M.get(p, j), b2 = M.get(q, j), t1, t2;
+      if (CPLX) {
+        t1 = cadd(cmulc(r.u[0][0], b1), cmulc(r.u[1][0], b2));
+        t2 = cadd(cmulc(r.u[0][1], b1), cmulc(r.u[1][1], b2));
+      } else {
+        t1 = {fmaT(r.u[0][0].re, b1.re, r.u[1][0].re * b2.re), T(0)};
+        t2 = {fmaT(r.u[0][1].re, b1.re, r.u[1][1].re * b2.re), T(0)};
+      }
+      M.set(p, j, t1); M.set(q, j, t2);
+    }
+  }
+  /* columns: [a_.p, a_.q] <- [a_.p, a_.q] V_l */
+  for (int l = 0; l < n; ++l) {
+    int p = pr[2 * l], q = pr[2 * l + 1];
+    const Rot<T> &r = R[l];
+    for (int i = 0; i < N; ++i) {
+      Cx<T> c1 = M.get(i, p), c2 = M.get(i, q), o1, o2;
+      if (CPLX) {
+        o1 = cadd(cmul(c1, r.v[0][0]), cmul(c2, r.v[1][0]));
+        o2 = cadd(cmul(c1, r.v[0][1]), cmul(c2, r.v[1][1]));
+      } else {
+        o1 = {fmaT(c1.re, r.v[0][0].re, c2.re * r.v[1][0].re), T(0)};
+        o2 = {fmaT(c1.re, r.v[0][1].re, c2.re * r.v[1][1].re), T(0)};
+      }
+      M.set(i, p, o1); M.set(i, q, o2);
+    }
+  }
+  /* pivot blocks become diag(sigma_max, sigma_min) */
+  for (int k = 0; k < n; ++k) {
+    int p = pr[2 * k], q = pr[2 * k + 1];
+    M.set(p, p, {R[k].smax, T(0)}); M.set(q, q, {R[k].smin, T(0)});
+    M.set(p, q, {T(0), T(0)}); M.set(q, p, {T(0), T(0)});
+  }
+  delete[] R;
+  delete[] pr;
+}
+
+template <class T, bool CPLX> void kog_norms(int N, const T *A, int lda, double &off2, double &tot2) {
+  off2 = 0; tot2 = 0;
+  Mat<T, CPLX> M{const_cast<T *>(A), lda};
+  for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N; ++i) {
+      Cx<T> v = M.get(i, j);
+      double a2 = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+      tot2 += a2;
+      if (i != j) off2 += a2;
+    }
+}
+
+template <class T, bool CPLX>
+int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, double *off_rel,
+              double *history) {
+  double off2, tot2;
+  kog_norms<T, CPLX>(N, A, lda, off2, tot2);
+  const double nrm0 = std::sqrt(tot2);
+  int sw = 0;
+  int status = 7;
+  for (;;) {
+    double rel = nrm0 > 0 ? std::sqrt(off2) / nrm0 : 0.0;
+    if (history) history[sw] = rel;
+    if (off_rel) *off_rel = rel;
+    if (rel < tol || nrm0 == 0) { status = 0; break; }
+    if (sw == max_sweeps) break;
+    for (int t = 0; t < N - 1; ++t) kog_step<T, CPLX>(N, A, lda, t);
+    ++sw;
+    kog_norms<T, CPLX>(N, A, lda, off2, tot2);
+  }
+  if (sweeps) *sweeps = sw;
+  return status;
+}
+
+} /* namespace */
+
+extern "C" {
+int oracle_kog_pairs(int N, int t, int *pairs) { kog_pairs(N, t, pairs); return 0; }
+int oracle_kog_step_d(int N, double *A, int lda, int t) { kog_step<double, false>(N, A, lda, t); return 0; }
+int oracle_kog_step_z(int N, double *A, int lda, int t) { kog_step<double, true>(N, A, lda, t); return 0; }
+int oracle_kog_step_s(int N, float *A, int lda, int t) { kog_step<float, false>(N, A, lda, t); return 0; }
+int oracle_kog_step_c(int N, float *A, int lda, int t) { kog_step<float, true>(N, A, lda, t); return 0; }
+int oracle_kog_norms_d(int N, const double *A, int lda, int cplx, double *off2, double *tot2) {
+  if (cplx) kog_norms<double, true>(N, A, lda, *off2, *tot2);
+  else kog_norms<double, false>(N, A, lda, *off2, *tot2);
+  return 0;
+}
+int oracle_kog_norms_s(int N, const float *A, int lda, int cplx, double *off2, double *tot2) {
+  if (cplx) kog_norms<float, true>(N, A, lda, *off2, *tot2);
+  else kog_norms<float, false>(N, A, lda, *off2, *tot2);
+  return 0;
+}
+int oracle_kog_solve_d(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history) {
+  return kog_solve<double, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, history);
+}
+int oracle_kog_solve_z(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history) {
+  return kog_solve<double, true>(N, A, lda, tol, max_sweeps, sweeps, off_rel, history);
+}
+int oracle_kog_solve_s(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history) {
+  return kog_solve<float, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, history);
+}
+int oracle_kog_solve_c(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history) {
+  return kog_solve<float, true>(N, A, lda, tol, max_sweeps, sweeps, off_rel, history);
+}
+} /* extern "C" */

@@ -79,6 +79,50 @@ int oracle_metrics_s(size_t n, int cplx, const float *const *in,
                      const float *const *out, double *kappa, double *rho,
                      double *delta, double *eta, int nthreads);
 
+
+/* ---------------------------------------------------------------------------
+ * Kogbetliantz method for the SVD of a square matrix of even order N = 2n
+ * (section 1): a step gathers the pivots (p,p), (q,p), (p,q), (q,q) of n
+ * disjoint pairs, computes their 2x2 SVDs (backscaled, Sigma = 2^-s Sigma'),
+ * updates rows p,q by U_k^* and columns p,q by V_k, and writes
+ * diag(sigma_max, sigma_min) with exact zeros into each pivot block.
+ * The pivot ordering is not given by the paper; this is the circle-method
+ * round robin: at step t (0 <= t < N-1) pair 0 is (t, N-1) and pair k >= 1 is
+ * ((t+k) mod (N-1), (t-k) mod (N-1)), each oriented so that p < q.
+ * Matrices are column-major with leading dimension lda; complex matrices are
+ * interleaved (re, im) per element, lda counted in complex elements.
+ * Block update order: T = U^* B first (rows), then T V (columns):
+ *   real:    T1j = fma(u11, b1j, u21*b2j), T2j = fma(u12, b1j, u22*b2j),
+ *            Bi1 = fma(Ti1, v11, Ti2*v21), Bi2 = fma(Ti1, v12, Ti2*v22)
+ *   complex: T1j = conj(u11) b1j + conj(u21) b2j (each product as eq. (5)),
+ *            Bi1 = Ti1 v11 + Ti2 v21, Bi2 = Ti1 v12 + Ti2 v22.
+ * Pivot placement (reading): if |b_pp| < |b_qq| the columns of U_k and V_k
+ * and the two singular values are swapped (sigma_min goes to (p,p)); with the
+ * descending order of Theorem 1 alone the iteration converges only linearly.
+ * FP32 matrices use the FP32 2x2 SVD with the FP64 rescue of near-degenerate
+ * pivots.  Stopping rule: off(A) = sqrt(sum_{i != j} |a_ij|^2) below
+ * tol * ||A_0||_F, tested before every sweep; a sweep is N-1 steps.
+ * ------------------------------------------------------------------------- */
+int oracle_kog_pairs(int N, int t, int *pairs /* n x 2, row-major */);
+int oracle_kog_step_d(int N, double *A, int lda, int t);
+int oracle_kog_step_z(int N, double *A, int lda, int t);
+int oracle_kog_step_s(int N, float *A, int lda, int t);
+int oracle_kog_step_c(int N, float *A, int lda, int t);
+/* off^2 and ||A||_F^2, accumulated in FP64 */
+int oracle_kog_norms_d(int N, const double *A, int lda, int cplx, double *off2, double *tot2);
+int oracle_kog_norms_s(int N, const float *A, int lda, int cplx, double *off2, double *tot2);
+/* Full solve: returns 0 on convergence, 7 when max_sweeps is reached.
+ * sweeps: sweeps performed; off_rel: off(A)/||A_0||_F at exit;
+ * history (optional, max_sweeps+1 doubles): off/||A_0||_F before each sweep. */
+int oracle_kog_solve_d(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history);
+int oracle_kog_solve_z(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history);
+int oracle_kog_solve_s(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history);
+int oracle_kog_solve_c(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, double *history);
+
 #ifdef __cplusplus
 }
 #endif

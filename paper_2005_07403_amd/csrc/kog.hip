@@ -1,0 +1,745 @@
+// kog.hip -- Kogbetliantz method for the SVD of a square matrix of even order
+// N = 2n on gfx950, built on the batched 2x2 SVD (section 1 of the paper:
+// one parallel step gathers the pivots (p,p), (q,p), (p,q), (q,q) of n
+// disjoint pairs, computes their 2x2 SVDs, and updates rows p,q from the left
+// by U_k^* and columns p,q from the right by V_k).
+//
+// Pivot ordering (not given by the paper): the circle-method round robin in
+// closed form.  At step t (0 <= t < N-1), M = N-1: pair 0 = (t, M) and pair
+// k >= 1 = ((t+k) mod M, (t-k) mod M), oriented p < q.  For consecutive k the
+// rows (t+k) mod M run forward and (t-k) mod M run backward through memory,
+// so a wavefront reads and writes both rows of its pairs as contiguous runs:
+// the in-place update is coalesced without LDS staging or a second buffer,
+// and the matrix keeps a footprint that fits the 256 MB Infinity Cache for
+// N = 4096 in FP64.
+//
+// Pivot placement (reading): if |b_pp| < |b_qq| the columns of U_k and V_k and
+// the two singular values are swapped, so sigma_min goes to (p,p); with the
+// descending order of Theorem 1 alone the sweep keeps re-sorting the diagonal
+// and converges only linearly.
+//
+// Two drivers per step: an unfused chain (gather kernel -> batched SVD entry
+// point -> update kernel, optionally replayed from a hipGraph per sweep) and a
+// fused persistent cooperative kernel that runs all steps of a sweep with two
+// grid barriers per step.
+#include "svd2.h"
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "svd2_lane.hpp"
+
+using namespace svd2;
+
+namespace {
+
+constexpr int kUpdBlock = 256;   // threads per update tile = row pairs per tile
+constexpr int kUpdL = 8;         // column pairs per update tile
+constexpr int kRedBlocks = 1024; // partial sums of the norm reduction
+constexpr unsigned kSpinLimit = 1u << 26;
+
+__device__ __forceinline__ void pair_ab(int t, int k, int M, int &a, int &b) {
+  if (k == 0) {
+    a = t;
+    b = M;
+  } else {
+    a = t + k;
+    if (a >= M) a -= M;
+    b = t - k;
+    if (b < 0) b += M;
+  }
+}
+
+template <class T, bool CPLX> struct Mat {
+  T *A;
+  size_t lda;
+  __device__ __forceinline__ Cx<T> ld(int i, int j) const {
+    size_t o = (size_t)i + (size_t)j * lda;
+    if constexpr (CPLX) {
+      typedef T V __attribute__((ext_vector_type(2)));
+      V v = *reinterpret_cast<const V *>(A + 2 * o);
+      return {v.x, v.y};
+    } else {
+      return {A[o], T(0)};
+    }
+  }
+  __device__ __forceinline__ void st(int i, int j, Cx<T> x) const {
+    size_t o = (size_t)i + (size_t)j * lda;
+    if constexpr (CPLX) {
+      typedef T V __attribute__((ext_vector_type(2)));
+      V v;
+      v.x = x.re;
+      v.y = x.im;
+      *reinterpret_cast<V *>(A + 2 * o) = v;
+    } else {
+      A[o] = x.re;
+    }
+  }
+};
+
+// Device-side view of the workspace: gathered pivots (SoA, NIN arrays of n)
+// and the batched-SVD outputs (NOUT arrays of n), as the batched kernels
+// read and write them.
+template <class T, bool CPLX> struct Bufs {
+  static constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  T *piv[NIN];
+  T *out[NOUT];
+};
+
+struct Bar {
+  unsigned count, gen, abort, pad;
+};
+
+struct Layout {
+  size_t piv, out, red, res, bar, total;
+};
+
+Layout layout(int N, size_t esz, bool cplx) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t n = (size_t)N / 2;
+  size_t nin = cplx ? 8 : 4, nout = cplx ? 19 : 11;
+  Layout L;
+  size_t arr = up(n * esz);
+  L.piv = 0;
+  L.out = L.piv + nin * arr;
+  L.red = L.out + nout * arr;
+  L.res = L.red + up(2 * kRedBlocks * sizeof(double));
+  L.bar = L.res + 256;
+  L.total = L.bar + 256;
+  return L;
+}
+
+template <class T, bool CPLX> Bufs<T, CPLX> make_bufs(void *ws, int N) {
+  Layout L = layout(N, sizeof(T), CPLX);
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t arr = up((size_t)(N / 2) * sizeof(T));
+  Bufs<T, CPLX> b;
+  char *base = (char *)ws;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + L.piv + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + L.out + i * arr);
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// gather: pivot block of pair k into the SoA trains (record order 11, 21, 12, 22)
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX>
+__device__ __forceinline__ void gather_one(const Mat<T, CPLX> &M, int N, int t, int k, T *x) {
+  int a, b;
+  pair_ab(t, k, N - 1, a, b);
+  int p = a < b ? a : b, q = a < b ? b : a;
+  Cx<T> e[4] = {M.ld(p, p), M.ld(q, p), M.ld(p, q), M.ld(q, q)};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x[2 * i] = e[i].re;
+      x[2 * i + 1] = e[i].im;
+    } else {
+      x[i] = e[i].re;
+    }
+  }
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_gather_kernel(int N, Mat<T, CPLX> M, int t,
+                                                         Bufs<T, CPLX> B) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N / 2) return;
+  T x[Bufs<T, CPLX>::NIN];
+  gather_one<T, CPLX>(M, N, t, k, x);
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// rotation of pair k as used by the update: U, V (swap applied), sigma at (p,p), (q,q)
+// ---------------------------------------------------------------------------
+template <class T> struct Rot {
+  Cx<T> u11, u21, u12, u22, v11, v21, v12, v22;
+  T sp, sq;
+};
+
+template <class T, bool CPLX>
+__device__ __forceinline__ Rot<T> load_rot(const Bufs<T, CPLX> &B, int k) {
+  Rot<T> r;
+  constexpr int K = CPLX ? 16 : 8;
+  auto g = [&](int e) -> Cx<T> {
+    if constexpr (CPLX) return {B.out[2 * e][k], B.out[2 * e + 1][k]};
+    else return {B.out[e][k], T(0)};
+  };
+  r.u11 = g(0); r.u21 = g(1); r.u12 = g(2); r.u22 = g(3);
+  r.v11 = g(4); r.v21 = g(5); r.v12 = g(6); r.v22 = g(7);
+  r.sp = B.out[K][k];
+  r.sq = B.out[K + 1][k];
+  bool sw;
+  if constexpr (CPLX) {
+    T pr = B.piv[0][k], pi = B.piv[1][k], qr = B.piv[6][k], qi = B.piv[7][k];
+    sw = pr * pr + pi * pi < qr * qr + qi * qi;
+  } else {
+    sw = vabs(B.piv[0][k]) < vabs(B.piv[3][k]);
+  }
+  if (sw) {
+    Cx<T> t;
+    t = r.u11; r.u11 = r.u12; r.u12 = t;
+    t = r.u21; r.u21 = r.u22; r.u22 = t;
+    t = r.v11; r.v11 = r.v12; r.v12 = t;
+    t = r.v21; r.v21 = r.v22; r.v22 = t;
+    T s = r.sp; r.sp = r.sq; r.sq = s;
+  }
+  return r;
+}
+
+template <class T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+
+// B' = (U_k^* B) V_l, in the oracle's rounding order
+template <class T, bool CPLX>
+__device__ __forceinline__ void rotate_block(const Rot<T> &u, const Rot<T> &v, Cx<T> &b11,
+                                             Cx<T> &b21, Cx<T> &b12, Cx<T> &b22) {
+  if constexpr (CPLX) {
+    Cx<T> t11 = cadd(cmulc(u.u11, b11), cmulc(u.u21, b21));
+    Cx<T> t21 = cadd(cmulc(u.u12, b11), cmulc(u.u22, b21));
+    Cx<T> t12 = cadd(cmulc(u.u11, b12), cmulc(u.u21, b22));
+    Cx<T> t22 = cadd(cmulc(u.u12, b12), cmulc(u.u22, b22));
+    b11 = cadd(cmul(t11, v.v11), cmul(t12, v.v21));
+    b12 = cadd(cmul(t11, v.v12), cmul(t12, v.v22));
+    b21 = cadd(cmul(t21, v.v11), cmul(t22, v.v21));
+    b22 = cadd(cmul(t21, v.v12), cmul(t22, v.v22));
+  } else {
+    T t11 = vfma(u.u11.re, b11.re, u.u21.re * b21.re);
+    T t21 = vfma(u.u12.re, b11.re, u.u22.re * b21.re);
+    T t12 = vfma(u.u11.re, b12.re, u.u21.re * b22.re);
+    T t22 = vfma(u.u12.re, b12.re, u.u22.re * b22.re);
+    b11.re = vfma(t11, v.v11.re, t12 * v.v21.re);
+    b12.re = vfma(t11, v.v12.re, t12 * v.v22.re);
+    b21.re = vfma(t21, v.v11.re, t22 * v.v21.re);
+    b22.re = vfma(t21, v.v12.re, t22 * v.v22.re);
+  }
+}
+
+// One update tile: row pairs [k0, k0 + 256) (one per thread) x column pairs
+// [l0, l0 + kUpdL).  Rows are addressed by (a, b) so that the loads and stores
+// of a wavefront form contiguous runs; the orientation p < q is applied in
+// registers.  The loads of UpdG column pairs are issued before their stores
+// (4 UpdG loads in flight per lane): the compiler cannot move a load past a
+// store to the same matrix.
+template <bool CPLX> struct UpdG { static constexpr int v = CPLX ? 2 : 4; };
+template <class T, bool CPLX>
+__device__ __forceinline__ void update_tile(const Mat<T, CPLX> &M, int N, int t,
+                                            const Bufs<T, CPLX> &B, int k0, int l0) {
+  const int n = N / 2, Mo = N - 1;
+  int k = k0 + (int)threadIdx.x;
+  if (k >= n) return;
+  int ra, rb;
+  pair_ab(t, k, Mo, ra, rb);
+  const bool kflip = ra > rb;  // then p = rb, q = ra
+  Rot<T> u = load_rot<T, CPLX>(B, k);
+  const int lend = l0 + kUpdL < n ? l0 + kUpdL : n;
+  for (int lg = l0; lg < lend; lg += UpdG<CPLX>::v) {
+    Cx<T> xa1[UpdG<CPLX>::v], xb1[UpdG<CPLX>::v], xa2[UpdG<CPLX>::v], xb2[UpdG<CPLX>::v];
+    int cp[UpdG<CPLX>::v], cq[UpdG<CPLX>::v];
+#pragma unroll
+    for (int j = 0; j < UpdG<CPLX>::v; ++j) {
+      int l = lg + j;
+      if (l < lend) {
+        int ca, cb;
+        pair_ab(t, l, Mo, ca, cb);
+        cp[j] = ca < cb ? ca : cb;
+        cq[j] = ca < cb ? cb : ca;
+        xa1[j] = M.ld(ra, cp[j]);
+        xb1[j] = M.ld(rb, cp[j]);
+        xa2[j] = M.ld(ra, cq[j]);
+        xb2[j] = M.ld(rb, cq[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < UpdG<CPLX>::v; ++j) {
+      int l = lg + j;
+      if (l < lend) {
+        Cx<T> b11 = kflip ? xb1[j] : xa1[j], b21 = kflip ? xa1[j] : xb1[j];
+        Cx<T> b12 = kflip ? xb2[j] : xa2[j], b22 = kflip ? xa2[j] : xb2[j];
+        if (l == k) {  // pivot block: diag(sigma_p, sigma_q), exact zeros elsewhere
+          b11 = Cx<T>{u.sp, T(0)};
+          b22 = Cx<T>{u.sq, T(0)};
+          b12 = b21 = Cx<T>{T(0), T(0)};
+        } else {
+          Rot<T> v = load_rot<T, CPLX>(B, l);
+          rotate_block<T, CPLX>(u, v, b11, b21, b12, b22);
+        }
+        M.st(ra, cp[j], kflip ? b21 : b11);
+        M.st(rb, cp[j], kflip ? b11 : b21);
+        M.st(ra, cq[j], kflip ? b22 : b12);
+        M.st(rb, cq[j], kflip ? b12 : b22);
+      }
+    }
+  }
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(kUpdBlock) void kog_update_kernel(int N, Mat<T, CPLX> M, int t,
+                                                               Bufs<T, CPLX> B) {
+  update_tile<T, CPLX>(M, N, t, B, blockIdx.x * kUpdBlock, blockIdx.y * kUpdL);
+}
+
+// ---------------------------------------------------------------------------
+// fused persistent sweep: for t in [t0, t1): gather + SVD, barrier, update, barrier
+// ---------------------------------------------------------------------------
+// Grid-wide barrier for a cooperative launch (all workgroups co-resident).
+// The spin is bounded: after kSpinLimit polls the barrier sets the abort flag
+// and every workgroup leaves its loop, so the kernel always terminates.
+__device__ __forceinline__ bool grid_sync(Bar *bar, unsigned nblocks, unsigned &gen) {
+  __shared__ unsigned s_abort;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned my = gen;
+    __atomic_thread_fence(__ATOMIC_RELEASE);
+    unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned ab = 0;
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar->gen, my + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    ab = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gen = my + 1;
+    s_abort = ab;
+  }
+  __syncthreads();
+  return s_abort == 0;
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX> M, int t0, int t1,
+                                                              Bufs<T, CPLX> B, Bar *bar) {
+  constexpr bool RESC = sizeof(T) == 4;
+  const int n = N / 2;
+  const unsigned G = gridDim.x;
+  const int kt = (n + kUpdBlock - 1) / kUpdBlock, lt = (n + kUpdL - 1) / kUpdL;
+  unsigned gen = 0;
+  if (threadIdx.x == 0) gen = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  for (int t = t0; t < t1; ++t) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += G * blockDim.x) {
+      T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
+      gather_one<T, CPLX>(M, N, t, k, x);
+      one_matrix<T, CPLX, RESC ? 1 : 0>(x, y, 2);
+#pragma unroll
+      for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
+#pragma unroll
+      for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
+    }
+    if (!grid_sync(bar, G, gen)) return;
+    for (int tile = blockIdx.x; tile < kt * lt; tile += G)
+      update_tile<T, CPLX>(M, N, t, B, (tile % kt) * kUpdBlock, (tile / kt) * kUpdL);
+    if (!grid_sync(bar, G, gen)) return;
+  }
+}
+
+__global__ void kog_bar_reset_kernel(Bar *bar) {
+  bar->count = 0;
+  bar->abort = 0;
+}
+
+// ---------------------------------------------------------------------------
+// off(A)^2 and ||A||_F^2 in FP64: fixed-order two-pass reduction
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_norm_partial_kernel(int N, Mat<T, CPLX> M, double *part) {
+  __shared__ double so[256], st[256];
+  double off = 0, tot = 0;
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      Cx<T> v = M.ld(i, j);
+      double a2 = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+      tot += a2;
+      if (i != j) off += a2;
+    }
+  so[threadIdx.x] = off;
+  st[threadIdx.x] = tot;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      so[threadIdx.x] += so[threadIdx.x + s];
+      st[threadIdx.x] += st[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = so[0];
+    part[2 * blockIdx.x + 1] = st[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void kog_norm_final_kernel(int nparts, const double *part, double *res) {
+  __shared__ double so[256], st[256];
+  double off = 0, tot = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    off += part[2 * i];
+    tot += part[2 * i + 1];
+  }
+  so[threadIdx.x] = off;
+  st[threadIdx.x] = tot;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      so[threadIdx.x] += so[threadIdx.x + s];
+      st[threadIdx.x] += st[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    res[0] = so[0];
+    res[1] = st[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+thread_local int g_kog_hip = 0;
+int g_fused_per_cu = 4;  // co-resident workgroups per CU used by the fused kernel
+
+svd2_status hip_st(hipError_t e) {
+  if (e == hipSuccess) return SVD2_OK;
+  g_kog_hip = (int)e;
+  return SVD2_ERR_HIP;
+}
+
+template <class T, bool CPLX> struct Ctx {
+  int N;
+  Mat<T, CPLX> M;
+  Bufs<T, CPLX> B;
+  Layout L;
+  char *ws;
+  unsigned flags;
+  hipStream_t st;
+};
+
+template <class T, bool CPLX>
+svd2_status validate(int N, T *A, int lda, void *ws, size_t ws_bytes, unsigned flags, Ctx<T, CPLX> &c) {
+  if (!A || !ws) return SVD2_ERR_NULL;
+  if (N < 2 || N % 2 || lda < N || N > (1 << 20)) return SVD2_ERR_SIZE;
+  if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH)) return SVD2_ERR_FLAGS;
+  if ((flags & SVD2_KOG_GRAPH) && !(flags & SVD2_KOG_UNFUSED)) return SVD2_ERR_FLAGS;
+  if ((uintptr_t)A % (CPLX ? 2 * sizeof(T) : sizeof(T))) return SVD2_ERR_ALIGN;
+  if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
+  c.L = layout(N, sizeof(T), CPLX);
+  if (ws_bytes < c.L.total) return SVD2_ERR_SIZE;
+  size_t abytes = ((size_t)lda * (N - 1) + N) * sizeof(T) * (CPLX ? 2 : 1);
+  uintptr_t a0 = (uintptr_t)A, a1 = a0 + abytes, w0 = (uintptr_t)ws, w1 = w0 + c.L.total;
+  if (a0 < w1 && w0 < a1) return SVD2_ERR_ALIAS;
+  c.N = N;
+  c.M = Mat<T, CPLX>{A, (size_t)lda};
+  c.B = make_bufs<T, CPLX>(ws, N);
+  c.ws = (char *)ws;
+  c.flags = flags;
+  return SVD2_OK;
+}
+
+// the batched 2x2 SVD of the gathered pivots, backscaled (FP32: with the FP64 rescue)
+template <class T, bool CPLX> svd2_status batch_svd(const Ctx<T, CPLX> &c);
+template <> svd2_status batch_svd<double, false>(const Ctx<double, false> &c) {
+  dsvd2_args a = {c.B.piv[0], c.B.piv[1], c.B.piv[2], c.B.piv[3], c.B.out[0], c.B.out[1], c.B.out[2],
+                  c.B.out[3], c.B.out[4], c.B.out[5], c.B.out[6], c.B.out[7], c.B.out[8], c.B.out[9],
+                  c.B.out[10]};
+  return dsvd2_batch(c.N / 2, &a, SVD2_BACKSCALE_ALL, c.st);
+}
+template <> svd2_status batch_svd<double, true>(const Ctx<double, true> &c) {
+  const Bufs<double, true> &b = c.B;
+  zsvd2_args a = {b.piv[0], b.piv[1], b.piv[2], b.piv[3], b.piv[4], b.piv[5], b.piv[6], b.piv[7],
+                  b.out[0], b.out[1], b.out[2], b.out[3], b.out[4], b.out[5], b.out[6], b.out[7],
+                  b.out[8], b.out[9], b.out[10], b.out[11], b.out[12], b.out[13], b.out[14],
+                  b.out[15], b.out[16], b.out[17], b.out[18]};
+  return zsvd2_batch(c.N / 2, &a, SVD2_BACKSCALE_ALL, c.st);
+}
+template <> svd2_status batch_svd<float, false>(const Ctx<float, false> &c) {
+  ssvd2_args a = {c.B.piv[0], c.B.piv[1], c.B.piv[2], c.B.piv[3], c.B.out[0], c.B.out[1], c.B.out[2],
+                  c.B.out[3], c.B.out[4], c.B.out[5], c.B.out[6], c.B.out[7], c.B.out[8], c.B.out[9],
+                  c.B.out[10], nullptr};
+  return ssvd2_batch(c.N / 2, &a, SVD2_BACKSCALE_ALL | SVD2_RESCUE_FP64, nullptr, 0, c.st);
+}
+template <> svd2_status batch_svd<float, true>(const Ctx<float, true> &c) {
+  const Bufs<float, true> &b = c.B;
+  csvd2_args a = {b.piv[0], b.piv[1], b.piv[2], b.piv[3], b.piv[4], b.piv[5], b.piv[6], b.piv[7],
+                  b.out[0], b.out[1], b.out[2], b.out[3], b.out[4], b.out[5], b.out[6], b.out[7],
+                  b.out[8], b.out[9], b.out[10], b.out[11], b.out[12], b.out[13], b.out[14],
+                  b.out[15], b.out[16], b.out[17], b.out[18], nullptr};
+  return csvd2_batch(c.N / 2, &a, SVD2_BACKSCALE_ALL | SVD2_RESCUE_FP64, nullptr, 0, c.st);
+}
+
+template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, int t) {
+  const int n = c.N / 2;
+  hipLaunchKernelGGL((kog_gather_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, c.M,
+                     t, c.B);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  s = batch_svd<T, CPLX>(c);
+  if (s != SVD2_OK) return s;
+  dim3 grid((n + kUpdBlock - 1) / kUpdBlock, (n + kUpdL - 1) / kUpdL);
+  hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, c.M, t, c.B);
+  return hip_st(hipGetLastError());
+}
+
+template <class T, bool CPLX> int fused_grid(int N) {
+  static int max_blocks = 0;  // co-resident workgroups of this kernel on device 0's shape
+  if (max_blocks == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kog_fused_kernel<T, CPLX>,
+                                                     kUpdBlock, 0) != hipSuccess)
+      return 0;
+    max_blocks = cus * (per > g_fused_per_cu ? g_fused_per_cu : per);
+  }
+  const int n = N / 2;
+  int tiles = ((n + kUpdBlock - 1) / kUpdBlock) * ((n + kUpdL - 1) / kUpdL);
+  return tiles < max_blocks ? tiles : max_blocks;
+}
+
+template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int t0, int t1) {
+  Bar *bar = (Bar *)(c.ws + c.L.bar);
+  hipLaunchKernelGGL(kog_bar_reset_kernel, dim3(1), dim3(1), 0, c.st, bar);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  int grid = fused_grid<T, CPLX>(c.N);
+  if (grid <= 0) return SVD2_ERR_HIP;
+  int N = c.N;
+  Mat<T, CPLX> M = c.M;
+  Bufs<T, CPLX> B = c.B;
+  void *args[] = {&N, &M, &t0, &t1, &B, &bar};
+  return hip_st(hipLaunchCooperativeKernel((const void *)kog_fused_kernel<T, CPLX>, dim3(grid),
+                                           dim3(kUpdBlock), args, 0, c.st));
+}
+
+template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
+  if (!(c.flags & SVD2_KOG_UNFUSED)) return fused_steps<T, CPLX>(c, 0, c.N - 1);
+  for (int t = 0; t < c.N - 1; ++t) {
+    svd2_status s = unfused_step<T, CPLX>(c, t);
+    if (s != SVD2_OK) return s;
+  }
+  return SVD2_OK;
+}
+
+template <class T, bool CPLX> svd2_status norms_async(const Ctx<T, CPLX> &c) {
+  double *part = (double *)(c.ws + c.L.red), *res = (double *)(c.ws + c.L.res);
+  int nb = c.N < kRedBlocks ? c.N : kRedBlocks;
+  hipLaunchKernelGGL((kog_norm_partial_kernel<T, CPLX>), dim3(nb), dim3(256), 0, c.st, c.N, c.M, part);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_norm_final_kernel, dim3(1), dim3(256), 0, c.st, nb, part, res);
+  return hip_st(hipGetLastError());
+}
+
+template <class T, bool CPLX> svd2_status read_norms(const Ctx<T, CPLX> &c, double &off2, double &tot2) {
+  double h[2];
+  svd2_status s = hip_st(hipMemcpyAsync(h, c.ws + c.L.res, sizeof h, hipMemcpyDeviceToHost, c.st));
+  if (s != SVD2_OK) return s;
+  s = hip_st(hipStreamSynchronize(c.st));
+  if (s != SVD2_OK) return s;
+  off2 = h[0];
+  tot2 = h[1];
+  return SVD2_OK;
+}
+
+template <class T, bool CPLX> svd2_status check_abort(const Ctx<T, CPLX> &c) {
+  if (c.flags & SVD2_KOG_UNFUSED) return SVD2_OK;
+  Bar h;
+  svd2_status s = hip_st(hipMemcpyAsync(&h, c.ws + c.L.bar, sizeof h, hipMemcpyDeviceToHost, c.st));
+  if (s != SVD2_OK) return s;
+  s = hip_st(hipStreamSynchronize(c.st));
+  if (s != SVD2_OK) return s;
+  return h.abort ? SVD2_ERR_HIP : SVD2_OK;
+}
+
+// sweep replay from a hipGraph (unfused chain captured on a private stream)
+template <class T, bool CPLX> svd2_status graph_build(Ctx<T, CPLX> c, hipGraphExec_t *exec) {
+  hipStream_t cap;
+  svd2_status s = hip_st(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  if (s != SVD2_OK) return s;
+  c.st = cap;
+  hipGraph_t g = nullptr;
+  s = hip_st(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  if (s == SVD2_OK) {
+    svd2_status s1 = SVD2_OK;
+    for (int t = 0; t < c.N - 1 && s1 == SVD2_OK; ++t) s1 = unfused_step<T, CPLX>(c, t);
+    svd2_status s2 = hip_st(hipStreamEndCapture(cap, &g));
+    s = s1 != SVD2_OK ? s1 : s2;
+  }
+  if (s == SVD2_OK) s = hip_st(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+  if (g) hipGraphDestroy(g);
+  hipStreamDestroy(cap);
+  return s;
+}
+
+template <class T, bool CPLX>
+svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, double *off_rel) {
+  if (max_sweeps < 0 || !(tol >= 0)) return SVD2_ERR_SIZE;
+  hipGraphExec_t exec = nullptr;
+  svd2_status s = SVD2_OK;
+  if (c.flags & SVD2_KOG_GRAPH) s = graph_build<T, CPLX>(c, &exec);
+  double off2 = 0, tot2 = 0, nrm0 = 0;
+  int sw = 0;
+  if (s == SVD2_OK) s = norms_async<T, CPLX>(c);
+  if (s == SVD2_OK) s = read_norms<T, CPLX>(c, off2, tot2);
+  nrm0 = __builtin_sqrt(tot2);
+  svd2_status result = SVD2_NOT_CONVERGED;
+  while (s == SVD2_OK) {
+    double rel = nrm0 > 0 ? __builtin_sqrt(off2) / nrm0 : 0.0;
+    if (off_rel) *off_rel = rel;
+    if (rel < tol || nrm0 == 0) {
+      result = SVD2_OK;
+      break;
+    }
+    if (sw == max_sweeps) break;
+    if (exec) s = hip_st(hipGraphLaunch(exec, c.st));
+    else s = sweep<T, CPLX>(c);
+    if (s == SVD2_OK) s = norms_async<T, CPLX>(c);
+    if (s == SVD2_OK) s = read_norms<T, CPLX>(c, off2, tot2);
+    if (s == SVD2_OK) s = check_abort<T, CPLX>(c);
+    ++sw;
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (sweeps) *sweeps = sw;
+  return s != SVD2_OK ? s : result;
+}
+
+template <class T, bool CPLX>
+svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  Ctx<T, CPLX> c;
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags & ~(unsigned)SVD2_KOG_GRAPH, c);
+  if (s != SVD2_OK) return s;
+  if (t < 0 || t >= N - 1) return SVD2_ERR_SIZE;
+  c.st = st;
+  return (c.flags & SVD2_KOG_UNFUSED) ? unfused_step<T, CPLX>(c, t) : fused_steps<T, CPLX>(c, t, t + 1);
+}
+
+template <class T, bool CPLX>
+svd2_status api_sweep(int N, T *A, int lda, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  Ctx<T, CPLX> c;
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags & ~(unsigned)SVD2_KOG_GRAPH, c);
+  if (s != SVD2_OK) return s;
+  c.st = st;
+  return sweep<T, CPLX>(c);
+}
+
+template <class T, bool CPLX>
+svd2_status api_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, double *off_rel,
+                      void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  Ctx<T, CPLX> c;
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
+  if (s != SVD2_OK) return s;
+  c.st = st;
+  return solve<T, CPLX>(c, tol, max_sweeps, sweeps, off_rel);
+}
+
+template <class T, bool CPLX>
+svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, void *ws, size_t wsb,
+                      hipStream_t st) {
+  Ctx<T, CPLX> c;
+  svd2_status s = validate<T, CPLX>(N, const_cast<T *>(A), lda, ws, wsb, 0, c);
+  if (s != SVD2_OK) return s;
+  if (!off2 || !tot2) return SVD2_ERR_NULL;
+  c.st = st;
+  s = norms_async<T, CPLX>(c);
+  if (s == SVD2_OK) s = read_norms<T, CPLX>(c, *off2, *tot2);
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kog_workspace_bytes(int N, int dtype) {
+  if (N < 2 || N % 2) return 0;
+  switch (dtype) {
+    case SVD2_KOG_F64: return layout(N, 8, false).total;
+    case SVD2_KOG_C128: return layout(N, 8, true).total;
+    case SVD2_KOG_F32: return layout(N, 4, false).total;
+    case SVD2_KOG_C64: return layout(N, 4, true).total;
+  }
+  return 0;
+}
+
+svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream) {
+  return api_step<double, false>(N, A, lda, t, ws, ws_bytes, flags, stream);
+}
+svd2_status zkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream) {
+  return api_step<double, true>(N, A, lda, t, ws, ws_bytes, flags, stream);
+}
+svd2_status skog_step(int N, float *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream) {
+  return api_step<float, false>(N, A, lda, t, ws, ws_bytes, flags, stream);
+}
+svd2_status ckog_step(int N, float *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
+                      hipStream_t stream) {
+  return api_step<float, true>(N, A, lda, t, ws, ws_bytes, flags, stream);
+}
+
+svd2_status dkog_sweep(int N, double *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream) {
+  return api_sweep<double, false>(N, A, lda, ws, ws_bytes, flags, stream);
+}
+svd2_status zkog_sweep(int N, double *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream) {
+  return api_sweep<double, true>(N, A, lda, ws, ws_bytes, flags, stream);
+}
+svd2_status skog_sweep(int N, float *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream) {
+  return api_sweep<float, false>(N, A, lda, ws, ws_bytes, flags, stream);
+}
+svd2_status ckog_sweep(int N, float *A, int lda, void *ws, size_t ws_bytes, unsigned flags,
+                       hipStream_t stream) {
+  return api_sweep<float, true>(N, A, lda, ws, ws_bytes, flags, stream);
+}
+
+svd2_status dkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
+  return api_solve<double, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
+}
+svd2_status zkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
+  return api_solve<double, true>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
+}
+svd2_status skog_solve(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
+  return api_solve<float, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
+}
+svd2_status ckog_solve(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
+                       double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
+  return api_solve<float, true>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
+}
+
+svd2_status dkog_norms(int N, const double *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  return api_norms<double, false>(N, A, lda, off2, tot2, ws, ws_bytes, stream);
+}
+svd2_status zkog_norms(int N, const double *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  return api_norms<double, true>(N, A, lda, off2, tot2, ws, ws_bytes, stream);
+}
+svd2_status skog_norms(int N, const float *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  return api_norms<float, false>(N, A, lda, off2, tot2, ws, ws_bytes, stream);
+}
+svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot2, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  return api_norms<float, true>(N, A, lda, off2, tot2, ws, ws_bytes, stream);
+}
+
+int kog_last_hip_error(void) { return g_kog_hip; }
+
+}  // extern "C"

@@ -367,4 +367,46 @@ template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &sm
   return -T(0);
 }
 
+// ---------------------------------------------------------------------------
+// one matrix: inputs x[NIN] -> outputs y[NOUT]; returns the rescue flag
+// RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX, int RESCUE>
+__device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
+  bool flagged = false;
+  if constexpr (!CPLX) {
+    RealRes<T> o;
+    real_lane<T>(x[0], x[1], x[2], x[3], o);
+    if constexpr (RESCUE != 0) {
+      flagged = near_degenerate(o.smax, o.smin);
+      if constexpr (RESCUE == 1) {
+        if (flagged) real_rescue(o);
+      }
+    }
+    y[0] = o.u11; y[1] = o.u21; y[2] = o.u12; y[3] = o.u22;
+    y[4] = o.v11; y[5] = o.v21; y[6] = o.v12; y[7] = o.v22;
+    T smax = o.smax, smin = o.smin;
+    T sv = backscale<T>(bs, o.s, smax, smin);
+    y[8] = smax; y[9] = smin; y[10] = sv;
+  } else {
+    CplxRes<T> o;
+    cplx_lane<T>(x, o);
+    if constexpr (RESCUE != 0) {
+      flagged = near_degenerate(o.smax, o.smin);
+      if constexpr (RESCUE == 1) {
+        if (flagged) cplx_rescue(o);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      y[2 * e] = o.u[e].re; y[2 * e + 1] = o.u[e].im;
+      y[8 + 2 * e] = o.v[e].re; y[8 + 2 * e + 1] = o.v[e].im;
+    }
+    T smax = o.smax, smin = o.smin;
+    T sv = backscale<T>(bs, o.s, smax, smin);
+    y[16] = smax; y[17] = smin; y[18] = sv;
+  }
+  return flagged;
+}
+
 }  // namespace svd2

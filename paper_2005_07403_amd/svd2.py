@@ -54,6 +54,9 @@ class Svd2Error(RuntimeError):
 _lib = None
 
 EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_workspace_bytes",
+           "kog_workspace_bytes", "dkog_step", "zkog_step", "skog_step", "ckog_step", "dkog_sweep",
+           "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
+           "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "svd2_set_launch", "svd2_get_launch", "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32"]
 
@@ -198,3 +201,102 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
     else:
         raise TypeError(dt)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Kogbetliantz entry points
+# ---------------------------------------------------------------------------
+SVD2_KOG_UNFUSED = 1
+SVD2_KOG_GRAPH = 2
+KOG_DTYPE = {"d": 0, "z": 1, "s": 2, "c": 3}
+_kog_ready = False
+
+
+def _kog():
+    global _kog_ready
+    L = lib()
+    if not _kog_ready:
+        i, sz, ui, d = ctypes.c_int, ctypes.c_size_t, ctypes.c_uint, ctypes.c_double
+        L.kog_workspace_bytes.argtypes = [i, i]
+        L.kog_workspace_bytes.restype = sz
+        for x in "dzsc":
+            getattr(L, f"{x}kog_step").argtypes = [i, _P, i, i, _P, sz, ui, _P]
+            getattr(L, f"{x}kog_sweep").argtypes = [i, _P, i, _P, sz, ui, _P]
+            getattr(L, f"{x}kog_solve").argtypes = [i, _P, i, d, i, _P, _P, _P, sz, ui, _P]
+            getattr(L, f"{x}kog_norms").argtypes = [i, _P, i, _P, _P, _P, sz, _P]
+            for f in ("step", "sweep", "solve", "norms"):
+                getattr(L, f"{x}kog_{f}").restype = i
+        L.kog_last_hip_error.restype = i
+        _kog_ready = True
+    return L
+
+
+def _kog_check(fn: str, st: int) -> None:
+    if st not in (SVD2_OK, 7):
+        raise Svd2Error(fn, st, _kog().kog_last_hip_error() if st == 5 else 0)
+
+
+def kog_kind(A) -> str:
+    """'d', 'z', 's' or 'c' for a square column-major torch tensor."""
+    import torch
+    return {torch.float64: "d", torch.complex128: "z", torch.float32: "s",
+            torch.complex64: "c"}[A.dtype]
+
+
+def kog_workspace_bytes(N: int, kind: str) -> int:
+    return int(_kog().kog_workspace_bytes(N, KOG_DTYPE[kind]))
+
+
+def _kog_args(A):
+    """A: (N, N) device tensor stored column-major (A.t() contiguous, or a
+    Fortran-ordered view).  Returns N, lda, data pointer."""
+    N = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != N or A.stride(0) != 1:
+        raise ValueError("A must be a square column-major device tensor (stride(0) == 1)")
+    return N, A.stride(1), A.data_ptr()
+
+
+def kog_workspace(A):
+    import torch
+    N = A.shape[0]
+    return torch.empty(kog_workspace_bytes(N, kog_kind(A)), dtype=torch.uint8, device=A.device)
+
+
+def kog_step(A, t: int, ws=None, flags: int = 0, stream=None) -> None:
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    ws = kog_workspace(A) if ws is None else ws
+    _kog_check(f"{k}kog_step", getattr(_kog(), f"{k}kog_step")(N, ptr, lda, t, ws.data_ptr(),
+                                                              ws.numel(), flags, _stream(stream)))
+
+
+def kog_sweep(A, ws=None, flags: int = 0, stream=None) -> None:
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    ws = kog_workspace(A) if ws is None else ws
+    _kog_check(f"{k}kog_sweep", getattr(_kog(), f"{k}kog_sweep")(N, ptr, lda, ws.data_ptr(),
+                                                                ws.numel(), flags, _stream(stream)))
+
+
+def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int = 0,
+              stream=None) -> dict:
+    """Sweeps until off(A) < tol ||A_0||_F.  Returns status, sweeps, off_rel."""
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    ws = kog_workspace(A) if ws is None else ws
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    st = getattr(_kog(), f"{k}kog_solve")(N, ptr, lda, tol, max_sweeps, ctypes.byref(sw),
+                                          ctypes.byref(off), ws.data_ptr(), ws.numel(), flags,
+                                          _stream(stream))
+    _kog_check(f"{k}kog_solve", st)
+    return dict(status=st, sweeps=sw.value, off_rel=off.value)
+
+
+def kog_norms(A, ws=None, stream=None):
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    ws = kog_workspace(A) if ws is None else ws
+    o, t = ctypes.c_double(), ctypes.c_double()
+    _kog_check(f"{k}kog_norms", getattr(_kog(), f"{k}kog_norms")(
+        N, ptr, lda, ctypes.byref(o), ctypes.byref(t), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return o.value, t.value

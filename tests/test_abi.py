@@ -116,3 +116,27 @@ def test_binding_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         S.lib()
+
+
+def test_kog_argument_errors():
+    """Kogbetliantz entry points validate before any HIP call."""
+    import ctypes
+    L = S._kog()
+    A, ws = FAKE, FAKE + (64 << 30)
+    wsb = S.kog_workspace_bytes(64, "d")
+    assert wsb > 0 and S.kog_workspace_bytes(63, "d") == 0
+    call = lambda N, a, lda, t, w, b, f: L.dkog_step(N, a, lda, t, w, b, f, None)
+    assert call(64, 0, 64, 0, ws, wsb, 0) == 1          # NULL matrix
+    assert call(64, A, 64, 0, 0, wsb, 0) == 1           # NULL workspace
+    assert call(63, A, 64, 0, ws, wsb, 0) == 6          # odd order
+    assert call(64, A, 63, 0, ws, wsb, 0) == 6          # lda < N
+    assert call(64, A, 64, 0, ws, wsb - 8, 0) == 6      # workspace too small
+    assert call(64, A + 4, 64, 0, ws, wsb, 0) == 2      # misaligned matrix
+    assert call(64, A, 64, 0, ws + 8, wsb, 0) == 2      # misaligned workspace
+    assert call(64, A, 64, 0, A + 256, wsb, 0) == 3     # workspace overlaps A
+    assert call(64, A, 64, 0, ws, wsb, 8) == 4          # unknown flag
+    assert call(64, A, 64, 0, ws, wsb, 2) == 4          # GRAPH without UNFUSED
+    assert call(64, A, 64, 63, ws, wsb, 0) == 6         # step out of range
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    assert L.dkog_solve(64, A, 64, 1e-14, -1, ctypes.byref(sw), ctypes.byref(off), ws, wsb, 0,
+                        None) == 6                      # negative max_sweeps
