@@ -618,7 +618,8 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
 template <class T, bool CPLX>
 svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
   Ctx<T, CPLX> c;
-  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags & ~(unsigned)SVD2_KOG_GRAPH, c);
+  if (flags & SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;  // graph replay is a solve-only mode
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
   if (s != SVD2_OK) return s;
   if (t < 0 || t >= N - 1) return SVD2_ERR_SIZE;
   c.st = st;
@@ -628,7 +629,8 @@ svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned
 template <class T, bool CPLX>
 svd2_status api_sweep(int N, T *A, int lda, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
   Ctx<T, CPLX> c;
-  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags & ~(unsigned)SVD2_KOG_GRAPH, c);
+  if (flags & SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;  // graph replay is a solve-only mode
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
   if (s != SVD2_OK) return s;
   c.st = st;
   return sweep<T, CPLX>(c);

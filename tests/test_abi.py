@@ -136,6 +136,8 @@ def test_kog_argument_errors():
     assert call(64, A, 64, 0, A + 256, wsb, 0) == 3     # workspace overlaps A
     assert call(64, A, 64, 0, ws, wsb, 8) == 4          # unknown flag
     assert call(64, A, 64, 0, ws, wsb, 2) == 4          # GRAPH without UNFUSED
+    assert call(64, A, 64, 0, ws, wsb, 3) == 4          # GRAPH is solve-only
+    assert L.dkog_sweep(64, A, 64, ws, wsb, 3, None) == 4
     assert call(64, A, 64, 63, ws, wsb, 0) == 6         # step out of range
     sw, off = ctypes.c_int(), ctypes.c_double()
     assert L.dkog_solve(64, A, 64, 1e-14, -1, ctypes.byref(sw), ctypes.byref(off), ws, wsb, 0,
