@@ -127,6 +127,50 @@ def read_traffic(kernel_key: str):
     return float(b.group(1))
 
 
+def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
+    """Kogbetliantz on the one-problem workload: real FP64, A = Q1 diag(s) Q2^T
+    with s geometric from 1 to 1e-12.  Sweeps/s of the fused kernel, the
+    unfused gather -> SVD -> update chain and its hipGraph replay, each timed
+    over `sweeps` sweeps from the same matrix; then a full fused solve."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    from workloads import SEED_BASE, kog_matrix
+    A, s = kog_matrix(order, SEED_BASE + 3, cond=1e12, return_sigma=True)
+    G0 = torch.from_numpy(A).cuda()
+    bytes_per_step = 2 * order * order * 8
+    out = {"order": order, "dtype": "f64", "steps_per_sweep": order - 1,
+           "algorithmic_bytes_per_step": bytes_per_step}
+    modes = {"fused": 0, "unfused": S.SVD2_KOG_UNFUSED, "graph": S.SVD2_KOG_UNFUSED | S.SVD2_KOG_GRAPH}
+    for name, fl in modes.items():
+        G = G0.clone(memory_format=torch.preserve_format)
+        ws = S.kog_workspace(G)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.kog_solve(G, tol=0.0, max_sweeps=sweeps, ws=ws, flags=fl)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"sweeps_per_s": sweeps / el, "us_per_step": el / sweeps / (order - 1) * 1e6,
+                     "GBs": bytes_per_step * (order - 1) * sweeps / el / 1e9}
+        log(f"[bench] kog {name}: {json.dumps(out[name])}")
+        del G, ws
+    if solve:
+        best = max(modes, key=lambda m: out[m]["sweeps_per_s"])
+        G = G0.clone(memory_format=torch.preserve_format)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = S.kog_solve(G, tol=1e-14, max_sweeps=60, flags=modes[best])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sig = np.sort(np.diag(G.cpu().numpy()))[::-1]
+        out["solve"] = {"mode": best, "status": r["status"], "sweeps": r["sweeps"],
+                        "off_rel": r["off_rel"], "seconds": el, "sweeps_per_s": r["sweeps"] / el,
+                        "sigma_max_abs_err_rel": float(np.max(np.abs(sig - s)) / s[0])}
+        log(f"[bench] kog solve: {json.dumps(out['solve'])}")
+    del G0
+    torch.cuda.empty_cache()
+    return out
+
+
 def summarize(variant, r, flags_desc=""):
     n = r["n"]
     kms = float(np.mean(r["kernel_ms"]))
@@ -147,6 +191,8 @@ def main():
                     help="time one variant only (for profiling runs)")
     ap.add_argument("--n", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kog", action="store_true", help="skip the Kogbetliantz measurement")
+    ap.add_argument("--kog-order", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -189,6 +235,11 @@ def main():
         else:
             del tr
 
+    kog = None
+    if not args.no_kog and not args.only:
+        log(f"[bench] Kogbetliantz, order {args.kog_order}")
+        kog = kog_bench(args.kog_order)
+
     head = "z" if "z" in results else variants[0]
     h = results[head]
     steps = args.steps
@@ -225,6 +276,7 @@ def main():
                      "traffic": traffic},
         "cpu_baseline": cpu,
         "variants": results,
+        "kogbetliantz": kog,
         "kernel_source_sha": source_hash(),
     }
     print(json.dumps(line), flush=True)

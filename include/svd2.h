@@ -230,6 +230,10 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
                        size_t ws_bytes, hipStream_t stream);
 /* last hipError_t seen by a Kogbetliantz entry point on this thread */
 int kog_last_hip_error(void);
+/* Workgroups per CU of the fused kernel's cooperative grid, 1..16 (capped by
+   the kernel's occupancy); a tuning knob, default 1.  SVD2_ERR_SIZE if out of
+   range. */
+svd2_status kog_set_fused_blocks_per_cu(int per_cu);
 
 #ifdef __cplusplus
 }

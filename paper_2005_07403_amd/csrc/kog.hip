@@ -38,7 +38,7 @@ namespace {
 constexpr int kUpdBlock = 256;   // threads per update tile = row pairs per tile
 constexpr int kUpdL = 8;         // column pairs per update tile
 constexpr int kRedBlocks = 1024; // partial sums of the norm reduction
-constexpr unsigned kSpinLimit = 1u << 26;
+constexpr unsigned kSpinLimit = 1u << 20;
 
 __device__ __forceinline__ void pair_ab(int t, int k, int M, int &a, int &b) {
   if (k == 0) {
@@ -93,8 +93,9 @@ struct Bar {
 };
 
 struct Layout {
-  size_t piv, out, red, res, bar, total;
+  size_t piv, out, red, res, bar, flags, total;
 };
+constexpr int kMaxFusedBlocks = 4096;  // barrier slots (64 bytes each)
 
 Layout layout(int N, size_t esz, bool cplx) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -107,7 +108,8 @@ Layout layout(int N, size_t esz, bool cplx) {
   L.red = L.out + nout * arr;
   L.res = L.red + up(2 * kRedBlocks * sizeof(double));
   L.bar = L.res + 256;
-  L.total = L.bar + 256;
+  L.flags = L.bar + 256;
+  L.total = L.flags + (size_t)kMaxFusedBlocks * 64;
   return L;
 }
 
@@ -287,49 +289,64 @@ __global__ __launch_bounds__(kUpdBlock) void kog_update_kernel(int N, Mat<T, CPL
 // ---------------------------------------------------------------------------
 // fused persistent sweep: for t in [t0, t1): gather + SVD, barrier, update, barrier
 // ---------------------------------------------------------------------------
-// Grid-wide barrier for a cooperative launch (all workgroups co-resident).
-// The spin is bounded: after kSpinLimit polls the barrier sets the abort flag
-// and every workgroup leaves its loop, so the kernel always terminates.
-__device__ __forceinline__ bool grid_sync(Bar *bar, unsigned nblocks, unsigned &gen) {
+// Grid-wide barrier for a cooperative launch (all workgroups co-resident),
+// without a contended counter: workgroup g publishes the barrier epoch in its
+// own 64-byte slot flags[16 g]; the first wavefront of workgroup 0 polls all
+// slots and then publishes the epoch in bar->gen, which the other workgroups
+// poll.  Memory ordering at agent scope: a release before publishing (one L2
+// write-back), relaxed polling (no cache invalidation per poll), one acquire
+// after.  Every wait is bounded: after kSpinLimit polls the waiter sets the
+// abort flag, all workgroups leave their loops, and the kernel terminates.
+__device__ __forceinline__ bool spin_until(const unsigned *word, unsigned epoch, Bar *bar) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if ((spins & 255u) == 0 && __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool grid_sync(Bar *bar, unsigned *flags, unsigned nblocks, unsigned &epoch) {
   __shared__ unsigned s_abort;
+  const unsigned e = ++epoch;
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned my = gen;
-    __atomic_thread_fence(__ATOMIC_RELEASE);
-    unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned ab = 0;
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar->gen, my + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
-        __builtin_amdgcn_s_sleep(1);
-        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&flags[16 * blockIdx.x], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) {
+      bool ok = true;
+      for (unsigned g = threadIdx.x; g < nblocks && ok; g += 64) ok = spin_until(&flags[16 * g], e, bar);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&bar->gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    ab = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    gen = my + 1;
-    s_abort = ab;
+  } else if (threadIdx.x == 0) {
+    spin_until(&bar->gen, e, bar);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  if (threadIdx.x == 0) s_abort = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   return s_abort == 0;
 }
 
 template <class T, bool CPLX>
 __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX> M, int t0, int t1,
-                                                              Bufs<T, CPLX> B, Bar *bar) {
+                                                              Bufs<T, CPLX> B, Bar *bar,
+                                                              unsigned *flags) {
   constexpr bool RESC = sizeof(T) == 4;
   const int n = N / 2;
   const unsigned G = gridDim.x;
   const int kt = (n + kUpdBlock - 1) / kUpdBlock, lt = (n + kUpdL - 1) / kUpdL;
-  unsigned gen = 0;
-  if (threadIdx.x == 0) gen = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned epoch = 0;  // barrier epochs restart at 1 in every launch
   for (int t = t0; t < t1; ++t) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += G * blockDim.x) {
       T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
@@ -340,16 +357,21 @@ __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX
 #pragma unroll
       for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
     }
-    if (!grid_sync(bar, G, gen)) return;
+    if (!grid_sync(bar, flags, G, epoch)) return;
     for (int tile = blockIdx.x; tile < kt * lt; tile += G)
       update_tile<T, CPLX>(M, N, t, B, (tile % kt) * kUpdBlock, (tile / kt) * kUpdL);
-    if (!grid_sync(bar, G, gen)) return;
+    if (!grid_sync(bar, flags, G, epoch)) return;
   }
 }
 
-__global__ void kog_bar_reset_kernel(Bar *bar) {
-  bar->count = 0;
-  bar->abort = 0;
+__global__ void kog_bar_reset_kernel(Bar *bar, unsigned *flags, int nflags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    bar->count = 0;
+    bar->gen = 0;
+    bar->abort = 0;
+  }
+  if (i < nflags) flags[16 * i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +431,7 @@ __global__ __launch_bounds__(256) void kog_norm_final_kernel(int nparts, const d
 // host side
 // ---------------------------------------------------------------------------
 thread_local int g_kog_hip = 0;
-int g_fused_per_cu = 4;  // co-resident workgroups per CU used by the fused kernel
+int g_fused_per_cu = 1;  // co-resident workgroups per CU used by the fused kernel
 
 svd2_status hip_st(hipError_t e) {
   if (e == hipSuccess) return SVD2_OK;
@@ -430,7 +452,7 @@ template <class T, bool CPLX> struct Ctx {
 template <class T, bool CPLX>
 svd2_status validate(int N, T *A, int lda, void *ws, size_t ws_bytes, unsigned flags, Ctx<T, CPLX> &c) {
   if (!A || !ws) return SVD2_ERR_NULL;
-  if (N < 2 || N % 2 || lda < N || N > (1 << 20)) return SVD2_ERR_SIZE;
+  if (N < 2 || N % 2 || lda < N || N > (1 << 19)) return SVD2_ERR_SIZE;
   if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH)) return SVD2_ERR_FLAGS;
   if ((flags & SVD2_KOG_GRAPH) && !(flags & SVD2_KOG_UNFUSED)) return SVD2_ERR_FLAGS;
   if ((uintptr_t)A % (CPLX ? 2 * sizeof(T) : sizeof(T))) return SVD2_ERR_ALIGN;
@@ -493,16 +515,19 @@ template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, in
 }
 
 template <class T, bool CPLX> int fused_grid(int N) {
-  static int max_blocks = 0;  // co-resident workgroups of this kernel on device 0's shape
-  if (max_blocks == 0) {
-    int dev = 0, cus = 0, per = 0;
+  static int cus = 0, per = 0;  // CU count and occupancy of this kernel (device 0's shape)
+  if (cus == 0) {
+    int dev = 0, c = 0, p = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kog_fused_kernel<T, CPLX>,
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, (const void *)kog_fused_kernel<T, CPLX>,
                                                      kUpdBlock, 0) != hipSuccess)
       return 0;
-    max_blocks = cus * (per > g_fused_per_cu ? g_fused_per_cu : per);
+    per = p;
+    cus = c;
   }
+  int want = g_fused_per_cu < per ? g_fused_per_cu : per;
+  int max_blocks = cus * want;
   const int n = N / 2;
   int tiles = ((n + kUpdBlock - 1) / kUpdBlock) * ((n + kUpdL - 1) / kUpdL);
   return tiles < max_blocks ? tiles : max_blocks;
@@ -510,15 +535,16 @@ template <class T, bool CPLX> int fused_grid(int N) {
 
 template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int t0, int t1) {
   Bar *bar = (Bar *)(c.ws + c.L.bar);
-  hipLaunchKernelGGL(kog_bar_reset_kernel, dim3(1), dim3(1), 0, c.st, bar);
+  unsigned *flags = (unsigned *)(c.ws + c.L.flags);
+  int grid = fused_grid<T, CPLX>(c.N);
+  if (grid <= 0 || grid > kMaxFusedBlocks) return SVD2_ERR_HIP;
+  hipLaunchKernelGGL(kog_bar_reset_kernel, dim3((grid + 255) / 256), dim3(256), 0, c.st, bar, flags, grid);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
-  int grid = fused_grid<T, CPLX>(c.N);
-  if (grid <= 0) return SVD2_ERR_HIP;
   int N = c.N;
   Mat<T, CPLX> M = c.M;
   Bufs<T, CPLX> B = c.B;
-  void *args[] = {&N, &M, &t0, &t1, &B, &bar};
+  void *args[] = {&N, &M, &t0, &t1, &B, &bar, &flags};
   return hip_st(hipLaunchCooperativeKernel((const void *)kog_fused_kernel<T, CPLX>, dim3(grid),
                                            dim3(kUpdBlock), args, 0, c.st));
 }
@@ -743,5 +769,11 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
 }
 
 int kog_last_hip_error(void) { return g_kog_hip; }
+
+svd2_status kog_set_fused_blocks_per_cu(int per_cu) {
+  if (per_cu < 1 || per_cu > 16) return SVD2_ERR_SIZE;
+  g_fused_per_cu = per_cu;
+  return SVD2_OK;
+}
 
 }  // extern "C"

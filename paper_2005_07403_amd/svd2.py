@@ -57,6 +57,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_workspace_bytes", "dkog_step", "zkog_step", "skog_step", "ckog_step", "dkog_sweep",
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
+           "kog_set_fused_blocks_per_cu",
            "svd2_set_launch", "svd2_get_launch", "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32"]
 
@@ -227,6 +228,8 @@ def _kog():
             for f in ("step", "sweep", "solve", "norms"):
                 getattr(L, f"{x}kog_{f}").restype = i
         L.kog_last_hip_error.restype = i
+        L.kog_set_fused_blocks_per_cu.argtypes = [i]
+        L.kog_set_fused_blocks_per_cu.restype = i
         _kog_ready = True
     return L
 
@@ -300,3 +303,7 @@ def kog_norms(A, ws=None, stream=None):
     _kog_check(f"{k}kog_norms", getattr(_kog(), f"{k}kog_norms")(
         N, ptr, lda, ctypes.byref(o), ctypes.byref(t), ws.data_ptr(), ws.numel(), _stream(stream)))
     return o.value, t.value
+
+
+def kog_set_fused_blocks_per_cu(per_cu: int) -> None:
+    _kog_check("kog_set_fused_blocks_per_cu", _kog().kog_set_fused_blocks_per_cu(per_cu))
