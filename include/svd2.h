@@ -228,12 +228,50 @@ svd2_status skog_norms(int N, const float *A, int lda, double *off2, double *tot
                        size_t ws_bytes, hipStream_t stream);
 svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot2, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+/* ---------------------------------------------------------------------------
+ * Many Kogbetliantz problems of uneven order and mixed element type in one
+ * solve.  Each step of the batch runs three kernels over all running problems
+ * at once (pivot gathers + 2x2 SVDs; updates, with each problem's tile shape
+ * from kog_set_tile_rules; a per-problem finish that advances the problem's
+ * own step and, at the end of its sweep, decides convergence on the device
+ * from the off-diagonal mass the update wrote).  Problems keep their own
+ * sweep length N_p - 1; a converged problem stops.  The host checks one
+ * counter every 64 steps and compacts the work lists as problems finish.
+ * With SVD2_KOG_GRAPH the 64 steps are captured once into a hipGraph and
+ * replayed.  Synchronises the stream; returns SVD2_OK if every problem
+ * converged, SVD2_NOT_CONVERGED otherwise (see each problem's status).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int dtype;      /* in: SVD2_KOG_F64, _C128, _F32 or _C64                       */
+  int N;          /* in: even order                                              */
+  int lda;        /* in: leading dimension (elements), >= N                      */
+  void *A;        /* in/out: device matrix, column-major; diagonal = sigma on exit */
+  double tol;     /* in: stop when off(A) < tol ||A_0||_F (checked per sweep)    */
+  int max_sweeps; /* in                                                          */
+  int status;     /* out: SVD2_OK or SVD2_NOT_CONVERGED                          */
+  int sweeps;     /* out: sweeps done                                            */
+  double off_rel; /* out: off(A) / ||A_0||_F at the last check                   */
+} kog_problem;
+
+/* Device workspace for kog_batch_solve (0 on invalid descriptors). */
+size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs);
+/* probs: host array, read and updated.  Matrices must not overlap each other
+   or the workspace (the latter is checked).  flags: 0 or SVD2_KOG_GRAPH. */
+svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
+                            hipStream_t stream);
+
 /* last hipError_t seen by a Kogbetliantz entry point on this thread */
 int kog_last_hip_error(void);
 /* Workgroups per CU of the fused kernel's cooperative grid, 1..16 (capped by
    the kernel's occupancy); a tuning knob, default 1.  SVD2_ERR_SIZE if out of
    range. */
 svd2_status kog_set_fused_blocks_per_cu(int per_cu);
+/* Update-tile shapes by order (set by the autotuner): for an order N the
+   first rule i with N <= max_order[i] applies; a tile covers kc[i] row pairs
+   (64, 128 or 256) and lc[i] column pairs (1..4096) on one 256-thread
+   workgroup.  max_order must increase.  count == 0 restores the default
+   (kc 256, lc 8 for every order).  Host arrays, copied.  Affects later calls. */
+svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, const int *lc);
 
 #ifdef __cplusplus
 }

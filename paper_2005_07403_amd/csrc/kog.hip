@@ -29,14 +29,15 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <vector>
+
 #include "svd2_lane.hpp"
 
 using namespace svd2;
 
 namespace {
 
-constexpr int kUpdBlock = 256;   // threads per update tile = row pairs per tile
-constexpr int kUpdL = 8;         // column pairs per update tile
+constexpr int kUpdBlock = 256;   // threads per update workgroup
 constexpr int kRedBlocks = 1024; // partial sums of the norm reduction
 constexpr unsigned kSpinLimit = 1u << 20;
 
@@ -222,30 +223,45 @@ __device__ __forceinline__ void rotate_block(const Rot<T> &u, const Rot<T> &v, C
   }
 }
 
-// One update tile: row pairs [k0, k0 + 256) (one per thread) x column pairs
-// [l0, l0 + kUpdL).  Rows are addressed by (a, b) so that the loads and stores
-// of a wavefront form contiguous runs; the orientation p < q is applied in
-// registers.  The loads of UpdG column pairs are issued before their stores
-// (4 UpdG loads in flight per lane): the compiler cannot move a load past a
-// store to the same matrix.
+// One update tile: row pairs [k0, k0 + kc) x column pairs [l0, l0 + lc), on a
+// workgroup of kUpdBlock threads: thread i takes row pair k0 + i % kc and every
+// (kUpdBlock / kc)-th column pair of the tile (kc in {64, 128, 256}, so small
+// orders still fill the workgroup).  Rows are addressed by (a, b) so that the
+// loads and stores of a wavefront form contiguous runs; the orientation
+// p < q is applied in registers.  The loads of UpdG column pairs are issued
+// before their stores (the compiler cannot move a load past a store to the
+// same matrix).  With ACC the thread returns the sum of |a_ij|^2 over the
+// off-diagonal entries it wrote (FP64), for the convergence test.
+struct Tile {
+  int k0, kc, l0, lc;
+};
 template <bool CPLX> struct UpdG { static constexpr int v = CPLX ? 2 : 4; };
-template <class T, bool CPLX>
-__device__ __forceinline__ void update_tile(const Mat<T, CPLX> &M, int N, int t,
-                                            const Bufs<T, CPLX> &B, int k0, int l0) {
+
+template <class T> __device__ __forceinline__ double abs2(Cx<T> x) {
+  return (double)x.re * (double)x.re + (double)x.im * (double)x.im;
+}
+
+template <class T, bool CPLX, bool ACC>
+__device__ __forceinline__ double update_tile(const Mat<T, CPLX> &M, int N, int t,
+                                              const Bufs<T, CPLX> &B, Tile tl) {
+  constexpr int G = UpdG<CPLX>::v;
   const int n = N / 2, Mo = N - 1;
-  int k = k0 + (int)threadIdx.x;
-  if (k >= n) return;
+  const int groups = kUpdBlock / tl.kc;
+  const int k = tl.k0 + (int)threadIdx.x % tl.kc;
+  const int g = (int)threadIdx.x / tl.kc;
+  double off2 = 0.0;
+  if (k >= n) return off2;
   int ra, rb;
   pair_ab(t, k, Mo, ra, rb);
   const bool kflip = ra > rb;  // then p = rb, q = ra
   Rot<T> u = load_rot<T, CPLX>(B, k);
-  const int lend = l0 + kUpdL < n ? l0 + kUpdL : n;
-  for (int lg = l0; lg < lend; lg += UpdG<CPLX>::v) {
-    Cx<T> xa1[UpdG<CPLX>::v], xb1[UpdG<CPLX>::v], xa2[UpdG<CPLX>::v], xb2[UpdG<CPLX>::v];
-    int cp[UpdG<CPLX>::v], cq[UpdG<CPLX>::v];
+  const int lend = tl.l0 + tl.lc < n ? tl.l0 + tl.lc : n;
+  for (int lb = tl.l0 + g; lb < lend; lb += groups * G) {
+    Cx<T> xa1[G], xb1[G], xa2[G], xb2[G];
+    int cp[G], cq[G];
 #pragma unroll
-    for (int j = 0; j < UpdG<CPLX>::v; ++j) {
-      int l = lg + j;
+    for (int j = 0; j < G; ++j) {
+      int l = lb + groups * j;
       if (l < lend) {
         int ca, cb;
         pair_ab(t, l, Mo, ca, cb);
@@ -258,8 +274,8 @@ __device__ __forceinline__ void update_tile(const Mat<T, CPLX> &M, int N, int t,
       }
     }
 #pragma unroll
-    for (int j = 0; j < UpdG<CPLX>::v; ++j) {
-      int l = lg + j;
+    for (int j = 0; j < G; ++j) {
+      int l = lb + groups * j;
       if (l < lend) {
         Cx<T> b11 = kflip ? xb1[j] : xa1[j], b21 = kflip ? xa1[j] : xb1[j];
         Cx<T> b12 = kflip ? xb2[j] : xa2[j], b22 = kflip ? xa2[j] : xb2[j];
@@ -270,6 +286,7 @@ __device__ __forceinline__ void update_tile(const Mat<T, CPLX> &M, int N, int t,
         } else {
           Rot<T> v = load_rot<T, CPLX>(B, l);
           rotate_block<T, CPLX>(u, v, b11, b21, b12, b22);
+          if (ACC) off2 += (abs2(b11) + abs2(b21)) + (abs2(b12) + abs2(b22));
         }
         M.st(ra, cp[j], kflip ? b21 : b11);
         M.st(rb, cp[j], kflip ? b11 : b21);
@@ -278,12 +295,20 @@ __device__ __forceinline__ void update_tile(const Mat<T, CPLX> &M, int N, int t,
       }
     }
   }
+  return off2;
 }
+
+// tile shape by order: the first rule with N <= max_order applies
+struct TileRule {
+  int max_order, kc, lc;
+};
+constexpr int kMaxRules = 16;
+__host__ __device__ inline TileRule default_rule() { return TileRule{0x7fffffff, 256, 8}; }
 
 template <class T, bool CPLX>
 __global__ __launch_bounds__(kUpdBlock) void kog_update_kernel(int N, Mat<T, CPLX> M, int t,
-                                                               Bufs<T, CPLX> B) {
-  update_tile<T, CPLX>(M, N, t, B, blockIdx.x * kUpdBlock, blockIdx.y * kUpdL);
+                                                               Bufs<T, CPLX> B, int kc, int lc) {
+  update_tile<T, CPLX, false>(M, N, t, B, Tile{(int)blockIdx.x * kc, kc, (int)blockIdx.y * lc, lc});
 }
 
 // ---------------------------------------------------------------------------
@@ -341,11 +366,11 @@ __device__ __forceinline__ bool grid_sync(Bar *bar, unsigned *flags, unsigned nb
 template <class T, bool CPLX>
 __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX> M, int t0, int t1,
                                                               Bufs<T, CPLX> B, Bar *bar,
-                                                              unsigned *flags) {
+                                                              unsigned *flags, int kc, int lc) {
   constexpr bool RESC = sizeof(T) == 4;
   const int n = N / 2;
   const unsigned G = gridDim.x;
-  const int kt = (n + kUpdBlock - 1) / kUpdBlock, lt = (n + kUpdL - 1) / kUpdL;
+  const int kt = (n + kc - 1) / kc, lt = (n + lc - 1) / lc;
   unsigned epoch = 0;  // barrier epochs restart at 1 in every launch
   for (int t = t0; t < t1; ++t) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += G * blockDim.x) {
@@ -359,7 +384,7 @@ __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX
     }
     if (!grid_sync(bar, flags, G, epoch)) return;
     for (int tile = blockIdx.x; tile < kt * lt; tile += G)
-      update_tile<T, CPLX>(M, N, t, B, (tile % kt) * kUpdBlock, (tile / kt) * kUpdL);
+      update_tile<T, CPLX, false>(M, N, t, B, Tile{(tile % kt) * kc, kc, (tile / kt) * lc, lc});
     if (!grid_sync(bar, flags, G, epoch)) return;
   }
 }
@@ -427,11 +452,187 @@ __global__ __launch_bounds__(256) void kog_norm_final_kernel(int nparts, const d
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Many problems of uneven order and mixed element type in one launch per
+// phase.  A step of the batch is three kernels over a static work list:
+// pivot chunks (gather + 2x2 SVD) of every active problem, update tiles of
+// every active problem (each with its own tile shape and the off-diagonal mass
+// it wrote), and a per-problem finish (advance the step, and at the end of a
+// problem's sweep decide convergence on the device).  The host replays a
+// hipGraph of K such steps and reads one counter per replay.
+// ---------------------------------------------------------------------------
+struct DevProb {
+  void *A;
+  long long lda, piv_off, out_off;  // buffer offsets in bytes from the workspace base
+  int N, kind, kc, lc;
+  int part_off, ntiles, max_sweeps, pad0;
+  double tol, tot0;                 // tot0 = ||A_0||_F
+  int t, sweeps, status, pad1;      // status: 0 running, 1 converged, 2 max_sweeps reached
+  double off_rel;
+};
+struct BatchHdr {
+  int nA, nB, nprob, active;
+};
+
+__host__ __device__ inline size_t arr_bytes(int N, int esz) {
+  return (((size_t)(N / 2) * esz) + 255) & ~size_t(255);
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ Bufs<T, CPLX> bufs_of(char *ws, const DevProb &P) {
+  Bufs<T, CPLX> b;
+  size_t arr = arr_bytes(P.N, sizeof(T));
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(ws + P.piv_off + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(ws + P.out_off + i * arr);
+  return b;
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ void batch_pivot(char *ws, const DevProb &P, int k) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  Bufs<T, CPLX> B = bufs_of<T, CPLX>(ws, P);
+  T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
+  gather_one<T, CPLX>(M, P.N, P.t, k, x);
+  one_matrix<T, CPLX, RESC>(x, y, 2);
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ double batch_update(char *ws, const DevProb &P, Tile tl) {
+  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  return update_tile<T, CPLX, true>(M, P.N, P.t, bufs_of<T, CPLX>(ws, P), tl);
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ void batch_norm(const DevProb &P, double &off, double &tot) {
+  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  for (int j = 0; j < P.N; ++j)
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) {
+      double a2 = abs2(M.ld(i, j));
+      tot += a2;
+      if (i != j) off += a2;
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kUpdBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_init_kernel(BatchHdr *hdr, DevProb *probs) {
+  __shared__ double red[kUpdBlock];
+  for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
+    DevProb &P = probs[p];
+    double off = 0, tot = 0;
+    switch (P.kind) {
+      case SVD2_KOG_F64: batch_norm<double, false>(P, off, tot); break;
+      case SVD2_KOG_C128: batch_norm<double, true>(P, off, tot); break;
+      case SVD2_KOG_F32: batch_norm<float, false>(P, off, tot); break;
+      default: batch_norm<float, true>(P, off, tot); break;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (threadIdx.x == 0) {
+      double nrm = __builtin_sqrt(tot);
+      double rel = nrm > 0 ? __builtin_sqrt(off) / nrm : 0.0;
+      P.tot0 = nrm;
+      P.off_rel = rel;
+      P.t = 0;
+      P.sweeps = 0;
+      P.status = (rel < P.tol || nrm == 0) ? 1 : (P.max_sweeps == 0 ? 2 : 0);
+      if (P.status != 0) atomicSub(&hdr->active, 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, const BatchHdr *hdr,
+                                                                    const int2 *items, const DevProb *probs) {
+  const int nA = hdr->nA;
+  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
+    const int2 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0) continue;
+    const int k = item.y * kUpdBlock + (int)threadIdx.x;
+    if (k >= P.N / 2) continue;
+    switch (P.kind) {
+      case SVD2_KOG_F64: batch_pivot<double, false>(ws, P, k); break;
+      case SVD2_KOG_C128: batch_pivot<double, true>(ws, P, k); break;
+      case SVD2_KOG_F32: batch_pivot<float, false>(ws, P, k); break;
+      default: batch_pivot<float, true>(ws, P, k); break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, const BatchHdr *hdr,
+                                                                     const int4 *items, const DevProb *probs,
+                                                                     double *partials) {
+  __shared__ double red[kUpdBlock];
+  const int nB = hdr->nB;
+  for (int it = blockIdx.x; it < nB; it += gridDim.x) {
+    const int4 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0) continue;
+    const Tile tl{item.y, P.kc, item.z, P.lc};
+    double off2;
+    switch (P.kind) {
+      case SVD2_KOG_F64: off2 = batch_update<double, false>(ws, P, tl); break;
+      case SVD2_KOG_C128: off2 = batch_update<double, true>(ws, P, tl); break;
+      case SVD2_KOG_F32: off2 = batch_update<float, false>(ws, P, tl); break;
+      default: off2 = batch_update<float, true>(ws, P, tl); break;
+    }
+    off2 = block_sum(off2, red);
+    if (threadIdx.x == 0) partials[P.part_off + item.w] = off2;
+  }
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *hdr, DevProb *probs,
+                                                                     const double *partials) {
+  __shared__ double red[kUpdBlock];
+  for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
+    DevProb &P = probs[p];
+    if (P.status != 0) continue;
+    const bool sweep_end = P.t == P.N - 2;
+    double off2 = 0;
+    if (sweep_end) {
+      for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) off2 += partials[P.part_off + i];
+      off2 = block_sum(off2, red);
+    }
+    if (threadIdx.x == 0) {
+      if (sweep_end) {
+        int sw = P.sweeps + 1;
+        double rel = P.tot0 > 0 ? __builtin_sqrt(off2) / P.tot0 : 0.0;
+        P.sweeps = sw;
+        P.off_rel = rel;
+        if (rel < P.tol) P.status = 1;
+        else if (sw >= P.max_sweeps) P.status = 2;
+        if (P.status != 0) atomicSub(&hdr->active, 1);
+      }
+      P.t = (P.t + 1 == P.N - 1) ? 0 : P.t + 1;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 thread_local int g_kog_hip = 0;
 int g_fused_per_cu = 1;  // co-resident workgroups per CU used by the fused kernel
+TileRule g_rules[kMaxRules] = {default_rule()};
+int g_nrules = 1;
+
+TileRule rule_for(int N) {
+  for (int i = 0; i < g_nrules; ++i)
+    if (N <= g_rules[i].max_order) return g_rules[i];
+  return default_rule();
+}
 
 svd2_status hip_st(hipError_t e) {
   if (e == hipSuccess) return SVD2_OK;
@@ -509,8 +710,10 @@ template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, in
   if (s != SVD2_OK) return s;
   s = batch_svd<T, CPLX>(c);
   if (s != SVD2_OK) return s;
-  dim3 grid((n + kUpdBlock - 1) / kUpdBlock, (n + kUpdL - 1) / kUpdL);
-  hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, c.M, t, c.B);
+  TileRule r = rule_for(c.N);
+  dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
+  hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, c.M, t, c.B,
+                     r.kc, r.lc);
   return hip_st(hipGetLastError());
 }
 
@@ -529,7 +732,8 @@ template <class T, bool CPLX> int fused_grid(int N) {
   int want = g_fused_per_cu < per ? g_fused_per_cu : per;
   int max_blocks = cus * want;
   const int n = N / 2;
-  int tiles = ((n + kUpdBlock - 1) / kUpdBlock) * ((n + kUpdL - 1) / kUpdL);
+  TileRule r = rule_for(N);
+  int tiles = ((n + r.kc - 1) / r.kc) * ((n + r.lc - 1) / r.lc);
   return tiles < max_blocks ? tiles : max_blocks;
 }
 
@@ -544,7 +748,9 @@ template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int
   int N = c.N;
   Mat<T, CPLX> M = c.M;
   Bufs<T, CPLX> B = c.B;
-  void *args[] = {&N, &M, &t0, &t1, &B, &bar, &flags};
+  TileRule r = rule_for(N);
+  int kc = r.kc, lc = r.lc;
+  void *args[] = {&N, &M, &t0, &t1, &B, &bar, &flags, &kc, &lc};
   return hip_st(hipLaunchCooperativeKernel((const void *)kog_fused_kernel<T, CPLX>, dim3(grid),
                                            dim3(kUpdBlock), args, 0, c.st));
 }
@@ -685,6 +891,220 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
   return s;
 }
 
+
+// ---------------------------------------------------------------------------
+// batch host driver
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+  size_t hdr, probs, itemsA, itemsB, parts, bufs, total;
+  int maxA, maxB, nparts;
+};
+
+int esz_of(int kind) { return (kind == SVD2_KOG_F64 || kind == SVD2_KOG_C128) ? 8 : 4; }
+bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
+
+svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::vector<DevProb> *dp) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  if (nprob < 0 || nprob > (1 << 20)) return SVD2_ERR_SIZE;
+  if (nprob > 0 && !pr) return SVD2_ERR_NULL;
+  L.maxA = L.maxB = L.nparts = 0;
+  size_t bufs = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const kog_problem &q = pr[p];
+    if (q.dtype < SVD2_KOG_F64 || q.dtype > SVD2_KOG_C64) return SVD2_ERR_FLAGS;
+    if (q.N < 2 || q.N % 2 || q.lda < q.N || q.N > (1 << 19)) return SVD2_ERR_SIZE;
+    if (q.max_sweeps < 0 || !(q.tol >= 0)) return SVD2_ERR_SIZE;
+    int n = q.N / 2;
+    TileRule r = rule_for(q.N);
+    int kt = (n + r.kc - 1) / r.kc, lt = (n + r.lc - 1) / r.lc;
+    int nin = cplx_of(q.dtype) ? 8 : 4, nout = cplx_of(q.dtype) ? 19 : 11;
+    size_t arr = arr_bytes(q.N, esz_of(q.dtype));
+    if (dp) {
+      DevProb d = {};
+      d.A = q.A;
+      d.lda = q.lda;
+      d.N = q.N;
+      d.kind = q.dtype;
+      d.kc = r.kc;
+      d.lc = r.lc;
+      d.part_off = L.nparts;
+      d.ntiles = kt * lt;
+      d.max_sweeps = q.max_sweeps;
+      d.tol = q.tol;
+      d.piv_off = (long long)bufs;  // relative to the buffer region; rebased below
+      d.out_off = (long long)(bufs + nin * arr);
+      dp->push_back(d);
+    }
+    bufs += (nin + nout) * arr;
+    L.maxA += (n + kUpdBlock - 1) / kUpdBlock;
+    L.maxB += kt * lt;
+    L.nparts += kt * lt;
+  }
+  L.hdr = 0;
+  L.probs = 256;
+  L.itemsA = L.probs + up((size_t)nprob * sizeof(DevProb));
+  L.itemsB = L.itemsA + up((size_t)L.maxA * sizeof(int2));
+  L.parts = L.itemsB + up((size_t)L.maxB * sizeof(int4));
+  L.bufs = L.parts + up((size_t)L.nparts * sizeof(double));
+  L.total = L.bufs + bufs;
+  if (dp)
+    for (DevProb &d : *dp) {
+      d.piv_off += (long long)L.bufs;
+      d.out_off += (long long)L.bufs;
+    }
+  return SVD2_OK;
+}
+
+// work lists of the problems still running
+void build_items(const std::vector<DevProb> &dp, std::vector<int2> &A, std::vector<int4> &B) {
+  A.clear();
+  B.clear();
+  for (int p = 0; p < (int)dp.size(); ++p) {
+    const DevProb &d = dp[p];
+    if (d.status != 0) continue;
+    int n = d.N / 2;
+    for (int c = 0; c * kUpdBlock < n; ++c) A.push_back(int2{p, c});
+    int kt = (n + d.kc - 1) / d.kc, lt = (n + d.lc - 1) / d.lc;
+    for (int j = 0; j < lt; ++j)
+      for (int i = 0; i < kt; ++i) B.push_back(int4{p, i * d.kc, j * d.lc, j * kt + i});
+  }
+}
+
+struct BatchRun {
+  char *ws;
+  BatchLayout L;
+  hipStream_t st;
+  int gA, gB, gF;
+};
+
+svd2_status batch_step(const BatchRun &r, hipStream_t st) {
+  BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
+  DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  hipLaunchKernelGGL(kog_batch_pivot_kernel, dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int2 *)(r.ws + r.L.itemsA), probs);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts));
+  s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_finish_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, hdr, probs,
+                     (const double *)(r.ws + r.L.parts));
+  return hip_st(hipGetLastError());
+}
+
+svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int active) {
+  std::vector<int2> A;
+  std::vector<int4> B;
+  build_items(dp, A, B);
+  BatchHdr h = {(int)A.size(), (int)B.size(), (int)dp.size(), active};
+  svd2_status s = hip_st(hipMemcpyAsync(r.ws + r.L.hdr, &h, sizeof h, hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !A.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsA, A.data(), A.size() * sizeof(int2), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !B.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsB, B.data(), B.size() * sizeof(int4), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(r.st));
+  return s;
+}
+
+svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  if (flags & ~(unsigned)SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;
+  BatchRun r;
+  std::vector<DevProb> dp;
+  svd2_status s = batch_layout(nprob, pr, r.L, &dp);
+  if (s != SVD2_OK) return s;
+  if (nprob == 0) return SVD2_OK;
+  if (!ws) return SVD2_ERR_NULL;
+  if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
+  if (wsb < r.L.total) return SVD2_ERR_SIZE;
+  for (int p = 0; p < nprob; ++p) {
+    const kog_problem &q = pr[p];
+    if (!q.A) return SVD2_ERR_NULL;
+    int e = esz_of(q.dtype) * (cplx_of(q.dtype) ? 2 : 1);
+    if ((uintptr_t)q.A % e) return SVD2_ERR_ALIGN;
+    uintptr_t a0 = (uintptr_t)q.A, a1 = a0 + ((size_t)q.lda * (q.N - 1) + q.N) * e;
+    uintptr_t w0 = (uintptr_t)ws, w1 = w0 + r.L.total;
+    if (a0 < w1 && w0 < a1) return SVD2_ERR_ALIAS;
+  }
+  r.ws = (char *)ws;
+  r.st = st;
+  r.gA = r.L.maxA < 8192 ? r.L.maxA : 8192;
+  r.gB = r.L.maxB < 16384 ? r.L.maxB : 16384;
+  r.gF = nprob < 1024 ? nprob : 1024;
+  // problem table and the full work lists
+  s = hip_st(hipMemcpyAsync(r.ws + r.L.probs, dp.data(), dp.size() * sizeof(DevProb), hipMemcpyHostToDevice, st));
+  if (s == SVD2_OK) s = upload_items(r, dp, nprob);
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_init_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, (BatchHdr *)(r.ws + r.L.hdr),
+                     (DevProb *)(r.ws + r.L.probs));
+  s = hip_st(hipGetLastError());
+  long long max_steps = 0;
+  for (const DevProb &d : dp) {
+    long long m = (long long)d.max_sweeps * (d.N - 1);
+    if (m > max_steps) max_steps = m;
+  }
+  const int K = 64;  // steps per replay / between host checks
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  auto capture = [&]() -> svd2_status {
+    if (exec) {
+      hipGraphExecDestroy(exec);
+      exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    svd2_status c = hip_st(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    if (c != SVD2_OK) return c;
+    svd2_status c1 = SVD2_OK;
+    for (int i = 0; i < K && c1 == SVD2_OK; ++i) c1 = batch_step(r, cap);
+    svd2_status c2 = hip_st(hipStreamEndCapture(cap, &g));
+    c = c1 != SVD2_OK ? c1 : c2;
+    if (c == SVD2_OK) c = hip_st(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    if (g) hipGraphDestroy(g);
+    return c;
+  };
+  if (s == SVD2_OK && (flags & SVD2_KOG_GRAPH)) {
+    s = hip_st(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (s == SVD2_OK) s = capture();
+  }
+  int active = nprob, built_for = nprob;
+  long long steps = 0;
+  while (s == SVD2_OK) {
+    BatchHdr h;
+    s = hip_st(hipMemcpyAsync(&h, r.ws + r.L.hdr, sizeof h, hipMemcpyDeviceToHost, st));
+    if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+    if (s != SVD2_OK) break;
+    active = h.active;
+    if (active <= 0 || steps > max_steps) break;
+    if (active * 10 < built_for * 7) {  // compact the work lists to the running problems
+      s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
+      if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+      if (s == SVD2_OK) s = upload_items(r, dp, active);
+      if (s != SVD2_OK) break;
+      built_for = active;
+    }
+    if (exec) {
+      s = hip_st(hipGraphLaunch(exec, st));
+    } else {
+      for (int i = 0; i < K && s == SVD2_OK; ++i) s = batch_step(r, st);
+    }
+    steps += K;
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (cap) hipStreamDestroy(cap);
+  if (s != SVD2_OK) return s;
+  s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+  if (s != SVD2_OK) return s;
+  svd2_status all = SVD2_OK;
+  for (int p = 0; p < nprob; ++p) {
+    pr[p].sweeps = dp[p].sweeps;
+    pr[p].off_rel = dp[p].off_rel;
+    pr[p].status = dp[p].status == 1 ? SVD2_OK : SVD2_NOT_CONVERGED;
+    if (dp[p].status != 1) all = SVD2_NOT_CONVERGED;
+  }
+  return all;
+}
+
 }  // namespace
 
 extern "C" {
@@ -769,6 +1189,34 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
 }
 
 int kog_last_hip_error(void) { return g_kog_hip; }
+
+size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs) {
+  BatchLayout L;
+  if (batch_layout(nprob, probs, L, nullptr) != SVD2_OK) return 0;
+  return L.total;
+}
+
+svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
+                            hipStream_t stream) {
+  return batch_solve(nprob, probs, ws, ws_bytes, flags, stream);
+}
+
+svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, const int *lc) {
+  if (count < 0 || count > kMaxRules) return SVD2_ERR_SIZE;
+  if (count > 0 && (!max_order || !kc || !lc)) return SVD2_ERR_NULL;
+  for (int i = 0; i < count; ++i) {
+    if (kc[i] != 64 && kc[i] != 128 && kc[i] != 256) return SVD2_ERR_SIZE;
+    if (lc[i] < 1 || lc[i] > 4096 || max_order[i] < 2) return SVD2_ERR_SIZE;
+    if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
+  }
+  for (int i = 0; i < count; ++i) g_rules[i] = TileRule{max_order[i], kc[i], lc[i]};
+  g_nrules = count;
+  if (count == 0) {
+    g_rules[0] = default_rule();
+    g_nrules = 1;
+  }
+  return SVD2_OK;
+}
 
 svd2_status kog_set_fused_blocks_per_cu(int per_cu) {
   if (per_cu < 1 || per_cu > 16) return SVD2_ERR_SIZE;

@@ -57,7 +57,8 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_workspace_bytes", "dkog_step", "zkog_step", "skog_step", "ckog_step", "dkog_sweep",
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
-           "kog_set_fused_blocks_per_cu",
+           "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
+           "kog_batch_solve",
            "svd2_set_launch", "svd2_get_launch", "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32"]
 
@@ -307,3 +308,61 @@ def kog_norms(A, ws=None, stream=None):
 
 def kog_set_fused_blocks_per_cu(per_cu: int) -> None:
     _kog_check("kog_set_fused_blocks_per_cu", _kog().kog_set_fused_blocks_per_cu(per_cu))
+
+
+class kog_problem(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("N", ctypes.c_int), ("lda", ctypes.c_int), ("A", _P),
+                ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("status", ctypes.c_int),
+                ("sweeps", ctypes.c_int), ("off_rel", ctypes.c_double)]
+
+
+_batch_ready = False
+
+
+def _batch():
+    global _batch_ready
+    L = _kog()
+    if not _batch_ready:
+        L.kog_batch_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(kog_problem)]
+        L.kog_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.kog_batch_solve.argtypes = [ctypes.c_int, ctypes.POINTER(kog_problem), _P, ctypes.c_size_t,
+                                      ctypes.c_uint, _P]
+        L.kog_batch_solve.restype = ctypes.c_int
+        L.kog_set_tile_rules.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.kog_set_tile_rules.restype = ctypes.c_int
+        _batch_ready = True
+    return L
+
+
+def kog_set_tile_rules(rules) -> None:
+    """rules: list of (max_order, kc, lc) with increasing max_order; [] = default."""
+    n = len(rules)
+    arr = lambda i: (ctypes.c_int * max(n, 1))(*[r[i] for r in rules])
+    _kog_check("kog_set_tile_rules", _batch().kog_set_tile_rules(n, arr(0), arr(1), arr(2)))
+
+
+def kog_batch_solve(mats, tols, max_sweeps=40, flags: int = 0, ws=None, stream=None) -> list:
+    """Solve many problems at once.  mats: list of square column-major device
+    tensors (float64, complex128, float32, complex64); tols: one per problem
+    (or a scalar).  Returns a list of dicts (status, sweeps, off_rel)."""
+    import torch
+    n = len(mats)
+    if not hasattr(tols, "__len__"):
+        tols = [tols] * n
+    if not hasattr(max_sweeps, "__len__"):
+        max_sweeps = [max_sweeps] * n
+    probs = (kog_problem * max(n, 1))()
+    for i, A in enumerate(mats):
+        N, lda, ptr = _kog_args(A)
+        probs[i].dtype = KOG_DTYPE[kog_kind(A)]
+        probs[i].N, probs[i].lda, probs[i].A = N, lda, ptr
+        probs[i].tol, probs[i].max_sweeps = float(tols[i]), int(max_sweeps[i])
+    L = _batch()
+    wsb = int(L.kog_batch_workspace_bytes(n, probs))
+    if ws is None:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=mats[0].device)
+    st = L.kog_batch_solve(n, probs, ws.data_ptr(), ws.numel(), flags, _stream(stream))
+    _kog_check("kog_batch_solve", st)
+    return [dict(status=probs[i].status, sweeps=probs[i].sweeps, off_rel=probs[i].off_rel)
+            for i in range(n)]

@@ -142,3 +142,31 @@ def test_kog_argument_errors():
     sw, off = ctypes.c_int(), ctypes.c_double()
     assert L.dkog_solve(64, A, 64, 1e-14, -1, ctypes.byref(sw), ctypes.byref(off), ws, wsb, 0,
                         None) == 6                      # negative max_sweeps
+
+
+def test_kog_batch_argument_errors():
+    import ctypes
+    L = S._batch()
+    P = (S.kog_problem * 2)()
+    for i in range(2):
+        P[i].dtype, P[i].N, P[i].lda, P[i].A = 0, 64, 64, FAKE + i * (1 << 30)
+        P[i].tol, P[i].max_sweeps = 1e-14, 10
+    wsb = L.kog_batch_workspace_bytes(2, P)
+    assert wsb > 0
+    ws = FAKE + (64 << 30)
+    assert L.kog_batch_solve(0, P, 0, 0, 0, None) == 0           # nothing to do
+    assert L.kog_batch_solve(2, P, 0, wsb, 0, None) == 1         # NULL workspace
+    assert L.kog_batch_solve(2, P, ws, wsb - 1, 0, None) == 6    # too small
+    assert L.kog_batch_solve(2, P, ws + 8, wsb, 0, None) == 2    # misaligned
+    assert L.kog_batch_solve(2, P, ws, wsb, 1, None) == 4        # UNFUSED is not a batch flag
+    P[1].N = 63
+    assert L.kog_batch_workspace_bytes(2, P) == 0
+    assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 6        # odd order
+    P[1].N, P[1].dtype = 64, 9
+    assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 4        # unknown dtype
+    P[1].dtype, P[1].A = 0, 0
+    assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 1        # NULL matrix
+    P[1].A = ws + 4096
+    assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 3        # matrix inside the workspace
+    assert S.lib().kog_set_tile_rules(1, (ctypes.c_int * 1)(100), (ctypes.c_int * 1)(100),
+                                      (ctypes.c_int * 1)(8)) == 6  # kc must be 64/128/256
