@@ -171,6 +171,49 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
     return out
 
 
+def kog_batch_bench(nprob: int = 256):
+    """The uneven batch: nprob problems of order 32..2048 (log-uniform), half
+    complex FP64 (tol 1e-14), half real FP32 (tol 1e-7), condition numbers
+    1e2..1e12, solved together by kog_batch_solve with hipGraph replay."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    from workloads import SEED_BASE, kog_problem_set_device
+    t0 = time.perf_counter()
+    probs = kog_problem_set_device(nprob, SEED_BASE + 5)
+    torch.cuda.synchronize()
+    log(f"[bench] kog batch: {nprob} problems built in {time.perf_counter() - t0:.1f} s")
+    mats = [p["A"] for p in probs]
+    tols = [1e-14 if p["cplx"] else 1e-7 for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per = []
+    for p, r in zip(probs, res):
+        d = torch.diagonal(p["A"]).real.double().cpu().numpy()
+        sig = np.sort(np.abs(d))[::-1]
+        per.append({"order": p["order"], "dtype": "c128" if p["cplx"] else "f32",
+                    "cond": float(p["cond"]), "status": r["status"], "sweeps": r["sweeps"],
+                    "off_rel": r["off_rel"],
+                    "sigma_err_rel": float(np.max(np.abs(sig - p["sigma"])) / p["sigma"][0])})
+    total_sweeps = sum(r["sweeps"] for r in res)
+    bytes_moved = sum(2 * p["order"] ** 2 * (16 if p["cplx"] else 4) * (p["order"] - 1) * r["sweeps"]
+                      for p, r in zip(probs, res))
+    out = {"nprob": nprob, "seconds": el, "converged": sum(r["status"] == 0 for r in res),
+           "problem_sweeps_per_s": total_sweeps / el, "algorithmic_GBs": bytes_moved / el / 1e9,
+           "max_sweeps": max(r["sweeps"] for r in res),
+           "max_sigma_err_rel_c128": max(q["sigma_err_rel"] for q in per if q["dtype"] == "c128"),
+           "max_sigma_err_rel_f32": max(q["sigma_err_rel"] for q in per if q["dtype"] == "f32"),
+           "max_off_rel_c128": max(q["off_rel"] for q in per if q["dtype"] == "c128"),
+           "max_off_rel_f32": max(q["off_rel"] for q in per if q["dtype"] == "f32"),
+           "problems": per}
+    log(f"[bench] kog batch: {json.dumps({k: v for k, v in out.items() if k != 'problems'})}")
+    del probs, mats
+    torch.cuda.empty_cache()
+    return out
+
+
 def summarize(variant, r, flags_desc=""):
     n = r["n"]
     kms = float(np.mean(r["kernel_ms"]))
@@ -193,6 +236,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kog", action="store_true", help="skip the Kogbetliantz measurement")
     ap.add_argument("--kog-order", type=int, default=4096)
+    ap.add_argument("--no-kog-batch", action="store_true", help="skip the uneven Kogbetliantz batch")
+    ap.add_argument("--kog-batch", type=int, default=256, help="problems in the uneven batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -206,6 +251,10 @@ def main():
     import torch
     from paper_2005_07403_amd import svd2 as S
     S.lib()
+    tuning = S.apply_tuning()
+    if tuning:
+        for k, v in tuning.get("svd2_launch", {}).items():
+            DEFAULT_LAUNCH[k] = tuple(v)
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
@@ -239,6 +288,10 @@ def main():
     if not args.no_kog and not args.only:
         log(f"[bench] Kogbetliantz, order {args.kog_order}")
         kog = kog_bench(args.kog_order)
+    kog_batch = None
+    if not args.no_kog_batch and not args.only:
+        log(f"[bench] uneven Kogbetliantz batch of {args.kog_batch}")
+        kog_batch = kog_batch_bench(args.kog_batch)
 
     head = "z" if "z" in results else variants[0]
     h = results[head]
@@ -277,6 +330,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": results,
         "kogbetliantz": kog,
+        "kogbetliantz_batch": kog_batch,
         "kernel_source_sha": source_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -132,12 +132,18 @@ svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws,
 /* Workspace needed by the FP32 entry points: 0 unless SVD2_RESCUE_QUEUE. */
 size_t svd2_workspace_bytes(size_t n, unsigned flags);
 
-/* Launch shape of the batched kernels (all dtypes).  block: threads per
-   workgroup, a multiple of 64 in [64, 1024]; per_thread: matrices per lane,
-   1 or 2 (2 uses 16-byte loads and stores).  Takes effect for later calls
-   from any thread.  Returns SVD2_ERR_SIZE for values out of range. */
+/* Launch shape of the batched kernels (set by the autotuner).  block: threads
+   per workgroup, 64, 128, 192 or 256; per_thread: matrices per lane, 1 or 2
+   (2 uses 16-byte loads and stores when every array is 16-byte aligned).
+   svd2_set_launch sets every element type; svd2_set_launch_kind one of them:
+   kind 0 real FP64, 1 complex FP64, 2 real FP32, 3 complex FP32 (the
+   SVD2_KOG_* dtype codes).  Takes effect for later calls from any thread.
+   SVD2_ERR_SIZE / SVD2_ERR_FLAGS for values out of range.
+   svd2_get_launch reports the real-FP64 shape. */
 svd2_status svd2_set_launch(int block, int per_thread);
+svd2_status svd2_set_launch_kind(int kind, int block, int per_thread);
 void svd2_get_launch(int *block, int *per_thread);
+void svd2_get_launch_kind(int kind, int *block, int *per_thread);
 
 /* Text of a status code, and the last hipError_t seen by this thread. */
 const char *svd2_status_string(svd2_status st);

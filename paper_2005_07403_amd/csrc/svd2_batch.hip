@@ -22,8 +22,10 @@ using namespace svd2;
 namespace {
 
 thread_local int g_last_hip = 0;
-std::atomic<int> g_block{256};
-std::atomic<int> g_per_thread{1};
+// launch shape per element type: 0 real FP64, 1 complex FP64, 2 real FP32, 3 complex FP32
+std::atomic<int> g_block[4] = {{256}, {256}, {256}, {256}};
+std::atomic<int> g_per_thread[4] = {{1}, {1}, {1}, {1}};
+template <class T, bool CPLX> constexpr int kind_of() { return (sizeof(T) == 8 ? 0 : 2) + (CPLX ? 1 : 0); }
 
 template <class T, int NIN, int NOUT> struct KArgs {
   const T *in[NIN];
@@ -216,7 +218,8 @@ svd2_status hip_status(hipError_t e) {
 template <class T, bool CPLX, int RESCUE>
 svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
                    uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
-  int block = g_block.load(), pt = g_per_thread.load();
+  constexpr int kind = kind_of<T, CPLX>();
+  int block = g_block[kind].load(), pt = g_per_thread[kind].load();
   if (pt == 2 && !all_aligned16(a)) pt = 1;
   size_t lanes = (n + pt - 1) / pt;
   size_t grid = (lanes + block - 1) / block;
@@ -330,17 +333,28 @@ size_t svd2_workspace_bytes(size_t n, unsigned flags) {
   return 256 + n * sizeof(uint32_t);
 }
 
-svd2_status svd2_set_launch(int block, int per_thread) {
+svd2_status svd2_set_launch_kind(int kind, int block, int per_thread) {
+  if (kind < 0 || kind > 3) return SVD2_ERR_FLAGS;
   if (block < 64 || block > 256 || block % 64) return SVD2_ERR_SIZE;
   if (per_thread != 1 && per_thread != 2) return SVD2_ERR_SIZE;
-  g_block.store(block);
-  g_per_thread.store(per_thread);
+  g_block[kind].store(block);
+  g_per_thread[kind].store(per_thread);
   return SVD2_OK;
 }
 
-void svd2_get_launch(int *block, int *per_thread) {
-  if (block) *block = g_block.load();
-  if (per_thread) *per_thread = g_per_thread.load();
+svd2_status svd2_set_launch(int block, int per_thread) {
+  if (block < 64 || block > 256 || block % 64) return SVD2_ERR_SIZE;
+  if (per_thread != 1 && per_thread != 2) return SVD2_ERR_SIZE;
+  for (int k = 0; k < 4; ++k) svd2_set_launch_kind(k, block, per_thread);
+  return SVD2_OK;
+}
+
+void svd2_get_launch(int *block, int *per_thread) { svd2_get_launch_kind(0, block, per_thread); }
+
+void svd2_get_launch_kind(int kind, int *block, int *per_thread) {
+  if (kind < 0 || kind > 3) kind = 0;
+  if (block) *block = g_block[kind].load();
+  if (per_thread) *per_thread = g_per_thread[kind].load();
 }
 
 const char *svd2_status_string(svd2_status st) {

@@ -59,7 +59,8 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
            "kog_batch_solve",
-           "svd2_set_launch", "svd2_get_launch", "svd2_status_string", "svd2_last_hip_error",
+           "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
+           "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32"]
 
 
@@ -84,6 +85,10 @@ def lib() -> ctypes.CDLL:
         L.svd2_set_launch.restype = i
         L.svd2_get_launch.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i)]
         L.svd2_get_launch.restype = None
+        L.svd2_set_launch_kind.argtypes = [i, i, i]
+        L.svd2_set_launch_kind.restype = i
+        L.svd2_get_launch_kind.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.svd2_get_launch_kind.restype = None
         L.svd2_status_string.argtypes = [i]
         L.svd2_status_string.restype = ctypes.c_char_p
         L.svd2_last_hip_error.argtypes = []
@@ -158,6 +163,38 @@ def svd2_get_launch() -> tuple:
     b, p = ctypes.c_int(), ctypes.c_int()
     lib().svd2_get_launch(ctypes.byref(b), ctypes.byref(p))
     return b.value, p.value
+
+
+KIND = {"d": 0, "z": 1, "s": 2, "c": 3}
+
+
+def svd2_set_launch_kind(kind: str, block: int, per_thread: int) -> None:
+    _check("svd2_set_launch_kind", lib().svd2_set_launch_kind(KIND[kind], block, per_thread))
+
+
+def svd2_get_launch_kind(kind: str) -> tuple:
+    b, p = ctypes.c_int(), ctypes.c_int()
+    lib().svd2_get_launch_kind(KIND[kind], ctypes.byref(b), ctypes.byref(p))
+    return b.value, p.value
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def apply_tuning(path: str = TUNING_PATH) -> dict | None:
+    """Load the autotuner's table (if present) into the library: launch shapes
+    per element type and Kogbetliantz tile rules.  Returns the table."""
+    import json
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tab = json.load(fh)
+    for k, (b, p) in tab.get("svd2_launch", {}).items():
+        svd2_set_launch_kind(k, int(b), int(p))
+    rules = tab.get("kog_tile_rules")
+    if rules:
+        kog_set_tile_rules([tuple(int(x) for x in r) for r in rules])
+    return tab
 
 
 def svd2_probe(op: int, x, y=None, z=None, out=None, stream=None) -> None:

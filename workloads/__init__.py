@@ -6,5 +6,5 @@ produces.  Everything is deterministic in the seed (numpy PCG64).
 """
 from .gen import (  # noqa: F401
     SEED_BASE, KINDS, uniform_real, scaled_law, random_bits, to_trains, kog_matrix,
-    kog_problem_set, round_robin_pairs,
+    kog_problem_set, kog_problem_set_device, round_robin_pairs,
 )

@@ -239,3 +239,39 @@ def round_robin_pairs(N: int) -> np.ndarray:
         # keep players[0] fixed, rotate the rest by one
         players = [players[0]] + [players[-1]] + players[1:-1]
     return rounds
+
+
+def kog_problem_set_device(nprob: int, seed: int, omin: int = 32, omax: int = 2048,
+                           device: str = "cuda"):
+    """The uneven batch built on the GPU (for benchmarking): orders
+    2 round(2^U[log2(omin/2), log2(omax/2)]), condition numbers 10^U[2, 12],
+    sigma geometric from 1 to 1/cond, A = Q1 diag(sigma) Q2^* with Q1, Q2 the
+    Q factors (phase-fixed) of seeded Gaussian matrices, formed in FP64 with
+    torch on the device; the first half complex FP64, the second half real and
+    rounded to FP32.  Gaussians come from numpy's seeded PCG64.  Matrices are
+    column-major (stride(0) == 1).  Returns a list of dicts."""
+    import torch
+    rng = np.random.default_rng(seed)
+    lo, hi = np.log2(omin / 2), np.log2(omax / 2)
+    out = []
+    for p in range(nprob):
+        order = 2 * int(round(2 ** rng.uniform(lo, hi)))
+        cond = 10 ** rng.uniform(2, 12)
+        cplx = p < nprob // 2
+        qs = []
+        for _ in range(2):
+            G = rng.standard_normal((order, order))
+            if cplx:
+                G = G + 1j * rng.standard_normal((order, order))
+            Q, R = torch.linalg.qr(torch.from_numpy(G).to(device))
+            d = torch.diagonal(R)
+            ph = d / torch.where(d.abs() == 0, torch.ones_like(d.abs()), d.abs())
+            qs.append(Q * ph[None, :])
+        sig = cond ** (-np.arange(order, dtype=np.float64) / max(order - 1, 1))
+        s_t = torch.from_numpy(sig).to(device)
+        A = (qs[0] * s_t[None, :].to(qs[0].dtype)) @ qs[1].conj().T
+        if not cplx:
+            A = A.real.to(torch.float32)
+        A = A.t().contiguous().t()  # column-major
+        out.append(dict(order=order, cond=cond, cplx=cplx, A=A, sigma=sig))
+    return out
