@@ -55,39 +55,47 @@ def make_inputs(variant: str, n: int, seed_off: int = 1):
     return to_trains(A, dtype)
 
 
-def time_variant(variant: str, trains_np, steps: int, warmup: int, flags: int):
-    """Time `steps` batched calls on inputs resident in HBM.  Returns a dict
-    with the wall-clock time of the timed region and the per-launch kernel
-    time from HIP events recorded on the launch stream."""
+def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
+    """Time `steps` batched calls on inputs resident in HBM, once per flag set
+    in `flagsets` (same inputs).  Returns {flags: dict} with the wall-clock
+    time of the timed region and the per-launch kernel time from HIP events
+    recorded on the launch stream; the memory-pattern probe (same loads and
+    stores, no arithmetic) is timed the same way under key 'pattern'."""
     import torch
     from paper_2005_07403_amd import svd2 as S
-    S.svd2_set_launch(*DEFAULT_LAUNCH[variant])
+    S.svd2_set_launch_kind(variant, *DEFAULT_LAUNCH[variant])
     dev = [torch.from_numpy(t).cuda() for t in trains_np]
     n = dev[0].numel()
     nout = 19 if len(dev) == 8 else 11
     out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(nout)]
-    ws = None
-    wsb = S.svd2_workspace_bytes(n, flags) if dev[0].dtype == torch.float32 else 0
-    if wsb:
-        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        S.svd2(dev, flags=flags, out=out, ws=ws)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        ev[i][0].record(stream)
-        S.svd2(dev, flags=flags, out=out, ws=ws)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kms = [a.elapsed_time(b) for a, b in ev]
-    del dev, out, ws
+    res = {}
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return dict(n=n, wall_s=t1 - t0, kernel_ms=[a.elapsed_time(b) for a, b in ev])
+
+    for flags in flagsets:
+        ws = None
+        wsb = S.svd2_workspace_bytes(n, flags) if dev[0].dtype == torch.float32 else 0
+        if wsb:
+            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        res[flags] = timed(lambda: S.svd2(dev, flags=flags, out=out, ws=ws))
+    res["pattern"] = timed(lambda: S.svd2_stream_probe(variant, dev, out))
+    del dev, out
     torch.cuda.empty_cache()
-    return dict(n=n, wall_s=t1 - t0, kernel_ms=kms)
+    return res
 
 
 def cpu_baseline(variant: str, trains_np, budget_s: float = 12.0):
@@ -214,15 +222,17 @@ def kog_batch_bench(nprob: int = 256):
     return out
 
 
-def summarize(variant, r, flags_desc=""):
+def summarize(variant, r, pattern, flags_desc=""):
     n = r["n"]
     kms = float(np.mean(r["kernel_ms"]))
     wall_ms = r["wall_s"] * 1e3 / len(r["kernel_ms"])
     gbs = BYTES_PER_SVD[variant] * n / (kms * 1e-3) / 1e9
+    pms = float(np.mean(pattern["kernel_ms"]))
+    pgbs = BYTES_PER_SVD[variant] * n / (pms * 1e-3) / 1e9
     return dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
                 kernel_ms_min=float(np.min(r["kernel_ms"])), algorithmic_GBs=gbs,
                 hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=BYTES_PER_SVD[variant],
-                flags=flags_desc)
+                pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
 
 
 def main():
@@ -269,16 +279,20 @@ def main():
         return
 
     variants = [args.only] if args.only else ["z", "d", "s", "c"]
-    flags = {"d": 0, "z": 0, "s": S.SVD2_RESCUE_FP64, "c": S.SVD2_RESCUE_FP64}
-    flag_desc = {"d": "", "z": "", "s": "RESCUE_FP64", "c": "RESCUE_FP64"}
+    F = S.SVD2_RESCUE_FP64
+    flagsets = {"d": {"": 0}, "z": {"": 0},
+                "s": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0},
+                "c": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0}}
     results, inputs_z = {}, None
     for v in variants:
         log(f"[bench] generating {v} inputs n={args.n}")
         tr = make_inputs(v, args.n)
         log(f"[bench] timing {v}: warmup {args.warmup}, steps {args.steps}")
-        r = time_variant(v, tr, args.steps, args.warmup, flags[v])
-        results[v] = summarize(v, r, flag_desc[v])
-        log(f"[bench] {v}: {json.dumps(results[v])}")
+        r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()))
+        for desc, fl in flagsets[v].items():
+            key = v if desc in ("", "RESCUE_FP64") else f"{v}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
+            results[key] = summarize(v, r[fl], r["pattern"], desc)
+            log(f"[bench] {key}: {json.dumps(results[key])}")
         if v == "z":
             inputs_z = tr
         else:
@@ -326,7 +340,10 @@ def main():
                    "launch": list(DEFAULT_LAUNCH[head])},
         "roofline": {"bound": "hbm", "achieved": h["algorithmic_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": h["hbm_frac"],
-                     "traffic": traffic},
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": BYTES_PER_SVD[head] * h["n"],
+                     "pattern_ceiling_GBs": h["pattern_ceiling_GBs"],
+                     "frac_of_pattern_ceiling": h["frac_of_pattern_ceiling"]},
         "cpu_baseline": cpu,
         "variants": results,
         "kogbetliantz": kog,

@@ -71,9 +71,14 @@ enum {
      On such lanes the (2,2) entry of R is recomputed from det(A^) in FP64 (exact
      products, compensated sum), and eqs. (9), (13)-(17), (29) run in FP64. */
   SVD2_RESCUE_FP64 = 4,     /* rescue inside the main kernel (divergent, no queue)  */
-  SVD2_RESCUE_QUEUE = 8     /* with RESCUE_FP64: flagged lanes are compacted into a
+  SVD2_RESCUE_QUEUE = 8,    /* with RESCUE_FP64: flagged lanes are compacted into a
                                queue (one atomic per wavefront) and redone by a
                                second kernel; needs a workspace                     */
+  SVD2_RESCUE_SIGMA = 16    /* with RESCUE_FP64: on flagged lanes only sigma'_min is
+                               recomputed, as |det(A^)| / sigma'_max in FP64 (the
+                               product of the singular values is |det|); U, V and
+                               sigma'_max keep their FP32 values.  Same relative
+                               accuracy of sigma_min for a fraction of the FP64 work */
 };
 
 /* Real FP64: a_ij in, u_ij, v_ij, smax, smin, s out (all length n). */
@@ -119,7 +124,7 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 
 /* FP32 form (the paper notes the method carries over to single precision,
    section 1; the tan 2phi clamp becomes sqrt(FLT_MAX), section 7).
-   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE].
+   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA].
    ws / ws_bytes: device workspace, at least svd2_workspace_bytes(n, flags)
    bytes (may be NULL/0 when that is 0).  With RESCUE_QUEUE, n must be below
    2^32 (SVD2_ERR_SIZE otherwise).  Calls sharing one workspace must not
@@ -154,6 +159,15 @@ int svd2_last_hip_error(void);
    handling of fmin/fmax), for tests.  op: 0 div, 1 sqrt, 2 fma, 3 ldexp(x,
    (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y).
    x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
+/* Memory-pattern probe, a diagnostic: the loads and stores of the batched
+   kernel of element type `kind` (0 real FP64, 1 complex FP64, 2 real FP32,
+   3 complex FP32) with the same launch shape, but no SVD arithmetic (each
+   output = the sum of the inputs plus its index).  in/out: host arrays of
+   4 or 8 input and 11 or 19 output device pointers of n elements.  Its time
+   is the ceiling the memory system sets for that access pattern. */
+svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *const *out,
+                              hipStream_t stream);
+
 svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y,
                            const double *z, double *out, hipStream_t stream);
 svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,

@@ -337,9 +337,9 @@ inline double sum4(double a, double b, double c, double d) {
   return s + acc;
 }
 
-template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
-  Prim<double> P{ORACLE_MIRROR};
-  const double one = 1.0;
+/* det(A^) in FP64 from the scaled FP32 entries: every product of two FP32
+   numbers is exact in FP64; the complex case sums four exact terms per part. */
+template <bool CPLX> Cx<double> det_fp64(const Mid<float> &m) {
   Cx<double> a[2][2];
   for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) a[i][j] = {(double)m.ah[i][j].re, (double)m.ah[i][j].im};
   Cx<double> det;
@@ -352,6 +352,21 @@ template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
     det.re = a[0][0].re * a[1][1].re - a[0][1].re * a[1][0].re;
     det.im = 0.0;
   }
+  return det;
+}
+
+/* The cheaper rescue: only sigma'_min = |det(A^)| / sigma'_max in FP64 (the
+   product of the singular values is |det|); U, V and sigma'_max stay FP32. */
+template <bool CPLX> void rescue_sigma(const Mid<float> &m, Res<float> &o) {
+  Cx<double> det = det_fp64<CPLX>(m);
+  double ad = CPLX ? hypot_mirror<double>(det.re, det.im) : std::fabs(det.re);
+  o.smin = (float)(ad / (double)o.smax);
+}
+
+template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
+  Prim<double> P{ORACLE_MIRROR};
+  const double one = 1.0;
+  Cx<double> det = det_fp64<CPLX>(m);
   double sgn = (m.c != m.r) ? -one : one;
   Mid<double> w{};
   w.r11 = m.r11; w.r12 = m.r12; w.mt = m.mt; w.ca = m.ca;
@@ -459,7 +474,8 @@ void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int 
     bool fl = false;
     if constexpr (std::is_same<T, float>::value) {
       if (rescue && near_degenerate(o.smax, o.smin)) {
-        rescue_fp64<CPLX>(m, o);
+        if (rescue == 2) rescue_sigma<CPLX>(m, o);
+        else rescue_fp64<CPLX>(m, o);
         fl = true;
       }
     }
@@ -589,7 +605,11 @@ int oracle_trace_s(const float *a, int cplx, int policy, int rescue, double *tra
   if (cplx) zsvd2_one(P, a, o, m); else dsvd2_one(P, a, o, m);
   fill_trace(m, o, trace);
   if (rescue && near_degenerate(o.smax, o.smin)) {
-    if (cplx) rescue_fp64<true>(m, o); else rescue_fp64<false>(m, o);
+    if (rescue == 2) {
+      if (cplx) rescue_sigma<true>(m, o); else rescue_sigma<false>(m, o);
+    } else {
+      if (cplx) rescue_fp64<true>(m, o); else rescue_fp64<false>(m, o);
+    }
     trace[17] = o.smax; trace[18] = o.smin; trace[21] = 1.0;
   }
   return 0;

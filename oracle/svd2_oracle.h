@@ -44,7 +44,8 @@ enum { ORACLE_BS_NONE = 0, /* write sigma' and s (the paper's default)          
 /* Batched SVD over n matrices.  in/out are arrays of host pointers as above.
  * rescue (float only): 0 = plain FP32 algorithm; 1 = recompute R's (2,2)
  * entry from det(A^) in FP64 on lanes with smin' < 2^-20 smax', then run the
- * triangular SVD and the assembly of U, V in FP64 for those lanes.
+ * triangular SVD and the assembly of U, V in FP64 for those lanes; 2 = on
+ * those lanes only smin' = |det(A^)| / smax' in FP64 (U, V stay FP32).
  * flagged (optional, may be NULL): per-lane 0/1 marks of rescued lanes.
  * nthreads <= 0: use the OpenMP default.  Returns 0. */
 int oracle_dsvd2(size_t n, const double *const *in, double *const *out,

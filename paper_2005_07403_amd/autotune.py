@@ -2,7 +2,7 @@
 
 Tuned:
 * the batched 2x2 SVD kernels: threads per workgroup (64/128/256) and
-  matrices per lane (1/2), per element type, at n = 2^22 on the +-m 2^e law;
+  matrices per lane (1/2), per element type, at n = 2^24 on the +-m 2^e law;
 * the Kogbetliantz update tile: row pairs per workgroup kc (64/128/256) and
   column pairs per tile lc, per order bucket, timing unfused steps of a real
   FP64 and a complex FP64 matrix of that order.
@@ -35,27 +35,31 @@ def _median_ms(fn, reps: int) -> float:
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
-def tune_svd2(n: int, reps: int) -> dict:
+def tune_svd2(n: int, reps: int, rounds: int = 3) -> dict:
+    """Launch shape per element type, timed at the batch size of interest with
+    `rounds` interleaved passes over the candidates (the median of `reps`
+    launches each); the best minimum over rounds wins."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     from workloads import SEED_BASE, scaled_law, to_trains
     best = {}
+    shapes = [(64, 1), (64, 2), (128, 1), (128, 2), (256, 1), (256, 2)]
     for kind in "dzsc":
         cplx = kind in "zc"
         dt = np.float64 if kind in "dz" else np.float32
         dev = [torch.from_numpy(t).cuda() for t in to_trains(scaled_law(n, SEED_BASE + 7, cplx, dtype=dt), dt)]
         out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(19 if cplx else 11)]
         flags = 0 if kind in "dz" else S.SVD2_RESCUE_FP64
-        res = {}
-        for block in (64, 128, 256):
-            for pt in (1, 2):
+        res = {sh: [] for sh in shapes}
+        for _ in range(rounds):
+            for block, pt in shapes:
                 S.svd2_set_launch_kind(kind, block, pt)
                 for _ in range(2):
                     S.svd2(dev, flags=flags, out=out)
-                res[(block, pt)] = _median_ms(lambda: S.svd2(dev, flags=flags, out=out), reps)
-        b = min(res, key=res.get)
+                res[(block, pt)].append(_median_ms(lambda: S.svd2(dev, flags=flags, out=out), reps))
+        b = min(res, key=lambda k: min(res[k]))
         best[kind] = list(b)
-        print(f"svd2 {kind}: " + ", ".join(f"{k}={v:.4f}ms" for k, v in sorted(res.items())) + f" -> {b}",
+        print(f"svd2 {kind}: " + ", ".join(f"{k}={min(v):.4f}ms" for k, v in sorted(res.items())) + f" -> {b}",
               flush=True)
         S.svd2_set_launch_kind(kind, *b)
         del dev, out
@@ -107,7 +111,7 @@ def main():
     S.lib()
     assert torch.cuda.is_available()
     t0 = time.time()
-    launch = tune_svd2(1 << (20 if args.quick else 22), 10 if args.quick else 20)
+    launch = tune_svd2(1 << (22 if args.quick else 24), 10 if args.quick else 20)
     orders = [64, 256, 1024, 4096] if args.quick else [32, 64, 128, 256, 512, 1024, 2048, 4096]
     rules = tune_kog(orders, 5 if args.quick else 10)
     tab = {"device": torch.cuda.get_device_name(0), "svd2_launch": launch, "kog_tile_rules": rules,

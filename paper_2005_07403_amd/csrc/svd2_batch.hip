@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
 
 // Second pass for RESCUE == 2: redo each queued lane with the FP64 tail.  The
 // grid is fixed; every lane loops until the device-side count is exhausted.
-template <class T, bool CPLX>
+template <class T, bool CPLX, int TAIL>
 __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                           int bs, const uint32_t *queue,
                                                           const uint32_t *qcount) {
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4,
     T x[NIN], y[NOUT];
 #pragma unroll
     for (int e = 0; e < NIN; ++e) x[e] = a.in[e][k];
-    one_matrix<T, CPLX, 1>(x, y, bs);
+    one_matrix<T, CPLX, TAIL>(x, y, bs);
 #pragma unroll
     for (int e = 0; e < NOUT; ++e) st_nt(a.out[e] + k, y[e]);
   }
@@ -239,9 +239,13 @@ template <class T, bool CPLX>
 svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, unsigned flags,
                      uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
   int bs = (int)(flags & 3u);
-  bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE;
+  bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE,
+       sigma = flags & SVD2_RESCUE_SIGMA;
   if (!resc) return launch<T, CPLX, 0>(n, a, bs, nullptr, nullptr, nullptr, st);
-  if (!queue) return launch<T, CPLX, 1>(n, a, bs, nresc, nullptr, nullptr, st);
+  if (!queue) {
+    if (sigma) return launch<T, CPLX, 3>(n, a, bs, nresc, nullptr, nullptr, st);
+    return launch<T, CPLX, 1>(n, a, bs, nresc, nullptr, nullptr, st);
+  }
   if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
   if (!ws) return SVD2_ERR_NULL;
   if (ws_bytes < svd2_workspace_bytes(n, flags)) return SVD2_ERR_SIZE;
@@ -253,7 +257,10 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
   if (s0 != SVD2_OK) return s0;
   svd2_status s1 = launch<T, CPLX, 2>(n, a, bs, nresc, q, qcount, st);
   if (s1 != SVD2_OK) return s1;
-  hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
+  if (sigma)
+    hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
+  else
+    hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
   return hip_status(hipGetLastError());
 }
 
@@ -267,6 +274,47 @@ svd2_status probe(int op, size_t n, const T *x, const T *y, const T *z, T *out,
   if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
   hipLaunchKernelGGL((probe_kernel<T>), dim3((unsigned)grid), dim3(256), 0, stream, op, n, x, y, z,
                      out);
+  return hip_status(hipGetLastError());
+}
+
+
+// ---------------------------------------------------------------------------
+// memory-pattern probe: the batched kernels' loads and stores with no SVD
+// arithmetic (each output = sum of the inputs + its index), same launch shape
+// ---------------------------------------------------------------------------
+template <class T, int NIN, int NOUT, int PT>
+__global__ __launch_bounds__(256) void stream_probe_kernel(size_t n, KArgs<T, NIN, NOUT> a) {
+  size_t k = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  int cnt = (k < n) ? (int)((n - k < (size_t)PT) ? (n - k) : PT) : 0;
+  if (cnt == 0) return;
+  T x[PT][NIN], y[PT][NOUT];
+  load_lanes<T, NIN, PT>(a.in, k, cnt, x);
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    T acc = T(0);
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) acc += x[j][i];
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) y[j][i] = acc + T(i);
+  }
+  store_lanes<T, NOUT, PT>(a.out, k, cnt, y);
+}
+
+template <class T, int NIN, int NOUT>
+svd2_status stream_probe(size_t n, const void *const *in, void *const *out, hipStream_t st, int kind) {
+  KArgs<T, NIN, NOUT> a;
+  for (int i = 0; i < NIN; ++i) a.in[i] = (const T *)in[i];
+  for (int i = 0; i < NOUT; ++i) a.out[i] = (T *)out[i];
+  svd2_status s = check_ptrs<T>(n, a.in, NIN, a.out, NOUT);
+  if (s != SVD2_OK || n == 0) return s;
+  int block = g_block[kind].load(), pt = g_per_thread[kind].load();
+  if (pt == 2 && !all_aligned16(a)) pt = 1;
+  size_t lanes = (n + pt - 1) / pt, grid = (lanes + block - 1) / block;
+  if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
+  if (pt == 2)
+    hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 2>), dim3((unsigned)grid), dim3(block), 0, st, n, a);
+  else
+    hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 1>), dim3((unsigned)grid), dim3(block), 0, st, n, a);
   return hip_status(hipGetLastError());
 }
 
@@ -298,8 +346,8 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 }
 
 static bool bad_fp32_flags(unsigned flags) {
-  if (flags & ~15u || bad_bs_flags(flags)) return true;
-  if ((flags & SVD2_RESCUE_QUEUE) && !(flags & SVD2_RESCUE_FP64)) return true;
+  if (flags & ~31u || bad_bs_flags(flags)) return true;
+  if ((flags & (SVD2_RESCUE_QUEUE | SVD2_RESCUE_SIGMA)) && !(flags & SVD2_RESCUE_FP64)) return true;
   return false;
 }
 
@@ -372,6 +420,18 @@ const char *svd2_status_string(svd2_status st) {
 }
 
 int svd2_last_hip_error(void) { return g_last_hip; }
+
+svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *const *out,
+                              hipStream_t stream) {
+  if (!in || !out) return SVD2_ERR_NULL;
+  switch (kind) {
+    case 0: return stream_probe<double, 4, 11>(n, in, out, stream, 0);
+    case 1: return stream_probe<double, 8, 19>(n, in, out, stream, 1);
+    case 2: return stream_probe<float, 4, 11>(n, in, out, stream, 2);
+    case 3: return stream_probe<float, 8, 19>(n, in, out, stream, 3);
+  }
+  return SVD2_ERR_FLAGS;
+}
 
 svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y, const double *z,
                            double *out, hipStream_t stream) {

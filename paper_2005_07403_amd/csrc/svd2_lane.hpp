@@ -312,6 +312,24 @@ __device__ __forceinline__ bool near_degenerate(float smax, float smin) {
   return smin < vldexp(smax, -20);
 }
 
+// the cheaper rescue: only sigma'_min = |det(A^)| / sigma'_max in FP64
+__device__ __forceinline__ void real_rescue_sigma(RealRes<float> &o) {
+  double det = (double)o.ah11 * (double)o.ah22 - (double)o.ah12 * (double)o.ah21;
+  o.smin = (float)(vabs(det) / (double)o.smax);
+}
+
+__device__ __forceinline__ Cx<double> cplx_det(const CplxRes<float> &o) {
+  Cx<double> a11 = {o.ah[0].re, o.ah[0].im}, a21 = {o.ah[1].re, o.ah[1].im};
+  Cx<double> a12 = {o.ah[2].re, o.ah[2].im}, a22 = {o.ah[3].re, o.ah[3].im};
+  return {sum4(a11.re * a22.re, -(a11.im * a22.im), -(a12.re * a21.re), a12.im * a21.im),
+          sum4(a11.re * a22.im, a11.im * a22.re, -(a12.re * a21.im), -(a12.im * a21.re))};
+}
+
+__device__ __forceinline__ void cplx_rescue_sigma(CplxRes<float> &o) {
+  Cx<double> det = cplx_det(o);
+  o.smin = (float)(hyp(det.re, det.im) / (double)o.smax);
+}
+
 __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
   double det = (double)o.ah11 * (double)o.ah22 - (double)o.ah12 * (double)o.ah21;
   bool neg = (o.c != o.r) != ((o.neg1 != o.neg2) != o.negt);
@@ -330,10 +348,7 @@ __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
 }
 
 __device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
-  Cx<double> a11 = {o.ah[0].re, o.ah[0].im}, a21 = {o.ah[1].re, o.ah[1].im};
-  Cx<double> a12 = {o.ah[2].re, o.ah[2].im}, a22 = {o.ah[3].re, o.ah[3].im};
-  Cx<double> det = {sum4(a11.re * a22.re, -(a11.im * a22.im), -(a12.re * a21.re), a12.im * a21.im),
-                    sum4(a11.re * a22.im, a11.im * a22.re, -(a12.re * a21.im), -(a12.im * a21.re))};
+  Cx<double> det = cplx_det(o);
   double sgn = (o.c != o.r) ? -1.0 : 1.0;
   Cx<double> d1 = {o.d1.re, o.d1.im}, d2 = {o.d2.re, o.d2.im}, e = {o.e12.re, o.e12.im};
   Cx<double> ph = cmul(cmul(d1, d2), e);
@@ -369,7 +384,8 @@ template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &sm
 
 // ---------------------------------------------------------------------------
 // one matrix: inputs x[NIN] -> outputs y[NOUT]; returns the rescue flag
-// RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only
+// RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only,
+// 3 in place (FP64 sigma_min quotient only)
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int RESCUE>
 __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
@@ -381,6 +397,8 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {
         if (flagged) real_rescue(o);
+      } else if constexpr (RESCUE == 3) {
+        if (flagged) real_rescue_sigma(o);
       }
     }
     y[0] = o.u11; y[1] = o.u21; y[2] = o.u12; y[3] = o.u22;
@@ -395,6 +413,8 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {
         if (flagged) cplx_rescue(o);
+      } else if constexpr (RESCUE == 3) {
+        if (flagged) cplx_rescue_sigma(o);
       }
     }
 #pragma unroll

@@ -21,6 +21,7 @@ SVD2_BACKSCALE_SAFE = 1
 SVD2_BACKSCALE_ALL = 2
 SVD2_RESCUE_FP64 = 4
 SVD2_RESCUE_QUEUE = 8
+SVD2_RESCUE_SIGMA = 16
 
 _P = ctypes.c_void_p
 REAL_IN = ["a11", "a21", "a12", "a22"]
@@ -61,7 +62,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_batch_solve",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
-           "svd2_probe_f64", "svd2_probe_f32"]
+           "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
 
 
 def lib() -> ctypes.CDLL:
@@ -97,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.svd2_probe_f32.argtypes = [i, sz, _P, _P, _P, _P, _P]
         L.svd2_probe_f64.restype = i
         L.svd2_probe_f32.restype = i
+        L.svd2_stream_probe.argtypes = [i, sz, _P, _P, _P]
+        L.svd2_stream_probe.restype = i
         _lib = L
     return _lib
 
@@ -203,6 +206,13 @@ def svd2_probe(op: int, x, y=None, z=None, out=None, stream=None) -> None:
     fn = lib().svd2_probe_f64 if x.dtype == torch.float64 else lib().svd2_probe_f32
     ptr = lambda t: 0 if t is None else t.data_ptr()
     _check("svd2_probe", fn(op, x.numel(), ptr(x), ptr(y), ptr(z), ptr(out), _stream(stream)))
+
+
+def svd2_stream_probe(kind: str, ins, outs, stream=None) -> None:
+    """The batched kernel's memory pattern without its arithmetic (diagnostic)."""
+    pi = (ctypes.c_void_p * len(ins))(*[t.data_ptr() for t in ins])
+    po = (ctypes.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check("svd2_stream_probe", lib().svd2_stream_probe(KIND[kind], ins[0].numel(), pi, po, _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

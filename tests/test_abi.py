@@ -82,6 +82,8 @@ def test_fp64_rejects_fp32_flags():
 def test_fp32_queue_needs_rescue_and_workspace():
     ins, outs = _ptrs(4), _ptrs(11, base=FAKE + (64 << 30))
     assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_QUEUE) == 4
+    assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_SIGMA) == 4
+    assert _call(S.dsvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_SIGMA) == 4
     # queue without workspace
     assert _call(S.ssvd2_batch, 10, ins, outs,
                  flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE) == 1

@@ -212,6 +212,23 @@ def test_unaligned_falls_back_and_matches():
     assert st["bitwise_lanes"] == n
 
 
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+def test_stream_probe(kind):
+    """The memory-pattern probe touches exactly the batched kernel's arrays."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    n = 10007
+    dt = torch.float64 if kind in "dz" else torch.float32
+    nin, nout = (8, 19) if kind in "zc" else (4, 11)
+    ins = [torch.full((n,), float(i + 1), dtype=dt, device="cuda") for i in range(nin)]
+    outs = [torch.zeros(n, dtype=dt, device="cuda") for _ in range(nout)]
+    S.svd2_stream_probe(kind, ins, outs)
+    torch.cuda.synchronize()
+    tot = nin * (nin + 1) / 2
+    for i, o in enumerate(outs):
+        assert torch.all(o == tot + i)
+
+
 def test_lane_isolation_nonfinite():
     """A lane with Inf/NaN input must not disturb the other lanes."""
     A = scaled_law(4096, SEED_BASE + 41, True)
@@ -241,15 +258,28 @@ def test_complex_full_size_2_24():
 # FP32 form and the FP64 rescue
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cplx", [False, True])
-@pytest.mark.parametrize("mode", ["plain", "inplace", "queue"])
-def test_fp32_modes(cplx, mode):
+RESCUE_MODES = ["plain", "inplace", "queue", "sigma", "sigma_queue"]
+
+
+def _fp32_flags(mode):
     from paper_2005_07403_amd import svd2 as S
+    return {"plain": 0, "inplace": S.SVD2_RESCUE_FP64,
+            "queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE,
+            "sigma": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA,
+            "sigma_queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA | S.SVD2_RESCUE_QUEUE}[mode]
+
+
+def _oracle_rescue(mode):
+    return 0 if mode == "plain" else (2 if mode.startswith("sigma") else 1)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("mode", RESCUE_MODES)
+def test_fp32_modes(cplx, mode):
     _set_launch(256, 2)
-    flags = {"plain": 0, "inplace": S.SVD2_RESCUE_FP64,
-             "queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE}[mode]
     A = scaled_law((1 << 17) + 5, SEED_BASE + 2, cplx, dtype=np.float32)
-    _check(A, np.float32, flags=flags, rescue=(mode != "plain"), metrics=(mode != "plain"))
+    _check(A, np.float32, flags=_fp32_flags(mode), rescue=_oracle_rescue(mode),
+           metrics=(mode != "plain"))
 
 
 @pytest.mark.parametrize("cplx", [False, True])
@@ -262,8 +292,8 @@ def test_fp32_rescue_near_singular(cplx):
     A = np.stack([u[0] * np.conj(v[0]), u[1] * np.conj(v[0]), u[0] * np.conj(v[1]),
                   u[1] * np.conj(v[1])]) + 3e-8 * rng.standard_normal((4, n))
     A = A.astype(np.complex64 if cplx else np.float32)
-    for flags in (S.SVD2_RESCUE_FP64, S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE):
-        _check(A, np.float32, flags=flags, rescue=True)
+    for mode in RESCUE_MODES[1:]:
+        _check(A, np.float32, flags=_fp32_flags(mode), rescue=_oracle_rescue(mode))
 
 
 @pytest.mark.slow

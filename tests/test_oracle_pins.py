@@ -386,8 +386,9 @@ def test_fp32_closed_form_exhaustive_real():
         assert abs(smin - ns) / xs <= 4 * EPS32
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_fp32_rescue_restores_relative_sigma_min(cplx):
+def test_fp32_rescue_restores_relative_sigma_min(cplx, mode):
     """On near-singular FP32 inputs the plain FP32 sigma_min is only accurate
     normwise; with the FP64 rescue it must be accurate relatively, checked
     against the closed form in 60-digit arithmetic on the exact inputs."""
@@ -401,7 +402,7 @@ def test_fp32_rescue_restores_relative_sigma_min(cplx):
                   u[1] * np.conj(v[1])])
     A = (A + 3e-8 * rng.standard_normal((4, n))).astype(dt)
     plain = O.svd2(A, dtype=np.float32, rescue=False)
-    resc = O.svd2(A, dtype=np.float32, rescue=True)
+    resc = O.svd2(A, dtype=np.float32, rescue=mode)
     assert resc["flagged"].sum() > 0.5 * n
     worst_plain = worst_resc = 0.0
     for j in range(n):
