@@ -205,11 +205,21 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  * gather kernel, the batched SVD entry point and an update kernel,
  * SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH = that chain captured once per solve
  * into a hipGraph and replayed per sweep (solve only).
+ * SVD2_KOG_TWO_STEP (sweep and solve only, alone): two steps per pass over
+ * the matrix, out of place between A and a matrix buffer in the workspace.
+ * Under the circle ordering each 2x2 block after step t+1 depends on a 4x4
+ * neighbourhood before step t, and the pivots of step t+1 follow from the
+ * rotations of step t and two blocks each, so both steps' rotations are known
+ * before the matrix is read; every entry is computed with the operations of
+ * the single-step update (bitwise the same result) and the matrix is read and
+ * written once per two steps.  The result is always returned in A.
  * ------------------------------------------------------------------------- */
-enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2 };
+enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2, SVD2_KOG_TWO_STEP = 4 };
 enum { SVD2_KOG_F64 = 0, SVD2_KOG_C128 = 1, SVD2_KOG_F32 = 2, SVD2_KOG_C64 = 3 };
 
 size_t kog_workspace_bytes(int N, int dtype);
+/* the same for the given flags (SVD2_KOG_TWO_STEP adds N^2 elements) */
+size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags);
 
 /* one step t (0 <= t < N-1) */
 svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,

@@ -95,6 +95,7 @@ struct Bar {
 
 struct Layout {
   size_t piv, out, red, res, bar, flags, total;
+  size_t piv1, out1, mat, total2;  // two-step mode: second rotation set and a matrix buffer
 };
 constexpr int kMaxFusedBlocks = 4096;  // barrier slots (64 bytes each)
 
@@ -111,17 +112,22 @@ Layout layout(int N, size_t esz, bool cplx) {
   L.bar = L.res + 256;
   L.flags = L.bar + 256;
   L.total = L.flags + (size_t)kMaxFusedBlocks * 64;
+  L.piv1 = L.total;
+  L.out1 = L.piv1 + nin * arr;
+  L.mat = L.out1 + nout * arr;
+  L.total2 = L.mat + up((size_t)N * N * esz * (cplx ? 2 : 1));
   return L;
 }
 
-template <class T, bool CPLX> Bufs<T, CPLX> make_bufs(void *ws, int N) {
+template <class T, bool CPLX> Bufs<T, CPLX> make_bufs(void *ws, int N, int set = 0) {
   Layout L = layout(N, sizeof(T), CPLX);
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t arr = up((size_t)(N / 2) * sizeof(T));
   Bufs<T, CPLX> b;
   char *base = (char *)ws;
-  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + L.piv + i * arr);
-  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + L.out + i * arr);
+  size_t piv = set ? L.piv1 : L.piv, out = set ? L.out1 : L.out;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + piv + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + out + i * arr);
   return b;
 }
 
@@ -309,6 +315,228 @@ template <class T, bool CPLX>
 __global__ __launch_bounds__(kUpdBlock) void kog_update_kernel(int N, Mat<T, CPLX> M, int t,
                                                                Bufs<T, CPLX> B, int kc, int lc) {
   update_tile<T, CPLX, false>(M, N, t, B, Tile{(int)blockIdx.x * kc, kc, (int)blockIdx.y * lc, lc});
+}
+
+// ---------------------------------------------------------------------------
+// two steps per pass (out of place).  Under the circle ordering row x is paired
+// with partner_t(x) = (2t - x) mod (N-1) at step t, so a 2x2 output block of
+// step t+1 (rows {p', q'}, columns {p'', q''}) depends only on the rows
+// {p', q', partner_t(p'), partner_t(q')} and the matching columns of the
+// matrix before step t: each entry after step t is one entry of one rotated
+// 2x2 block of step t.  Every entry is computed with exactly the operations of
+// the single-step update, so two steps per pass are bitwise equal to two
+// single steps; the pivots of step t+1 are such entries too, so the rotations
+// of step t+1 are known before the matrix is touched.
+// ---------------------------------------------------------------------------
+// pair index of row x at step t and its partner
+__device__ __forceinline__ void pos_at(int t, int x, int M, int n, int &k, int &partner) {
+  if (x == t) {
+    k = 0;
+    partner = M;
+  } else if (x == M) {
+    k = 0;
+    partner = t;
+  } else {
+    int d = x - t;
+    if (d < 0) d += M;
+    k = d < n ? d : M - d;
+    int pr = 2 * t - x;
+    if (pr < 0) pr += M;
+    if (pr >= M) pr -= M;
+    partner = pr;
+  }
+}
+
+// one row (or column) of a step-(t+1) block, seen from step t
+struct Side {
+  int x, partner, k;
+  bool isq;  // x is the q (larger) index of its step-t pair
+};
+__device__ __forceinline__ Side side_at(int t, int x, int M, int n) {
+  Side s;
+  s.x = x;
+  pos_at(t, x, M, n, s.k, s.partner);
+  s.isq = x > s.partner;
+  return s;
+}
+
+template <class T> struct RotU {
+  Cx<T> u11, u21, u12, u22;
+  T sp, sq;
+};
+template <class T> struct RotV {
+  Cx<T> v11, v21, v12, v22;
+};
+template <class T, bool CPLX> __device__ __forceinline__ RotU<T> load_u(const Bufs<T, CPLX> &B, int k) {
+  Rot<T> r = load_rot<T, CPLX>(B, k);
+  return RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
+}
+template <class T, bool CPLX> __device__ __forceinline__ RotV<T> load_v(const Bufs<T, CPLX> &B, int k) {
+  Rot<T> r = load_rot<T, CPLX>(B, k);
+  return RotV<T>{r.v11, r.v21, r.v12, r.v22};
+}
+
+// entry (role of the row, role of the column) of U^* B V for a step-t block
+// B given in (p-row, q-row) x (p-col, q-col) order; the operations are those
+// of rotate_block for that entry
+template <class T, bool CPLX>
+__device__ __forceinline__ Cx<T> rotated_entry(const RotU<T> &u, bool rq, const RotV<T> &v, bool cq, Cx<T> b11,
+                                               Cx<T> b21, Cx<T> b12, Cx<T> b22) {
+  if constexpr (CPLX) {
+    Cx<T> ua = rq ? u.u12 : u.u11, ub = rq ? u.u22 : u.u21;
+    Cx<T> t1 = cadd(cmulc(ua, b11), cmulc(ub, b21));
+    Cx<T> t2 = cadd(cmulc(ua, b12), cmulc(ub, b22));
+    Cx<T> va = cq ? v.v12 : v.v11, vb = cq ? v.v22 : v.v21;
+    return cadd(cmul(t1, va), cmul(t2, vb));
+  } else {
+    T ua = rq ? u.u12.re : u.u11.re, ub = rq ? u.u22.re : u.u21.re;
+    T t1 = vfma(ua, b11.re, ub * b21.re);
+    T t2 = vfma(ua, b12.re, ub * b22.re);
+    T va = cq ? v.v12.re : v.v11.re, vb = cq ? v.v22.re : v.v21.re;
+    return Cx<T>{vfma(t1, va, t2 * vb), T(0)};
+  }
+}
+
+// A(r, c) after step t, from the matrix before it: xrc = A(r, c), xrp = A(r,
+// partner_c), xpc = A(partner_r, c), xpp = A(partner_r, partner_c)
+template <class T, bool CPLX>
+__device__ __forceinline__ Cx<T> after_step(const Side &r, const RotU<T> &ur, const Side &c, const RotV<T> &vc,
+                                            Cx<T> xrc, Cx<T> xrp, Cx<T> xpc, Cx<T> xpp) {
+  if (r.k == c.k) {  // inside a pivot block of step t: diag(sigma_p, sigma_q), zeros elsewhere
+    if (r.x == c.x) return Cx<T>{r.isq ? ur.sq : ur.sp, T(0)};
+    return Cx<T>{T(0), T(0)};
+  }
+  // the step-t block in (p-row, q-row) x (p-col, q-col) order
+  Cx<T> b11 = r.isq ? (c.isq ? xpp : xpc) : (c.isq ? xrp : xrc);
+  Cx<T> b12 = r.isq ? (c.isq ? xpc : xpp) : (c.isq ? xrc : xrp);
+  Cx<T> b21 = r.isq ? (c.isq ? xrp : xrc) : (c.isq ? xpp : xpc);
+  Cx<T> b22 = r.isq ? (c.isq ? xrc : xrp) : (c.isq ? xpc : xpp);
+  return rotated_entry<T, CPLX>(ur, r.isq, vc, c.isq, b11, b21, b12, b22);
+}
+
+// the 2x2 block (rows ra, rb) x (columns ca, cb) after step t
+template <class T, bool CPLX>
+__device__ __forceinline__ void block_after_step(const Mat<T, CPLX> &M, const Side (&R)[2], const RotU<T> (&U)[2],
+                                                 const Side (&C)[2], const RotV<T> (&V)[2], Cx<T> (&out)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    Cx<T> x[2][2];  // [row or partner][col or partner] for column j below
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      x[0][0] = M.ld(R[i].x, C[j].x);
+      x[0][1] = M.ld(R[i].x, C[j].partner);
+      x[1][0] = M.ld(R[i].partner, C[j].x);
+      x[1][1] = M.ld(R[i].partner, C[j].partner);
+      out[i][j] = after_step<T, CPLX>(R[i], U[i], C[j], V[j], x[0][0], x[0][1], x[1][0], x[1][1]);
+    }
+  }
+}
+
+// pivots of step t+1 from the matrix before step t, and their 2x2 SVDs
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_predict_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
+                                                          Bufs<T, CPLX> B1) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  const int n = N / 2, Mo = N - 1;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int a, b;
+  pair_ab(t + 1, k, Mo, a, b);
+  int p = a < b ? a : b, q = a < b ? b : a;
+  Side S[2] = {side_at(t, p, Mo, n), side_at(t, q, Mo, n)};
+  RotU<T> U[2] = {load_u<T, CPLX>(B0, S[0].k), load_u<T, CPLX>(B0, S[1].k)};
+  RotV<T> V[2] = {load_v<T, CPLX>(B0, S[0].k), load_v<T, CPLX>(B0, S[1].k)};
+  Cx<T> e[2][2];
+  block_after_step<T, CPLX>(M, S, U, S, V, e);
+  // record order 11, 21, 12, 22 = (p,p), (q,p), (p,q), (q,q)
+  Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
+  T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x[2 * i] = rec[i].re;
+      x[2 * i + 1] = rec[i].im;
+    } else {
+      x[i] = rec[i].re;
+    }
+  }
+  one_matrix<T, CPLX, RESC>(x, y, 2);
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B1.piv[i][k] = x[i];
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B1.out[i][k] = y[i];
+}
+
+// gather + 2x2 SVD of the pivots of step t in one kernel
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_pivot_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N / 2) return;
+  T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
+  gather_one<T, CPLX>(M, N, t, k, x);
+  one_matrix<T, CPLX, RESC>(x, y, 2);
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
+}
+
+// one tile of the two-step update: reads Mc (before step t), writes Mn (after step t+1)
+template <class T, bool CPLX>
+__device__ __forceinline__ void two_step_tile(const Mat<T, CPLX> &Mc, const Mat<T, CPLX> &Mn, int N, int t,
+                                              const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1, Tile tl) {
+  const int n = N / 2, Mo = N - 1, t1 = t + 1;
+  const int groups = kUpdBlock / tl.kc;
+  const int k = tl.k0 + (int)threadIdx.x % tl.kc;
+  const int g = (int)threadIdx.x / tl.kc;
+  if (k >= n) return;
+  int ra, rb;
+  pair_ab(t1, k, Mo, ra, rb);
+  const bool kflip = ra > rb;
+  Side R[2] = {side_at(t, ra, Mo, n), side_at(t, rb, Mo, n)};
+  RotU<T> UR[2] = {load_u<T, CPLX>(B0, R[0].k), load_u<T, CPLX>(B0, R[1].k)};
+  RotU<T> u1 = load_u<T, CPLX>(B1, k);
+  const int lend = tl.l0 + tl.lc < n ? tl.l0 + tl.lc : n;
+  for (int l = tl.l0 + g; l < lend; l += groups) {
+    int ca, cb;
+    pair_ab(t1, l, Mo, ca, cb);
+    Side C[2] = {side_at(t, ca, Mo, n), side_at(t, cb, Mo, n)};
+    RotV<T> VC[2] = {load_v<T, CPLX>(B0, C[0].k), load_v<T, CPLX>(B0, C[1].k)};
+    Cx<T> e[2][2];  // (ra, rb) x (ca, cb) after step t
+    block_after_step<T, CPLX>(Mc, R, UR, C, VC, e);
+    const bool lflip = ca > cb;
+    Cx<T> b11 = e[kflip][lflip], b21 = e[!kflip][lflip], b12 = e[kflip][!lflip], b22 = e[!kflip][!lflip];
+    if (l == k) {
+      b11 = Cx<T>{u1.sp, T(0)};
+      b22 = Cx<T>{u1.sq, T(0)};
+      b12 = b21 = Cx<T>{T(0), T(0)};
+    } else {
+      RotV<T> v1 = load_v<T, CPLX>(B1, l);
+      Rot<T> uu{u1.u11, u1.u21, u1.u12, u1.u22, {}, {}, {}, {}, u1.sp, u1.sq};
+      Rot<T> vv{{}, {}, {}, {}, v1.v11, v1.v21, v1.v12, v1.v22, T(0), T(0)};
+      rotate_block<T, CPLX>(uu, vv, b11, b21, b12, b22);
+    }
+    const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
+    Mn.st(ra, cp, kflip ? b21 : b11);
+    Mn.st(rb, cp, kflip ? b11 : b21);
+    Mn.st(ra, cq, kflip ? b22 : b12);
+    Mn.st(rb, cq, kflip ? b12 : b22);
+  }
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(kUpdBlock) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
+                                                                 Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int kc,
+                                                                 int lc) {
+  two_step_tile<T, CPLX>(Mc, Mn, N, t, B0, B1,
+                         Tile{(int)blockIdx.x * kc, kc, (int)blockIdx.y * lc, lc});
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_copy_kernel(int N, Mat<T, CPLX> src, Mat<T, CPLX> dst) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) dst.st(i, j, src.ld(i, j));
 }
 
 // ---------------------------------------------------------------------------
@@ -643,7 +871,8 @@ svd2_status hip_st(hipError_t e) {
 template <class T, bool CPLX> struct Ctx {
   int N;
   Mat<T, CPLX> M;
-  Bufs<T, CPLX> B;
+  Bufs<T, CPLX> B, B1;
+  Mat<T, CPLX> W;  // two-step mode: the second matrix buffer (lda = N)
   Layout L;
   char *ws;
   unsigned flags;
@@ -654,18 +883,22 @@ template <class T, bool CPLX>
 svd2_status validate(int N, T *A, int lda, void *ws, size_t ws_bytes, unsigned flags, Ctx<T, CPLX> &c) {
   if (!A || !ws) return SVD2_ERR_NULL;
   if (N < 2 || N % 2 || lda < N || N > (1 << 19)) return SVD2_ERR_SIZE;
-  if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH)) return SVD2_ERR_FLAGS;
+  if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;
   if ((flags & SVD2_KOG_GRAPH) && !(flags & SVD2_KOG_UNFUSED)) return SVD2_ERR_FLAGS;
+  if ((flags & SVD2_KOG_TWO_STEP) && (flags & (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))) return SVD2_ERR_FLAGS;
   if ((uintptr_t)A % (CPLX ? 2 * sizeof(T) : sizeof(T))) return SVD2_ERR_ALIGN;
   if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
   c.L = layout(N, sizeof(T), CPLX);
-  if (ws_bytes < c.L.total) return SVD2_ERR_SIZE;
+  const size_t need = (flags & SVD2_KOG_TWO_STEP) ? c.L.total2 : c.L.total;
+  if (ws_bytes < need) return SVD2_ERR_SIZE;
   size_t abytes = ((size_t)lda * (N - 1) + N) * sizeof(T) * (CPLX ? 2 : 1);
-  uintptr_t a0 = (uintptr_t)A, a1 = a0 + abytes, w0 = (uintptr_t)ws, w1 = w0 + c.L.total;
+  uintptr_t a0 = (uintptr_t)A, a1 = a0 + abytes, w0 = (uintptr_t)ws, w1 = w0 + need;
   if (a0 < w1 && w0 < a1) return SVD2_ERR_ALIAS;
   c.N = N;
   c.M = Mat<T, CPLX>{A, (size_t)lda};
-  c.B = make_bufs<T, CPLX>(ws, N);
+  c.B = make_bufs<T, CPLX>(ws, N, 0);
+  c.B1 = make_bufs<T, CPLX>(ws, N, 1);
+  c.W = Mat<T, CPLX>{(T *)((char *)ws + c.L.mat), (size_t)N};
   c.ws = (char *)ws;
   c.flags = flags;
   return SVD2_OK;
@@ -755,7 +988,63 @@ template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int
                                            dim3(kUpdBlock), args, 0, c.st));
 }
 
+// two steps t, t+1 from `cur` into `nxt`
+template <class T, bool CPLX>
+svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t) {
+  const int n = c.N / 2;
+  hipLaunchKernelGGL((kog_pivot_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL((kog_predict_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B,
+                     c.B1);
+  s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  TileRule r = rule_for(c.N);
+  dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
+  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, cur, nxt, t, c.B,
+                     c.B1, r.kc, r.lc);
+  return hip_st(hipGetLastError());
+}
+
+// one step t in place on `cur` (gather + SVD in one kernel, then the update)
+template <class T, bool CPLX> svd2_status one_step_on(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, int t) {
+  const int n = c.N / 2;
+  hipLaunchKernelGGL((kog_pivot_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  TileRule r = rule_for(c.N);
+  dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
+  hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, cur, t, c.B, r.kc, r.lc);
+  return hip_st(hipGetLastError());
+}
+
+// a sweep of the two-step mode; *in_w tells (and is updated with) which
+// buffer holds the iterate (false: the caller's A, true: the workspace copy)
+template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, bool *in_w) {
+  svd2_status s = SVD2_OK;
+  int t = 0;
+  for (; t + 1 < c.N - 1 && s == SVD2_OK; t += 2) {
+    const Mat<T, CPLX> &cur = *in_w ? c.W : c.M, &nxt = *in_w ? c.M : c.W;
+    s = two_steps<T, CPLX>(c, cur, nxt, t);
+    *in_w = !*in_w;
+  }
+  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t);
+  return s;
+}
+
+template <class T, bool CPLX> svd2_status copy_back(const Ctx<T, CPLX> &c) {
+  int grid = c.N < 4096 ? c.N : 4096;
+  hipLaunchKernelGGL((kog_copy_kernel<T, CPLX>), dim3(grid), dim3(256), 0, c.st, c.N, c.W, c.M);
+  return hip_st(hipGetLastError());
+}
+
 template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
+  if (c.flags & SVD2_KOG_TWO_STEP) {
+    bool in_w = false;
+    svd2_status s = sweep_two_step<T, CPLX>(c, &in_w);
+    if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
+    return s;
+  }
   if (!(c.flags & SVD2_KOG_UNFUSED)) return fused_steps<T, CPLX>(c, 0, c.N - 1);
   for (int t = 0; t < c.N - 1; ++t) {
     svd2_status s = unfused_step<T, CPLX>(c, t);
@@ -764,10 +1053,11 @@ template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
   return SVD2_OK;
 }
 
-template <class T, bool CPLX> svd2_status norms_async(const Ctx<T, CPLX> &c) {
+template <class T, bool CPLX> svd2_status norms_async(const Ctx<T, CPLX> &c, bool in_w = false) {
   double *part = (double *)(c.ws + c.L.red), *res = (double *)(c.ws + c.L.res);
   int nb = c.N < kRedBlocks ? c.N : kRedBlocks;
-  hipLaunchKernelGGL((kog_norm_partial_kernel<T, CPLX>), dim3(nb), dim3(256), 0, c.st, c.N, c.M, part);
+  hipLaunchKernelGGL((kog_norm_partial_kernel<T, CPLX>), dim3(nb), dim3(256), 0, c.st, c.N, in_w ? c.W : c.M,
+                     part);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_norm_final_kernel, dim3(1), dim3(256), 0, c.st, nb, part, res);
@@ -786,7 +1076,7 @@ template <class T, bool CPLX> svd2_status read_norms(const Ctx<T, CPLX> &c, doub
 }
 
 template <class T, bool CPLX> svd2_status check_abort(const Ctx<T, CPLX> &c) {
-  if (c.flags & SVD2_KOG_UNFUSED) return SVD2_OK;
+  if (c.flags & (SVD2_KOG_UNFUSED | SVD2_KOG_TWO_STEP)) return SVD2_OK;
   Bar h;
   svd2_status s = hip_st(hipMemcpyAsync(&h, c.ws + c.L.bar, sizeof h, hipMemcpyDeviceToHost, c.st));
   if (s != SVD2_OK) return s;
@@ -821,6 +1111,8 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
   hipGraphExec_t exec = nullptr;
   svd2_status s = SVD2_OK;
   if (c.flags & SVD2_KOG_GRAPH) s = graph_build<T, CPLX>(c, &exec);
+  const bool two = c.flags & SVD2_KOG_TWO_STEP;
+  bool in_w = false;
   double off2 = 0, tot2 = 0, nrm0 = 0;
   int sw = 0;
   if (s == SVD2_OK) s = norms_async<T, CPLX>(c);
@@ -836,11 +1128,16 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     }
     if (sw == max_sweeps) break;
     if (exec) s = hip_st(hipGraphLaunch(exec, c.st));
+    else if (two) s = sweep_two_step<T, CPLX>(c, &in_w);
     else s = sweep<T, CPLX>(c);
-    if (s == SVD2_OK) s = norms_async<T, CPLX>(c);
+    if (s == SVD2_OK) s = norms_async<T, CPLX>(c, in_w);
     if (s == SVD2_OK) s = read_norms<T, CPLX>(c, off2, tot2);
     if (s == SVD2_OK) s = check_abort<T, CPLX>(c);
     ++sw;
+  }
+  if (s == SVD2_OK && in_w) {
+    s = copy_back<T, CPLX>(c);
+    if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
   }
   if (exec) hipGraphExecDestroy(exec);
   if (sweeps) *sweeps = sw;
@@ -850,7 +1147,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
 template <class T, bool CPLX>
 svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
   Ctx<T, CPLX> c;
-  if (flags & SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;  // graph replay is a solve-only mode
+  if (flags & (SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;  // solve/sweep modes
   svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
   if (s != SVD2_OK) return s;
   if (t < 0 || t >= N - 1) return SVD2_ERR_SIZE;
@@ -1109,16 +1406,20 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
 
 extern "C" {
 
-size_t kog_workspace_bytes(int N, int dtype) {
+size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags) {
   if (N < 2 || N % 2) return 0;
+  Layout L;
   switch (dtype) {
-    case SVD2_KOG_F64: return layout(N, 8, false).total;
-    case SVD2_KOG_C128: return layout(N, 8, true).total;
-    case SVD2_KOG_F32: return layout(N, 4, false).total;
-    case SVD2_KOG_C64: return layout(N, 4, true).total;
+    case SVD2_KOG_F64: L = layout(N, 8, false); break;
+    case SVD2_KOG_C128: L = layout(N, 8, true); break;
+    case SVD2_KOG_F32: L = layout(N, 4, false); break;
+    case SVD2_KOG_C64: L = layout(N, 4, true); break;
+    default: return 0;
   }
-  return 0;
+  return (flags & SVD2_KOG_TWO_STEP) ? L.total2 : L.total;
 }
+
+size_t kog_workspace_bytes(int N, int dtype) { return kog_workspace_bytes_flags(N, dtype, 0); }
 
 svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
                       hipStream_t stream) {

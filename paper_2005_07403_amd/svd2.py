@@ -59,7 +59,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
-           "kog_batch_solve",
+           "kog_batch_solve", "kog_workspace_bytes_flags",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -257,6 +257,7 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
 # ---------------------------------------------------------------------------
 SVD2_KOG_UNFUSED = 1
 SVD2_KOG_GRAPH = 2
+SVD2_KOG_TWO_STEP = 4
 KOG_DTYPE = {"d": 0, "z": 1, "s": 2, "c": 3}
 _kog_ready = False
 
@@ -268,6 +269,8 @@ def _kog():
         i, sz, ui, d = ctypes.c_int, ctypes.c_size_t, ctypes.c_uint, ctypes.c_double
         L.kog_workspace_bytes.argtypes = [i, i]
         L.kog_workspace_bytes.restype = sz
+        L.kog_workspace_bytes_flags.argtypes = [i, i, ui]
+        L.kog_workspace_bytes_flags.restype = sz
         for x in "dzsc":
             getattr(L, f"{x}kog_step").argtypes = [i, _P, i, i, _P, sz, ui, _P]
             getattr(L, f"{x}kog_sweep").argtypes = [i, _P, i, _P, sz, ui, _P]
@@ -294,8 +297,8 @@ def kog_kind(A) -> str:
             torch.complex64: "c"}[A.dtype]
 
 
-def kog_workspace_bytes(N: int, kind: str) -> int:
-    return int(_kog().kog_workspace_bytes(N, KOG_DTYPE[kind]))
+def kog_workspace_bytes(N: int, kind: str, flags: int = 0) -> int:
+    return int(_kog().kog_workspace_bytes_flags(N, KOG_DTYPE[kind], flags))
 
 
 def _kog_args(A):
@@ -307,10 +310,10 @@ def _kog_args(A):
     return N, A.stride(1), A.data_ptr()
 
 
-def kog_workspace(A):
+def kog_workspace(A, flags: int = 0):
     import torch
     N = A.shape[0]
-    return torch.empty(kog_workspace_bytes(N, kog_kind(A)), dtype=torch.uint8, device=A.device)
+    return torch.empty(kog_workspace_bytes(N, kog_kind(A), flags), dtype=torch.uint8, device=A.device)
 
 
 def kog_step(A, t: int, ws=None, flags: int = 0, stream=None) -> None:
@@ -324,7 +327,7 @@ def kog_step(A, t: int, ws=None, flags: int = 0, stream=None) -> None:
 def kog_sweep(A, ws=None, flags: int = 0, stream=None) -> None:
     k = kog_kind(A)
     N, lda, ptr = _kog_args(A)
-    ws = kog_workspace(A) if ws is None else ws
+    ws = kog_workspace(A, flags) if ws is None else ws
     _kog_check(f"{k}kog_sweep", getattr(_kog(), f"{k}kog_sweep")(N, ptr, lda, ws.data_ptr(),
                                                                 ws.numel(), flags, _stream(stream)))
 
@@ -334,7 +337,7 @@ def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int =
     """Sweeps until off(A) < tol ||A_0||_F.  Returns status, sweeps, off_rel."""
     k = kog_kind(A)
     N, lda, ptr = _kog_args(A)
-    ws = kog_workspace(A) if ws is None else ws
+    ws = kog_workspace(A, flags) if ws is None else ws
     sw, off = ctypes.c_int(), ctypes.c_double()
     st = getattr(_kog(), f"{k}kog_solve")(N, ptr, lda, tol, max_sweeps, ctypes.byref(sw),
                                           ctypes.byref(off), ws.data_ptr(), ws.numel(), flags,

@@ -124,3 +124,76 @@ def test_full_order_4096_solve():
     assert np.all(sig >= 0)
     assert np.max(np.abs(sig - s)) <= 8 * N * EPS["d"] * s[0]
     print(f"N=4096 solve: {r['sweeps']} sweeps, off/||A|| = {r['off_rel']:.3e}")
+
+
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+@pytest.mark.parametrize("N", [2, 4, 6, 8, 64, 130, 1030])
+def test_two_step_sweep_bitwise(kind, N):
+    """Two steps per pass (out of place, ping-pong with the workspace matrix):
+    one sweep, then a second, each bitwise equal to N-1 oracle steps.  The
+    sweep count of passes is odd or even depending on N, so both the result
+    left in the workspace (copied back) and in A are covered."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    A = _make(N, kind, SEED_BASE + 330 + N)
+    G = _dev(A)
+    ws = S.kog_workspace(G, S.SVD2_KOG_TWO_STEP)
+    for _ in range(2):
+        S.kog_sweep(G, ws=ws, flags=S.SVD2_KOG_TWO_STEP)
+        for t in range(N - 1):
+            O.kog_step(A, t)
+        torch.cuda.synchronize()
+        assert _same(G.cpu().numpy(), A), (kind, N)
+
+
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+def test_two_step_padded_lda(kind):
+    """A with lda > N (a view into a larger column-major buffer): the
+    workspace matrix uses lda = N, the padding rows stay untouched."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N, pad = 66, 5
+    A = _make(N, kind, SEED_BASE + 340)
+    big = np.asfortranarray(np.full((N + pad, N), 7, dtype=DT[kind]))
+    big[:N, :] = A
+    Gbig = _dev(big)
+    G = Gbig[:N, :]
+    assert G.stride(1) == N + pad
+    S.kog_sweep(G, flags=S.SVD2_KOG_TWO_STEP)
+    for t in range(N - 1):
+        O.kog_step(A, t)
+    torch.cuda.synchronize()
+    out = Gbig.cpu().numpy()
+    assert _same(out[:N, :], A)
+    assert np.all(out[N:, :] == 7)
+
+
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+@pytest.mark.parametrize("N", [64, 130])
+def test_two_step_solve_bitwise(kind, N):
+    """Full solve in the two-step mode: same sweep count, status and final
+    matrix as the oracle."""
+    from paper_2005_07403_amd import svd2 as S
+    tol = 1e-14 if kind in "dz" else 1e-6
+    A = _make(N, kind, SEED_BASE + 350 + N, cond=1e10 if kind in "dz" else 1e4)
+    G = _dev(A)
+    r = S.kog_solve(G, tol=tol, flags=S.SVD2_KOG_TWO_STEP)
+    ro = O.kog_solve(A, tol=tol)
+    assert r["status"] == ro["status"] == 0
+    assert r["sweeps"] == ro["sweeps"]
+    assert abs(r["off_rel"] - ro["off_rel"]) <= 1e-12 + 1e-10 * ro["off_rel"]
+    assert _same(G.cpu().numpy(), A)
+
+
+def test_two_step_full_order_4096_sweep():
+    """One two-step sweep of the one-problem workload (real FP64, N = 4096)
+    against the single-step unfused sweep on the GPU (bitwise)."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N = 4096
+    A = kog_matrix(N, SEED_BASE + 3, cond=1e12)
+    G1, G2 = _dev(A), _dev(A)
+    S.kog_sweep(G1, flags=S.SVD2_KOG_UNFUSED)
+    S.kog_sweep(G2, flags=S.SVD2_KOG_TWO_STEP)
+    torch.cuda.synchronize()
+    assert torch.equal(G1.view(torch.int64), G2.view(torch.int64))
