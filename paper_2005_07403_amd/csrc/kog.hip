@@ -482,55 +482,212 @@ __global__ __launch_bounds__(256) void kog_pivot_kernel(int N, Mat<T, CPLX> M, i
   for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
 }
 
-// one tile of the two-step update: reads Mc (before step t), writes Mn (after step t+1)
-template <class T, bool CPLX>
-__device__ __forceinline__ void two_step_tile(const Mat<T, CPLX> &Mc, const Mat<T, CPLX> &Mn, int N, int t,
-                                              const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1, Tile tl) {
-  const int n = N / 2, Mo = N - 1, t1 = t + 1;
-  const int groups = kUpdBlock / tl.kc;
-  const int k = tl.k0 + (int)threadIdx.x % tl.kc;
-  const int g = (int)threadIdx.x / tl.kc;
-  if (k >= n) return;
-  int ra, rb;
-  pair_ab(t1, k, Mo, ra, rb);
-  const bool kflip = ra > rb;
-  Side R[2] = {side_at(t, ra, Mo, n), side_at(t, rb, Mo, n)};
-  RotU<T> UR[2] = {load_u<T, CPLX>(B0, R[0].k), load_u<T, CPLX>(B0, R[1].k)};
-  RotU<T> u1 = load_u<T, CPLX>(B1, k);
-  const int lend = tl.l0 + tl.lc < n ? tl.l0 + tl.lc : n;
-  for (int l = tl.l0 + g; l < lend; l += groups) {
-    int ca, cb;
-    pair_ab(t1, l, Mo, ca, cb);
-    Side C[2] = {side_at(t, ca, Mo, n), side_at(t, cb, Mo, n)};
-    RotV<T> VC[2] = {load_v<T, CPLX>(B0, C[0].k), load_v<T, CPLX>(B0, C[1].k)};
-    Cx<T> e[2][2];  // (ra, rb) x (ca, cb) after step t
-    block_after_step<T, CPLX>(Mc, R, UR, C, VC, e);
-    const bool lflip = ca > cb;
-    Cx<T> b11 = e[kflip][lflip], b21 = e[!kflip][lflip], b12 = e[kflip][!lflip], b22 = e[!kflip][!lflip];
-    if (l == k) {
-      b11 = Cx<T>{u1.sp, T(0)};
-      b22 = Cx<T>{u1.sq, T(0)};
-      b12 = b21 = Cx<T>{T(0), T(0)};
-    } else {
-      RotV<T> v1 = load_v<T, CPLX>(B1, l);
-      Rot<T> uu{u1.u11, u1.u21, u1.u12, u1.u22, {}, {}, {}, {}, u1.sp, u1.sq};
-      Rot<T> vv{{}, {}, {}, {}, v1.v11, v1.v21, v1.v12, v1.v22, T(0), T(0)};
-      rotate_block<T, CPLX>(uu, vv, b11, b21, b12, b22);
-    }
-    const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
-    Mn.st(ra, cp, kflip ? b21 : b11);
-    Mn.st(rb, cp, kflip ? b11 : b21);
-    Mn.st(ra, cq, kflip ? b22 : b12);
-    Mn.st(rb, cq, kflip ? b12 : b22);
+// The two-step update proper ("lane-shift" form).  Lane j of a wavefront
+// holds the rows of pair j of step t (P_j = t + j and Q_j = t - j mod N-1;
+// pair 0 is rows t and N-1) and walks the column pairs j' of step t in
+// increasing order: it reads each 2x2 block (P_j, Q_j) x (P_j', Q_j') once and
+// rotates it with U_j, V_j' as the single-step update would.  Pair k of step
+// t+1 is made of rows P_{k+1} and Q_{k-1} (k = 0: P_1 and N-1; k = 1: P_2 and
+// t = P_0; k = n-1: Q_{n-1} and Q_{n-2}), held one lane down and one lane up:
+// they are exchanged with lane shuffles.  Its column pair l is made of the
+// columns of iterations l+1 and l-1 of the walk (same exceptions), kept in a
+// three-deep register window.  A wavefront computes 64 pairs of step t and
+// writes the 62 pairs of step t+1 it holds both neighbours for; a workgroup
+// of `wpg` wavefronts shares one column tile of `lc` pairs, walked over
+// [l0 - 1, l0 + lc], with the V rotations of both steps staged in LDS.
+constexpr int kShiftOut = 62;
+
+// value select (a ternary on lvalues would select addresses and spill)
+template <class T> __device__ __forceinline__ Cx<T> sel(bool c, Cx<T> x, Cx<T> y) {
+  return Cx<T>{c ? x.re : y.re, c ? x.im : y.im};
+}
+
+template <class T, bool CPLX> struct VPack {
+  static constexpr int W = CPLX ? 8 : 4;
+  T v[W];
+};
+template <class T, bool CPLX> __device__ __forceinline__ VPack<T, CPLX> pack_v(const Rot<T> &r) {
+  VPack<T, CPLX> p;
+  if constexpr (CPLX) {
+    p.v[0] = r.v11.re; p.v[1] = r.v11.im; p.v[2] = r.v21.re; p.v[3] = r.v21.im;
+    p.v[4] = r.v12.re; p.v[5] = r.v12.im; p.v[6] = r.v22.re; p.v[7] = r.v22.im;
+  } else {
+    p.v[0] = r.v11.re; p.v[1] = r.v21.re; p.v[2] = r.v12.re; p.v[3] = r.v22.re;
+  }
+  return p;
+}
+template <class T, bool CPLX> __device__ __forceinline__ Rot<T> with_v(const RotU<T> &u, const VPack<T, CPLX> &p) {
+  Rot<T> r;
+  r.u11 = u.u11; r.u21 = u.u21; r.u12 = u.u12; r.u22 = u.u22;
+  if constexpr (CPLX) {
+    r.v11 = Cx<T>{p.v[0], p.v[1]}; r.v21 = Cx<T>{p.v[2], p.v[3]};
+    r.v12 = Cx<T>{p.v[4], p.v[5]}; r.v22 = Cx<T>{p.v[6], p.v[7]};
+  } else {
+    r.v11 = Cx<T>{p.v[0], T(0)}; r.v21 = Cx<T>{p.v[1], T(0)};
+    r.v12 = Cx<T>{p.v[2], T(0)}; r.v22 = Cx<T>{p.v[3], T(0)};
+  }
+  r.sp = u.sp;
+  r.sq = u.sq;
+  return r;
+}
+
+// rows of pair j of step t
+__device__ __forceinline__ void rows_at(int t, int j, int Mo, int &P, int &Q) {
+  if (j == 0) {
+    P = t;
+    Q = Mo;
+  } else {
+    P = t + j;
+    if (P >= Mo) P -= Mo;
+    Q = t - j;
+    if (Q < 0) Q += Mo;
   }
 }
 
+template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_dn1(Cx<T> x) {
+  Cx<T> r;
+  r.re = __shfl_down(x.re, 1, 64);
+  if constexpr (CPLX) r.im = __shfl_down(x.im, 1, 64);
+  else r.im = T(0);
+  return r;
+}
+template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_up1(Cx<T> x) {
+  Cx<T> r;
+  r.re = __shfl_up(x.re, 1, 64);
+  if constexpr (CPLX) r.im = __shfl_up(x.im, 1, 64);
+  else r.im = T(0);
+  return r;
+}
+
+// one column of the walk after the row exchange: the entries of rows
+// ra(k) (xp) and rb(k) (xm) of step t+1's pair k = j
+template <class T> struct ColPair {
+  Cx<T> xp, xm;
+};
+template <class T> __device__ __forceinline__ ColPair<T> selp(bool c, ColPair<T> x, ColPair<T> y) {
+  return ColPair<T>{sel(c, x.xp, y.xp), sel(c, x.xm, y.xm)};
+}
+
 template <class T, bool CPLX>
-__global__ __launch_bounds__(kUpdBlock) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
-                                                                 Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int kc,
-                                                                 int lc) {
-  two_step_tile<T, CPLX>(Mc, Mn, N, t, B0, B1,
-                         Tile{(int)blockIdx.x * kc, kc, (int)blockIdx.y * lc, lc});
+__global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
+                                                           Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int wpg,
+                                                           int lc) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int n = N / 2, Mo = N - 1, t1 = t + 1;
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const int l0 = (int)blockIdx.y * lc;
+  const int lend = l0 + lc < n ? l0 + lc : n;
+  const int jlo = l0 > 0 ? l0 - 1 : 0;
+  const int jhi = l0 + lc < n - 1 ? l0 + lc : n - 1;  // inclusive
+  VPack<T, CPLX> *sv = (VPack<T, CPLX> *)kog_smem;     // V of step t, index j' - jlo
+  VPack<T, CPLX> *sv1 = sv + (lc + 2);                // V of step t+1, index l - l0
+  for (int i = threadIdx.x; i <= jhi - jlo; i += blockDim.x) sv[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B0, jlo + i));
+  for (int i = threadIdx.x; i < lend - l0; i += blockDim.x) sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, l0 + i));
+  __syncthreads();
+
+  const int j = ((int)blockIdx.x * wpg + w) * kShiftOut - 1 + lane;
+  const bool act = j >= 0 && j < n;
+  const bool out = act && lane >= 1 && lane <= kShiftOut;
+  int P = 0, Q = 0, ra = 0, rb = 0;
+  RotU<T> u{}, u1{};
+  if (act) {
+    rows_at(t, j, Mo, P, Q);
+    u = load_u<T, CPLX>(B0, j);
+  }
+  if (out) {
+    pair_ab(t1, j, Mo, ra, rb);
+    u1 = load_u<T, CPLX>(B1, j);
+  }
+  const bool rflip = P > Q, kflip = ra > rb;
+  const Cx<T> zero{T(0), T(0)};
+
+  // the block (P, Q) x (Pc, Qc) of one iteration, as loaded
+  struct Blk {
+    Cx<T> pp, qp, pq, qq;
+  };
+  auto load_blk = [&](int jj) -> Blk {
+    int Pc, Qc;
+    rows_at(t, jj, Mo, Pc, Qc);
+    Blk d{zero, zero, zero, zero};
+    if (act) {
+      d.pp = Mc.ld(P, Pc);
+      d.qp = Mc.ld(Q, Pc);
+      d.pq = Mc.ld(P, Qc);
+      d.qq = Mc.ld(Q, Qc);
+    }
+    return d;
+  };
+  Blk nx = load_blk(jlo);
+  ColPair<T> prev1P{zero, zero}, prev1Q{zero, zero}, prev2m{zero, zero};
+  for (int jj = jlo; jj <= jhi; ++jj) {
+    const Blk a = nx;
+    if (jj < jhi) nx = load_blk(jj + 1);
+    // step t on the block (j, jj), in P/Q labels
+    int Pc, Qc;
+    rows_at(t, jj, Mo, Pc, Qc);
+    const bool cflip = Pc > Qc;
+    Cx<T> b11 = sel(rflip, sel(cflip, a.qq, a.qp), sel(cflip, a.pq, a.pp));
+    Cx<T> b21 = sel(rflip, sel(cflip, a.pq, a.pp), sel(cflip, a.qq, a.qp));
+    Cx<T> b12 = sel(rflip, sel(cflip, a.qp, a.qq), sel(cflip, a.pp, a.pq));
+    Cx<T> b22 = sel(rflip, sel(cflip, a.pp, a.pq), sel(cflip, a.qp, a.qq));
+    if (j == jj) {
+      b11 = Cx<T>{u.sp, T(0)};
+      b22 = Cx<T>{u.sq, T(0)};
+      b12 = b21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u, sv[jj - jlo]);
+      rotate_block<T, CPLX>(r, r, b11, b21, b12, b22);
+    }
+    const Cx<T> ePP = sel(rflip, sel(cflip, b22, b21), sel(cflip, b12, b11));
+    const Cx<T> eQP = sel(rflip, sel(cflip, b12, b11), sel(cflip, b22, b21));
+    const Cx<T> ePQ = sel(rflip, sel(cflip, b21, b22), sel(cflip, b11, b12));
+    const Cx<T> eQQ = sel(rflip, sel(cflip, b11, b12), sel(cflip, b21, b22));
+    // row exchange: ra(k) = P_{k+1} (one lane down) or Q_{n-1} (own, k = n-1);
+    // rb(k) = Q_{k-1} (one lane up), P_0 (k = 1) or N-1 = Q_0 (own, k = 0)
+    ColPair<T> curP, curQ;
+    {
+      Cx<T> dn = shfl_dn1<T, CPLX>(ePP), up = shfl_up1<T, CPLX>(sel(j == 0, ePP, eQP));
+      curP.xp = sel(j == n - 1, eQP, dn);
+      curP.xm = sel(j == 0, eQP, up);
+      dn = shfl_dn1<T, CPLX>(ePQ);
+      up = shfl_up1<T, CPLX>(sel(j == 0, ePQ, eQQ));
+      curQ.xp = sel(j == n - 1, eQQ, dn);
+      curQ.xm = sel(j == 0, eQQ, up);
+    }
+    // emit column pair l of step t+1: columns ca(l) (cplus) and cb(l) (cminus)
+    auto emit = [&](int l, const ColPair<T> &cplus, const ColPair<T> &cminus) {
+      int ca, cb;
+      pair_ab(t1, l, Mo, ca, cb);
+      const bool lflip = ca > cb;
+      // e[row: 0 = ra, 1 = rb][col: 0 = ca, 1 = cb]
+      Cx<T> e00 = cplus.xp, e10 = cplus.xm, e01 = cminus.xp, e11 = cminus.xm;
+      Cx<T> c11 = sel(kflip, sel(lflip, e11, e10), sel(lflip, e01, e00));
+      Cx<T> c21 = sel(kflip, sel(lflip, e01, e00), sel(lflip, e11, e10));
+      Cx<T> c12 = sel(kflip, sel(lflip, e10, e11), sel(lflip, e00, e01));
+      Cx<T> c22 = sel(kflip, sel(lflip, e00, e01), sel(lflip, e10, e11));
+      if (l == j) {
+        c11 = Cx<T>{u1.sp, T(0)};
+        c22 = Cx<T>{u1.sq, T(0)};
+        c12 = c21 = zero;
+      } else {
+        Rot<T> r = with_v<T, CPLX>(u1, sv1[l - l0]);
+        rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+      }
+      if (out) {
+        const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
+        Mn.st(ra, cp, sel(kflip, c21, c11));
+        Mn.st(rb, cp, sel(kflip, c11, c21));
+        Mn.st(ra, cq, sel(kflip, c22, c12));
+        Mn.st(rb, cq, sel(kflip, c12, c22));
+      }
+    };
+    const int l = jj - 1;
+    if (l >= l0 && l < lend) emit(l, curP, selp(l == 0, prev1Q, prev2m));
+    if (jj == n - 1 && n - 1 >= l0 && n - 1 < lend) emit(n - 1, curQ, selp(n - 1 == 1, prev1P, prev1Q));
+    prev2m = selp(jj - 1 == 0, prev1P, prev1Q);
+    prev1P = curP;
+    prev1Q = curQ;
+  }
 }
 
 template <class T, bool CPLX>
@@ -862,6 +1019,16 @@ TileRule rule_for(int N) {
   return default_rule();
 }
 
+// two-step kernel shapes: kc = wavefronts per workgroup, lc = column pairs per tile
+TileRule default_rule2() { return TileRule{0x7fffffff, 2, 16}; }
+TileRule g_rules2[kMaxRules] = {default_rule2()};
+int g_nrules2 = 1;
+TileRule rule2_for(int N) {
+  for (int i = 0; i < g_nrules2; ++i)
+    if (N <= g_rules2[i].max_order) return g_rules2[i];
+  return default_rule2();
+}
+
 svd2_status hip_st(hipError_t e) {
   if (e == hipSuccess) return SVD2_OK;
   g_kog_hip = (int)e;
@@ -999,10 +1166,13 @@ svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<
                      c.B1);
   s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
-  TileRule r = rule_for(c.N);
-  dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
-  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, cur, nxt, t, c.B,
-                     c.B1, r.kc, r.lc);
+  TileRule r = rule2_for(c.N);
+  const int wpg = r.kc, lc = r.lc;
+  const int waves = (n + kShiftOut - 1) / kShiftOut;
+  dim3 grid((waves + wpg - 1) / wpg, (n + lc - 1) / lc);
+  size_t lds = (size_t)(2 * lc + 2) * sizeof(VPack<T, CPLX>);
+  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), grid, dim3(64 * wpg), lds, c.st, c.N, cur, nxt, t, c.B,
+                     c.B1, wpg, lc);
   return hip_st(hipGetLastError());
 }
 
@@ -1515,6 +1685,23 @@ svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, c
   if (count == 0) {
     g_rules[0] = default_rule();
     g_nrules = 1;
+  }
+  return SVD2_OK;
+}
+
+svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *wpg, const int *lc) {
+  if (count < 0 || count > kMaxRules) return SVD2_ERR_SIZE;
+  if (count > 0 && (!max_order || !wpg || !lc)) return SVD2_ERR_NULL;
+  for (int i = 0; i < count; ++i) {
+    if (wpg[i] != 1 && wpg[i] != 2 && wpg[i] != 4) return SVD2_ERR_SIZE;
+    if (lc[i] < 1 || lc[i] > 256 || max_order[i] < 2) return SVD2_ERR_SIZE;
+    if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
+  }
+  for (int i = 0; i < count; ++i) g_rules2[i] = TileRule{max_order[i], wpg[i], lc[i]};
+  g_nrules2 = count;
+  if (count == 0) {
+    g_rules2[0] = default_rule2();
+    g_nrules2 = 1;
   }
   return SVD2_OK;
 }

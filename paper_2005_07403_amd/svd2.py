@@ -59,7 +59,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
-           "kog_batch_solve", "kog_workspace_bytes_flags",
+           "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -381,6 +381,8 @@ def _batch():
         L.kog_set_tile_rules.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.kog_set_tile_rules.restype = ctypes.c_int
+        L.kog_set_two_step_tiles.argtypes = L.kog_set_tile_rules.argtypes
+        L.kog_set_two_step_tiles.restype = ctypes.c_int
         _batch_ready = True
     return L
 
@@ -390,6 +392,14 @@ def kog_set_tile_rules(rules) -> None:
     n = len(rules)
     arr = lambda i: (ctypes.c_int * max(n, 1))(*[r[i] for r in rules])
     _kog_check("kog_set_tile_rules", _batch().kog_set_tile_rules(n, arr(0), arr(1), arr(2)))
+
+
+def kog_set_two_step_tiles(rules) -> None:
+    """rules: list of (max_order, wavefronts per workgroup, lc) with increasing
+    max_order, for the two-step kernel; [] = default."""
+    n = len(rules)
+    arr = lambda i: (ctypes.c_int * max(n, 1))(*[r[i] for r in rules])
+    _kog_check("kog_set_two_step_tiles", _batch().kog_set_two_step_tiles(n, arr(0), arr(1), arr(2)))
 
 
 def kog_batch_solve(mats, tols, max_sweeps=40, flags: int = 0, ws=None, stream=None) -> list:
