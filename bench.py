@@ -137,36 +137,46 @@ def read_traffic(kernel_key: str):
 
 def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
     """Kogbetliantz on the one-problem workload: real FP64, A = Q1 diag(s) Q2^T
-    with s geometric from 1 to 1e-12.  Sweeps/s of the fused kernel, the
-    unfused gather -> SVD -> update chain and its hipGraph replay, each timed
-    over `sweeps` sweeps from the same matrix; then a full fused solve."""
+    with s geometric from 1 to 1e-12.  Sweeps/s of each driver, timed over
+    `sweeps` sweeps from the same matrix: the fused persistent kernel, the
+    unfused gather -> SVD -> update chain, its hipGraph replay, and two steps
+    per pass over the matrix; then a full solve with the fastest."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     from workloads import SEED_BASE, kog_matrix
     A, s = kog_matrix(order, SEED_BASE + 3, cond=1e12, return_sigma=True)
     G0 = torch.from_numpy(A).cuda()
-    bytes_per_step = 2 * order * order * 8
-    out = {"order": order, "dtype": "f64", "steps_per_sweep": order - 1,
-           "algorithmic_bytes_per_step": bytes_per_step}
-    modes = {"fused": 0, "unfused": S.SVD2_KOG_UNFUSED, "graph": S.SVD2_KOG_UNFUSED | S.SVD2_KOG_GRAPH}
+    mat = order * order * 8
+    steps = order - 1
+    # HBM bytes of the matrix per sweep: one read and one write per step for
+    # the single-step drivers; one per pass of two steps (plus the odd last
+    # step) for the two-step driver
+    passes = (steps - 1) // 2 if steps > 1 else 0
+    hbm_sweep = {"fused": 2 * mat * steps, "unfused": 2 * mat * steps, "graph": 2 * mat * steps,
+                 "two_step": 2 * mat * (passes + (steps - 2 * passes))}
+    out = {"order": order, "dtype": "f64", "steps_per_sweep": steps,
+           "algorithmic_bytes_per_step": 2 * mat}
+    modes = {"fused": 0, "unfused": S.SVD2_KOG_UNFUSED, "graph": S.SVD2_KOG_UNFUSED | S.SVD2_KOG_GRAPH,
+             "two_step": S.SVD2_KOG_TWO_STEP}
     for name, fl in modes.items():
         G = G0.clone(memory_format=torch.preserve_format)
-        ws = S.kog_workspace(G)
+        ws = S.kog_workspace(G, fl)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         S.kog_solve(G, tol=0.0, max_sweeps=sweeps, ws=ws, flags=fl)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[name] = {"sweeps_per_s": sweeps / el, "us_per_step": el / sweeps / (order - 1) * 1e6,
-                     "GBs": bytes_per_step * (order - 1) * sweeps / el / 1e9}
+        out[name] = {"sweeps_per_s": sweeps / el, "us_per_step": el / sweeps / steps * 1e6,
+                     "hbm_GBs": hbm_sweep[name] * sweeps / el / 1e9}
         log(f"[bench] kog {name}: {json.dumps(out[name])}")
         del G, ws
     if solve:
         best = max(modes, key=lambda m: out[m]["sweeps_per_s"])
         G = G0.clone(memory_format=torch.preserve_format)
+        ws = S.kog_workspace(G, modes[best])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = S.kog_solve(G, tol=1e-14, max_sweeps=60, flags=modes[best])
+        r = S.kog_solve(G, tol=1e-14, max_sweeps=60, ws=ws, flags=modes[best])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         sig = np.sort(np.diag(G.cpu().numpy()))[::-1]
@@ -174,6 +184,7 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
                         "off_rel": r["off_rel"], "seconds": el, "sweeps_per_s": r["sweeps"] / el,
                         "sigma_max_abs_err_rel": float(np.max(np.abs(sig - s)) / s[0])}
         log(f"[bench] kog solve: {json.dumps(out['solve'])}")
+        del G, ws
     del G0
     torch.cuda.empty_cache()
     return out

@@ -170,24 +170,25 @@ template <class T> struct Rot {
   T sp, sq;
 };
 
-template <class T, bool CPLX>
-__device__ __forceinline__ Rot<T> load_rot(const Bufs<T, CPLX> &B, int k) {
+// out(e): element e of the SVD record (U, V, sigma); piv(e): of the pivot block
+template <class T, bool CPLX, class FO, class FP>
+__device__ __forceinline__ Rot<T> rot_of(FO out, FP piv) {
   Rot<T> r;
   constexpr int K = CPLX ? 16 : 8;
   auto g = [&](int e) -> Cx<T> {
-    if constexpr (CPLX) return {B.out[2 * e][k], B.out[2 * e + 1][k]};
-    else return {B.out[e][k], T(0)};
+    if constexpr (CPLX) return {out(2 * e), out(2 * e + 1)};
+    else return {out(e), T(0)};
   };
   r.u11 = g(0); r.u21 = g(1); r.u12 = g(2); r.u22 = g(3);
   r.v11 = g(4); r.v21 = g(5); r.v12 = g(6); r.v22 = g(7);
-  r.sp = B.out[K][k];
-  r.sq = B.out[K + 1][k];
+  r.sp = out(K);
+  r.sq = out(K + 1);
   bool sw;
   if constexpr (CPLX) {
-    T pr = B.piv[0][k], pi = B.piv[1][k], qr = B.piv[6][k], qi = B.piv[7][k];
+    T pr = piv(0), pi = piv(1), qr = piv(6), qi = piv(7);
     sw = pr * pr + pi * pi < qr * qr + qi * qi;
   } else {
-    sw = vabs(B.piv[0][k]) < vabs(B.piv[3][k]);
+    sw = vabs(piv(0)) < vabs(piv(3));
   }
   if (sw) {
     Cx<T> t;
@@ -198,6 +199,11 @@ __device__ __forceinline__ Rot<T> load_rot(const Bufs<T, CPLX> &B, int k) {
     T s = r.sp; r.sp = r.sq; r.sq = s;
   }
   return r;
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ Rot<T> load_rot(const Bufs<T, CPLX> &B, int k) {
+  return rot_of<T, CPLX>([&](int e) { return B.out[e][k]; }, [&](int e) { return B.piv[e][k]; });
 }
 
 template <class T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) {
@@ -432,41 +438,6 @@ __device__ __forceinline__ void block_after_step(const Mat<T, CPLX> &M, const Si
   }
 }
 
-// pivots of step t+1 from the matrix before step t, and their 2x2 SVDs
-template <class T, bool CPLX>
-__global__ __launch_bounds__(256) void kog_predict_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
-                                                          Bufs<T, CPLX> B1) {
-  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
-  const int n = N / 2, Mo = N - 1;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int a, b;
-  pair_ab(t + 1, k, Mo, a, b);
-  int p = a < b ? a : b, q = a < b ? b : a;
-  Side S[2] = {side_at(t, p, Mo, n), side_at(t, q, Mo, n)};
-  RotU<T> U[2] = {load_u<T, CPLX>(B0, S[0].k), load_u<T, CPLX>(B0, S[1].k)};
-  RotV<T> V[2] = {load_v<T, CPLX>(B0, S[0].k), load_v<T, CPLX>(B0, S[1].k)};
-  Cx<T> e[2][2];
-  block_after_step<T, CPLX>(M, S, U, S, V, e);
-  // record order 11, 21, 12, 22 = (p,p), (q,p), (p,q), (q,q)
-  Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
-  T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if constexpr (CPLX) {
-      x[2 * i] = rec[i].re;
-      x[2 * i + 1] = rec[i].im;
-    } else {
-      x[i] = rec[i].re;
-    }
-  }
-  one_matrix<T, CPLX, RESC>(x, y, 2);
-#pragma unroll
-  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B1.piv[i][k] = x[i];
-#pragma unroll
-  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B1.out[i][k] = y[i];
-}
-
 // gather + 2x2 SVD of the pivots of step t in one kernel
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_pivot_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B) {
@@ -480,6 +451,77 @@ __global__ __launch_bounds__(256) void kog_pivot_kernel(int N, Mat<T, CPLX> M, i
   for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
 #pragma unroll
   for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
+}
+
+// pivots of steps t and t+1 in one launch: lane k computes the SVD of pair k
+// of step t (into B0) and, for pair k of step t+1, recomputes the step-t SVDs
+// of the two pairs its rows belong to (the same arithmetic on the same
+// inputs, so bitwise the rotations in B0), forms that pivot block after step
+// t and computes its SVD (into B1)
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_pivots2_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
+                                                          Bufs<T, CPLX> B1) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  constexpr int NI = Bufs<T, CPLX>::NIN, NO = Bufs<T, CPLX>::NOUT;
+  const int n = N / 2, Mo = N - 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int a, b;
+  pair_ab(t + 1, k, Mo, a, b);
+  const int p = a < b ? a : b, q = a < b ? b : a;
+  Side S[2] = {side_at(t, p, Mo, n), side_at(t, q, Mo, n)};
+  // every load first (the stores below could alias the matrix as far as the
+  // compiler knows): the three step-t pivot blocks and the 4x4 neighbourhood
+  T x0[NI], x1[NI], x2[NI];
+  gather_one<T, CPLX>(M, N, t, k, x0);
+  gather_one<T, CPLX>(M, N, t, S[0].k, x1);
+  gather_one<T, CPLX>(M, N, t, S[1].k, x2);
+  Cx<T> nb[2][2][2][2];  // [row i][col j][row or partner][col or partner]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      nb[i][j][0][0] = M.ld(S[i].x, S[j].x);
+      nb[i][j][0][1] = M.ld(S[i].x, S[j].partner);
+      nb[i][j][1][0] = M.ld(S[i].partner, S[j].x);
+      nb[i][j][1][1] = M.ld(S[i].partner, S[j].partner);
+    }
+  T y0[NO], y1[NO], y2[NO];
+  one_matrix<T, CPLX, RESC>(x0, y0, 2);
+  one_matrix<T, CPLX, RESC>(x1, y1, 2);
+  one_matrix<T, CPLX, RESC>(x2, y2, 2);
+  Rot<T> r1 = rot_of<T, CPLX>([&](int e) { return y1[e]; }, [&](int e) { return x1[e]; });
+  Rot<T> r2 = rot_of<T, CPLX>([&](int e) { return y2[e]; }, [&](int e) { return x2[e]; });
+  RotU<T> U[2] = {RotU<T>{r1.u11, r1.u21, r1.u12, r1.u22, r1.sp, r1.sq},
+                  RotU<T>{r2.u11, r2.u21, r2.u12, r2.u22, r2.sp, r2.sq}};
+  RotV<T> V[2] = {RotV<T>{r1.v11, r1.v21, r1.v12, r1.v22}, RotV<T>{r2.v11, r2.v21, r2.v12, r2.v22}};
+  Cx<T> e[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      e[i][j] = after_step<T, CPLX>(S[i], U[i], S[j], V[j], nb[i][j][0][0], nb[i][j][0][1], nb[i][j][1][0],
+                                    nb[i][j][1][1]);
+  Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
+  T x3[NI], y3[NO];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x3[2 * i] = rec[i].re;
+      x3[2 * i + 1] = rec[i].im;
+    } else {
+      x3[i] = rec[i].re;
+    }
+  }
+  one_matrix<T, CPLX, RESC>(x3, y3, 2);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) B0.piv[i][k] = x0[i];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) B0.out[i][k] = y0[i];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) B1.piv[i][k] = x3[i];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) B1.out[i][k] = y3[i];
 }
 
 // The two-step update proper ("lane-shift" form).  Lane j of a wavefront
@@ -568,14 +610,25 @@ template <class T> __device__ __forceinline__ ColPair<T> selp(bool c, ColPair<T>
   return ColPair<T>{sel(c, x.xp, y.xp), sel(c, x.xm, y.xm)};
 }
 
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; XCD c takes a contiguous run of the tiles (row
+// tile fastest), so tiles that share halo rows or columns run on the same L2
+// at about the same time.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7, c = bid & 7, k = bid >> 3;
+  return c * q + (c < r ? c : r) + k;
+}
+
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
                                                            Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int wpg,
-                                                           int lc) {
+                                                           int lc, int gx, int ntiles) {
   extern __shared__ __align__(16) char kog_smem[];
   const int n = N / 2, Mo = N - 1, t1 = t + 1;
   const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-  const int l0 = (int)blockIdx.y * lc;
+  const int tile = xcd_tile((int)blockIdx.x, ntiles);
+  const int bx = tile % gx, by = tile / gx;
+  const int l0 = by * lc;
   const int lend = l0 + lc < n ? l0 + lc : n;
   const int jlo = l0 > 0 ? l0 - 1 : 0;
   const int jhi = l0 + lc < n - 1 ? l0 + lc : n - 1;  // inclusive
@@ -585,7 +638,7 @@ __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> M
   for (int i = threadIdx.x; i < lend - l0; i += blockDim.x) sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, l0 + i));
   __syncthreads();
 
-  const int j = ((int)blockIdx.x * wpg + w) * kShiftOut - 1 + lane;
+  const int j = (bx * wpg + w) * kShiftOut - 1 + lane;
   const bool act = j >= 0 && j < n;
   const bool out = act && lane >= 1 && lane <= kShiftOut;
   int P = 0, Q = 0, ra = 0, rb = 0;
@@ -1020,7 +1073,7 @@ TileRule rule_for(int N) {
 }
 
 // two-step kernel shapes: kc = wavefronts per workgroup, lc = column pairs per tile
-TileRule default_rule2() { return TileRule{0x7fffffff, 2, 16}; }
+TileRule default_rule2() { return TileRule{0x7fffffff, 4, 8}; }
 TileRule g_rules2[kMaxRules] = {default_rule2()};
 int g_nrules2 = 1;
 TileRule rule2_for(int N) {
@@ -1159,20 +1212,17 @@ template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int
 template <class T, bool CPLX>
 svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t) {
   const int n = c.N / 2;
-  hipLaunchKernelGGL((kog_pivot_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B);
-  svd2_status s = hip_st(hipGetLastError());
-  if (s != SVD2_OK) return s;
-  hipLaunchKernelGGL((kog_predict_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B,
+  hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, c.B,
                      c.B1);
-  s = hip_st(hipGetLastError());
+  svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   TileRule r = rule2_for(c.N);
   const int wpg = r.kc, lc = r.lc;
   const int waves = (n + kShiftOut - 1) / kShiftOut;
-  dim3 grid((waves + wpg - 1) / wpg, (n + lc - 1) / lc);
+  const int gx = (waves + wpg - 1) / wpg, ntiles = gx * ((n + lc - 1) / lc);
   size_t lds = (size_t)(2 * lc + 2) * sizeof(VPack<T, CPLX>);
-  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), grid, dim3(64 * wpg), lds, c.st, c.N, cur, nxt, t, c.B,
-                     c.B1, wpg, lc);
+  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), dim3(ntiles), dim3(64 * wpg), lds, c.st, c.N, cur, nxt, t,
+                     c.B, c.B1, wpg, lc, gx, ntiles);
   return hip_st(hipGetLastError());
 }
 
