@@ -135,7 +135,7 @@ def read_traffic(kernel_key: str):
     return float(b.group(1))
 
 
-def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
+def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
     """Kogbetliantz on the one-problem workload: real FP64, A = Q1 diag(s) Q2^T
     with s geometric from 1 to 1e-12.  Sweeps/s of each driver, timed over
     `sweeps` sweeps from the same matrix: the fused persistent kernel, the
@@ -158,6 +158,8 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True):
            "algorithmic_bytes_per_step": 2 * mat}
     modes = {"fused": 0, "unfused": S.SVD2_KOG_UNFUSED, "graph": S.SVD2_KOG_UNFUSED | S.SVD2_KOG_GRAPH,
              "two_step": S.SVD2_KOG_TWO_STEP}
+    if only:
+        modes = {m: modes[m] for m in only}
     for name, fl in modes.items():
         G = G0.clone(memory_format=torch.preserve_format)
         ws = S.kog_workspace(G, fl)
@@ -259,6 +261,9 @@ def main():
     ap.add_argument("--kog-order", type=int, default=4096)
     ap.add_argument("--no-kog-batch", action="store_true", help="skip the uneven Kogbetliantz batch")
     ap.add_argument("--kog-batch", type=int, default=256, help="problems in the uneven batch")
+    ap.add_argument("--kog-only", default=None, metavar="MODES",
+                    help="run only the Kogbetliantz drivers named (comma list of fused, unfused, graph, "
+                         "two_step), one sweep each, no solve; prints their JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -287,6 +292,11 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 1 GiB done")
+        return
+
+    if args.kog_only:
+        out = kog_bench(args.kog_order, sweeps=1, solve=False, only=args.kog_only.split(","))
+        print(json.dumps(out), flush=True)
         return
 
     variants = [args.only] if args.only else ["z", "d", "s", "c"]
