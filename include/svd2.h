@@ -305,9 +305,11 @@ svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, c
 
 /* Workgroup shapes of the two-step kernel (SVD2_KOG_TWO_STEP), by order: the
  * first rule with N <= max_order[i] applies.  wpg[i] in {1, 2, 4} wavefronts
- * per workgroup (each writes 62 row pairs of step t+1), lc[i] in [1, 256]
- * column pairs per tile.  count = 0 restores the default (4, 8).  Host
- * state, not thread-safe against concurrent launches. */
+ * per workgroup; all of them share one block of 62 row pairs.  lc[i] in
+ * [2, 64] fixes the column pairs each wavefront writes; lc[i] in [-3, 0]
+ * sizes the column split so that the grid fills 1 - lc[i] whole rounds of
+ * the workgroups the GPU holds at once.  count = 0 restores the default
+ * (4, 8).  Host state, not thread-safe against concurrent launches. */
 svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *wpg, const int *lc);
 
 #ifdef __cplusplus

@@ -526,17 +526,22 @@ __global__ __launch_bounds__(256) void kog_pivots2_kernel(int N, Mat<T, CPLX> M,
 
 // The two-step update proper ("lane-shift" form).  Lane j of a wavefront
 // holds the rows of pair j of step t (P_j = t + j and Q_j = t - j mod N-1;
-// pair 0 is rows t and N-1) and walks the column pairs j' of step t in
-// increasing order: it reads each 2x2 block (P_j, Q_j) x (P_j', Q_j') once and
-// rotates it with U_j, V_j' as the single-step update would.  Pair k of step
-// t+1 is made of rows P_{k+1} and Q_{k-1} (k = 0: P_1 and N-1; k = 1: P_2 and
-// t = P_0; k = n-1: Q_{n-1} and Q_{n-2}), held one lane down and one lane up:
-// they are exchanged with lane shuffles.  Its column pair l is made of the
-// columns of iterations l+1 and l-1 of the walk (same exceptions), kept in a
-// three-deep register window.  A wavefront computes 64 pairs of step t and
-// writes the 62 pairs of step t+1 it holds both neighbours for; a workgroup
-// of `wpg` wavefronts shares one column tile of `lc` pairs, walked over
-// [l0 - 1, l0 + lc], with the V rotations of both steps staged in LDS.
+// pair 0 is rows t and N-1) and walks column pairs j' of step t in increasing
+// order: it reads each 2x2 block (P_j, Q_j) x (P_j', Q_j') once and rotates it
+// with U_j, V_j' as the single-step update would.  Pair k of step t+1 is made
+// of rows P_{k+1} and Q_{k-1} (k = 0: P_1 and N-1; k = 1: P_2 and t = P_0;
+// k = n-1: Q_{n-1} and Q_{n-2}), held one lane down and one lane up: they are
+// exchanged with lane shuffles.  Its column pair l is made of the columns of
+// iterations l+1 and l-1 of the walk (same exceptions), kept in a three-deep
+// register window.  A wavefront computes 64 pairs of step t and writes the 62
+// pairs of step t+1 it holds both neighbours for.
+//
+// The wavefronts of a workgroup share one block of rows and take consecutive
+// runs of lc output column pairs.  A wavefront's first output needs a column
+// of the wavefront before it and its last output one of the wavefront after
+// it: each publishes its first and last walked columns in LDS, and those two
+// outputs are written after a barrier.  Only the workgroup's outer edges read
+// a column pair outside their own outputs.
 constexpr int kShiftOut = 62;
 
 // value select (a ternary on lvalues would select addresses and spill)
@@ -601,13 +606,13 @@ template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_up1(Cx<T> x)
   return r;
 }
 
-// one column of the walk after the row exchange: the entries of rows
-// ra(k) (xp) and rb(k) (xm) of step t+1's pair k = j
+// one column of the walk after the row exchange: the entries of the two rows
+// of step t+1's pair k = j, smaller row index first
 template <class T> struct ColPair {
-  Cx<T> xp, xm;
+  Cx<T> lo, hi;
 };
 template <class T> __device__ __forceinline__ ColPair<T> selp(bool c, ColPair<T> x, ColPair<T> y) {
-  return ColPair<T>{sel(c, x.xp, y.xp), sel(c, x.xm, y.xm)};
+  return ColPair<T>{sel(c, x.lo, y.lo), sel(c, x.hi, y.hi)};
 }
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
@@ -619,29 +624,47 @@ __device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
   return c * q + (c < r ? c : r) + k;
 }
 
+// LDS bytes of the two-step kernel: a workgroup of wpg wavefronts writes
+// span output column pairs
+template <class T, bool CPLX> constexpr size_t two_step_lds(int wpg, int span) {
+  return (size_t)(2 * span + 2) * sizeof(VPack<T, CPLX>) + (size_t)2 * wpg * 64 * sizeof(ColPair<T>);
+}
+
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
                                                            Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int wpg,
-                                                           int lc, int gx, int ntiles) {
+                                                           int span, int lc, int gx, int ntiles) {
   extern __shared__ __align__(16) char kog_smem[];
   const int n = N / 2, Mo = N - 1, t1 = t + 1;
-  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wavefront-uniform
   const int tile = xcd_tile((int)blockIdx.x, ntiles);
   const int bx = tile % gx, by = tile / gx;
-  const int l0 = by * lc;
-  const int lend = l0 + lc < n ? l0 + lc : n;
-  const int jlo = l0 > 0 ? l0 - 1 : 0;
-  const int jhi = l0 + lc < n - 1 ? l0 + lc : n - 1;  // inclusive
-  VPack<T, CPLX> *sv = (VPack<T, CPLX> *)kog_smem;     // V of step t, index j' - jlo
-  VPack<T, CPLX> *sv1 = sv + (lc + 2);                // V of step t+1, index l - l0
+  const int L0 = by * span;                              // outputs of the workgroup: [L0, Lend)
+  const int Lend = L0 + span < n ? L0 + span : n;
+  const int jlo = L0 > 0 ? L0 - 1 : 0;                   // pairs walked by the workgroup: [jlo, jhi]
+  const int jhi = L0 + span < n - 1 ? L0 + span : n - 1;
+  VPack<T, CPLX> *sv = (VPack<T, CPLX> *)kog_smem;      // V of step t, index j' - jlo
+  VPack<T, CPLX> *sv1 = sv + (span + 2);                // V of step t+1, index l - L0
+  ColPair<T> *xhead = (ColPair<T> *)(sv1 + span);       // [wavefront][lane]: first walked P column
+  ColPair<T> *xtail = xhead + wpg * 64;                 // [wavefront][lane]: last own Q column
   for (int i = threadIdx.x; i <= jhi - jlo; i += blockDim.x) sv[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B0, jlo + i));
-  for (int i = threadIdx.x; i < lend - l0; i += blockDim.x) sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, l0 + i));
+  for (int i = threadIdx.x; i < Lend - L0; i += blockDim.x) sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, L0 + i));
   __syncthreads();
 
-  const int j = (bx * wpg + w) * kShiftOut - 1 + lane;
+  // this wavefront: outputs [l0w, oend), walk [aw, bw] (lc >= 2; the last
+  // wavefronts of a workgroup may have fewer outputs or none)
+  const int l0w = L0 + w * lc;
+  const int oend = l0w + lc < Lend ? l0w + lc : Lend;
+  const bool has = l0w < oend;
+  const bool next_has = w + 1 < wpg && l0w + lc < Lend;
+  const int aw = w == 0 ? jlo : l0w;
+  const int bw = next_has ? l0w + lc - 1 : (l0w + lc < n - 1 ? l0w + lc : n - 1);
+
+  const int j = bx * kShiftOut - 1 + lane;
   const bool act = j >= 0 && j < n;
   const bool out = act && lane >= 1 && lane <= kShiftOut;
-  int P = 0, Q = 0, ra = 0, rb = 0;
+  int P = 0, Q = 1, ra = 0, rb = 0;
   RotU<T> u{}, u1{};
   if (act) {
     rows_at(t, j, Mo, P, Q);
@@ -652,95 +675,108 @@ __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> M
     u1 = load_u<T, CPLX>(B1, j);
   }
   const bool rflip = P > Q, kflip = ra > rb;
+  const int rp = rflip ? Q : P, rq = rflip ? P : Q;        // rows of step t's pair j in (p, q) order
+  const int op = kflip ? rb : ra, oq = kflip ? ra : rb;     // rows of step t+1's pair j in (p, q) order
+  // the smaller output row takes the value from one lane up (rb) when kflip,
+  // else from one lane down (ra); the own-row exceptions of k = 0 and k = n-1
+  const bool lo_own = kflip ? j == 0 : j == n - 1, hi_own = kflip ? j == n - 1 : j == 0;
   const Cx<T> zero{T(0), T(0)};
 
-  // the block (P, Q) x (Pc, Qc) of one iteration, as loaded
+  // column pair l of step t+1 from its columns ca(l) (cplus) and cb(l) (cminus)
+  auto emit = [&](int l, const ColPair<T> &cplus, const ColPair<T> &cminus) {
+    int ca, cb;
+    pair_ab(t1, l, Mo, ca, cb);
+    const bool lflip = ca > cb;
+    const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
+    Cx<T> c11 = sel(lflip, cminus.lo, cplus.lo), c21 = sel(lflip, cminus.hi, cplus.hi);
+    Cx<T> c12 = sel(lflip, cplus.lo, cminus.lo), c22 = sel(lflip, cplus.hi, cminus.hi);
+    if (l == j) {
+      c11 = Cx<T>{u1.sp, T(0)};
+      c22 = Cx<T>{u1.sq, T(0)};
+      c12 = c21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u1, sv1[l - L0]);
+      rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+    }
+    if (out) {
+      Mn.st(op, cp, c11);
+      Mn.st(oq, cp, c21);
+      Mn.st(op, cq, c12);
+      Mn.st(oq, cq, c22);
+    }
+  };
+
+  // the block (rp, rq) x (cp, cq) of one iteration, as loaded
   struct Blk {
-    Cx<T> pp, qp, pq, qq;
+    Cx<T> b11, b21, b12, b22;
   };
   auto load_blk = [&](int jj) -> Blk {
     int Pc, Qc;
     rows_at(t, jj, Mo, Pc, Qc);
+    const int cp = Pc < Qc ? Pc : Qc, cq = Pc < Qc ? Qc : Pc;
     Blk d{zero, zero, zero, zero};
     if (act) {
-      d.pp = Mc.ld(P, Pc);
-      d.qp = Mc.ld(Q, Pc);
-      d.pq = Mc.ld(P, Qc);
-      d.qq = Mc.ld(Q, Qc);
+      d.b11 = Mc.ld(rp, cp);
+      d.b21 = Mc.ld(rq, cp);
+      d.b12 = Mc.ld(rp, cq);
+      d.b22 = Mc.ld(rq, cq);
     }
     return d;
   };
-  Blk nx = load_blk(jlo);
-  ColPair<T> prev1P{zero, zero}, prev1Q{zero, zero}, prev2m{zero, zero};
-  for (int jj = jlo; jj <= jhi; ++jj) {
-    const Blk a = nx;
-    if (jj < jhi) nx = load_blk(jj + 1);
-    // step t on the block (j, jj), in P/Q labels
-    int Pc, Qc;
-    rows_at(t, jj, Mo, Pc, Qc);
-    const bool cflip = Pc > Qc;
-    Cx<T> b11 = sel(rflip, sel(cflip, a.qq, a.qp), sel(cflip, a.pq, a.pp));
-    Cx<T> b21 = sel(rflip, sel(cflip, a.pq, a.pp), sel(cflip, a.qq, a.qp));
-    Cx<T> b12 = sel(rflip, sel(cflip, a.qp, a.qq), sel(cflip, a.pp, a.pq));
-    Cx<T> b22 = sel(rflip, sel(cflip, a.pp, a.pq), sel(cflip, a.qp, a.qq));
-    if (j == jj) {
-      b11 = Cx<T>{u.sp, T(0)};
-      b22 = Cx<T>{u.sq, T(0)};
-      b12 = b21 = zero;
-    } else {
-      Rot<T> r = with_v<T, CPLX>(u, sv[jj - jlo]);
-      rotate_block<T, CPLX>(r, r, b11, b21, b12, b22);
-    }
-    const Cx<T> ePP = sel(rflip, sel(cflip, b22, b21), sel(cflip, b12, b11));
-    const Cx<T> eQP = sel(rflip, sel(cflip, b12, b11), sel(cflip, b22, b21));
-    const Cx<T> ePQ = sel(rflip, sel(cflip, b21, b22), sel(cflip, b11, b12));
-    const Cx<T> eQQ = sel(rflip, sel(cflip, b11, b12), sel(cflip, b21, b22));
-    // row exchange: ra(k) = P_{k+1} (one lane down) or Q_{n-1} (own, k = n-1);
-    // rb(k) = Q_{k-1} (one lane up), P_0 (k = 1) or N-1 = Q_0 (own, k = 0)
-    ColPair<T> curP, curQ;
-    {
-      Cx<T> dn = shfl_dn1<T, CPLX>(ePP), up = shfl_up1<T, CPLX>(sel(j == 0, ePP, eQP));
-      curP.xp = sel(j == n - 1, eQP, dn);
-      curP.xm = sel(j == 0, eQP, up);
-      dn = shfl_dn1<T, CPLX>(ePQ);
-      up = shfl_up1<T, CPLX>(sel(j == 0, ePQ, eQQ));
-      curQ.xp = sel(j == n - 1, eQQ, dn);
-      curQ.xm = sel(j == 0, eQQ, up);
-    }
-    // emit column pair l of step t+1: columns ca(l) (cplus) and cb(l) (cminus)
-    auto emit = [&](int l, const ColPair<T> &cplus, const ColPair<T> &cminus) {
-      int ca, cb;
-      pair_ab(t1, l, Mo, ca, cb);
-      const bool lflip = ca > cb;
-      // e[row: 0 = ra, 1 = rb][col: 0 = ca, 1 = cb]
-      Cx<T> e00 = cplus.xp, e10 = cplus.xm, e01 = cminus.xp, e11 = cminus.xm;
-      Cx<T> c11 = sel(kflip, sel(lflip, e11, e10), sel(lflip, e01, e00));
-      Cx<T> c21 = sel(kflip, sel(lflip, e01, e00), sel(lflip, e11, e10));
-      Cx<T> c12 = sel(kflip, sel(lflip, e10, e11), sel(lflip, e00, e01));
-      Cx<T> c22 = sel(kflip, sel(lflip, e00, e01), sel(lflip, e10, e11));
-      if (l == j) {
-        c11 = Cx<T>{u1.sp, T(0)};
-        c22 = Cx<T>{u1.sq, T(0)};
-        c12 = c21 = zero;
+  ColPair<T> prev1P{zero, zero}, prev1Q{zero, zero}, prev2m{zero, zero}, firstc{zero, zero};
+  if (has) {
+    Blk nx = load_blk(aw);  // the block of the next iteration is in flight
+    for (int jj = aw; jj <= bw; ++jj) {
+      const Blk a = nx;
+      if (jj < bw) nx = load_blk(jj + 1);
+      // step t on the block (j, jj), in (p, q) order
+      int Pc, Qc;
+      rows_at(t, jj, Mo, Pc, Qc);
+      const bool cflip = Pc > Qc;
+      Cx<T> b11 = a.b11, b21 = a.b21, b12 = a.b12, b22 = a.b22;
+      if (j == jj) {
+        b11 = Cx<T>{u.sp, T(0)};
+        b22 = Cx<T>{u.sq, T(0)};
+        b12 = b21 = zero;
       } else {
-        Rot<T> r = with_v<T, CPLX>(u1, sv1[l - l0]);
-        rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+        Rot<T> r = with_v<T, CPLX>(u, sv[jj - jlo]);
+        rotate_block<T, CPLX>(r, r, b11, b21, b12, b22);
       }
-      if (out) {
-        const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
-        Mn.st(ra, cp, sel(kflip, c21, c11));
-        Mn.st(rb, cp, sel(kflip, c11, c21));
-        Mn.st(ra, cq, sel(kflip, c22, c12));
-        Mn.st(rb, cq, sel(kflip, c12, c22));
+      // to P/Q labels
+      const Cx<T> ePP = sel(rflip, sel(cflip, b22, b21), sel(cflip, b12, b11));
+      const Cx<T> eQP = sel(rflip, sel(cflip, b12, b11), sel(cflip, b22, b21));
+      const Cx<T> ePQ = sel(rflip, sel(cflip, b21, b22), sel(cflip, b11, b12));
+      const Cx<T> eQQ = sel(rflip, sel(cflip, b11, b12), sel(cflip, b21, b22));
+      // row exchange: ra(k) = P_{k+1} (one lane down) or Q_{n-1} (own, k = n-1);
+      // rb(k) = Q_{k-1} (one lane up), P_0 (k = 1) or N-1 = Q_0 (own, k = 0)
+      ColPair<T> curP, curQ;
+      {
+        Cx<T> dn = shfl_dn1<T, CPLX>(ePP), up = shfl_up1<T, CPLX>(sel(j == 0, ePP, eQP));
+        curP.lo = sel(lo_own, eQP, sel(kflip, up, dn));
+        curP.hi = sel(hi_own, eQP, sel(kflip, dn, up));
+        dn = shfl_dn1<T, CPLX>(ePQ);
+        up = shfl_up1<T, CPLX>(sel(j == 0, ePQ, eQQ));
+        curQ.lo = sel(lo_own, eQQ, sel(kflip, up, dn));
+        curQ.hi = sel(hi_own, eQQ, sel(kflip, dn, up));
       }
-    };
-    const int l = jj - 1;
-    if (l >= l0 && l < lend) emit(l, curP, selp(l == 0, prev1Q, prev2m));
-    if (jj == n - 1 && n - 1 >= l0 && n - 1 < lend) emit(n - 1, curQ, selp(n - 1 == 1, prev1P, prev1Q));
-    prev2m = selp(jj - 1 == 0, prev1P, prev1Q);
-    prev1P = curP;
-    prev1Q = curQ;
+      if (jj == l0w && w > 0) {
+        xhead[w * 64 + lane] = curP;
+        if (l0w == n - 1) firstc = curQ;
+      }
+      if (jj == l0w + 1) firstc = curP;
+      if (next_has && jj == l0w + lc - 1) xtail[w * 64 + lane] = curQ;
+      const int l = jj - 1;
+      if (l >= l0w && l < oend && (l == 0 || l - 1 >= aw)) emit(l, curP, selp(l == 0, prev1Q, prev2m));
+      if (jj == n - 1 && n - 1 >= l0w && n - 1 < oend && n - 2 >= aw)
+        emit(n - 1, curQ, selp(n - 1 == 1, prev1P, prev1Q));
+      prev2m = selp(jj - 1 == 0, prev1P, prev1Q);
+      prev1P = curP;
+      prev1Q = curQ;
+    }
   }
+  __syncthreads();
+  if (has && w > 0) emit(l0w, firstc, xtail[(w - 1) * 64 + lane]);
+  if (has && next_has) emit(l0w + lc - 1, xhead[(w + 1) * 64 + lane], prev2m);
 }
 
 template <class T, bool CPLX>
@@ -1208,6 +1244,60 @@ template <class T, bool CPLX> svd2_status fused_steps(const Ctx<T, CPLX> &c, int
                                            dim3(kUpdBlock), args, 0, c.st));
 }
 
+// Launch shape of the two-step kernel for order N.  With a fixed rule (lc > 0)
+// each wavefront writes lc column pairs.  With lc <= 0 the column pairs are
+// split so that the grid fills 1 - lc whole rounds of the workgroups the GPU
+// holds at once (occupancy x CUs): all workgroups do the same work, so a
+// partly filled last round would cost a whole round.
+struct TwoStepShape {
+  int wpg, span, lc, gx, ntiles;
+  size_t lds;
+};
+template <class T, bool CPLX> TwoStepShape two_step_shape(int N) {
+  static int cached_N = 0, cached_wpg = 0, cached_lc = 0;
+  static TwoStepShape cached{};
+  const TileRule r = rule2_for(N);
+  if (N == cached_N && r.kc == cached_wpg && r.lc == cached_lc) return cached;
+  TwoStepShape sh{};
+  const int n = N / 2, wpg = r.kc;
+  sh.wpg = wpg;
+  sh.gx = (n + kShiftOut - 1) / kShiftOut;
+  auto fix = [&](int span) {
+    int lc = (span + wpg - 1) / wpg;
+    lc = lc < 2 ? 2 : (lc > 64 ? 64 : lc);
+    sh.lc = lc;
+    sh.span = span < wpg * lc ? span : wpg * lc;
+    if (sh.span < 2) sh.span = 2;
+    sh.lds = two_step_lds<T, CPLX>(wpg, sh.span);
+  };
+  if (r.lc > 0) {
+    fix(wpg * r.lc);
+  } else {
+    const int rounds = 1 - r.lc;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return sh;
+    fix(64 * wpg);  // the largest tile first, then refine with the occupancy it allows
+    for (int it = 0; it < 3; ++it) {
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kog_two_step_kernel<T, CPLX>, 64 * wpg,
+                                                       sh.lds) != hipSuccess || per < 1)
+        return sh;
+      const long cap = (long)per * cus * rounds;
+      long tc = cap / sh.gx;
+      if (tc < 1) tc = 1;
+      fix((int)((n + tc - 1) / tc));
+    }
+  }
+  sh.ntiles = sh.gx * ((n + sh.span - 1) / sh.span);
+  cached_N = N;
+  cached_wpg = r.kc;
+  cached_lc = r.lc;
+  cached = sh;
+  return sh;
+}
+
 // two steps t, t+1 from `cur` into `nxt`
 template <class T, bool CPLX>
 svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t) {
@@ -1216,13 +1306,10 @@ svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<
                      c.B1);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
-  TileRule r = rule2_for(c.N);
-  const int wpg = r.kc, lc = r.lc;
-  const int waves = (n + kShiftOut - 1) / kShiftOut;
-  const int gx = (waves + wpg - 1) / wpg, ntiles = gx * ((n + lc - 1) / lc);
-  size_t lds = (size_t)(2 * lc + 2) * sizeof(VPack<T, CPLX>);
-  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), dim3(ntiles), dim3(64 * wpg), lds, c.st, c.N, cur, nxt, t,
-                     c.B, c.B1, wpg, lc, gx, ntiles);
+  const TwoStepShape sh = two_step_shape<T, CPLX>(c.N);
+  if (sh.ntiles <= 0) return SVD2_ERR_HIP;
+  hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), dim3(sh.ntiles), dim3(64 * sh.wpg), sh.lds, c.st, c.N, cur,
+                     nxt, t, c.B, c.B1, sh.wpg, sh.span, sh.lc, sh.gx, sh.ntiles);
   return hip_st(hipGetLastError());
 }
 
@@ -1744,7 +1831,7 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
   if (count > 0 && (!max_order || !wpg || !lc)) return SVD2_ERR_NULL;
   for (int i = 0; i < count; ++i) {
     if (wpg[i] != 1 && wpg[i] != 2 && wpg[i] != 4) return SVD2_ERR_SIZE;
-    if (lc[i] < 1 || lc[i] > 256 || max_order[i] < 2) return SVD2_ERR_SIZE;
+    if (lc[i] < -3 || lc[i] == 1 || lc[i] > 64 || max_order[i] < 2) return SVD2_ERR_SIZE;
     if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
   }
   for (int i = 0; i < count; ++i) g_rules2[i] = TileRule{max_order[i], wpg[i], lc[i]};

@@ -179,3 +179,20 @@ def test_kog_batch_argument_errors():
     assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 3        # matrix inside the workspace
     assert S.lib().kog_set_tile_rules(1, (ctypes.c_int * 1)(100), (ctypes.c_int * 1)(100),
                                       (ctypes.c_int * 1)(8)) == 6  # kc must be 64/128/256
+
+
+def test_kog_two_step_tile_rules():
+    """Shape table of the two-step kernel: wavefronts per workgroup in {1, 2,
+    4}; lc in [2, 64] (fixed) or [-3, 0] (fill whole rounds)."""
+    import ctypes
+    L = S.lib()
+    one = lambda x: (ctypes.c_int * 1)(x)
+    assert L.kog_set_two_step_tiles(1, one(1 << 20), one(3), one(8)) == 6
+    assert L.kog_set_two_step_tiles(1, one(1 << 20), one(4), one(1)) == 6
+    assert L.kog_set_two_step_tiles(1, one(1 << 20), one(4), one(65)) == 6
+    assert L.kog_set_two_step_tiles(1, one(1 << 20), one(4), one(-4)) == 6
+    assert L.kog_set_two_step_tiles(1, one(1 << 20), one(4), one(0)) == 0
+    assert L.kog_set_two_step_tiles(2, (ctypes.c_int * 2)(64, 32), (ctypes.c_int * 2)(4, 4),
+                                    (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
+    assert L.kog_set_two_step_tiles(1, None, None, None) == 1
+    assert L.kog_set_two_step_tiles(0, None, None, None) == 0      # back to the default
