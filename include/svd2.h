@@ -268,8 +268,14 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
  * sweep length N_p - 1; a converged problem stops.  The host checks one
  * counter every 64 steps and compacts the work lists as problems finish.
  * With SVD2_KOG_GRAPH the 64 steps are captured once into a hipGraph and
- * replayed.  Synchronises the stream; returns SVD2_OK if every problem
- * converged, SVD2_NOT_CONVERGED otherwise (see each problem's status).
+ * replayed.  With SVD2_KOG_TWO_STEP each pass takes every running problem
+ * two steps further (the single-problem two-step mode: pivots of both
+ * steps, then one out-of-place pass over the matrix), except the last step
+ * of each sweep, which stays a single in-place step; every problem gets a
+ * second matrix in the workspace, and results end in the caller's matrices,
+ * bitwise equal to single steps.  Synchronises the stream; returns SVD2_OK if
+ * every problem converged, SVD2_NOT_CONVERGED otherwise (see each problem's
+ * status).
  * ------------------------------------------------------------------------- */
 typedef struct {
   int dtype;      /* in: SVD2_KOG_F64, _C128, _F32 or _C64                       */
@@ -283,10 +289,15 @@ typedef struct {
   double off_rel; /* out: off(A) / ||A_0||_F at the last check                   */
 } kog_problem;
 
-/* Device workspace for kog_batch_solve (0 on invalid descriptors). */
+/* Device workspace for kog_batch_solve without SVD2_KOG_TWO_STEP (0 on
+   invalid descriptors). */
 size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs);
+/* the same for the given flags (SVD2_KOG_TWO_STEP adds a second rotation set
+   and an N^2 matrix per problem) */
+size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsigned flags);
 /* probs: host array, read and updated.  Matrices must not overlap each other
-   or the workspace (the latter is checked).  flags: 0 or SVD2_KOG_GRAPH. */
+   or the workspace (the latter is checked).  flags: SVD2_KOG_GRAPH and/or
+   SVD2_KOG_TWO_STEP. */
 svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
                             hipStream_t stream);
 

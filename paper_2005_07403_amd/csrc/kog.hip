@@ -459,13 +459,11 @@ __global__ __launch_bounds__(256) void kog_pivot_kernel(int N, Mat<T, CPLX> M, i
 // inputs, so bitwise the rotations in B0), forms that pivot block after step
 // t and computes its SVD (into B1)
 template <class T, bool CPLX>
-__global__ __launch_bounds__(256) void kog_pivots2_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
-                                                          Bufs<T, CPLX> B1) {
+__device__ __forceinline__ void pivots2_one(int N, const Mat<T, CPLX> &M, int t, const Bufs<T, CPLX> &B0,
+                                            const Bufs<T, CPLX> &B1, int k) {
   constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
   constexpr int NI = Bufs<T, CPLX>::NIN, NO = Bufs<T, CPLX>::NOUT;
   const int n = N / 2, Mo = N - 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
   int a, b;
   pair_ab(t + 1, k, Mo, a, b);
   const int p = a < b ? a : b, q = a < b ? b : a;
@@ -522,6 +520,13 @@ __global__ __launch_bounds__(256) void kog_pivots2_kernel(int N, Mat<T, CPLX> M,
   for (int i = 0; i < NI; ++i) B1.piv[i][k] = x3[i];
 #pragma unroll
   for (int i = 0; i < NO; ++i) B1.out[i][k] = y3[i];
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_pivots2_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
+                                                          Bufs<T, CPLX> B1) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N / 2) pivots2_one<T, CPLX>(N, M, t, B0, B1, k);
 }
 
 // The two-step update proper ("lane-shift" form).  Lane j of a wavefront
@@ -630,16 +635,15 @@ template <class T, bool CPLX> constexpr size_t two_step_lds(int wpg, int span) {
   return (size_t)(2 * span + 2) * sizeof(VPack<T, CPLX>) + (size_t)2 * wpg * 64 * sizeof(ColPair<T>);
 }
 
+// one tile: row block bx (62 row pairs), column tile by (span column pairs);
+// all threads of the workgroup call it (it synchronises the workgroup)
 template <class T, bool CPLX>
-__global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
-                                                           Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int wpg,
-                                                           int span, int lc, int gx, int ntiles) {
-  extern __shared__ __align__(16) char kog_smem[];
+__device__ __forceinline__ void two_step_tile(char *kog_smem, int N, const Mat<T, CPLX> &Mc,
+                                              const Mat<T, CPLX> &Mn, int t, const Bufs<T, CPLX> &B0,
+                                              const Bufs<T, CPLX> &B1, int wpg, int span, int lc, int bx, int by) {
   const int n = N / 2, Mo = N - 1, t1 = t + 1;
   const int lane = (int)threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wavefront-uniform
-  const int tile = xcd_tile((int)blockIdx.x, ntiles);
-  const int bx = tile % gx, by = tile / gx;
   const int L0 = by * span;                              // outputs of the workgroup: [L0, Lend)
   const int Lend = L0 + span < n ? L0 + span : n;
   const int jlo = L0 > 0 ? L0 - 1 : 0;                   // pairs walked by the workgroup: [jlo, jhi]
@@ -777,6 +781,15 @@ __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> M
   __syncthreads();
   if (has && w > 0) emit(l0w, firstc, xtail[(w - 1) * 64 + lane]);
   if (has && next_has) emit(l0w + lc - 1, xhead[(w + 1) * 64 + lane], prev2m);
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
+                                                           Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int wpg,
+                                                           int span, int lc, int gx, int ntiles) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int tile = xcd_tile((int)blockIdx.x, ntiles);
+  two_step_tile<T, CPLX>(kog_smem, N, Mc, Mn, t, B0, B1, wpg, span, lc, tile % gx, tile / gx);
 }
 
 template <class T, bool CPLX>
@@ -935,35 +948,57 @@ __global__ __launch_bounds__(256) void kog_norm_final_kernel(int nparts, const d
 // it wrote), and a per-problem finish (advance the step, and at the end of a
 // problem's sweep decide convergence on the device).  The host replays a
 // hipGraph of K such steps and reads one counter per replay.
+//
+// In the two-step mode a pass takes every running problem two steps further
+// (pivots of both steps, then the two-step tiles, out of place between the
+// problem's matrix and a second one in the workspace), except the last step
+// of a sweep (t = N-2; a sweep has an odd number of steps), which is a single
+// in-place step with the convergence test as above.  The work list holds the
+// tiles of both kinds; a tile of the kind a problem does not need in this
+// pass returns at once.
 // ---------------------------------------------------------------------------
 struct DevProb {
   void *A;
   long long lda, piv_off, out_off;  // buffer offsets in bytes from the workspace base
+  long long piv1_off, out1_off;     // second rotation set (two-step mode)
+  long long w_off;                  // second matrix (two-step mode), lda = N
   int N, kind, kc, lc;
-  int part_off, ntiles, max_sweeps, pad0;
+  int part_off, ntiles, max_sweeps, in_w;  // in_w: the iterate is in the second matrix
+  int gx2, ny2, lc2, pad0;          // two-step tiles: row blocks, column tiles, pairs per wavefront
   double tol, tot0;                 // tot0 = ||A_0||_F
   int t, sweeps, status, pad1;      // status: 0 running, 1 converged, 2 max_sweeps reached
   double off_rel;
 };
 struct BatchHdr {
   int nA, nB, nprob, active;
+  int c0[5];  // two-step tiles of element type k: items [c0[k], c0[k+1])
+  int pad[3];
 };
 
 __host__ __device__ inline size_t arr_bytes(int N, int esz) {
   return (((size_t)(N / 2) * esz) + 255) & ~size_t(255);
 }
 
-template <class T, bool CPLX> __device__ __forceinline__ Bufs<T, CPLX> bufs_of(char *ws, const DevProb &P) {
+template <class T, bool CPLX>
+__device__ __forceinline__ Bufs<T, CPLX> bufs_of(char *ws, const DevProb &P, int set = 0) {
   Bufs<T, CPLX> b;
   size_t arr = arr_bytes(P.N, sizeof(T));
-  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(ws + P.piv_off + i * arr);
-  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(ws + P.out_off + i * arr);
+  const long long po = set ? P.piv1_off : P.piv_off, oo = set ? P.out1_off : P.out_off;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(ws + po + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(ws + oo + i * arr);
   return b;
+}
+
+// the matrix that holds the iterate (other = false) or the other one
+template <class T, bool CPLX>
+__device__ __forceinline__ Mat<T, CPLX> mat_of(char *ws, const DevProb &P, bool other = false) {
+  if (P.in_w != (other ? 1 : 0)) return Mat<T, CPLX>{(T *)(ws + P.w_off), (size_t)P.N};
+  return Mat<T, CPLX>{(T *)P.A, (size_t)P.lda};
 }
 
 template <class T, bool CPLX> __device__ __forceinline__ void batch_pivot(char *ws, const DevProb &P, int k) {
   constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
-  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  Mat<T, CPLX> M = mat_of<T, CPLX>(ws, P);
   Bufs<T, CPLX> B = bufs_of<T, CPLX>(ws, P);
   T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
   gather_one<T, CPLX>(M, P.N, P.t, k, x);
@@ -974,9 +1009,20 @@ template <class T, bool CPLX> __device__ __forceinline__ void batch_pivot(char *
   for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
 }
 
+template <class T, bool CPLX> __device__ __forceinline__ void batch_pivots2(char *ws, const DevProb &P, int k) {
+  pivots2_one<T, CPLX>(P.N, mat_of<T, CPLX>(ws, P), P.t, bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1),
+                       k);
+}
+
 template <class T, bool CPLX> __device__ __forceinline__ double batch_update(char *ws, const DevProb &P, Tile tl) {
-  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
-  return update_tile<T, CPLX, true>(M, P.N, P.t, bufs_of<T, CPLX>(ws, P), tl);
+  return update_tile<T, CPLX, true>(mat_of<T, CPLX>(ws, P), P.N, P.t, bufs_of<T, CPLX>(ws, P), tl);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ void batch_two_step(char *smem, char *ws, const DevProb &P, int bx, int by) {
+  two_step_tile<T, CPLX>(smem, P.N, mat_of<T, CPLX>(ws, P), mat_of<T, CPLX>(ws, P, true), P.t,
+                         bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1), kUpdBlock / 64,
+                         (kUpdBlock / 64) * P.lc2, P.lc2, bx, by);
 }
 
 template <class T, bool CPLX> __device__ __forceinline__ void batch_norm(const DevProb &P, double &off, double &tot) {
@@ -988,6 +1034,9 @@ template <class T, bool CPLX> __device__ __forceinline__ void batch_norm(const D
       if (i != j) off += a2;
     }
 }
+
+// this pass takes problem P two steps further
+__device__ __forceinline__ bool two_this_pass(int two, const DevProb &P) { return two && P.t + 1 < P.N - 1; }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
@@ -1028,12 +1077,13 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_init_kernel(BatchHdr *hdr
 }
 
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, const BatchHdr *hdr,
-                                                                    const int2 *items, const DevProb *probs) {
+                                                                    const int2 *items, const DevProb *probs,
+                                                                    int two) {
   const int nA = hdr->nA;
   for (int it = blockIdx.x; it < nA; it += gridDim.x) {
     const int2 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.status != 0) continue;
+    if (P.status != 0 || two_this_pass(two, P)) continue;
     const int k = item.y * kUpdBlock + (int)threadIdx.x;
     if (k >= P.N / 2) continue;
     switch (P.kind) {
@@ -1045,15 +1095,48 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, co
   }
 }
 
+// the pivots of both steps of the problems of one element type in a
+// two-step pass
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots2_kernel(char *ws, const BatchHdr *hdr,
+                                                                      const int2 *items, const DevProb *probs) {
+  const int nA = hdr->nA;
+  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
+    const int2 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.kind != KIND || P.status != 0 || !two_this_pass(1, P)) continue;
+    const int k = item.y * kUpdBlock + (int)threadIdx.x;
+    if (k < P.N / 2) batch_pivots2<T, CPLX>(ws, P, k);
+  }
+}
+
+// the two-step tiles (problem, row block, column tile) of the problems of one
+// element type in a two-step pass
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_two_step_kernel(char *ws, const BatchHdr *hdr,
+                                                                       const int4 *items, const DevProb *probs) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int c0 = hdr->c0[KIND], c1 = hdr->c0[KIND + 1];
+  for (int it = c0 + (int)blockIdx.x; it < c1; it += gridDim.x) {
+    const int4 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0 || !two_this_pass(1, P)) continue;
+    batch_two_step<T, CPLX>(kog_smem, ws, P, item.y, item.z);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+// single-step update tiles (problem, k0, l0, partial index) of the problems
+// not in a two-step pass
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, const BatchHdr *hdr,
                                                                      const int4 *items, const DevProb *probs,
-                                                                     double *partials) {
+                                                                     double *partials, int two) {
   __shared__ double red[kUpdBlock];
   const int nB = hdr->nB;
   for (int it = blockIdx.x; it < nB; it += gridDim.x) {
     const int4 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.status != 0) continue;
+    if (P.status != 0 || two_this_pass(two, P)) continue;
     const Tile tl{item.y, P.kc, item.z, P.lc};
     double off2;
     switch (P.kind) {
@@ -1068,12 +1151,22 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, c
 }
 
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *hdr, DevProb *probs,
-                                                                     const double *partials) {
+                                                                     const double *partials, int two) {
   __shared__ double red[kUpdBlock];
   for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
     DevProb &P = probs[p];
-    if (P.status != 0) continue;
-    const bool sweep_end = P.t == P.N - 2;
+    // every thread reads the state before thread 0 changes it
+    const int status = P.status, t = P.t, N = P.N;
+    __syncthreads();
+    if (status != 0) continue;
+    if (two && t + 1 < N - 1) {  // a two-step pass: no sweep ends inside it
+      if (threadIdx.x == 0) {
+        P.t = t + 2;
+        P.in_w ^= 1;
+      }
+      continue;
+    }
+    const bool sweep_end = t == N - 2;
     double off2 = 0;
     if (sweep_end) {
       for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) off2 += partials[P.part_off + i];
@@ -1089,7 +1182,7 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *h
         else if (sw >= P.max_sweeps) P.status = 2;
         if (P.status != 0) atomicSub(&hdr->active, 1);
       }
-      P.t = (P.t + 1 == P.N - 1) ? 0 : P.t + 1;
+      P.t = t + 1 == N - 1 ? 0 : t + 1;
     }
   }
 }
@@ -1500,18 +1593,42 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
 // batch host driver
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-  size_t hdr, probs, itemsA, itemsB, parts, bufs, total;
-  int maxA, maxB, nparts;
+  size_t hdr, probs, itemsA, itemsB, itemsC, parts, bufs, total;
+  size_t lds[4];  // two-step LDS bytes per element type
+  int maxA, maxB, maxC, nparts;
+  int maxC_kind[4];
 };
 
 int esz_of(int kind) { return (kind == SVD2_KOG_F64 || kind == SVD2_KOG_C128) ? 8 : 4; }
 bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
 
-svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::vector<DevProb> *dp) {
+// column pairs per wavefront of the two-step tiles in a batch (workgroups of
+// kUpdBlock / 64 wavefronts)
+int batch_lc2(int N) {
+  TileRule r = rule2_for(N);
+  return r.lc > 0 ? r.lc : 8;
+}
+
+size_t two_step_lds_of(int kind, int span) {
+  const int wpg = kUpdBlock / 64;
+  switch (kind) {
+    case SVD2_KOG_F64: return two_step_lds<double, false>(wpg, span);
+    case SVD2_KOG_C128: return two_step_lds<double, true>(wpg, span);
+    case SVD2_KOG_F32: return two_step_lds<float, false>(wpg, span);
+    default: return two_step_lds<float, true>(wpg, span);
+  }
+}
+
+svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::vector<DevProb> *dp,
+                         bool two) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   if (nprob < 0 || nprob > (1 << 20)) return SVD2_ERR_SIZE;
   if (nprob > 0 && !pr) return SVD2_ERR_NULL;
-  L.maxA = L.maxB = L.nparts = 0;
+  L.maxA = L.maxB = L.maxC = L.nparts = 0;
+  for (int k = 0; k < 4; ++k) {
+    L.lds[k] = 0;
+    L.maxC_kind[k] = 0;
+  }
   size_t bufs = 0;
   for (int p = 0; p < nprob; ++p) {
     const kog_problem &q = pr[p];
@@ -1523,6 +1640,10 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
     int kt = (n + r.kc - 1) / r.kc, lt = (n + r.lc - 1) / r.lc;
     int nin = cplx_of(q.dtype) ? 8 : 4, nout = cplx_of(q.dtype) ? 19 : 11;
     size_t arr = arr_bytes(q.N, esz_of(q.dtype));
+    const int lc2 = batch_lc2(q.N), span = (kUpdBlock / 64) * lc2;
+    const int gx2 = (n + kShiftOut - 1) / kShiftOut, ny2 = (n + span - 1) / span;
+    const size_t set = (nin + nout) * arr;
+    const size_t wbytes = up((size_t)q.N * q.N * esz_of(q.dtype) * (cplx_of(q.dtype) ? 2 : 1));
     if (dp) {
       DevProb d = {};
       d.A = q.A;
@@ -1537,32 +1658,65 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
       d.tol = q.tol;
       d.piv_off = (long long)bufs;  // relative to the buffer region; rebased below
       d.out_off = (long long)(bufs + nin * arr);
+      if (two) {
+        d.piv1_off = (long long)(bufs + set);
+        d.out1_off = (long long)(bufs + set + nin * arr);
+        d.w_off = (long long)(bufs + 2 * set);
+        d.gx2 = gx2;
+        d.ny2 = ny2;
+        d.lc2 = lc2;
+      }
       dp->push_back(d);
     }
-    bufs += (nin + nout) * arr;
+    bufs += two ? 2 * set + wbytes : set;
     L.maxA += (n + kUpdBlock - 1) / kUpdBlock;
     L.maxB += kt * lt;
+    L.maxC += two ? gx2 * ny2 : 0;
+    L.maxC_kind[q.dtype] += two ? gx2 * ny2 : 0;
     L.nparts += kt * lt;
+    if (two) {
+      size_t l = two_step_lds_of(q.dtype, span);
+      if (l > L.lds[q.dtype]) L.lds[q.dtype] = l;
+    }
   }
   L.hdr = 0;
   L.probs = 256;
   L.itemsA = L.probs + up((size_t)nprob * sizeof(DevProb));
   L.itemsB = L.itemsA + up((size_t)L.maxA * sizeof(int2));
-  L.parts = L.itemsB + up((size_t)L.maxB * sizeof(int4));
+  L.itemsC = L.itemsB + up((size_t)L.maxB * sizeof(int4));
+  L.parts = L.itemsC + up((size_t)L.maxC * sizeof(int4));
   L.bufs = L.parts + up((size_t)L.nparts * sizeof(double));
   L.total = L.bufs + bufs;
   if (dp)
     for (DevProb &d : *dp) {
       d.piv_off += (long long)L.bufs;
       d.out_off += (long long)L.bufs;
+      if (two) {
+        d.piv1_off += (long long)L.bufs;
+        d.out1_off += (long long)L.bufs;
+        d.w_off += (long long)L.bufs;
+      }
     }
   return SVD2_OK;
 }
 
 // work lists of the problems still running
-void build_items(const std::vector<DevProb> &dp, std::vector<int2> &A, std::vector<int4> &B) {
+void build_items(const std::vector<DevProb> &dp, std::vector<int2> &A, std::vector<int4> &B,
+                 std::vector<int4> &C, int *c0, bool two) {
   A.clear();
   B.clear();
+  C.clear();
+  for (int kind = 0; kind < 4; ++kind) {  // two-step tiles, grouped by element type
+    c0[kind] = (int)C.size();
+    if (!two) continue;
+    for (int p = 0; p < (int)dp.size(); ++p) {
+      const DevProb &d = dp[p];
+      if (d.status != 0 || d.kind != kind) continue;
+      for (int y = 0; y < d.ny2; ++y)
+        for (int x = 0; x < d.gx2; ++x) C.push_back(int4{p, x, y, 0});
+    }
+  }
+  c0[4] = (int)C.size();
   for (int p = 0; p < (int)dp.size(); ++p) {
     const DevProb &d = dp[p];
     if (d.status != 0) continue;
@@ -1578,44 +1732,69 @@ struct BatchRun {
   char *ws;
   BatchLayout L;
   hipStream_t st;
-  int gA, gB, gF;
+  int gA, gB, gF, two;
 };
+
+template <class T, bool CPLX, int KIND> svd2_status batch_two_step_launch(const BatchRun &r, hipStream_t st) {
+  if (r.L.maxC_kind[KIND] == 0) return SVD2_OK;
+  BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
+  DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  hipLaunchKernelGGL((kog_batch_pivots2_kernel<T, CPLX, KIND>), dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int2 *)(r.ws + r.L.itemsA), probs);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  const int g = r.L.maxC_kind[KIND] < 16384 ? r.L.maxC_kind[KIND] : 16384;
+  hipLaunchKernelGGL((kog_batch_two_step_kernel<T, CPLX, KIND>), dim3(g), dim3(kUpdBlock), r.L.lds[KIND], st,
+                     r.ws, hdr, (const int4 *)(r.ws + r.L.itemsC), probs);
+  return hip_st(hipGetLastError());
+}
 
 svd2_status batch_step(const BatchRun &r, hipStream_t st) {
   BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
   DevProb *probs = (DevProb *)(r.ws + r.L.probs);
   hipLaunchKernelGGL(kog_batch_pivot_kernel, dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
-                     (const int2 *)(r.ws + r.L.itemsA), probs);
+                     (const int2 *)(r.ws + r.L.itemsA), probs, r.two);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
-                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts));
+                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.two);
   s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, false, SVD2_KOG_F64>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, true, SVD2_KOG_C128>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, false, SVD2_KOG_F32>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, true, SVD2_KOG_C64>(r, st);
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_finish_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, hdr, probs,
-                     (const double *)(r.ws + r.L.parts));
+                     (const double *)(r.ws + r.L.parts), r.two);
   return hip_st(hipGetLastError());
 }
 
 svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int active) {
   std::vector<int2> A;
-  std::vector<int4> B;
-  build_items(dp, A, B);
-  BatchHdr h = {(int)A.size(), (int)B.size(), (int)dp.size(), active};
+  std::vector<int4> B, C;
+  BatchHdr h = {};
+  build_items(dp, A, B, C, h.c0, r.two != 0);
+  h.nA = (int)A.size();
+  h.nB = (int)B.size();
+  h.nprob = (int)dp.size();
+  h.active = active;
   svd2_status s = hip_st(hipMemcpyAsync(r.ws + r.L.hdr, &h, sizeof h, hipMemcpyHostToDevice, r.st));
   if (s == SVD2_OK && !A.empty())
     s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsA, A.data(), A.size() * sizeof(int2), hipMemcpyHostToDevice, r.st));
   if (s == SVD2_OK && !B.empty())
     s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsB, B.data(), B.size() * sizeof(int4), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !C.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsC, C.data(), C.size() * sizeof(int4), hipMemcpyHostToDevice, r.st));
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(r.st));
   return s;
 }
 
 svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
-  if (flags & ~(unsigned)SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;
+  if (flags & ~(unsigned)(SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;
   BatchRun r;
+  r.two = (flags & SVD2_KOG_TWO_STEP) ? 1 : 0;
   std::vector<DevProb> dp;
-  svd2_status s = batch_layout(nprob, pr, r.L, &dp);
+  svd2_status s = batch_layout(nprob, pr, r.L, &dp, r.two != 0);
   if (s != SVD2_OK) return s;
   if (nprob == 0) return SVD2_OK;
   if (!ws) return SVD2_ERR_NULL;
@@ -1642,12 +1821,12 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
   hipLaunchKernelGGL(kog_batch_init_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, (BatchHdr *)(r.ws + r.L.hdr),
                      (DevProb *)(r.ws + r.L.probs));
   s = hip_st(hipGetLastError());
-  long long max_steps = 0;
+  long long max_steps = 0;  // passes: steps, or (N/2 per sweep) two-step passes
   for (const DevProb &d : dp) {
-    long long m = (long long)d.max_sweeps * (d.N - 1);
+    long long m = (long long)d.max_sweeps * (r.two ? d.N / 2 : d.N - 1);
     if (m > max_steps) max_steps = m;
   }
-  const int K = 64;  // steps per replay / between host checks
+  const int K = 64;  // passes per replay / between host checks
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   auto capture = [&]() -> svd2_status {
@@ -1697,6 +1876,34 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
   if (cap) hipStreamDestroy(cap);
   if (s != SVD2_OK) return s;
   s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+  if (s != SVD2_OK) return s;
+  // iterates left in the second matrix go back to the caller's
+  for (int p = 0; p < nprob && s == SVD2_OK; ++p) {
+    const DevProb &d = dp[p];
+    if (!d.in_w) continue;
+    const int grid = d.N < 4096 ? d.N : 4096;
+    char *w = r.ws + d.w_off;
+    switch (d.kind) {
+      case SVD2_KOG_F64:
+        hipLaunchKernelGGL((kog_copy_kernel<double, false>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<double, false>{(double *)w, (size_t)d.N}, Mat<double, false>{(double *)d.A, (size_t)d.lda});
+        break;
+      case SVD2_KOG_C128:
+        hipLaunchKernelGGL((kog_copy_kernel<double, true>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<double, true>{(double *)w, (size_t)d.N}, Mat<double, true>{(double *)d.A, (size_t)d.lda});
+        break;
+      case SVD2_KOG_F32:
+        hipLaunchKernelGGL((kog_copy_kernel<float, false>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<float, false>{(float *)w, (size_t)d.N}, Mat<float, false>{(float *)d.A, (size_t)d.lda});
+        break;
+      default:
+        hipLaunchKernelGGL((kog_copy_kernel<float, true>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<float, true>{(float *)w, (size_t)d.N}, Mat<float, true>{(float *)d.A, (size_t)d.lda});
+        break;
+    }
+    s = hip_st(hipGetLastError());
+  }
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
   if (s != SVD2_OK) return s;
   svd2_status all = SVD2_OK;
@@ -1798,10 +2005,14 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
 
 int kog_last_hip_error(void) { return g_kog_hip; }
 
-size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs) {
+size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsigned flags) {
   BatchLayout L;
-  if (batch_layout(nprob, probs, L, nullptr) != SVD2_OK) return 0;
+  if (batch_layout(nprob, probs, L, nullptr, (flags & SVD2_KOG_TWO_STEP) != 0) != SVD2_OK) return 0;
   return L.total;
+}
+
+size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs) {
+  return kog_batch_workspace_bytes_flags(nprob, probs, 0);
 }
 
 svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,

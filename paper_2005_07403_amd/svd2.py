@@ -60,6 +60,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
+           "kog_batch_workspace_bytes_flags",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -375,6 +376,8 @@ def _batch():
     if not _batch_ready:
         L.kog_batch_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(kog_problem)]
         L.kog_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.kog_batch_workspace_bytes_flags.argtypes = [ctypes.c_int, ctypes.POINTER(kog_problem), ctypes.c_uint]
+        L.kog_batch_workspace_bytes_flags.restype = ctypes.c_size_t
         L.kog_batch_solve.argtypes = [ctypes.c_int, ctypes.POINTER(kog_problem), _P, ctypes.c_size_t,
                                       ctypes.c_uint, _P]
         L.kog_batch_solve.restype = ctypes.c_int
@@ -419,7 +422,7 @@ def kog_batch_solve(mats, tols, max_sweeps=40, flags: int = 0, ws=None, stream=N
         probs[i].N, probs[i].lda, probs[i].A = N, lda, ptr
         probs[i].tol, probs[i].max_sweeps = float(tols[i]), int(max_sweeps[i])
     L = _batch()
-    wsb = int(L.kog_batch_workspace_bytes(n, probs))
+    wsb = int(L.kog_batch_workspace_bytes_flags(n, probs, flags))
     if ws is None:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=mats[0].device)
     st = L.kog_batch_solve(n, probs, ws.data_ptr(), ws.numel(), flags, _stream(stream))

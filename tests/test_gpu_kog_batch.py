@@ -26,16 +26,18 @@ def _batch(specs, seed):
 
 
 @pytest.mark.parametrize("graph", [False, True])
-def test_mixed_batch_bitwise(graph):
+@pytest.mark.parametrize("two", [False, True])
+def test_mixed_batch_bitwise(graph, two):
     import torch
     from paper_2005_07403_amd import svd2 as S
+    flags = (S.SVD2_KOG_GRAPH if graph else 0) | (S.SVD2_KOG_TWO_STEP if two else 0)
     specs = [(2, "d", 10.0), (4, "z", 1e3), (6, "s", 1e2), (32, "d", 1e12), (34, "z", 1e8),
              (64, "s", 1e4), (66, "c", 1e3), (128, "d", 1e6), (130, "z", 1e10), (96, "c", 1e2),
              (40, "s", 1e5), (2, "z", 1.0)]
     mats = _batch(specs, SEED_BASE + 400)
     dev = [torch.from_numpy(m).cuda() for m in mats]
     tols = [TOL[k] for _, k, _ in specs]
-    res = S.kog_batch_solve(dev, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH if graph else 0)
+    res = S.kog_batch_solve(dev, tols, max_sweeps=40, flags=flags)
     torch.cuda.synchronize()
     for i, ((N, kind, cond), A) in enumerate(zip(specs, mats)):
         ro = O.kog_solve(A, tol=TOL[kind], max_sweeps=40)
@@ -45,31 +47,42 @@ def test_mixed_batch_bitwise(graph):
         assert np.array_equal(_bits(got), _bits(A)), (i, N, kind)
 
 
-def test_batch_equals_single_problem_solver():
+@pytest.mark.parametrize("two", [False, True])
+def test_batch_equals_single_problem_solver(two):
     """A problem solved inside a batch ends bitwise equal to the same problem
     solved alone by the single-problem entry point (tile shape and batching do
     not change the arithmetic)."""
     import torch
     from paper_2005_07403_amd import svd2 as S
-    specs = [(256, "d", 1e12), (200, "z", 1e6), (128, "s", 1e3)]
+    specs = [(256, "d", 1e12), (200, "z", 1e6), (128, "s", 1e3), (150, "c", 1e3)]
     mats = _batch(specs, SEED_BASE + 410)
     dev = [torch.from_numpy(m).cuda() for m in mats]
     alone = [torch.from_numpy(m).cuda() for m in mats]
-    res = S.kog_batch_solve(dev, [TOL[k] for _, k, _ in specs])
+    res = S.kog_batch_solve(dev, [TOL[k] for _, k, _ in specs],
+                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
     for i, (_, kind, _) in enumerate(specs):
-        r = S.kog_solve(alone[i], tol=TOL[kind], flags=S.SVD2_KOG_UNFUSED)
+        r = S.kog_solve(alone[i], tol=TOL[kind], flags=S.SVD2_KOG_TWO_STEP if two else S.SVD2_KOG_UNFUSED)
         assert r["sweeps"] == res[i]["sweeps"]
         a, b = alone[i].cpu().numpy(), dev[i].cpu().numpy()
         assert np.array_equal(_bits(a), _bits(b))
 
 
-def test_batch_not_converged_and_already_diagonal():
+@pytest.mark.parametrize("two", [False, True])
+def test_batch_not_converged_and_already_diagonal(two):
+    """A problem stopped by max_sweeps keeps the iterate of its last sweep
+    (bitwise the oracle's after that many sweeps; in the two-step mode the
+    iterate of order 64 ends a sweep in the second matrix and is copied
+    back); a diagonal input is left untouched."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     A = np.asfortranarray(kog_matrix(64, SEED_BASE + 420, cond=1e12))
     D = np.asfortranarray(np.diag(np.arange(1.0, 33.0)))
     dev = [torch.from_numpy(A).cuda(), torch.from_numpy(D).cuda()]
-    res = S.kog_batch_solve(dev, [1e-14, 1e-14], max_sweeps=[2, 5])
-    assert res[0]["status"] == 7 and res[0]["sweeps"] == 2
+    res = S.kog_batch_solve(dev, [1e-14, 1e-14], max_sweeps=[1, 5],
+                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
+    assert res[0]["status"] == 7 and res[0]["sweeps"] == 1
     assert res[1]["status"] == 0 and res[1]["sweeps"] == 0
     assert torch.equal(dev[1].cpu(), torch.from_numpy(D))
+    ro = O.kog_solve(A, tol=1e-14, max_sweeps=1)
+    assert ro["status"] == 7 and ro["sweeps"] == 1
+    assert np.array_equal(_bits(dev[0].cpu().numpy()), _bits(A))
