@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--only", choices=["d", "z", "s", "c"], default=None,
                     help="time one variant only (for profiling runs)")
     ap.add_argument("--n", type=int, default=1 << 24)
+    ap.add_argument("--n32", type=int, default=1 << 26,
+                    help="batch size of the FP32 precision-form runs (reported as s26/c26; 0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kog", action="store_true", help="skip the Kogbetliantz measurement")
     ap.add_argument("--kog-order", type=int, default=4096)
@@ -318,13 +320,18 @@ def main():
                 "s": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0},
                 "c": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0}}
     results, inputs_z = {}, None
-    for v in variants:
-        log(f"[bench] generating {v} inputs n={args.n}")
-        tr = make_inputs(v, args.n)
-        log(f"[bench] timing {v}: warmup {args.warmup}, steps {args.steps}")
+    # FP32 also at the precision form's own size (2^26: its inputs exceed the
+    # 256 MB Infinity Cache, so they come from HBM on every launch)
+    runs = [(v, args.n, "") for v in variants]
+    if args.n32 and not args.only:
+        runs += [(v, args.n32, "26") for v in ("s", "c")]
+    for v, n, tag in runs:
+        log(f"[bench] generating {v} inputs n={n}")
+        tr = make_inputs(v, n)
+        log(f"[bench] timing {v}{tag}: warmup {args.warmup}, steps {args.steps}")
         r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()))
         for desc, fl in flagsets[v].items():
-            key = v if desc in ("", "RESCUE_FP64") else f"{v}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
+            key = v + tag if desc in ("", "RESCUE_FP64") else f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
             results[key] = summarize(v, r[fl], r["pattern"], desc)
             log(f"[bench] {key}: {json.dumps(results[key])}")
         if v == "z":

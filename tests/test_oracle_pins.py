@@ -419,10 +419,11 @@ def test_fp32_rescue_restores_relative_sigma_min(cplx, mode):
         assert met[key].max() <= 16 * EPS32, (key, met[key].max() / EPS32)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_fp32_scaled_law_bounds(cplx):
+def test_fp32_scaled_law_bounds(cplx, mode):
     A = scaled_law(20000, 24, cplx, dtype=np.float32)
-    r = O.svd2(A, dtype=np.float32, rescue=True)
+    r = O.svd2(A, dtype=np.float32, rescue=mode)
     met = O.metrics(r["inputs"], r["trains"], cplx)
     for key in ("rho", "delta", "eta"):
         assert met[key].max() <= 16 * EPS32, (key, met[key].max() / EPS32)
