@@ -197,3 +197,23 @@ def test_two_step_full_order_4096_sweep():
     S.kog_sweep(G2, flags=S.SVD2_KOG_TWO_STEP)
     torch.cuda.synchronize()
     assert torch.equal(G1.view(torch.int64), G2.view(torch.int64))
+
+
+@pytest.mark.slow
+def test_two_step_full_order_4096_solve_equals_unfused():
+    """The one-problem workload solved to 1e-14 by the two-step driver ends
+    bitwise equal to the unfused single-step solve (same sweep count), and its
+    sigma matches the construction."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N = 4096
+    A, s = kog_matrix(N, SEED_BASE + 3, cond=1e12, return_sigma=True)
+    G1, G2 = _dev(A), _dev(A)
+    r1 = S.kog_solve(G1, tol=1e-14, max_sweeps=60, flags=S.SVD2_KOG_UNFUSED)
+    r2 = S.kog_solve(G2, tol=1e-14, max_sweeps=60, flags=S.SVD2_KOG_TWO_STEP)
+    torch.cuda.synchronize()
+    assert r1["status"] == r2["status"] == 0
+    assert r1["sweeps"] == r2["sweeps"]
+    assert torch.equal(G1.view(torch.int64), G2.view(torch.int64))
+    sig = np.sort(np.diag(G2.cpu().numpy()))[::-1]
+    assert np.max(np.abs(sig - s)) <= 8 * N * EPS["d"] * s[0]

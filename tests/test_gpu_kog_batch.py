@@ -86,3 +86,22 @@ def test_batch_not_converged_and_already_diagonal(two):
     ro = O.kog_solve(A, tol=1e-14, max_sweeps=1)
     assert ro["status"] == 7 and ro["sweeps"] == 1
     assert np.array_equal(_bits(dev[0].cpu().numpy()), _bits(A))
+
+
+def test_two_step_batch_large_orders():
+    """Orders up to 1026 (several two-step tiles per problem in both
+    directions, a partial last column tile) in the two-step batch: each
+    problem bitwise equal to its single-problem two-step solve."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    specs = [(1026, "d", 1e10), (514, "z", 1e6), (770, "s", 1e3), (390, "c", 1e3), (258, "d", 1e2)]
+    mats = _batch(specs, SEED_BASE + 430)
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    alone = [torch.from_numpy(m).cuda() for m in mats]
+    tols = [TOL[k] for _, k, _ in specs]
+    res = S.kog_batch_solve(dev, tols, flags=S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_GRAPH)
+    for i, (N, kind, _) in enumerate(specs):
+        r = S.kog_solve(alone[i], tol=tols[i], flags=S.SVD2_KOG_TWO_STEP)
+        assert r["status"] == res[i]["status"] == 0
+        assert r["sweeps"] == res[i]["sweeps"], (N, kind)
+        assert np.array_equal(_bits(alone[i].cpu().numpy()), _bits(dev[i].cpu().numpy())), (N, kind)
