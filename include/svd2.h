@@ -301,6 +301,25 @@ size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsi
 svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
                             hipStream_t stream);
 
+/* Singular values of a Kogbetliantz iterate: sigma_out[0..N) = |a_ii| sorted
+ * into descending order (after at least one step the diagonal is real and
+ * non-negative, so these are the diagonal entries themselves; after
+ * convergence they are the singular values of the input, the diagonal of
+ * U* A V).  A: device, column-major, lda >= N (complex interleaved, read
+ * only); sigma_out: device, N elements of the real type; ws: device scratch
+ * of kog_sigma_workspace_bytes(N, dtype) bytes, 256-byte aligned.  A,
+ * sigma_out and ws must not overlap (SVD2_ERR_ALIAS).  Asynchronous on
+ * `stream` (a device radix sort). */
+size_t kog_sigma_workspace_bytes(int N, int dtype);
+svd2_status dkog_sigma(int N, const double *A, int lda, double *sigma_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+svd2_status zkog_sigma(int N, const double *A, int lda, double *sigma_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+svd2_status skog_sigma(int N, const float *A, int lda, float *sigma_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+
 /* last hipError_t seen by a Kogbetliantz entry point on this thread */
 int kog_last_hip_error(void);
 /* Workgroups per CU of the fused kernel's cooperative grid, 1..16 (capped by

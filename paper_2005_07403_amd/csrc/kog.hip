@@ -1918,6 +1918,9 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
 
 }  // namespace
 
+// the last HIP error of a Kogbetliantz entry point defined in another file
+void kog_note_hip_error(int e) { g_kog_hip = e; }
+
 extern "C" {
 
 size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags) {

@@ -60,7 +60,8 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
-           "kog_batch_workspace_bytes_flags",
+           "kog_batch_workspace_bytes_flags", "kog_sigma_workspace_bytes", "dkog_sigma", "zkog_sigma",
+           "skog_sigma", "ckog_sigma",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -277,8 +278,11 @@ def _kog():
             getattr(L, f"{x}kog_sweep").argtypes = [i, _P, i, _P, sz, ui, _P]
             getattr(L, f"{x}kog_solve").argtypes = [i, _P, i, d, i, _P, _P, _P, sz, ui, _P]
             getattr(L, f"{x}kog_norms").argtypes = [i, _P, i, _P, _P, _P, sz, _P]
-            for f in ("step", "sweep", "solve", "norms"):
+            getattr(L, f"{x}kog_sigma").argtypes = [i, _P, i, _P, _P, sz, _P]
+            for f in ("step", "sweep", "solve", "norms", "sigma"):
                 getattr(L, f"{x}kog_{f}").restype = i
+        L.kog_sigma_workspace_bytes.argtypes = [i, i]
+        L.kog_sigma_workspace_bytes.restype = sz
         L.kog_last_hip_error.restype = i
         L.kog_set_fused_blocks_per_cu.argtypes = [i]
         L.kog_set_fused_blocks_per_cu.restype = i
@@ -345,6 +349,22 @@ def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int =
                                           _stream(stream))
     _kog_check(f"{k}kog_solve", st)
     return dict(status=st, sweeps=sw.value, off_rel=off.value)
+
+
+def kog_sigma(A, out=None, ws=None, stream=None):
+    """|diag(A)| sorted into descending order, on the device (the singular
+    values once A has converged).  Returns a real tensor of length N."""
+    import torch
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    real = torch.float64 if k in "dz" else torch.float32
+    out = torch.empty(N, dtype=real, device=A.device) if out is None else out
+    if ws is None:
+        ws = torch.empty(max(int(_kog().kog_sigma_workspace_bytes(N, KOG_DTYPE[k])), 1), dtype=torch.uint8,
+                         device=A.device)
+    _kog_check(f"{k}kog_sigma", getattr(_kog(), f"{k}kog_sigma")(N, ptr, lda, out.data_ptr(), ws.data_ptr(),
+                                                                  ws.numel(), _stream(stream)))
+    return out
 
 
 def kog_norms(A, ws=None, stream=None):

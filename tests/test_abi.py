@@ -196,3 +196,22 @@ def test_kog_two_step_tile_rules():
                                     (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
     assert L.kog_set_two_step_tiles(1, None, None, None) == 1
     assert L.kog_set_two_step_tiles(0, None, None, None) == 0      # back to the default
+
+
+def test_kog_sigma_argument_errors():
+    """Sorted-diagonal extraction validates before any HIP call."""
+    L = S._kog()
+    A, out, ws = FAKE, FAKE + (64 << 30), FAKE + (128 << 30)
+    wsb = L.kog_sigma_workspace_bytes(100, 0)
+    assert wsb == 1024 and L.kog_sigma_workspace_bytes(100, 2) == 512   # 128 keys, 256-byte rounded
+    assert L.kog_sigma_workspace_bytes(0, 0) == 0 and L.kog_sigma_workspace_bytes(4, 9) == 0
+    call = lambda N, a, lda, o, w, b: L.dkog_sigma(N, a, lda, o, w, b, None)
+    assert call(100, 0, 100, out, ws, wsb) == 1           # NULL matrix
+    assert call(100, A, 100, 0, ws, wsb) == 1             # NULL output
+    assert call(100, A, 99, out, ws, wsb) == 6            # lda < N
+    assert call(0, A, 100, out, ws, wsb) == 6             # empty
+    assert call(100, A, 100, out, ws, wsb - 8) == 6       # workspace too small
+    assert call(100, A + 4, 100, out, ws, wsb) == 2       # misaligned matrix
+    assert call(100, A, 100, out, ws + 8, wsb) == 2       # misaligned workspace
+    assert call(100, A, 100, A + 800, ws, wsb) == 3       # output inside the matrix
+    assert call(100, A, 100, out, out + 256, wsb) == 3    # workspace overlaps the output

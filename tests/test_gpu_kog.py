@@ -217,3 +217,34 @@ def test_two_step_full_order_4096_solve_equals_unfused():
     assert torch.equal(G1.view(torch.int64), G2.view(torch.int64))
     sig = np.sort(np.diag(G2.cpu().numpy()))[::-1]
     assert np.max(np.abs(sig - s)) <= 8 * N * EPS["d"] * s[0]
+
+
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+def test_sigma_extraction(kind):
+    """kog_sigma after a solve: the diagonal magnitudes in descending order,
+    bitwise (the converged diagonal is real and non-negative), equal to the
+    oracle's sorted diagonal; also for an order that is not a power of two."""
+    from paper_2005_07403_amd import svd2 as S
+    N = 130
+    tol = 1e-14 if kind in "dz" else 1e-6
+    A = _make(N, kind, SEED_BASE + 360, cond=1e8 if kind in "dz" else 1e3)
+    G = _dev(A)
+    S.kog_solve(G, tol=tol)
+    O.kog_solve(A, tol=tol)
+    sig = S.kog_sigma(G).cpu().numpy()
+    d = np.diag(A)
+    assert np.all(np.imag(d) == 0) and np.all(np.real(d) >= 0)
+    want = np.sort(np.real(d))[::-1].astype(sig.dtype)
+    assert _same(sig, want)
+
+
+def test_sigma_extraction_general_input():
+    """On an arbitrary real matrix (signed diagonal, order 1..300) the
+    result is |diag| sorted descending, bitwise."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    rng = np.random.default_rng(SEED_BASE + 370)
+    for N in (1, 2, 3, 7, 64, 255, 256, 257, 300):
+        A = np.asfortranarray(rng.standard_normal((N, N)))
+        sig = S.kog_sigma(_dev(A)).cpu().numpy()
+        assert _same(sig, np.sort(np.abs(np.diag(A)))[::-1]), N
