@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--kog-order", type=int, default=4096)
     ap.add_argument("--no-kog-batch", action="store_true", help="skip the uneven Kogbetliantz batch")
     ap.add_argument("--kog-batch", type=int, default=256, help="problems in the uneven batch")
+    ap.add_argument("--kog-batch-only", action="store_true",
+                    help="run only the uneven Kogbetliantz batch; prints its JSON (for profiling runs)")
     ap.add_argument("--kog-only", default=None, metavar="MODES",
                     help="run only the Kogbetliantz drivers named (comma list of fused, unfused, graph, "
                          "two_step), one sweep each, no solve; prints their JSON (for profiling runs)")
@@ -312,6 +314,10 @@ def main():
     if args.kog_only:
         out = kog_bench(args.kog_order, sweeps=1, solve=False, only=args.kog_only.split(","))
         print(json.dumps(out), flush=True)
+        return
+    if args.kog_batch_only:
+        out = kog_batch_bench(args.kog_batch)
+        print(json.dumps({k: v for k, v in out.items() if k != "problems"}), flush=True)
         return
 
     variants = [args.only] if args.only else ["z", "d", "s", "c"]
