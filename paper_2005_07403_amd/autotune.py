@@ -5,7 +5,10 @@ Tuned:
   matrices per lane (1/2), per element type, at n = 2^24 on the +-m 2^e law;
 * the Kogbetliantz update tile: row pairs per workgroup kc (64/128/256) and
   column pairs per tile lc, per order bucket, timing unfused steps of a real
-  FP64 and a complex FP64 matrix of that order.
+  FP64 and a complex FP64 matrix of that order;
+* the two-step Kogbetliantz kernel: wavefronts per workgroup (1/2/4) and
+  column pairs per wavefront, per order bucket, timing two-step sweeps of the
+  same two matrices.
 
 Run:  python -m paper_2005_07403_amd.autotune [--quick]
 The binding applies the table with svd2.apply_tuning().
@@ -33,6 +36,16 @@ def _median_ms(fn, reps: int) -> float:
         b.record()
     torch.cuda.synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def _pick(res: dict, tiles) -> tuple:
+    """The fastest shape, except that among shapes within 3 % of it the one
+    with the fewest tiles wins (small orders are launch-bound and their
+    timings differ by noise; fewer, larger tiles are the safer choice when
+    the kernel also runs inside a batch)."""
+    best = min(res.values())
+    near = [k for k, v in res.items() if v <= 1.03 * best]
+    return min(near, key=lambda k: (tiles(k), res[k]))
 
 
 def tune_svd2(n: int, reps: int, rounds: int = 3) -> dict:
@@ -92,12 +105,48 @@ def tune_kog(orders, steps: int) -> list:
                     tot += _median_ms(lambda: S.kog_step(G, 1, ws=ws, flags=S.SVD2_KOG_UNFUSED), steps)
                     del G, ws
                 res[(kc, lc)] = tot
-        b = min(res, key=res.get)
+        b = _pick(res, lambda k: -(-n // k[0]) * -(-n // k[1]))
         print(f"kog N={N}: " + ", ".join(f"{k}={v:.3f}ms" for k, v in sorted(res.items())) + f" -> {b}",
               flush=True)
         rules.append([N, b[0], b[1]])
     rules[-1][0] = 1 << 19  # the last rule covers every larger order
     S.kog_set_tile_rules([tuple(r) for r in rules])
+    return rules
+
+
+def tune_kog_two_step(orders, reps: int) -> list:
+    """Workgroup shape of the two-step kernel per order: wavefronts per
+    workgroup x column pairs per wavefront, timed on one two-step sweep of a
+    real and a complex FP64 matrix."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    rules = []
+    rng = np.random.default_rng(12)
+    fl = S.SVD2_KOG_TWO_STEP
+    for N in orders:
+        n = N // 2
+        mats = {"d": np.asfortranarray(rng.standard_normal((N, N))),
+                "z": np.asfortranarray(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))}
+        res = {}
+        for wpg in (1, 2, 4):
+            for lc in (2, 4, 8, 16, 32):
+                if wpg * lc > 2 * max(n, 8):
+                    continue
+                S.kog_set_two_step_tiles([(1 << 19, wpg, lc)])
+                tot = 0.0
+                for kind, A in mats.items():
+                    G = torch.from_numpy(A).cuda()
+                    ws = S.kog_workspace(G, fl)
+                    S.kog_sweep(G, ws=ws, flags=fl)
+                    tot += _median_ms(lambda: S.kog_sweep(G, ws=ws, flags=fl), reps)
+                    del G, ws
+                res[(wpg, lc)] = tot
+        b = _pick(res, lambda k: -(-n // (k[0] * k[1])))
+        print(f"kog two-step N={N}: " + ", ".join(f"{k}={v:.3f}ms" for k, v in sorted(res.items())) +
+              f" -> {b}", flush=True)
+        rules.append([N, b[0], b[1]])
+    rules[-1][0] = 1 << 19
+    S.kog_set_two_step_tiles([tuple(r) for r in rules])
     return rules
 
 
@@ -114,8 +163,9 @@ def main():
     launch = tune_svd2(1 << (22 if args.quick else 24), 10 if args.quick else 20)
     orders = [64, 256, 1024, 4096] if args.quick else [32, 64, 128, 256, 512, 1024, 2048, 4096]
     rules = tune_kog(orders, 5 if args.quick else 10)
+    rules2 = tune_kog_two_step(orders, 2 if args.quick else 3)
     tab = {"device": torch.cuda.get_device_name(0), "svd2_launch": launch, "kog_tile_rules": rules,
-           "seconds": round(time.time() - t0, 1)}
+           "kog_two_step_tiles": rules2, "seconds": round(time.time() - t0, 1)}
     with open(args.out, "w") as fh:
         json.dump(tab, fh, indent=1)
     print(json.dumps(tab), flush=True)

@@ -1616,11 +1616,12 @@ int esz_of(int kind) { return (kind == SVD2_KOG_F64 || kind == SVD2_KOG_C128) ? 
 bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
 
 // column pairs per wavefront of the two-step tiles in a batch (workgroups of
-// kUpdBlock / 64 wavefronts)
-int batch_lc2(int N) {
-  TileRule r = rule2_for(N);
-  return r.lc > 0 ? r.lc : 8;
-}
+// kUpdBlock / 64 wavefronts).  Fixed rather than taken from the single-problem
+// shape table: a lone small problem wants many small tiles for parallelism,
+// while a batch has parallelism from its many problems and loses to the halo
+// reads of small tiles (256-problem batch: 8.6 s with 8, 9.5 s with the
+// single-problem shapes).
+int batch_lc2(int) { return 8; }
 
 size_t two_step_lds_of(int kind, int span) {
   const int wpg = kUpdBlock / 64;

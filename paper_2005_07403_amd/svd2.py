@@ -199,6 +199,9 @@ def apply_tuning(path: str = TUNING_PATH) -> dict | None:
     rules = tab.get("kog_tile_rules")
     if rules:
         kog_set_tile_rules([tuple(int(x) for x in r) for r in rules])
+    rules2 = tab.get("kog_two_step_tiles")
+    if rules2:
+        kog_set_two_step_tiles([tuple(int(x) for x in r) for r in rules2])
     return tab
 
 
