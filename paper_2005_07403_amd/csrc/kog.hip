@@ -377,11 +377,6 @@ template <class T, bool CPLX> __device__ __forceinline__ RotU<T> load_u(const Bu
   Rot<T> r = load_rot<T, CPLX>(B, k);
   return RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
 }
-template <class T, bool CPLX> __device__ __forceinline__ RotV<T> load_v(const Bufs<T, CPLX> &B, int k) {
-  Rot<T> r = load_rot<T, CPLX>(B, k);
-  return RotV<T>{r.v11, r.v21, r.v12, r.v22};
-}
-
 // entry (role of the row, role of the column) of U^* B V for a step-t block
 // B given in (p-row, q-row) x (p-col, q-col) order; the operations are those
 // of rotate_block for that entry
@@ -418,24 +413,6 @@ __device__ __forceinline__ Cx<T> after_step(const Side &r, const RotU<T> &ur, co
   Cx<T> b21 = r.isq ? (c.isq ? xrp : xrc) : (c.isq ? xpp : xpc);
   Cx<T> b22 = r.isq ? (c.isq ? xrc : xrp) : (c.isq ? xpc : xpp);
   return rotated_entry<T, CPLX>(ur, r.isq, vc, c.isq, b11, b21, b12, b22);
-}
-
-// the 2x2 block (rows ra, rb) x (columns ca, cb) after step t
-template <class T, bool CPLX>
-__device__ __forceinline__ void block_after_step(const Mat<T, CPLX> &M, const Side (&R)[2], const RotU<T> (&U)[2],
-                                                 const Side (&C)[2], const RotV<T> (&V)[2], Cx<T> (&out)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    Cx<T> x[2][2];  // [row or partner][col or partner] for column j below
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      x[0][0] = M.ld(R[i].x, C[j].x);
-      x[0][1] = M.ld(R[i].x, C[j].partner);
-      x[1][0] = M.ld(R[i].partner, C[j].x);
-      x[1][1] = M.ld(R[i].partner, C[j].partner);
-      out[i][j] = after_step<T, CPLX>(R[i], U[i], C[j], V[j], x[0][0], x[0][1], x[1][0], x[1][1]);
-    }
-  }
 }
 
 // gather + 2x2 SVD of the pivots of step t in one kernel
