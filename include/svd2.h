@@ -194,8 +194,10 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  *
  * Storage: column-major, leading dimension lda >= N (in elements; complex
  * elements are interleaved re, im).  A must be aligned to its element size.
- * ws: device workspace of kog_workspace_bytes(N, dtype) bytes, 256-byte
- * aligned, not overlapping A; calls sharing a workspace must not overlap.
+ * ws: device workspace of kog_workspace_bytes(N, dtype) bytes
+ * (kog_workspace_bytes_flags(N, dtype, flags) with SVD2_KOG_TWO_STEP),
+ * 256-byte aligned, not overlapping A; calls sharing a workspace must not
+ * overlap.
  * Entry points enqueue on `stream`; *_solve synchronises the stream once per
  * sweep and returns when done.  Errors are as for the batched calls; a fused
  * sweep whose grid barrier does not complete within its spin bound aborts all
@@ -301,7 +303,8 @@ size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsi
 svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
                             hipStream_t stream);
 
-/* Singular values of a Kogbetliantz iterate: sigma_out[0..N) = |a_ii| sorted
+/* Singular values of a Kogbetliantz iterate (section 1: the iteration drives
+ * A towards U* A V = diag(sigma)): sigma_out[0..N) = |a_ii| sorted
  * into descending order (after at least one step the diagonal is real and
  * non-negative, so these are the diagonal entries themselves; after
  * convergence they are the singular values of the input, the diagonal of
