@@ -114,7 +114,12 @@ int oracle_kog_norms_d(int N, const double *A, int lda, int cplx, double *off2, 
 int oracle_kog_norms_s(int N, const float *A, int lda, int cplx, double *off2, double *tot2);
 /* Full solve: returns 0 on convergence, 7 when max_sweeps is reached.
  * sweeps: sweeps performed; off_rel: off(A)/||A_0||_F at exit;
- * history (optional, max_sweeps+1 doubles): off/||A_0||_F before each sweep. */
+ * history (optional, max_sweeps+1 doubles): off/||A_0||_F before each sweep.
+ * Pinned by the tests: every step keeps ||A||_F and lowers off(A)^2 by the
+ * pivots' off-diagonal mass, and the converged diagonal matches an
+ * independent SVD within 8 N eps sigma_max.  Parity unpinned: the number of
+ * sweeps itself (the paper fixes neither the ordering nor the stopping rule,
+ * so nothing outside this code determines it). */
 int oracle_kog_solve_d(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
                        double *off_rel, double *history);
 int oracle_kog_solve_z(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
