@@ -105,3 +105,29 @@ def test_two_step_batch_large_orders():
         assert r["status"] == res[i]["status"] == 0
         assert r["sweeps"] == res[i]["sweeps"], (N, kind)
         assert np.array_equal(_bits(alone[i].cpu().numpy()), _bits(dev[i].cpu().numpy())), (N, kind)
+
+
+@pytest.mark.slow
+def test_full_uneven_batch_two_step():
+    """The 256-problem uneven workload (orders 32..2048, half complex FP64 at
+    tol 1e-14, half FP32 at tol 1e-7), solved two steps per pass with graph
+    replay as the benchmark times it: every problem converges, its singular
+    values match the construction within 8 N eps sigma_max, and the six
+    smallest problems end bitwise equal to the oracle's single-problem solve."""
+    from paper_2005_07403_amd import svd2 as S
+    from workloads import kog_problem_set_device
+    probs = kog_problem_set_device(256, SEED_BASE + 5)
+    mats = [p["A"] for p in probs]
+    tols = [1e-14 if p["cplx"] else 1e-7 for p in probs]
+    small = sorted(range(len(probs)), key=lambda i: probs[i]["order"])[:6]
+    host = {i: np.asfortranarray(mats[i].cpu().numpy()) for i in small}
+    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH | S.SVD2_KOG_TWO_STEP)
+    for i, (p, r) in enumerate(zip(probs, res)):
+        assert r["status"] == 0 and r["off_rel"] < tols[i], (i, p["order"], r)
+        sig = S.kog_sigma(mats[i]).cpu().numpy().astype(np.float64)
+        eps = 2.0 ** -52 if p["cplx"] else 2.0 ** -23
+        assert np.max(np.abs(sig - p["sigma"])) <= 8 * p["order"] * eps * p["sigma"][0], (i, p["order"])
+    for i in small:
+        ro = O.kog_solve(host[i], tol=tols[i], max_sweeps=40)
+        assert ro["status"] == 0 and ro["sweeps"] == res[i]["sweeps"], (i, probs[i]["order"])
+        assert np.array_equal(_bits(mats[i].cpu().numpy()), _bits(host[i])), (i, probs[i]["order"])
