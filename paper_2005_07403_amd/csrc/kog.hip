@@ -1290,7 +1290,7 @@ template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, in
 }
 
 template <class T, bool CPLX> int fused_grid(int N) {
-  static int cus = 0, per = 0;  // CU count and occupancy of this kernel (device 0's shape)
+  thread_local int cus = 0, per = 0;  // CU count and occupancy of this kernel (first device used)
   if (cus == 0) {
     int dev = 0, c = 0, p = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -1337,8 +1337,9 @@ struct TwoStepShape {
   size_t lds;
 };
 template <class T, bool CPLX> TwoStepShape two_step_shape(int N) {
-  static int cached_N = 0, cached_wpg = 0, cached_lc = 0;
-  static TwoStepShape cached{};
+  // per host thread: concurrent solves on other threads do not share it
+  thread_local int cached_N = 0, cached_wpg = 0, cached_lc = 0;
+  thread_local TwoStepShape cached{};
   const TileRule r = rule2_for(N);
   if (N == cached_N && r.kc == cached_wpg && r.lc == cached_lc) return cached;
   TwoStepShape sh{};
