@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsvd2.so")
-SOURCES = ["svd2_batch.hip", "kog.hip", "kog_sigma.hip"]
+SOURCES = ["svd2_batch.hip", "kog.hip", "kog_batch.hip", "kog_sigma.hip"]
 ARCH = os.environ.get("SVD2_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,612 @@
+// kog_batch.hip -- many Kogbetliantz problems of uneven order and mixed
+// element type solved together (device-side convergence, hipGraph replay,
+// work-list compaction; one or two steps per pass).  The shared device code is
+// in kog_device.hpp.
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "kog_device.hpp"
+
+namespace {
+
+using namespace kog;
+
+// ---------------------------------------------------------------------------
+// Many problems of uneven order and mixed element type in one launch per
+// phase.  A step of the batch is three kernels over a static work list:
+// pivot chunks (gather + 2x2 SVD) of every active problem, update tiles of
+// every active problem (each with its own tile shape and the off-diagonal mass
+// it wrote), and a per-problem finish (advance the step, and at the end of a
+// problem's sweep decide convergence on the device).  The host replays a
+// hipGraph of K such steps and reads one counter per replay.
+//
+// In the two-step mode a pass takes every running problem two steps further
+// (pivots of both steps, then the two-step tiles, out of place between the
+// problem's matrix and a second one in the workspace), except the last step
+// of a sweep (t = N-2; a sweep has an odd number of steps), which is a single
+// in-place step with the convergence test as above.  The work list holds the
+// tiles of both kinds; a tile of the kind a problem does not need in this
+// pass returns at once.
+// ---------------------------------------------------------------------------
+struct DevProb {
+  void *A;
+  long long lda, piv_off, out_off;  // buffer offsets in bytes from the workspace base
+  long long piv1_off, out1_off;     // second rotation set (two-step mode)
+  long long w_off;                  // second matrix (two-step mode), lda = N
+  int N, kind, kc, lc;
+  int part_off, ntiles, max_sweeps, in_w;  // in_w: the iterate is in the second matrix
+  int gx2, ny2, lc2, pad0;          // two-step tiles: row blocks, column tiles, pairs per wavefront
+  double tol, tot0;                 // tot0 = ||A_0||_F
+  int t, sweeps, status, pad1;      // status: 0 running, 1 converged, 2 max_sweeps reached
+  double off_rel;
+};
+struct BatchHdr {
+  int nA, nB, nprob, active;
+  int c0[5];  // two-step tiles of element type k: items [c0[k], c0[k+1])
+  int pad[3];
+};
+
+__host__ __device__ inline size_t arr_bytes(int N, int esz) {
+  return (((size_t)(N / 2) * esz) + 255) & ~size_t(255);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ Bufs<T, CPLX> bufs_of(char *ws, const DevProb &P, int set = 0) {
+  Bufs<T, CPLX> b;
+  size_t arr = arr_bytes(P.N, sizeof(T));
+  const long long po = set ? P.piv1_off : P.piv_off, oo = set ? P.out1_off : P.out_off;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(ws + po + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(ws + oo + i * arr);
+  return b;
+}
+
+// the matrix that holds the iterate (other = false) or the other one
+template <class T, bool CPLX>
+__device__ __forceinline__ Mat<T, CPLX> mat_of(char *ws, const DevProb &P, bool other = false) {
+  if (P.in_w != (other ? 1 : 0)) return Mat<T, CPLX>{(T *)(ws + P.w_off), (size_t)P.N};
+  return Mat<T, CPLX>{(T *)P.A, (size_t)P.lda};
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ void batch_pivot(char *ws, const DevProb &P, int k) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  Mat<T, CPLX> M = mat_of<T, CPLX>(ws, P);
+  Bufs<T, CPLX> B = bufs_of<T, CPLX>(ws, P);
+  T x[Bufs<T, CPLX>::NIN], y[Bufs<T, CPLX>::NOUT];
+  gather_one<T, CPLX>(M, P.N, P.t, k, x);
+  one_matrix<T, CPLX, RESC>(x, y, 2);
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) B.piv[i][k] = x[i];
+#pragma unroll
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) B.out[i][k] = y[i];
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ void batch_pivots2(char *ws, const DevProb &P, int k) {
+  pivots2_one<T, CPLX>(P.N, mat_of<T, CPLX>(ws, P), P.t, bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1),
+                       k);
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ double batch_update(char *ws, const DevProb &P, Tile tl) {
+  return update_tile<T, CPLX, true>(mat_of<T, CPLX>(ws, P), P.N, P.t, bufs_of<T, CPLX>(ws, P), tl);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ void batch_two_step(char *smem, char *ws, const DevProb &P, int bx, int by) {
+  two_step_tile<T, CPLX>(smem, P.N, mat_of<T, CPLX>(ws, P), mat_of<T, CPLX>(ws, P, true), P.t,
+                         bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1), kUpdBlock / 64,
+                         (kUpdBlock / 64) * P.lc2, P.lc2, bx, by);
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ void batch_norm(const DevProb &P, double &off, double &tot) {
+  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  for (int j = 0; j < P.N; ++j)
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) {
+      double a2 = abs2(M.ld(i, j));
+      tot += a2;
+      if (i != j) off += a2;
+    }
+}
+
+// this pass takes problem P two steps further
+__device__ __forceinline__ bool two_this_pass(int two, const DevProb &P) { return two && P.t + 1 < P.N - 1; }
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kUpdBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_init_kernel(BatchHdr *hdr, DevProb *probs) {
+  __shared__ double red[kUpdBlock];
+  for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
+    DevProb &P = probs[p];
+    double off = 0, tot = 0;
+    switch (P.kind) {
+      case SVD2_KOG_F64: batch_norm<double, false>(P, off, tot); break;
+      case SVD2_KOG_C128: batch_norm<double, true>(P, off, tot); break;
+      case SVD2_KOG_F32: batch_norm<float, false>(P, off, tot); break;
+      default: batch_norm<float, true>(P, off, tot); break;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (threadIdx.x == 0) {
+      double nrm = __builtin_sqrt(tot);
+      double rel = nrm > 0 ? __builtin_sqrt(off) / nrm : 0.0;
+      P.tot0 = nrm;
+      P.off_rel = rel;
+      P.t = 0;
+      P.sweeps = 0;
+      P.status = (rel < P.tol || nrm == 0) ? 1 : (P.max_sweeps == 0 ? 2 : 0);
+      if (P.status != 0) atomicSub(&hdr->active, 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, const BatchHdr *hdr,
+                                                                    const int2 *items, const DevProb *probs,
+                                                                    int two) {
+  const int nA = hdr->nA;
+  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
+    const int2 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0 || two_this_pass(two, P)) continue;
+    const int k = item.y * kUpdBlock + (int)threadIdx.x;
+    if (k >= P.N / 2) continue;
+    switch (P.kind) {
+      case SVD2_KOG_F64: batch_pivot<double, false>(ws, P, k); break;
+      case SVD2_KOG_C128: batch_pivot<double, true>(ws, P, k); break;
+      case SVD2_KOG_F32: batch_pivot<float, false>(ws, P, k); break;
+      default: batch_pivot<float, true>(ws, P, k); break;
+    }
+  }
+}
+
+// the pivots of both steps of the problems of one element type in a
+// two-step pass
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots2_kernel(char *ws, const BatchHdr *hdr,
+                                                                      const int2 *items, const DevProb *probs) {
+  const int nA = hdr->nA;
+  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
+    const int2 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.kind != KIND || P.status != 0 || !two_this_pass(1, P)) continue;
+    const int k = item.y * kUpdBlock + (int)threadIdx.x;
+    if (k < P.N / 2) batch_pivots2<T, CPLX>(ws, P, k);
+  }
+}
+
+// the two-step tiles (problem, row block, column tile) of the problems of one
+// element type in a two-step pass
+// (at least 3 wavefronts per SIMD: the complex FP64 instance would otherwise
+// take 171 VGPRs and run at 2; measured 3.5 % faster on the uneven batch)
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(kUpdBlock, 3) void kog_batch_two_step_kernel(char *ws, const BatchHdr *hdr,
+                                                                       const int4 *items, const DevProb *probs) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int c0 = hdr->c0[KIND], c1 = hdr->c0[KIND + 1];
+  for (int it = c0 + (int)blockIdx.x; it < c1; it += gridDim.x) {
+    const int4 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0 || !two_this_pass(1, P)) continue;
+    batch_two_step<T, CPLX>(kog_smem, ws, P, item.y, item.z);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+// single-step update tiles (problem, k0, l0, partial index) of the problems
+// not in a two-step pass
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, const BatchHdr *hdr,
+                                                                     const int4 *items, const DevProb *probs,
+                                                                     double *partials, int two) {
+  __shared__ double red[kUpdBlock];
+  const int nB = hdr->nB;
+  for (int it = blockIdx.x; it < nB; it += gridDim.x) {
+    const int4 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0 || two_this_pass(two, P)) continue;
+    const Tile tl{item.y, P.kc, item.z, P.lc};
+    double off2;
+    switch (P.kind) {
+      case SVD2_KOG_F64: off2 = batch_update<double, false>(ws, P, tl); break;
+      case SVD2_KOG_C128: off2 = batch_update<double, true>(ws, P, tl); break;
+      case SVD2_KOG_F32: off2 = batch_update<float, false>(ws, P, tl); break;
+      default: off2 = batch_update<float, true>(ws, P, tl); break;
+    }
+    off2 = block_sum(off2, red);
+    if (threadIdx.x == 0) partials[P.part_off + item.w] = off2;
+  }
+}
+
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *hdr, DevProb *probs,
+                                                                     const double *partials, int two) {
+  __shared__ double red[kUpdBlock];
+  for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
+    DevProb &P = probs[p];
+    // every thread reads the state before thread 0 changes it
+    const int status = P.status, t = P.t, N = P.N;
+    __syncthreads();
+    if (status != 0) continue;
+    if (two && t + 1 < N - 1) {  // a two-step pass: no sweep ends inside it
+      if (threadIdx.x == 0) {
+        P.t = t + 2;
+        P.in_w ^= 1;
+      }
+      continue;
+    }
+    const bool sweep_end = t == N - 2;
+    double off2 = 0;
+    if (sweep_end) {
+      for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) off2 += partials[P.part_off + i];
+      off2 = block_sum(off2, red);
+    }
+    if (threadIdx.x == 0) {
+      if (sweep_end) {
+        int sw = P.sweeps + 1;
+        double rel = P.tot0 > 0 ? __builtin_sqrt(off2) / P.tot0 : 0.0;
+        P.sweeps = sw;
+        P.off_rel = rel;
+        if (rel < P.tol) P.status = 1;
+        else if (sw >= P.max_sweeps) P.status = 2;
+        if (P.status != 0) atomicSub(&hdr->active, 1);
+      }
+      P.t = t + 1 == N - 1 ? 0 : t + 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batch host driver
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+  size_t hdr, probs, itemsA, itemsB, itemsC, parts, bufs, total;
+  size_t lds[4];  // two-step LDS bytes per element type
+  int maxA, maxB, maxC, nparts;
+  int maxC_kind[4];
+};
+
+int esz_of(int kind) { return (kind == SVD2_KOG_F64 || kind == SVD2_KOG_C128) ? 8 : 4; }
+bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
+
+// column pairs per wavefront of the two-step tiles in a batch (workgroups of
+// kUpdBlock / 64 wavefronts).  Fixed rather than taken from the single-problem
+// shape table: a lone small problem wants many small tiles for parallelism,
+// while a batch has parallelism from its many problems and loses to the halo
+// reads of small tiles (256-problem batch: 8.6 s with 8, 9.5 s with the
+// single-problem shapes).
+int batch_lc2(int) { return 8; }
+
+size_t two_step_lds_of(int kind, int span) {
+  const int wpg = kUpdBlock / 64;
+  switch (kind) {
+    case SVD2_KOG_F64: return two_step_lds<double, false>(wpg, span);
+    case SVD2_KOG_C128: return two_step_lds<double, true>(wpg, span);
+    case SVD2_KOG_F32: return two_step_lds<float, false>(wpg, span);
+    default: return two_step_lds<float, true>(wpg, span);
+  }
+}
+
+svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::vector<DevProb> *dp,
+                         bool two) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  if (nprob < 0 || nprob > (1 << 20)) return SVD2_ERR_SIZE;
+  if (nprob > 0 && !pr) return SVD2_ERR_NULL;
+  L.maxA = L.maxB = L.maxC = L.nparts = 0;
+  for (int k = 0; k < 4; ++k) {
+    L.lds[k] = 0;
+    L.maxC_kind[k] = 0;
+  }
+  size_t bufs = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const kog_problem &q = pr[p];
+    if (q.dtype < SVD2_KOG_F64 || q.dtype > SVD2_KOG_C64) return SVD2_ERR_FLAGS;
+    if (q.N < 2 || q.N % 2 || q.lda < q.N || q.N > (1 << 19)) return SVD2_ERR_SIZE;
+    if (q.max_sweeps < 0 || !(q.tol >= 0)) return SVD2_ERR_SIZE;
+    int n = q.N / 2;
+    TileRule r = rule_for(q.N);
+    int kt = (n + r.kc - 1) / r.kc, lt = (n + r.lc - 1) / r.lc;
+    int nin = cplx_of(q.dtype) ? 8 : 4, nout = cplx_of(q.dtype) ? 19 : 11;
+    size_t arr = arr_bytes(q.N, esz_of(q.dtype));
+    const int lc2 = batch_lc2(q.N), span = (kUpdBlock / 64) * lc2;
+    const int gx2 = (n + kShiftOut - 1) / kShiftOut, ny2 = (n + span - 1) / span;
+    const size_t set = (nin + nout) * arr;
+    const size_t wbytes = up((size_t)q.N * q.N * esz_of(q.dtype) * (cplx_of(q.dtype) ? 2 : 1));
+    if (dp) {
+      DevProb d = {};
+      d.A = q.A;
+      d.lda = q.lda;
+      d.N = q.N;
+      d.kind = q.dtype;
+      d.kc = r.kc;
+      d.lc = r.lc;
+      d.part_off = L.nparts;
+      d.ntiles = kt * lt;
+      d.max_sweeps = q.max_sweeps;
+      d.tol = q.tol;
+      d.piv_off = (long long)bufs;  // relative to the buffer region; rebased below
+      d.out_off = (long long)(bufs + nin * arr);
+      if (two) {
+        d.piv1_off = (long long)(bufs + set);
+        d.out1_off = (long long)(bufs + set + nin * arr);
+        d.w_off = (long long)(bufs + 2 * set);
+        d.gx2 = gx2;
+        d.ny2 = ny2;
+        d.lc2 = lc2;
+      }
+      dp->push_back(d);
+    }
+    bufs += two ? 2 * set + wbytes : set;
+    L.maxA += (n + kUpdBlock - 1) / kUpdBlock;
+    L.maxB += kt * lt;
+    L.maxC += two ? gx2 * ny2 : 0;
+    L.maxC_kind[q.dtype] += two ? gx2 * ny2 : 0;
+    L.nparts += kt * lt;
+    if (two) {
+      size_t l = two_step_lds_of(q.dtype, span);
+      if (l > L.lds[q.dtype]) L.lds[q.dtype] = l;
+    }
+  }
+  L.hdr = 0;
+  L.probs = 256;
+  L.itemsA = L.probs + up((size_t)nprob * sizeof(DevProb));
+  L.itemsB = L.itemsA + up((size_t)L.maxA * sizeof(int2));
+  L.itemsC = L.itemsB + up((size_t)L.maxB * sizeof(int4));
+  L.parts = L.itemsC + up((size_t)L.maxC * sizeof(int4));
+  L.bufs = L.parts + up((size_t)L.nparts * sizeof(double));
+  L.total = L.bufs + bufs;
+  if (dp)
+    for (DevProb &d : *dp) {
+      d.piv_off += (long long)L.bufs;
+      d.out_off += (long long)L.bufs;
+      if (two) {
+        d.piv1_off += (long long)L.bufs;
+        d.out1_off += (long long)L.bufs;
+        d.w_off += (long long)L.bufs;
+      }
+    }
+  return SVD2_OK;
+}
+
+// work lists of the problems still running
+void build_items(const std::vector<DevProb> &dp, std::vector<int2> &A, std::vector<int4> &B,
+                 std::vector<int4> &C, int *c0, bool two) {
+  A.clear();
+  B.clear();
+  C.clear();
+  for (int kind = 0; kind < 4; ++kind) {  // two-step tiles, grouped by element type
+    c0[kind] = (int)C.size();
+    if (!two) continue;
+    for (int p = 0; p < (int)dp.size(); ++p) {
+      const DevProb &d = dp[p];
+      if (d.status != 0 || d.kind != kind) continue;
+      for (int y = 0; y < d.ny2; ++y)
+        for (int x = 0; x < d.gx2; ++x) C.push_back(int4{p, x, y, 0});
+    }
+  }
+  c0[4] = (int)C.size();
+  for (int p = 0; p < (int)dp.size(); ++p) {
+    const DevProb &d = dp[p];
+    if (d.status != 0) continue;
+    int n = d.N / 2;
+    for (int c = 0; c * kUpdBlock < n; ++c) A.push_back(int2{p, c});
+    int kt = (n + d.kc - 1) / d.kc, lt = (n + d.lc - 1) / d.lc;
+    for (int j = 0; j < lt; ++j)
+      for (int i = 0; i < kt; ++i) B.push_back(int4{p, i * d.kc, j * d.lc, j * kt + i});
+  }
+}
+
+struct BatchRun {
+  char *ws;
+  BatchLayout L;
+  hipStream_t st;
+  int gA, gB, gF, two;
+};
+
+template <class T, bool CPLX, int KIND> svd2_status batch_two_step_launch(const BatchRun &r, hipStream_t st) {
+  if (r.L.maxC_kind[KIND] == 0) return SVD2_OK;
+  BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
+  DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  hipLaunchKernelGGL((kog_batch_pivots2_kernel<T, CPLX, KIND>), dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int2 *)(r.ws + r.L.itemsA), probs);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  const int g = r.L.maxC_kind[KIND] < 16384 ? r.L.maxC_kind[KIND] : 16384;
+  hipLaunchKernelGGL((kog_batch_two_step_kernel<T, CPLX, KIND>), dim3(g), dim3(kUpdBlock), r.L.lds[KIND], st,
+                     r.ws, hdr, (const int4 *)(r.ws + r.L.itemsC), probs);
+  return hip_st(hipGetLastError());
+}
+
+svd2_status batch_step(const BatchRun &r, hipStream_t st) {
+  BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
+  DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  hipLaunchKernelGGL(kog_batch_pivot_kernel, dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int2 *)(r.ws + r.L.itemsA), probs, r.two);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.two);
+  s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, false, SVD2_KOG_F64>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, true, SVD2_KOG_C128>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, false, SVD2_KOG_F32>(r, st);
+  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, true, SVD2_KOG_C64>(r, st);
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_finish_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, hdr, probs,
+                     (const double *)(r.ws + r.L.parts), r.two);
+  return hip_st(hipGetLastError());
+}
+
+svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int active) {
+  std::vector<int2> A;
+  std::vector<int4> B, C;
+  BatchHdr h = {};
+  build_items(dp, A, B, C, h.c0, r.two != 0);
+  h.nA = (int)A.size();
+  h.nB = (int)B.size();
+  h.nprob = (int)dp.size();
+  h.active = active;
+  svd2_status s = hip_st(hipMemcpyAsync(r.ws + r.L.hdr, &h, sizeof h, hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !A.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsA, A.data(), A.size() * sizeof(int2), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !B.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsB, B.data(), B.size() * sizeof(int4), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK && !C.empty())
+    s = hip_st(hipMemcpyAsync(r.ws + r.L.itemsC, C.data(), C.size() * sizeof(int4), hipMemcpyHostToDevice, r.st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(r.st));
+  return s;
+}
+
+svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  if (flags & ~(unsigned)(SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;
+  BatchRun r;
+  r.two = (flags & SVD2_KOG_TWO_STEP) ? 1 : 0;
+  std::vector<DevProb> dp;
+  svd2_status s = batch_layout(nprob, pr, r.L, &dp, r.two != 0);
+  if (s != SVD2_OK) return s;
+  if (nprob == 0) return SVD2_OK;
+  if (!ws) return SVD2_ERR_NULL;
+  if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
+  if (wsb < r.L.total) return SVD2_ERR_SIZE;
+  for (int p = 0; p < nprob; ++p) {
+    const kog_problem &q = pr[p];
+    if (!q.A) return SVD2_ERR_NULL;
+    int e = esz_of(q.dtype) * (cplx_of(q.dtype) ? 2 : 1);
+    if ((uintptr_t)q.A % e) return SVD2_ERR_ALIGN;
+    uintptr_t a0 = (uintptr_t)q.A, a1 = a0 + ((size_t)q.lda * (q.N - 1) + q.N) * e;
+    uintptr_t w0 = (uintptr_t)ws, w1 = w0 + r.L.total;
+    if (a0 < w1 && w0 < a1) return SVD2_ERR_ALIAS;
+  }
+  r.ws = (char *)ws;
+  r.st = st;
+  r.gA = r.L.maxA < 8192 ? r.L.maxA : 8192;
+  r.gB = r.L.maxB < 16384 ? r.L.maxB : 16384;
+  r.gF = nprob < 1024 ? nprob : 1024;
+  // problem table and the full work lists
+  s = hip_st(hipMemcpyAsync(r.ws + r.L.probs, dp.data(), dp.size() * sizeof(DevProb), hipMemcpyHostToDevice, st));
+  if (s == SVD2_OK) s = upload_items(r, dp, nprob);
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_batch_init_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, (BatchHdr *)(r.ws + r.L.hdr),
+                     (DevProb *)(r.ws + r.L.probs));
+  s = hip_st(hipGetLastError());
+  long long max_steps = 0;  // passes: steps, or (N/2 per sweep) two-step passes
+  for (const DevProb &d : dp) {
+    long long m = (long long)d.max_sweeps * (r.two ? d.N / 2 : d.N - 1);
+    if (m > max_steps) max_steps = m;
+  }
+  const int K = 64;  // passes per replay / between host checks
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  auto capture = [&]() -> svd2_status {
+    if (exec) {
+      hipGraphExecDestroy(exec);
+      exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    svd2_status c = hip_st(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    if (c != SVD2_OK) return c;
+    svd2_status c1 = SVD2_OK;
+    for (int i = 0; i < K && c1 == SVD2_OK; ++i) c1 = batch_step(r, cap);
+    svd2_status c2 = hip_st(hipStreamEndCapture(cap, &g));
+    c = c1 != SVD2_OK ? c1 : c2;
+    if (c == SVD2_OK) c = hip_st(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    if (g) hipGraphDestroy(g);
+    return c;
+  };
+  if (s == SVD2_OK && (flags & SVD2_KOG_GRAPH)) {
+    s = hip_st(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (s == SVD2_OK) s = capture();
+  }
+  int active = nprob, built_for = nprob;
+  long long steps = 0;
+  while (s == SVD2_OK) {
+    BatchHdr h;
+    s = hip_st(hipMemcpyAsync(&h, r.ws + r.L.hdr, sizeof h, hipMemcpyDeviceToHost, st));
+    if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+    if (s != SVD2_OK) break;
+    active = h.active;
+    if (active <= 0 || steps > max_steps) break;
+    if (active * 10 < built_for * 7) {  // compact the work lists to the running problems
+      s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
+      if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+      if (s == SVD2_OK) s = upload_items(r, dp, active);
+      if (s != SVD2_OK) break;
+      built_for = active;
+    }
+    if (exec) {
+      s = hip_st(hipGraphLaunch(exec, st));
+    } else {
+      for (int i = 0; i < K && s == SVD2_OK; ++i) s = batch_step(r, st);
+    }
+    steps += K;
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (cap) hipStreamDestroy(cap);
+  if (s != SVD2_OK) return s;
+  s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+  if (s != SVD2_OK) return s;
+  // iterates left in the second matrix go back to the caller's
+  for (int p = 0; p < nprob && s == SVD2_OK; ++p) {
+    const DevProb &d = dp[p];
+    if (!d.in_w) continue;
+    const int grid = d.N < 4096 ? d.N : 4096;
+    char *w = r.ws + d.w_off;
+    switch (d.kind) {
+      case SVD2_KOG_F64:
+        hipLaunchKernelGGL((kog_copy_kernel<double, false>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<double, false>{(double *)w, (size_t)d.N}, Mat<double, false>{(double *)d.A, (size_t)d.lda});
+        break;
+      case SVD2_KOG_C128:
+        hipLaunchKernelGGL((kog_copy_kernel<double, true>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<double, true>{(double *)w, (size_t)d.N}, Mat<double, true>{(double *)d.A, (size_t)d.lda});
+        break;
+      case SVD2_KOG_F32:
+        hipLaunchKernelGGL((kog_copy_kernel<float, false>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<float, false>{(float *)w, (size_t)d.N}, Mat<float, false>{(float *)d.A, (size_t)d.lda});
+        break;
+      default:
+        hipLaunchKernelGGL((kog_copy_kernel<float, true>), dim3(grid), dim3(256), 0, st, d.N,
+                           Mat<float, true>{(float *)w, (size_t)d.N}, Mat<float, true>{(float *)d.A, (size_t)d.lda});
+        break;
+    }
+    s = hip_st(hipGetLastError());
+  }
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+  if (s != SVD2_OK) return s;
+  svd2_status all = SVD2_OK;
+  for (int p = 0; p < nprob; ++p) {
+    pr[p].sweeps = dp[p].sweeps;
+    pr[p].off_rel = dp[p].off_rel;
+    pr[p].status = dp[p].status == 1 ? SVD2_OK : SVD2_NOT_CONVERGED;
+    if (dp[p].status != 1) all = SVD2_NOT_CONVERGED;
+  }
+  return all;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsigned flags) {
+  BatchLayout L;
+  if (batch_layout(nprob, probs, L, nullptr, (flags & SVD2_KOG_TWO_STEP) != 0) != SVD2_OK) return 0;
+  return L.total;
+}
+
+size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs) {
+  return kog_batch_workspace_bytes_flags(nprob, probs, 0);
+}
+
+svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
+                            hipStream_t stream) {
+  return batch_solve(nprob, probs, ws, ws_bytes, flags, stream);
+}
+
+}  // extern "C"

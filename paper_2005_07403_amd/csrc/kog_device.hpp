@@ -1,0 +1,730 @@
+// kog_device.hpp -- the device side of the Kogbetliantz method shared by the
+// single-problem drivers (kog.hip) and the uneven batch (kog_batch.hip): the
+// circle-ordering pairs, the column-major matrix view, the pivot gather, the
+// rotations with the placement rule, the single-step update tile, and the
+// two-step (lane-shift) tile with its helpers.  Host helpers defined in
+// kog.hip that the batch driver also uses are declared at the end.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "svd2.h"
+#include "svd2_lane.hpp"
+
+namespace kog {
+
+using namespace svd2;
+
+constexpr int kUpdBlock = 256;   // threads per update workgroup
+constexpr int kRedBlocks = 1024; // partial sums of the norm reduction
+constexpr unsigned kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ void pair_ab(int t, int k, int M, int &a, int &b) {
+  if (k == 0) {
+    a = t;
+    b = M;
+  } else {
+    a = t + k;
+    if (a >= M) a -= M;
+    b = t - k;
+    if (b < 0) b += M;
+  }
+}
+
+template <class T, bool CPLX> struct Mat {
+  T *A;
+  size_t lda;
+  __device__ __forceinline__ Cx<T> ld(int i, int j) const {
+    size_t o = (size_t)i + (size_t)j * lda;
+    if constexpr (CPLX) {
+      typedef T V __attribute__((ext_vector_type(2)));
+      V v = *reinterpret_cast<const V *>(A + 2 * o);
+      return {v.x, v.y};
+    } else {
+      return {A[o], T(0)};
+    }
+  }
+  __device__ __forceinline__ void st(int i, int j, Cx<T> x) const {
+    size_t o = (size_t)i + (size_t)j * lda;
+    if constexpr (CPLX) {
+      typedef T V __attribute__((ext_vector_type(2)));
+      V v;
+      v.x = x.re;
+      v.y = x.im;
+      *reinterpret_cast<V *>(A + 2 * o) = v;
+    } else {
+      A[o] = x.re;
+    }
+  }
+};
+
+// Device-side view of the workspace: gathered pivots (SoA, NIN arrays of n)
+// and the batched-SVD outputs (NOUT arrays of n), as the batched kernels
+// read and write them.
+template <class T, bool CPLX> struct Bufs {
+  static constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  T *piv[NIN];
+  T *out[NOUT];
+};
+
+struct Bar {
+  unsigned count, gen, abort, pad;
+};
+
+struct Layout {
+  size_t piv, out, red, res, bar, flags, total;
+  size_t piv1, out1, mat, total2;  // two-step mode: second rotation set and a matrix buffer
+};
+constexpr int kMaxFusedBlocks = 4096;  // barrier slots (64 bytes each)
+
+inline Layout layout(int N, size_t esz, bool cplx) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t n = (size_t)N / 2;
+  size_t nin = cplx ? 8 : 4, nout = cplx ? 19 : 11;
+  Layout L;
+  size_t arr = up(n * esz);
+  L.piv = 0;
+  L.out = L.piv + nin * arr;
+  L.red = L.out + nout * arr;
+  L.res = L.red + up(2 * kRedBlocks * sizeof(double));
+  L.bar = L.res + 256;
+  L.flags = L.bar + 256;
+  L.total = L.flags + (size_t)kMaxFusedBlocks * 64;
+  L.piv1 = L.total;
+  L.out1 = L.piv1 + nin * arr;
+  L.mat = L.out1 + nout * arr;
+  L.total2 = L.mat + up((size_t)N * N * esz * (cplx ? 2 : 1));
+  return L;
+}
+
+template <class T, bool CPLX> Bufs<T, CPLX> make_bufs(void *ws, int N, int set = 0) {
+  Layout L = layout(N, sizeof(T), CPLX);
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t arr = up((size_t)(N / 2) * sizeof(T));
+  Bufs<T, CPLX> b;
+  char *base = (char *)ws;
+  size_t piv = set ? L.piv1 : L.piv, out = set ? L.out1 : L.out;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + piv + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + out + i * arr);
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// gather: pivot block of pair k into the SoA trains (record order 11, 21, 12, 22)
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX>
+__device__ __forceinline__ void gather_one(const Mat<T, CPLX> &M, int N, int t, int k, T *x) {
+  int a, b;
+  pair_ab(t, k, N - 1, a, b);
+  int p = a < b ? a : b, q = a < b ? b : a;
+  Cx<T> e[4] = {M.ld(p, p), M.ld(q, p), M.ld(p, q), M.ld(q, q)};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x[2 * i] = e[i].re;
+      x[2 * i + 1] = e[i].im;
+    } else {
+      x[i] = e[i].re;
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// rotation of pair k as used by the update: U, V (swap applied), sigma at (p,p), (q,q)
+// ---------------------------------------------------------------------------
+template <class T> struct Rot {
+  Cx<T> u11, u21, u12, u22, v11, v21, v12, v22;
+  T sp, sq;
+};
+
+// out(e): element e of the SVD record (U, V, sigma); piv(e): of the pivot block
+template <class T, bool CPLX, class FO, class FP>
+__device__ __forceinline__ Rot<T> rot_of(FO out, FP piv) {
+  Rot<T> r;
+  constexpr int K = CPLX ? 16 : 8;
+  auto g = [&](int e) -> Cx<T> {
+    if constexpr (CPLX) return {out(2 * e), out(2 * e + 1)};
+    else return {out(e), T(0)};
+  };
+  r.u11 = g(0); r.u21 = g(1); r.u12 = g(2); r.u22 = g(3);
+  r.v11 = g(4); r.v21 = g(5); r.v12 = g(6); r.v22 = g(7);
+  r.sp = out(K);
+  r.sq = out(K + 1);
+  bool sw;
+  if constexpr (CPLX) {
+    T pr = piv(0), pi = piv(1), qr = piv(6), qi = piv(7);
+    sw = pr * pr + pi * pi < qr * qr + qi * qi;
+  } else {
+    sw = vabs(piv(0)) < vabs(piv(3));
+  }
+  if (sw) {
+    Cx<T> t;
+    t = r.u11; r.u11 = r.u12; r.u12 = t;
+    t = r.u21; r.u21 = r.u22; r.u22 = t;
+    t = r.v11; r.v11 = r.v12; r.v12 = t;
+    t = r.v21; r.v21 = r.v22; r.v22 = t;
+    T s = r.sp; r.sp = r.sq; r.sq = s;
+  }
+  return r;
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ Rot<T> load_rot(const Bufs<T, CPLX> &B, int k) {
+  return rot_of<T, CPLX>([&](int e) { return B.out[e][k]; }, [&](int e) { return B.piv[e][k]; });
+}
+
+template <class T> __device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+
+// B' = (U_k^* B) V_l, in the oracle's rounding order
+template <class T, bool CPLX>
+__device__ __forceinline__ void rotate_block(const Rot<T> &u, const Rot<T> &v, Cx<T> &b11,
+                                             Cx<T> &b21, Cx<T> &b12, Cx<T> &b22) {
+  if constexpr (CPLX) {
+    Cx<T> t11 = cadd(cmulc(u.u11, b11), cmulc(u.u21, b21));
+    Cx<T> t21 = cadd(cmulc(u.u12, b11), cmulc(u.u22, b21));
+    Cx<T> t12 = cadd(cmulc(u.u11, b12), cmulc(u.u21, b22));
+    Cx<T> t22 = cadd(cmulc(u.u12, b12), cmulc(u.u22, b22));
+    b11 = cadd(cmul(t11, v.v11), cmul(t12, v.v21));
+    b12 = cadd(cmul(t11, v.v12), cmul(t12, v.v22));
+    b21 = cadd(cmul(t21, v.v11), cmul(t22, v.v21));
+    b22 = cadd(cmul(t21, v.v12), cmul(t22, v.v22));
+  } else {
+    T t11 = vfma(u.u11.re, b11.re, u.u21.re * b21.re);
+    T t21 = vfma(u.u12.re, b11.re, u.u22.re * b21.re);
+    T t12 = vfma(u.u11.re, b12.re, u.u21.re * b22.re);
+    T t22 = vfma(u.u12.re, b12.re, u.u22.re * b22.re);
+    b11.re = vfma(t11, v.v11.re, t12 * v.v21.re);
+    b12.re = vfma(t11, v.v12.re, t12 * v.v22.re);
+    b21.re = vfma(t21, v.v11.re, t22 * v.v21.re);
+    b22.re = vfma(t21, v.v12.re, t22 * v.v22.re);
+  }
+}
+
+// One update tile: row pairs [k0, k0 + kc) x column pairs [l0, l0 + lc), on a
+// workgroup of kUpdBlock threads: thread i takes row pair k0 + i % kc and every
+// (kUpdBlock / kc)-th column pair of the tile (kc in {64, 128, 256}, so small
+// orders still fill the workgroup).  Rows are addressed by (a, b) so that the
+// loads and stores of a wavefront form contiguous runs; the orientation
+// p < q is applied in registers.  The loads of UpdG column pairs are issued
+// before their stores (the compiler cannot move a load past a store to the
+// same matrix).  With ACC the thread returns the sum of |a_ij|^2 over the
+// off-diagonal entries it wrote (FP64), for the convergence test.
+struct Tile {
+  int k0, kc, l0, lc;
+};
+template <bool CPLX> struct UpdG { static constexpr int v = CPLX ? 2 : 4; };
+
+template <class T> __device__ __forceinline__ double abs2(Cx<T> x) {
+  return (double)x.re * (double)x.re + (double)x.im * (double)x.im;
+}
+
+template <class T, bool CPLX, bool ACC>
+__device__ __forceinline__ double update_tile(const Mat<T, CPLX> &M, int N, int t,
+                                              const Bufs<T, CPLX> &B, Tile tl) {
+  constexpr int G = UpdG<CPLX>::v;
+  const int n = N / 2, Mo = N - 1;
+  const int groups = kUpdBlock / tl.kc;
+  const int k = tl.k0 + (int)threadIdx.x % tl.kc;
+  const int g = (int)threadIdx.x / tl.kc;
+  double off2 = 0.0;
+  if (k >= n) return off2;
+  int ra, rb;
+  pair_ab(t, k, Mo, ra, rb);
+  const bool kflip = ra > rb;  // then p = rb, q = ra
+  Rot<T> u = load_rot<T, CPLX>(B, k);
+  const int lend = tl.l0 + tl.lc < n ? tl.l0 + tl.lc : n;
+  for (int lb = tl.l0 + g; lb < lend; lb += groups * G) {
+    Cx<T> xa1[G], xb1[G], xa2[G], xb2[G];
+    int cp[G], cq[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      int l = lb + groups * j;
+      if (l < lend) {
+        int ca, cb;
+        pair_ab(t, l, Mo, ca, cb);
+        cp[j] = ca < cb ? ca : cb;
+        cq[j] = ca < cb ? cb : ca;
+        xa1[j] = M.ld(ra, cp[j]);
+        xb1[j] = M.ld(rb, cp[j]);
+        xa2[j] = M.ld(ra, cq[j]);
+        xb2[j] = M.ld(rb, cq[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      int l = lb + groups * j;
+      if (l < lend) {
+        Cx<T> b11 = kflip ? xb1[j] : xa1[j], b21 = kflip ? xa1[j] : xb1[j];
+        Cx<T> b12 = kflip ? xb2[j] : xa2[j], b22 = kflip ? xa2[j] : xb2[j];
+        if (l == k) {  // pivot block: diag(sigma_p, sigma_q), exact zeros elsewhere
+          b11 = Cx<T>{u.sp, T(0)};
+          b22 = Cx<T>{u.sq, T(0)};
+          b12 = b21 = Cx<T>{T(0), T(0)};
+        } else {
+          Rot<T> v = load_rot<T, CPLX>(B, l);
+          rotate_block<T, CPLX>(u, v, b11, b21, b12, b22);
+          if (ACC) off2 += (abs2(b11) + abs2(b21)) + (abs2(b12) + abs2(b22));
+        }
+        M.st(ra, cp[j], kflip ? b21 : b11);
+        M.st(rb, cp[j], kflip ? b11 : b21);
+        M.st(ra, cq[j], kflip ? b22 : b12);
+        M.st(rb, cq[j], kflip ? b12 : b22);
+      }
+    }
+  }
+  return off2;
+}
+
+// tile shape by order: the first rule with N <= max_order applies
+struct TileRule {
+  int max_order, kc, lc;
+};
+constexpr int kMaxRules = 16;
+__host__ __device__ inline TileRule default_rule() { return TileRule{0x7fffffff, 256, 8}; }
+
+
+// ---------------------------------------------------------------------------
+// two steps per pass (out of place).  Under the circle ordering row x is paired
+// with partner_t(x) = (2t - x) mod (N-1) at step t, so a 2x2 output block of
+// step t+1 (rows {p', q'}, columns {p'', q''}) depends only on the rows
+// {p', q', partner_t(p'), partner_t(q')} and the matching columns of the
+// matrix before step t: each entry after step t is one entry of one rotated
+// 2x2 block of step t.  Every entry is computed with exactly the operations of
+// the single-step update, so two steps per pass are bitwise equal to two
+// single steps; the pivots of step t+1 are such entries too, so the rotations
+// of step t+1 are known before the matrix is touched.
+// ---------------------------------------------------------------------------
+// pair index of row x at step t and its partner
+__device__ __forceinline__ void pos_at(int t, int x, int M, int n, int &k, int &partner) {
+  if (x == t) {
+    k = 0;
+    partner = M;
+  } else if (x == M) {
+    k = 0;
+    partner = t;
+  } else {
+    int d = x - t;
+    if (d < 0) d += M;
+    k = d < n ? d : M - d;
+    int pr = 2 * t - x;
+    if (pr < 0) pr += M;
+    if (pr >= M) pr -= M;
+    partner = pr;
+  }
+}
+
+// one row (or column) of a step-(t+1) block, seen from step t
+struct Side {
+  int x, partner, k;
+  bool isq;  // x is the q (larger) index of its step-t pair
+};
+__device__ __forceinline__ Side side_at(int t, int x, int M, int n) {
+  Side s;
+  s.x = x;
+  pos_at(t, x, M, n, s.k, s.partner);
+  s.isq = x > s.partner;
+  return s;
+}
+
+template <class T> struct RotU {
+  Cx<T> u11, u21, u12, u22;
+  T sp, sq;
+};
+template <class T> struct RotV {
+  Cx<T> v11, v21, v12, v22;
+};
+template <class T, bool CPLX> __device__ __forceinline__ RotU<T> load_u(const Bufs<T, CPLX> &B, int k) {
+  Rot<T> r = load_rot<T, CPLX>(B, k);
+  return RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
+}
+// entry (role of the row, role of the column) of U^* B V for a step-t block
+// B given in (p-row, q-row) x (p-col, q-col) order; the operations are those
+// of rotate_block for that entry
+template <class T, bool CPLX>
+__device__ __forceinline__ Cx<T> rotated_entry(const RotU<T> &u, bool rq, const RotV<T> &v, bool cq, Cx<T> b11,
+                                               Cx<T> b21, Cx<T> b12, Cx<T> b22) {
+  if constexpr (CPLX) {
+    Cx<T> ua = rq ? u.u12 : u.u11, ub = rq ? u.u22 : u.u21;
+    Cx<T> t1 = cadd(cmulc(ua, b11), cmulc(ub, b21));
+    Cx<T> t2 = cadd(cmulc(ua, b12), cmulc(ub, b22));
+    Cx<T> va = cq ? v.v12 : v.v11, vb = cq ? v.v22 : v.v21;
+    return cadd(cmul(t1, va), cmul(t2, vb));
+  } else {
+    T ua = rq ? u.u12.re : u.u11.re, ub = rq ? u.u22.re : u.u21.re;
+    T t1 = vfma(ua, b11.re, ub * b21.re);
+    T t2 = vfma(ua, b12.re, ub * b22.re);
+    T va = cq ? v.v12.re : v.v11.re, vb = cq ? v.v22.re : v.v21.re;
+    return Cx<T>{vfma(t1, va, t2 * vb), T(0)};
+  }
+}
+
+// A(r, c) after step t, from the matrix before it: xrc = A(r, c), xrp = A(r,
+// partner_c), xpc = A(partner_r, c), xpp = A(partner_r, partner_c)
+template <class T, bool CPLX>
+__device__ __forceinline__ Cx<T> after_step(const Side &r, const RotU<T> &ur, const Side &c, const RotV<T> &vc,
+                                            Cx<T> xrc, Cx<T> xrp, Cx<T> xpc, Cx<T> xpp) {
+  if (r.k == c.k) {  // inside a pivot block of step t: diag(sigma_p, sigma_q), zeros elsewhere
+    if (r.x == c.x) return Cx<T>{r.isq ? ur.sq : ur.sp, T(0)};
+    return Cx<T>{T(0), T(0)};
+  }
+  // the step-t block in (p-row, q-row) x (p-col, q-col) order
+  Cx<T> b11 = r.isq ? (c.isq ? xpp : xpc) : (c.isq ? xrp : xrc);
+  Cx<T> b12 = r.isq ? (c.isq ? xpc : xpp) : (c.isq ? xrc : xrp);
+  Cx<T> b21 = r.isq ? (c.isq ? xrp : xrc) : (c.isq ? xpp : xpc);
+  Cx<T> b22 = r.isq ? (c.isq ? xrc : xrp) : (c.isq ? xpc : xpp);
+  return rotated_entry<T, CPLX>(ur, r.isq, vc, c.isq, b11, b21, b12, b22);
+}
+
+
+// pivots of steps t and t+1 in one launch: lane k computes the SVD of pair k
+// of step t (into B0) and, for pair k of step t+1, recomputes the step-t SVDs
+// of the two pairs its rows belong to (the same arithmetic on the same
+// inputs, so bitwise the rotations in B0), forms that pivot block after step
+// t and computes its SVD (into B1)
+template <class T, bool CPLX>
+__device__ __forceinline__ void pivots2_one(int N, const Mat<T, CPLX> &M, int t, const Bufs<T, CPLX> &B0,
+                                            const Bufs<T, CPLX> &B1, int k) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  constexpr int NI = Bufs<T, CPLX>::NIN, NO = Bufs<T, CPLX>::NOUT;
+  const int n = N / 2, Mo = N - 1;
+  int a, b;
+  pair_ab(t + 1, k, Mo, a, b);
+  const int p = a < b ? a : b, q = a < b ? b : a;
+  Side S[2] = {side_at(t, p, Mo, n), side_at(t, q, Mo, n)};
+  // every load first (the stores below could alias the matrix as far as the
+  // compiler knows): the three step-t pivot blocks and the 4x4 neighbourhood
+  T x0[NI], x1[NI], x2[NI];
+  gather_one<T, CPLX>(M, N, t, k, x0);
+  gather_one<T, CPLX>(M, N, t, S[0].k, x1);
+  gather_one<T, CPLX>(M, N, t, S[1].k, x2);
+  Cx<T> nb[2][2][2][2];  // [row i][col j][row or partner][col or partner]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      nb[i][j][0][0] = M.ld(S[i].x, S[j].x);
+      nb[i][j][0][1] = M.ld(S[i].x, S[j].partner);
+      nb[i][j][1][0] = M.ld(S[i].partner, S[j].x);
+      nb[i][j][1][1] = M.ld(S[i].partner, S[j].partner);
+    }
+  T y0[NO], y1[NO], y2[NO];
+  one_matrix<T, CPLX, RESC>(x0, y0, 2);
+  one_matrix<T, CPLX, RESC>(x1, y1, 2);
+  one_matrix<T, CPLX, RESC>(x2, y2, 2);
+  Rot<T> r1 = rot_of<T, CPLX>([&](int e) { return y1[e]; }, [&](int e) { return x1[e]; });
+  Rot<T> r2 = rot_of<T, CPLX>([&](int e) { return y2[e]; }, [&](int e) { return x2[e]; });
+  RotU<T> U[2] = {RotU<T>{r1.u11, r1.u21, r1.u12, r1.u22, r1.sp, r1.sq},
+                  RotU<T>{r2.u11, r2.u21, r2.u12, r2.u22, r2.sp, r2.sq}};
+  RotV<T> V[2] = {RotV<T>{r1.v11, r1.v21, r1.v12, r1.v22}, RotV<T>{r2.v11, r2.v21, r2.v12, r2.v22}};
+  Cx<T> e[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      e[i][j] = after_step<T, CPLX>(S[i], U[i], S[j], V[j], nb[i][j][0][0], nb[i][j][0][1], nb[i][j][1][0],
+                                    nb[i][j][1][1]);
+  Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
+  T x3[NI], y3[NO];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x3[2 * i] = rec[i].re;
+      x3[2 * i + 1] = rec[i].im;
+    } else {
+      x3[i] = rec[i].re;
+    }
+  }
+  one_matrix<T, CPLX, RESC>(x3, y3, 2);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) B0.piv[i][k] = x0[i];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) B0.out[i][k] = y0[i];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) B1.piv[i][k] = x3[i];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) B1.out[i][k] = y3[i];
+}
+
+
+// The two-step update proper ("lane-shift" form).  Lane j of a wavefront
+// holds the rows of pair j of step t (P_j = t + j and Q_j = t - j mod N-1;
+// pair 0 is rows t and N-1) and walks column pairs j' of step t in increasing
+// order: it reads each 2x2 block (P_j, Q_j) x (P_j', Q_j') once and rotates it
+// with U_j, V_j' as the single-step update would.  Pair k of step t+1 is made
+// of rows P_{k+1} and Q_{k-1} (k = 0: P_1 and N-1; k = 1: P_2 and t = P_0;
+// k = n-1: Q_{n-1} and Q_{n-2}), held one lane down and one lane up: they are
+// exchanged with lane shuffles.  Its column pair l is made of the columns of
+// iterations l+1 and l-1 of the walk (same exceptions), kept in a three-deep
+// register window.  A wavefront computes 64 pairs of step t and writes the 62
+// pairs of step t+1 it holds both neighbours for.
+//
+// The wavefronts of a workgroup share one block of rows and take consecutive
+// runs of lc output column pairs.  A wavefront's first output needs a column
+// of the wavefront before it and its last output one of the wavefront after
+// it: each publishes its first and last walked columns in LDS, and those two
+// outputs are written after a barrier.  Only the workgroup's outer edges read
+// a column pair outside their own outputs.
+constexpr int kShiftOut = 62;
+
+// value select (a ternary on lvalues would select addresses and spill)
+template <class T> __device__ __forceinline__ Cx<T> sel(bool c, Cx<T> x, Cx<T> y) {
+  return Cx<T>{c ? x.re : y.re, c ? x.im : y.im};
+}
+
+template <class T, bool CPLX> struct VPack {
+  static constexpr int W = CPLX ? 8 : 4;
+  T v[W];
+};
+template <class T, bool CPLX> __device__ __forceinline__ VPack<T, CPLX> pack_v(const Rot<T> &r) {
+  VPack<T, CPLX> p;
+  if constexpr (CPLX) {
+    p.v[0] = r.v11.re; p.v[1] = r.v11.im; p.v[2] = r.v21.re; p.v[3] = r.v21.im;
+    p.v[4] = r.v12.re; p.v[5] = r.v12.im; p.v[6] = r.v22.re; p.v[7] = r.v22.im;
+  } else {
+    p.v[0] = r.v11.re; p.v[1] = r.v21.re; p.v[2] = r.v12.re; p.v[3] = r.v22.re;
+  }
+  return p;
+}
+template <class T, bool CPLX> __device__ __forceinline__ Rot<T> with_v(const RotU<T> &u, const VPack<T, CPLX> &p) {
+  Rot<T> r;
+  r.u11 = u.u11; r.u21 = u.u21; r.u12 = u.u12; r.u22 = u.u22;
+  if constexpr (CPLX) {
+    r.v11 = Cx<T>{p.v[0], p.v[1]}; r.v21 = Cx<T>{p.v[2], p.v[3]};
+    r.v12 = Cx<T>{p.v[4], p.v[5]}; r.v22 = Cx<T>{p.v[6], p.v[7]};
+  } else {
+    r.v11 = Cx<T>{p.v[0], T(0)}; r.v21 = Cx<T>{p.v[1], T(0)};
+    r.v12 = Cx<T>{p.v[2], T(0)}; r.v22 = Cx<T>{p.v[3], T(0)};
+  }
+  r.sp = u.sp;
+  r.sq = u.sq;
+  return r;
+}
+
+// rows of pair j of step t
+__device__ __forceinline__ void rows_at(int t, int j, int Mo, int &P, int &Q) {
+  if (j == 0) {
+    P = t;
+    Q = Mo;
+  } else {
+    P = t + j;
+    if (P >= Mo) P -= Mo;
+    Q = t - j;
+    if (Q < 0) Q += Mo;
+  }
+}
+
+template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_dn1(Cx<T> x) {
+  Cx<T> r;
+  r.re = __shfl_down(x.re, 1, 64);
+  if constexpr (CPLX) r.im = __shfl_down(x.im, 1, 64);
+  else r.im = T(0);
+  return r;
+}
+template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_up1(Cx<T> x) {
+  Cx<T> r;
+  r.re = __shfl_up(x.re, 1, 64);
+  if constexpr (CPLX) r.im = __shfl_up(x.im, 1, 64);
+  else r.im = T(0);
+  return r;
+}
+
+// one column of the walk after the row exchange: the entries of the two rows
+// of step t+1's pair k = j, smaller row index first
+template <class T> struct ColPair {
+  Cx<T> lo, hi;
+};
+template <class T> __device__ __forceinline__ ColPair<T> selp(bool c, ColPair<T> x, ColPair<T> y) {
+  return ColPair<T>{sel(c, x.lo, y.lo), sel(c, x.hi, y.hi)};
+}
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; XCD c takes a contiguous run of the tiles (row
+// tile fastest), so tiles that share halo rows or columns run on the same L2
+// at about the same time.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  const int q = ntiles >> 3, r = ntiles & 7, c = bid & 7, k = bid >> 3;
+  return c * q + (c < r ? c : r) + k;
+}
+
+// LDS bytes of the two-step kernel: a workgroup of wpg wavefronts writes
+// span output column pairs
+template <class T, bool CPLX> constexpr size_t two_step_lds(int wpg, int span) {
+  return (size_t)(2 * span + 2) * sizeof(VPack<T, CPLX>) + (size_t)2 * wpg * 64 * sizeof(ColPair<T>);
+}
+
+// one tile: row block bx (62 row pairs), column tile by (span column pairs);
+// all threads of the workgroup call it (it synchronises the workgroup)
+// (the matrices are passed as restrict pointers: the pass reads one and
+// writes the other, so loads of later iterations may move past stores)
+template <class T, bool CPLX>
+__device__ __forceinline__ void two_step_tile_r(char *kog_smem, int N, T *__restrict__ mc, size_t ldc,
+                                                T *__restrict__ mn, size_t ldn, int t, const Bufs<T, CPLX> &B0,
+                                                const Bufs<T, CPLX> &B1, int wpg, int span, int lc, int bx,
+                                                int by) {
+  const Mat<T, CPLX> Mc{mc, ldc}, Mn{mn, ldn};
+  const int n = N / 2, Mo = N - 1, t1 = t + 1;
+  const int lane = (int)threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wavefront-uniform
+  const int L0 = by * span;                              // outputs of the workgroup: [L0, Lend)
+  const int Lend = L0 + span < n ? L0 + span : n;
+  const int jlo = L0 > 0 ? L0 - 1 : 0;                   // pairs walked by the workgroup: [jlo, jhi]
+  const int jhi = L0 + span < n - 1 ? L0 + span : n - 1;
+  VPack<T, CPLX> *sv = (VPack<T, CPLX> *)kog_smem;      // V of step t, index j' - jlo
+  VPack<T, CPLX> *sv1 = sv + (span + 2);                // V of step t+1, index l - L0
+  ColPair<T> *xhead = (ColPair<T> *)(sv1 + span);       // [wavefront][lane]: first walked P column
+  ColPair<T> *xtail = xhead + wpg * 64;                 // [wavefront][lane]: last own Q column
+  for (int i = threadIdx.x; i <= jhi - jlo; i += blockDim.x) sv[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B0, jlo + i));
+  for (int i = threadIdx.x; i < Lend - L0; i += blockDim.x) sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, L0 + i));
+  __syncthreads();
+
+  // this wavefront: outputs [l0w, oend), walk [aw, bw] (lc >= 2; the last
+  // wavefronts of a workgroup may have fewer outputs or none)
+  const int l0w = L0 + w * lc;
+  const int oend = l0w + lc < Lend ? l0w + lc : Lend;
+  const bool has = l0w < oend;
+  const bool next_has = w + 1 < wpg && l0w + lc < Lend;
+  const int aw = w == 0 ? jlo : l0w;
+  const int bw = next_has ? l0w + lc - 1 : (l0w + lc < n - 1 ? l0w + lc : n - 1);
+
+  const int j = bx * kShiftOut - 1 + lane;
+  const bool act = j >= 0 && j < n;
+  const bool out = act && lane >= 1 && lane <= kShiftOut;
+  int P = 0, Q = 1, ra = 0, rb = 0;
+  RotU<T> u{}, u1{};
+  if (act) {
+    rows_at(t, j, Mo, P, Q);
+    u = load_u<T, CPLX>(B0, j);
+  }
+  if (out) {
+    pair_ab(t1, j, Mo, ra, rb);
+    u1 = load_u<T, CPLX>(B1, j);
+  }
+  const bool rflip = P > Q, kflip = ra > rb;
+  const int rp = rflip ? Q : P, rq = rflip ? P : Q;        // rows of step t's pair j in (p, q) order
+  const int op = kflip ? rb : ra, oq = kflip ? ra : rb;     // rows of step t+1's pair j in (p, q) order
+  // the smaller output row takes the value from one lane up (rb) when kflip,
+  // else from one lane down (ra); the own-row exceptions of k = 0 and k = n-1
+  const bool lo_own = kflip ? j == 0 : j == n - 1, hi_own = kflip ? j == n - 1 : j == 0;
+  const Cx<T> zero{T(0), T(0)};
+
+  // column pair l of step t+1 from its columns ca(l) (cplus) and cb(l) (cminus)
+  auto emit = [&](int l, const ColPair<T> &cplus, const ColPair<T> &cminus) {
+    int ca, cb;
+    pair_ab(t1, l, Mo, ca, cb);
+    const bool lflip = ca > cb;
+    const int cp = lflip ? cb : ca, cq = lflip ? ca : cb;
+    Cx<T> c11 = sel(lflip, cminus.lo, cplus.lo), c21 = sel(lflip, cminus.hi, cplus.hi);
+    Cx<T> c12 = sel(lflip, cplus.lo, cminus.lo), c22 = sel(lflip, cplus.hi, cminus.hi);
+    if (l == j) {
+      c11 = Cx<T>{u1.sp, T(0)};
+      c22 = Cx<T>{u1.sq, T(0)};
+      c12 = c21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u1, sv1[l - L0]);
+      rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+    }
+    if (out) {
+      Mn.st(op, cp, c11);
+      Mn.st(oq, cp, c21);
+      Mn.st(op, cq, c12);
+      Mn.st(oq, cq, c22);
+    }
+  };
+
+  // the block (rp, rq) x (cp, cq) of one iteration, as loaded
+  struct Blk {
+    Cx<T> b11, b21, b12, b22;
+  };
+  auto load_blk = [&](int jj) -> Blk {
+    int Pc, Qc;
+    rows_at(t, jj, Mo, Pc, Qc);
+    const int cp = Pc < Qc ? Pc : Qc, cq = Pc < Qc ? Qc : Pc;
+    Blk d{zero, zero, zero, zero};
+    if (act) {
+      d.b11 = Mc.ld(rp, cp);
+      d.b21 = Mc.ld(rq, cp);
+      d.b12 = Mc.ld(rp, cq);
+      d.b22 = Mc.ld(rq, cq);
+    }
+    return d;
+  };
+  ColPair<T> prev1P{zero, zero}, prev1Q{zero, zero}, prev2m{zero, zero}, firstc{zero, zero};
+  if (has) {
+    Blk nx = load_blk(aw);  // the block of the next iteration is in flight
+    for (int jj = aw; jj <= bw; ++jj) {
+      const Blk a = nx;
+      if (jj < bw) nx = load_blk(jj + 1);
+      // step t on the block (j, jj), in (p, q) order
+      int Pc, Qc;
+      rows_at(t, jj, Mo, Pc, Qc);
+      const bool cflip = Pc > Qc;
+      Cx<T> b11 = a.b11, b21 = a.b21, b12 = a.b12, b22 = a.b22;
+      if (j == jj) {
+        b11 = Cx<T>{u.sp, T(0)};
+        b22 = Cx<T>{u.sq, T(0)};
+        b12 = b21 = zero;
+      } else {
+        Rot<T> r = with_v<T, CPLX>(u, sv[jj - jlo]);
+        rotate_block<T, CPLX>(r, r, b11, b21, b12, b22);
+      }
+      // to P/Q labels
+      const Cx<T> ePP = sel(rflip, sel(cflip, b22, b21), sel(cflip, b12, b11));
+      const Cx<T> eQP = sel(rflip, sel(cflip, b12, b11), sel(cflip, b22, b21));
+      const Cx<T> ePQ = sel(rflip, sel(cflip, b21, b22), sel(cflip, b11, b12));
+      const Cx<T> eQQ = sel(rflip, sel(cflip, b11, b12), sel(cflip, b21, b22));
+      // row exchange: ra(k) = P_{k+1} (one lane down) or Q_{n-1} (own, k = n-1);
+      // rb(k) = Q_{k-1} (one lane up), P_0 (k = 1) or N-1 = Q_0 (own, k = 0)
+      ColPair<T> curP, curQ;
+      {
+        Cx<T> dn = shfl_dn1<T, CPLX>(ePP), up = shfl_up1<T, CPLX>(sel(j == 0, ePP, eQP));
+        curP.lo = sel(lo_own, eQP, sel(kflip, up, dn));
+        curP.hi = sel(hi_own, eQP, sel(kflip, dn, up));
+        dn = shfl_dn1<T, CPLX>(ePQ);
+        up = shfl_up1<T, CPLX>(sel(j == 0, ePQ, eQQ));
+        curQ.lo = sel(lo_own, eQQ, sel(kflip, up, dn));
+        curQ.hi = sel(hi_own, eQQ, sel(kflip, dn, up));
+      }
+      if (jj == l0w && w > 0) {
+        xhead[w * 64 + lane] = curP;
+        if (l0w == n - 1) firstc = curQ;
+      }
+      if (jj == l0w + 1) firstc = curP;
+      if (next_has && jj == l0w + lc - 1) xtail[w * 64 + lane] = curQ;
+      const int l = jj - 1;
+      if (l >= l0w && l < oend && (l == 0 || l - 1 >= aw)) emit(l, curP, selp(l == 0, prev1Q, prev2m));
+      if (jj == n - 1 && n - 1 >= l0w && n - 1 < oend && n - 2 >= aw)
+        emit(n - 1, curQ, selp(n - 1 == 1, prev1P, prev1Q));
+      prev2m = selp(jj - 1 == 0, prev1P, prev1Q);
+      prev1P = curP;
+      prev1Q = curQ;
+    }
+  }
+  __syncthreads();
+  if (has && w > 0) emit(l0w, firstc, xtail[(w - 1) * 64 + lane]);
+  if (has && next_has) emit(l0w + lc - 1, xhead[(w + 1) * 64 + lane], prev2m);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ void two_step_tile(char *kog_smem, int N, const Mat<T, CPLX> &Mc,
+                                              const Mat<T, CPLX> &Mn, int t, const Bufs<T, CPLX> &B0,
+                                              const Bufs<T, CPLX> &B1, int wpg, int span, int lc, int bx, int by) {
+  two_step_tile_r<T, CPLX>(kog_smem, N, Mc.A, Mc.lda, Mn.A, Mn.lda, t, B0, B1, wpg, span, lc, bx, by);
+}
+
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_copy_kernel(int N, Mat<T, CPLX> src, Mat<T, CPLX> dst) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) dst.st(i, j, src.ld(i, j));
+}
+
+// host helpers defined in kog.hip
+svd2_status hip_st(hipError_t e);  // maps a HIP error, recording it for kog_last_hip_error
+TileRule rule_for(int N);          // single-step update tile shape by order
+
+}  // namespace kog
