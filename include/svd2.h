@@ -189,7 +189,14 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  *    U_k, V_k are swapped (sigma_min goes to (p,p)), keeping the rotations
  *    near the identity as the iteration converges;
  *  - stopping: off(A) = sqrt(sum_{i != j} |a_ij|^2) < tol * ||A_0||_F, tested
- *    before every sweep (one device-to-host copy per sweep).
+ *    before every sweep (one device-to-host copy per sweep);
+ *  - scaling: *_solve and kog_batch_solve multiply A by 2^-E before the
+ *    first sweep and by 2^E after the last, E the largest binary exponent
+ *    among its finite nonzero components (eq. (2) applied to the whole
+ *    matrix).  The factor is exact and commutes with the steps unless a value
+ *    reaches the subnormal range; it keeps the sums of squares of the
+ *    stopping test finite and nonzero for any finite A.  *_step and *_sweep
+ *    do not scale.
  * On return A holds the singular values on its diagonal (unsorted, >= 0).
  *
  * Storage: column-major, leading dimension lda >= N (in elements; complex
@@ -199,7 +206,8 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  * 256-byte aligned, not overlapping A; calls sharing a workspace must not
  * overlap.
  * Entry points enqueue on `stream`; *_solve synchronises the stream once per
- * sweep and returns when done.  Errors are as for the batched calls; a fused
+ * sweep and returns when done.  After an error return the contents of A are
+ * unspecified.  Errors are as for the batched calls; a fused
  * sweep whose grid barrier does not complete within its spin bound aborts all
  * workgroups and *_solve returns SVD2_ERR_HIP.
  * flags: 0 = fused (one persistent cooperative kernel per sweep, gather + SVD

@@ -13,6 +13,7 @@
 #include "svd2_oracle.h"
 
 #include <cfloat>
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <omp.h>
@@ -768,6 +769,35 @@ template <class T, bool CPLX> void kog_norms(int N, const T *A, int lda, double 
 template <class T, bool CPLX>
 int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, double *off_rel,
               double *history) {
+  // Exact power-of-two scaling around the iteration (the idea of eq. (2)
+  // applied to the whole matrix): E is the largest binary exponent among the
+  // finite nonzero components, A is multiplied by 2^-E before the first
+  // sweep and by 2^E after the last.  Each step commutes with it exactly (the
+  // 2x2 SVD scales its pivot exactly, the rotations do not depend on scale)
+  // unless a value reaches the subnormal range, so the iterates are those of
+  // A up to the factor, while the stopping test's sums of squares can neither
+  // overflow nor underflow to zero whatever the magnitude of A.
+  const int ncomp = CPLX ? 2 : 1;
+  int E = 0;
+  bool any = false;
+  for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N * ncomp; ++i) {
+      T x = A[(size_t)j * lda * ncomp + i];
+      if (x != T(0) && std::isfinite(x)) {
+        int e;
+        std::frexp(x, &e);
+        E = any ? std::max(E, e) : e;
+        any = true;
+      }
+    }
+  auto scale = [&](int k) {
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N * ncomp; ++i) {
+        T &x = A[(size_t)j * lda * ncomp + i];
+        x = std::ldexp(x, k);
+      }
+  };
+  if (E != 0) scale(-E);
   double off2, tot2;
   kog_norms<T, CPLX>(N, A, lda, off2, tot2);
   const double nrm0 = std::sqrt(tot2);
@@ -783,6 +813,7 @@ int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, dou
     ++sw;
     kog_norms<T, CPLX>(N, A, lda, off2, tot2);
   }
+  if (E != 0) scale(E);
   if (sweeps) *sweeps = sw;
   return status;
 }

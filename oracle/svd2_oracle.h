@@ -102,7 +102,11 @@ int oracle_metrics_s(size_t n, int cplx, const float *const *in,
  * descending order of Theorem 1 alone the iteration converges only linearly.
  * FP32 matrices use the FP32 2x2 SVD with the FP64 rescue of near-degenerate
  * pivots.  Stopping rule: off(A) = sqrt(sum_{i != j} |a_ij|^2) below
- * tol * ||A_0||_F, tested before every sweep; a sweep is N-1 steps.
+ * tol * ||A_0||_F, tested before every sweep; a sweep is N-1 steps.  The solve
+ * multiplies A by 2^-E before the first sweep and by 2^E after the last (E =
+ * the largest binary exponent among its components), which changes no
+ * rounding but keeps the sums of squares of the stopping test finite and
+ * nonzero for any finite A.
  * ------------------------------------------------------------------------- */
 int oracle_kog_pairs(int N, int t, int *pairs /* n x 2, row-major */);
 int oracle_kog_step_d(int N, double *A, int lda, int t);

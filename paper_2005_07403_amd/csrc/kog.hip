@@ -252,6 +252,38 @@ __global__ __launch_bounds__(256) void kog_norm_final_kernel(int nparts, const d
   }
 }
 
+// largest binary exponent among the finite nonzero components (kNoExp if
+// none): per-block maxima, then one block over them
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_maxexp_partial_kernel(int N, Mat<T, CPLX> M, int *part) {
+  __shared__ int se[256];
+  int e = kNoExp;
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const int x = elem_exp(M.ld(i, j));
+      e = x > e ? x : e;
+    }
+  se[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && se[threadIdx.x + s] > se[threadIdx.x]) se[threadIdx.x] = se[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = se[0];
+}
+
+__global__ __launch_bounds__(256) void kog_maxexp_final_kernel(int nparts, const int *part, int *res) {
+  __shared__ int se[256];
+  int e = kNoExp;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) e = part[i] > e ? part[i] : e;
+  se[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && se[threadIdx.x + s] > se[threadIdx.x]) se[threadIdx.x] = se[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) res[0] = se[0];
+}
 
 // ---------------------------------------------------------------------------
 // host side
@@ -515,6 +547,29 @@ template <class T, bool CPLX> svd2_status read_norms(const Ctx<T, CPLX> &c, doub
   return SVD2_OK;
 }
 
+// E of the whole-matrix scaling (0 for a matrix with no finite nonzero
+// component); synchronises
+template <class T, bool CPLX> svd2_status max_exponent(const Ctx<T, CPLX> &c, int &E) {
+  int *part = (int *)(c.ws + c.L.red), *res = (int *)(c.ws + c.L.res);
+  int nb = c.N < kRedBlocks ? c.N : kRedBlocks;
+  hipLaunchKernelGGL((kog_maxexp_partial_kernel<T, CPLX>), dim3(nb), dim3(256), 0, c.st, c.N, c.M, part);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL(kog_maxexp_final_kernel, dim3(1), dim3(256), 0, c.st, nb, (const int *)part, res);
+  s = hip_st(hipGetLastError());
+  int h = kNoExp;
+  if (s == SVD2_OK) s = hip_st(hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, c.st));
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
+  E = h == kNoExp ? 0 : h;
+  return s;
+}
+
+template <class T, bool CPLX> svd2_status scale_by(const Ctx<T, CPLX> &c, int e) {
+  int grid = c.N < 4096 ? c.N : 4096;
+  hipLaunchKernelGGL((kog_scale_kernel<T, CPLX>), dim3(grid), dim3(256), 0, c.st, c.N, c.M, e);
+  return hip_st(hipGetLastError());
+}
+
 template <class T, bool CPLX> svd2_status check_abort(const Ctx<T, CPLX> &c) {
   if (c.flags & (SVD2_KOG_UNFUSED | SVD2_KOG_TWO_STEP)) return SVD2_OK;
   Bar h;
@@ -540,8 +595,8 @@ template <class T, bool CPLX> svd2_status graph_build(Ctx<T, CPLX> c, hipGraphEx
     s = s1 != SVD2_OK ? s1 : s2;
   }
   if (s == SVD2_OK) s = hip_st(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
-  if (g) hipGraphDestroy(g);
-  hipStreamDestroy(cap);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
   return s;
 }
 
@@ -554,7 +609,9 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
   const bool two = c.flags & SVD2_KOG_TWO_STEP;
   bool in_w = false;
   double off2 = 0, tot2 = 0, nrm0 = 0;
-  int sw = 0;
+  int sw = 0, E = 0;
+  if (s == SVD2_OK) s = max_exponent<T, CPLX>(c, E);
+  if (s == SVD2_OK && E != 0) s = scale_by<T, CPLX>(c, -E);
   if (s == SVD2_OK) s = norms_async<T, CPLX>(c);
   if (s == SVD2_OK) s = read_norms<T, CPLX>(c, off2, tot2);
   nrm0 = __builtin_sqrt(tot2);
@@ -575,11 +632,10 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     if (s == SVD2_OK) s = check_abort<T, CPLX>(c);
     ++sw;
   }
-  if (s == SVD2_OK && in_w) {
-    s = copy_back<T, CPLX>(c);
-    if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
-  }
-  if (exec) hipGraphExecDestroy(exec);
+  if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
+  if (s == SVD2_OK && E != 0) s = scale_by<T, CPLX>(c, E);
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
+  if (exec) (void)hipGraphExecDestroy(exec);
   if (sweeps) *sweeps = sw;
   return s != SVD2_OK ? s : result;
 }

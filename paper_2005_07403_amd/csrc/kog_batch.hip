@@ -37,7 +37,8 @@ struct DevProb {
   long long w_off;                  // second matrix (two-step mode), lda = N
   int N, kind, kc, lc;
   int part_off, ntiles, max_sweeps, in_w;  // in_w: the iterate is in the second matrix
-  int gx2, ny2, lc2, pad0;          // two-step tiles: row blocks, column tiles, pairs per wavefront
+  int gx2, ny2, lc2;                // two-step tiles: row blocks, column tiles, pairs per wavefront
+  int e;                            // the solve works on 2^-e A (kog_scale_kernel)
   double tol, tot0;                 // tot0 = ||A_0||_F
   int t, sweeps, status, pad1;      // status: 0 running, 1 converged, 2 max_sweeps reached
   double off_rel;
@@ -98,18 +99,50 @@ __device__ __forceinline__ void batch_two_step(char *smem, char *ws, const DevPr
                          (kUpdBlock / 64) * P.lc2, P.lc2, bx, by);
 }
 
-template <class T, bool CPLX> __device__ __forceinline__ void batch_norm(const DevProb &P, double &off, double &tot) {
+// this pass takes problem P two steps further
+__device__ __forceinline__ bool two_this_pass(int two, const DevProb &P) { return two && P.t + 1 < P.N - 1; }
+
+// the largest binary exponent among the finite nonzero components of this
+// thread's share of A
+template <class T, bool CPLX> __device__ __forceinline__ int batch_maxexp(const DevProb &P) {
+  Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
+  int e = kNoExp;
+  for (int j = 0; j < P.N; ++j)
+    for (int i = threadIdx.x; i < P.N; i += blockDim.x) {
+      const int x = elem_exp(M.ld(i, j));
+      e = x > e ? x : e;
+    }
+  return e;
+}
+
+// A <- 2^e A in place (e != 0) and the sums of squares of the result
+template <class T, bool CPLX>
+__device__ __forceinline__ void batch_scale_norm(const DevProb &P, int e, double &off, double &tot) {
   Mat<T, CPLX> M{(T *)P.A, (size_t)P.lda};
   for (int j = 0; j < P.N; ++j)
     for (int i = threadIdx.x; i < P.N; i += blockDim.x) {
-      double a2 = abs2(M.ld(i, j));
+      Cx<T> v = M.ld(i, j);
+      if (e != 0) {
+        v = Cx<T>{vldexp(v.re, e), vldexp(v.im, e)};
+        M.st(i, j, v);
+      }
+      const double a2 = abs2(v);
       tot += a2;
       if (i != j) off += a2;
     }
 }
 
-// this pass takes problem P two steps further
-__device__ __forceinline__ bool two_this_pass(int two, const DevProb &P) { return two && P.t + 1 < P.N - 1; }
+__device__ __forceinline__ int block_max(int v, int *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kUpdBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && red[threadIdx.x + s] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + s];
+    __syncthreads();
+  }
+  int r = red[0];
+  __syncthreads();
+  return r;
+}
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
@@ -125,20 +158,32 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_init_kernel(BatchHdr *hdr, DevProb *probs) {
   __shared__ double red[kUpdBlock];
+  __shared__ int redi[kUpdBlock];
   for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
     DevProb &P = probs[p];
+    // scale A exactly by 2^-E (E: largest binary exponent), then take norms
+    int E;
+    switch (P.kind) {
+      case SVD2_KOG_F64: E = batch_maxexp<double, false>(P); break;
+      case SVD2_KOG_C128: E = batch_maxexp<double, true>(P); break;
+      case SVD2_KOG_F32: E = batch_maxexp<float, false>(P); break;
+      default: E = batch_maxexp<float, true>(P); break;
+    }
+    E = block_max(E, redi);
+    if (E == kNoExp) E = 0;
     double off = 0, tot = 0;
     switch (P.kind) {
-      case SVD2_KOG_F64: batch_norm<double, false>(P, off, tot); break;
-      case SVD2_KOG_C128: batch_norm<double, true>(P, off, tot); break;
-      case SVD2_KOG_F32: batch_norm<float, false>(P, off, tot); break;
-      default: batch_norm<float, true>(P, off, tot); break;
+      case SVD2_KOG_F64: batch_scale_norm<double, false>(P, -E, off, tot); break;
+      case SVD2_KOG_C128: batch_scale_norm<double, true>(P, -E, off, tot); break;
+      case SVD2_KOG_F32: batch_scale_norm<float, false>(P, -E, off, tot); break;
+      default: batch_scale_norm<float, true>(P, -E, off, tot); break;
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
     if (threadIdx.x == 0) {
       double nrm = __builtin_sqrt(tot);
       double rel = nrm > 0 ? __builtin_sqrt(off) / nrm : 0.0;
+      P.e = E;
       P.tot0 = nrm;
       P.off_rel = rel;
       P.t = 0;
@@ -443,6 +488,22 @@ svd2_status batch_step(const BatchRun &r, hipStream_t st) {
   return hip_st(hipGetLastError());
 }
 
+// the iterate back into the caller's matrix (if it is in the second one),
+// then A <- 2^e A
+template <class T, bool CPLX> svd2_status finish_problem(const DevProb &d, char *ws, hipStream_t st) {
+  const int grid = d.N < 4096 ? d.N : 4096;
+  const Mat<T, CPLX> a{(T *)d.A, (size_t)d.lda};
+  if (d.in_w) {
+    hipLaunchKernelGGL((kog_copy_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, d.N,
+                       Mat<T, CPLX>{(T *)(ws + d.w_off), (size_t)d.N}, a);
+    svd2_status s = hip_st(hipGetLastError());
+    if (s != SVD2_OK) return s;
+  }
+  if (d.e == 0) return SVD2_OK;
+  hipLaunchKernelGGL((kog_scale_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, d.N, a, d.e);
+  return hip_st(hipGetLastError());
+}
+
 svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int active) {
   std::vector<int2> A;
   std::vector<int4> B, C;
@@ -505,7 +566,7 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
   hipStream_t cap = nullptr;
   auto capture = [&]() -> svd2_status {
     if (exec) {
-      hipGraphExecDestroy(exec);
+      (void)hipGraphExecDestroy(exec);
       exec = nullptr;
     }
     hipGraph_t g = nullptr;
@@ -516,7 +577,7 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
     svd2_status c2 = hip_st(hipStreamEndCapture(cap, &g));
     c = c1 != SVD2_OK ? c1 : c2;
     if (c == SVD2_OK) c = hip_st(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return c;
   };
   if (s == SVD2_OK && (flags & SVD2_KOG_GRAPH)) {
@@ -546,37 +607,21 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
     }
     steps += K;
   }
-  if (exec) hipGraphExecDestroy(exec);
-  if (cap) hipStreamDestroy(cap);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (cap) (void)hipStreamDestroy(cap);
   if (s != SVD2_OK) return s;
   s = hip_st(hipMemcpyAsync(dp.data(), r.ws + r.L.probs, dp.size() * sizeof(DevProb), hipMemcpyDeviceToHost, st));
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
   if (s != SVD2_OK) return s;
-  // iterates left in the second matrix go back to the caller's
+  // iterates left in the second matrix go back to the caller's, then every
+  // matrix is scaled back by 2^e
   for (int p = 0; p < nprob && s == SVD2_OK; ++p) {
-    const DevProb &d = dp[p];
-    if (!d.in_w) continue;
-    const int grid = d.N < 4096 ? d.N : 4096;
-    char *w = r.ws + d.w_off;
-    switch (d.kind) {
-      case SVD2_KOG_F64:
-        hipLaunchKernelGGL((kog_copy_kernel<double, false>), dim3(grid), dim3(256), 0, st, d.N,
-                           Mat<double, false>{(double *)w, (size_t)d.N}, Mat<double, false>{(double *)d.A, (size_t)d.lda});
-        break;
-      case SVD2_KOG_C128:
-        hipLaunchKernelGGL((kog_copy_kernel<double, true>), dim3(grid), dim3(256), 0, st, d.N,
-                           Mat<double, true>{(double *)w, (size_t)d.N}, Mat<double, true>{(double *)d.A, (size_t)d.lda});
-        break;
-      case SVD2_KOG_F32:
-        hipLaunchKernelGGL((kog_copy_kernel<float, false>), dim3(grid), dim3(256), 0, st, d.N,
-                           Mat<float, false>{(float *)w, (size_t)d.N}, Mat<float, false>{(float *)d.A, (size_t)d.lda});
-        break;
-      default:
-        hipLaunchKernelGGL((kog_copy_kernel<float, true>), dim3(grid), dim3(256), 0, st, d.N,
-                           Mat<float, true>{(float *)w, (size_t)d.N}, Mat<float, true>{(float *)d.A, (size_t)d.lda});
-        break;
+    switch (dp[p].kind) {
+      case SVD2_KOG_F64: s = finish_problem<double, false>(dp[p], r.ws, st); break;
+      case SVD2_KOG_C128: s = finish_problem<double, true>(dp[p], r.ws, st); break;
+      case SVD2_KOG_F32: s = finish_problem<float, false>(dp[p], r.ws, st); break;
+      default: s = finish_problem<float, true>(dp[p], r.ws, st); break;
     }
-    s = hip_st(hipGetLastError());
   }
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
   if (s != SVD2_OK) return s;

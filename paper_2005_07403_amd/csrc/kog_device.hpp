@@ -723,6 +723,33 @@ __global__ __launch_bounds__(256) void kog_copy_kernel(int N, Mat<T, CPLX> src, 
     for (int i = threadIdx.x; i < N; i += blockDim.x) dst.st(i, j, src.ld(i, j));
 }
 
+// Exact power-of-two scaling of the whole matrix around a solve (the idea of
+// eq. (2) applied to A): with E the largest binary exponent among the finite
+// nonzero components, the solve works on 2^-E A and returns 2^E times the
+// result.  The steps commute with the factor exactly (each 2x2 SVD scales its
+// pivot exactly and the rotations do not depend on scale) unless a value
+// reaches the subnormal range, while the stopping test's sums of squares can
+// neither overflow nor underflow to zero.
+constexpr int kNoExp = -0x7fffffff - 1;  // no finite nonzero component
+
+template <class T> __device__ __forceinline__ int comp_exp(T x) {
+  return (x != T(0) && __builtin_isfinite(x)) ? vfrexp_exp(x) : kNoExp;
+}
+template <class T> __device__ __forceinline__ int elem_exp(Cx<T> v) {
+  const int a = comp_exp(v.re), b = comp_exp(v.im);
+  return a > b ? a : b;
+}
+
+// A <- 2^e A, every component
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_scale_kernel(int N, Mat<T, CPLX> M, int e) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const Cx<T> v = M.ld(i, j);
+      M.st(i, j, Cx<T>{vldexp(v.re, e), vldexp(v.im, e)});
+    }
+}
+
 // host helpers defined in kog.hip
 svd2_status hip_st(hipError_t e);  // maps a HIP error, recording it for kog_last_hip_error
 TileRule rule_for(int N);          // single-step update tile shape by order

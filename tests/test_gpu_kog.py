@@ -248,3 +248,36 @@ def test_sigma_extraction_general_input():
         A = np.asfortranarray(rng.standard_normal((N, N)))
         sig = S.kog_sigma(_dev(A)).cpu().numpy()
         assert _same(sig, np.sort(np.abs(np.diag(A)))[::-1]), N
+
+
+def _scaled(A, k):
+    """A * 2^k, one component at a time, rounded to the nearest in A's type."""
+    if np.iscomplexobj(A):
+        return np.asfortranarray(_scaled(A.real, k) + 1j * _scaled(A.imag, k)).astype(A.dtype)
+    return np.asfortranarray(A * A.dtype.type(2.0 ** k))
+
+
+SCALES = [("d", 600), ("d", -600), ("d", -1000), ("z", 700), ("z", -700), ("s", 100), ("s", -60),
+          ("c", 100), ("c", -60)]
+
+
+@pytest.mark.parametrize("kind,k", SCALES)
+@pytest.mark.parametrize("mode", ["fused", "unfused", "graph", "two"])
+def test_solve_tiny_and_huge_matrices(kind, k, mode):
+    """A matrix scaled by 2^k far from 1 takes the sweeps of the unscaled one
+    and ends bitwise equal to the oracle's solve of it (both scale the matrix
+    exactly by a power of two around the iteration)."""
+    from paper_2005_07403_amd import svd2 as S
+    N = 64
+    tol = 1e-14 if kind in "dz" else 1e-6
+    A1 = _make(N, kind, SEED_BASE + 360, cond=1e6 if kind in "dz" else 1e3)
+    A = _scaled(A1, k)
+    assert _same(_scaled(A, -k), A1)
+    flags = S.SVD2_KOG_TWO_STEP if mode == "two" else MODES[mode]
+    G = _dev(A)
+    r = S.kog_solve(G, tol=tol, flags=flags)
+    ro = O.kog_solve(A, tol=tol)
+    r1 = O.kog_solve(A1, tol=tol)
+    assert r["status"] == ro["status"] == r1["status"] == 0
+    assert r["sweeps"] == ro["sweeps"] == r1["sweeps"] > 0
+    assert _same(G.cpu().numpy(), A)

@@ -131,3 +131,31 @@ def test_full_uneven_batch_two_step():
         ro = O.kog_solve(host[i], tol=tols[i], max_sweeps=40)
         assert ro["status"] == 0 and ro["sweeps"] == res[i]["sweeps"], (i, probs[i]["order"])
         assert np.array_equal(_bits(mats[i].cpu().numpy()), _bits(host[i])), (i, probs[i]["order"])
+
+
+def _scaled(A, k):
+    """A * 2^k, one component at a time, rounded to the nearest in A's type."""
+    if np.iscomplexobj(A):
+        return np.asfortranarray(_scaled(A.real, k) + 1j * _scaled(A.imag, k)).astype(A.dtype)
+    return np.asfortranarray(A * A.dtype.type(2.0 ** k))
+
+
+@pytest.mark.parametrize("two", [False, True])
+def test_batch_tiny_and_huge_matrices(two):
+    """Problems scaled far from 1 (2^+-600 and beyond in FP64, 2^100 and 2^-60
+    in FP32) each take the sweeps the oracle takes and end bitwise equal to
+    its solve; each problem is scaled by its own power of two."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    specs = [(64, "d", 1e6, 600), (66, "d", 1e6, -1000), (34, "z", 1e4, 700), (32, "z", 1e4, -700),
+             (64, "s", 1e3, 100), (40, "c", 1e2, -60), (6, "c", 1e2, 100), (130, "d", 1e8, 0)]
+    mats = [_scaled(m, k) for m, (_, _, _, k) in zip(_batch([s[:3] for s in specs], SEED_BASE + 430), specs)]
+    dev = [torch.from_numpy(m).cuda() for m in mats]
+    res = S.kog_batch_solve(dev, [TOL[s[1]] for s in specs], max_sweeps=40,
+                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
+    torch.cuda.synchronize()
+    for i, ((N, kind, _, k), A) in enumerate(zip(specs, mats)):
+        ro = O.kog_solve(A, tol=TOL[kind], max_sweeps=40)
+        assert res[i]["status"] == 0 == ro["status"], (i, res[i], ro["status"])
+        assert res[i]["sweeps"] == ro["sweeps"] > 0, (i, res[i], ro["sweeps"])
+        assert np.array_equal(_bits(dev[i].cpu().numpy()), _bits(A)), (i, N, kind, k)

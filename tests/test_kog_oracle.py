@@ -78,3 +78,30 @@ def test_fp32_solve():
     r = O.kog_solve(A32, tol=1e-6)
     assert r["status"] == 0
     assert np.max(np.abs(r["sigma"] - sv)) <= 8 * N * 2.0 ** -23 * sv[0]
+
+
+
+def _scaled(A, k):
+    """A * 2^k, one component at a time, rounded to the nearest in A's type."""
+    if np.iscomplexobj(A):
+        return np.asfortranarray(_scaled(A.real, k) + 1j * _scaled(A.imag, k)).astype(A.dtype)
+    return np.asfortranarray(A * A.dtype.type(2.0 ** k))
+
+
+@pytest.mark.parametrize("kind,k", [("d", 600), ("d", -600), ("d", 1000), ("d", -1000), ("z", 700),
+                                    ("z", -700), ("s", 100), ("s", -60), ("c", 100), ("c", -60)])
+def test_solve_is_scale_equivariant(kind, k):
+    """Scaling A by 2^k scales the solve's result by 2^k, rounded once, and
+    leaves the sweep count unchanged: the iteration works on an exactly
+    rescaled copy, so tiny or huge matrices are neither taken for zero nor
+    overflow the stopping test's sums of squares."""
+    dt = {"d": np.float64, "z": np.complex128, "s": np.float32, "c": np.complex64}[kind]
+    A = np.asfortranarray(kog_matrix(24, 77, cond=1e3, cplx=kind in "zc").astype(dt))
+    B = _scaled(A, k)
+    assert np.array_equal(_scaled(B, -k), A)  # the scaled input is exact
+    tol = 1e-5 if kind in "sc" else 1e-14
+    ra = O.kog_solve(A, tol=tol)
+    rb = O.kog_solve(B, tol=tol)
+    assert ra["status"] == rb["status"] == 0
+    assert ra["sweeps"] == rb["sweeps"] > 0
+    assert np.array_equal(B, _scaled(A, k))
