@@ -30,8 +30,11 @@ METRIC = "2×2 SVDs/s at n=2^24 (FP64, FP32) + % HBM roofline; Kogbetliantz swee
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per SVD: SoA inputs read once + U, V, smax, smin, s written once
 BYTES_PER_SVD = {"d": 120, "z": 216, "s": 60, "c": 108}
+# singular values only (SVD2_NO_UV): inputs + smax, smin, s
+BYTES_PER_SVD_NOUV = {"d": 56, "z": 88, "s": 28, "c": 44}
 # launch shape (threads per block, matrices per lane) used by the benchmark
-DEFAULT_LAUNCH = {"d": (256, 1), "z": (64, 2), "s": (256, 1), "c": (256, 1)}
+DEFAULT_LAUNCH = {"d": (256, 1), "z": (64, 2), "s": (256, 1), "c": (256, 1),
+                  "d_nouv": (256, 1), "z_nouv": (256, 1), "s_nouv": (256, 1), "c_nouv": (256, 1)}
 KERNEL_SOURCES = ["paper_2005_07403_amd/csrc/svd2_batch.hip", "paper_2005_07403_amd/csrc/svd2_lane.hpp"]
 
 
@@ -60,14 +63,18 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
     in `flagsets` (same inputs).  Returns {flags: dict} with the wall-clock
     time of the timed region and the per-launch kernel time from HIP events
     recorded on the launch stream; the memory-pattern probe (same loads and
-    stores, no arithmetic) is timed the same way under key 'pattern'."""
+    stores, no arithmetic) is timed the same way under key 'pattern', and
+    under 'pattern_nouv' for the singular-values-only pattern when a flag set
+    has SVD2_NO_UV."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     S.svd2_set_launch_kind(variant, *DEFAULT_LAUNCH[variant])
+    S.svd2_set_launch_kind(variant + "_nouv", *DEFAULT_LAUNCH[variant + "_nouv"])
     dev = [torch.from_numpy(t).cuda() for t in trains_np]
     n = dev[0].numel()
     nout = 19 if len(dev) == 8 else 11
     out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(nout)]
+    sig = out[nout - 3:]
     stream = torch.cuda.current_stream()
     res = {}
 
@@ -91,8 +98,11 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
         wsb = S.svd2_workspace_bytes(n, flags) if dev[0].dtype == torch.float32 else 0
         if wsb:
             ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-        res[flags] = timed(lambda: S.svd2(dev, flags=flags, out=out, ws=ws))
+        o = sig if flags & S.SVD2_NO_UV else out
+        res[flags] = timed(lambda: S.svd2(dev, flags=flags, out=o, ws=ws))
     res["pattern"] = timed(lambda: S.svd2_stream_probe(variant, dev, out))
+    if any(f & S.SVD2_NO_UV for f in flagsets):
+        res["pattern_nouv"] = timed(lambda: S.svd2_stream_probe(variant + "_nouv", dev, sig))
     del dev, out
     torch.cuda.empty_cache()
     return res
@@ -248,16 +258,17 @@ def kog_batch_bench(nprob: int = 256):
     return out
 
 
-def summarize(variant, r, pattern, flags_desc=""):
+def summarize(variant, r, pattern, flags_desc="", nouv=False):
     n = r["n"]
+    bps = (BYTES_PER_SVD_NOUV if nouv else BYTES_PER_SVD)[variant]
     kms = float(np.mean(r["kernel_ms"]))
     wall_ms = r["wall_s"] * 1e3 / len(r["kernel_ms"])
-    gbs = BYTES_PER_SVD[variant] * n / (kms * 1e-3) / 1e9
+    gbs = bps * n / (kms * 1e-3) / 1e9
     pms = float(np.mean(pattern["kernel_ms"]))
-    pgbs = BYTES_PER_SVD[variant] * n / (pms * 1e-3) / 1e9
+    pgbs = bps * n / (pms * 1e-3) / 1e9
     return dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
                 kernel_ms_min=float(np.min(r["kernel_ms"])), algorithmic_GBs=gbs,
-                hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=BYTES_PER_SVD[variant],
+                hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=bps,
                 pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
 
 
@@ -281,6 +292,8 @@ def main():
     ap.add_argument("--kog-only", default=None, metavar="MODES",
                     help="run only the Kogbetliantz drivers named (comma list of fused, unfused, graph, "
                          "two_step), one sweep each, no solve; prints their JSON (for profiling runs)")
+    ap.add_argument("--uv", choices=["both", "full", "nouv"], default="both",
+                    help="batched SVD: time the full kernels, the singular-values-only ones, or both")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -321,10 +334,13 @@ def main():
         return
 
     variants = [args.only] if args.only else ["z", "d", "s", "c"]
-    F = S.SVD2_RESCUE_FP64
-    flagsets = {"d": {"": 0}, "z": {"": 0},
-                "s": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0},
-                "c": {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0}}
+    F, NU = S.SVD2_RESCUE_FP64, S.SVD2_NO_UV
+    fp32 = {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0,
+            "RESCUE_FP64|SIGMA|NO_UV": F | S.SVD2_RESCUE_SIGMA | NU}
+    flagsets = {"d": {"": 0, "NO_UV": NU}, "z": {"": 0, "NO_UV": NU}, "s": fp32, "c": dict(fp32)}
+    if args.uv != "both":
+        keep_nouv = args.uv == "nouv"
+        flagsets = {v: {d: f for d, f in fs.items() if ("NO_UV" in d) == keep_nouv} for v, fs in flagsets.items()}
     results, inputs_z = {}, None
     # FP32 also at the precision form's own size (2^26: its inputs exceed the
     # 256 MB Infinity Cache, so they come from HBM on every launch)
@@ -337,8 +353,14 @@ def main():
         log(f"[bench] timing {v}{tag}: warmup {args.warmup}, steps {args.steps}")
         r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()))
         for desc, fl in flagsets[v].items():
-            key = v + tag if desc in ("", "RESCUE_FP64") else f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
-            results[key] = summarize(v, r[fl], r["pattern"], desc)
+            nouv = "NO_UV" in desc
+            if desc in ("", "RESCUE_FP64"):
+                key = v + tag
+            elif nouv:
+                key = f"{v}{tag}_nouv"
+            else:
+                key = f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
+            results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv)
             log(f"[bench] {key}: {json.dumps(results[key])}")
         if v == "z":
             inputs_z = tr
@@ -354,7 +376,7 @@ def main():
         log(f"[bench] uneven Kogbetliantz batch of {args.kog_batch}")
         kog_batch = kog_batch_bench(args.kog_batch)
 
-    head = "z" if "z" in results else variants[0]
+    head = "z" if "z" in results else next(iter(results))
     h = results[head]
     steps = args.steps
     cpu = None
@@ -363,7 +385,7 @@ def main():
         cpu = cpu_baseline("z", inputs_z)
         log(f"[bench] cpu: {json.dumps(cpu)}")
     traffic = read_traffic(f"svd2_{head}")
-    dtype_name = {"d": "f64", "z": "f64", "s": "f32", "c": "f32"}[head]
+    dtype_name = {"d": "f64", "z": "f64", "s": "f32", "c": "f32"}[head[0]]
     line = {
         "metric": METRIC,
         "value": h["svds_per_s"],
@@ -381,14 +403,15 @@ def main():
         "config": {"workload": {"z": "complex FP64 batched 2x2 SVD",
                                 "d": "real FP64 batched 2x2 SVD",
                                 "s": "real FP32 batched 2x2 SVD + FP64 rescue",
-                                "c": "complex FP32 batched 2x2 SVD + FP64 rescue"}[head],
-                   "n": h["n"], "layout": "SoA", "exponents": "e in [-1000,1000]" if head in "dz"
+                                "c": "complex FP32 batched 2x2 SVD + FP64 rescue"}[head[0]] +
+                   (", singular values only" if head.endswith("_nouv") else ""),
+                   "n": h["n"], "layout": "SoA", "exponents": "e in [-1000,1000]" if head[0] in "dz"
                    else "e in [-120,120]", "special_lanes": 0.01,
-                   "launch": list(DEFAULT_LAUNCH[head])},
+                   "launch": list(DEFAULT_LAUNCH[head[0] + ("_nouv" if head.endswith("_nouv") else "")])},
         "roofline": {"bound": "hbm", "achieved": h["algorithmic_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": h["hbm_frac"],
                      "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes_per_launch": BYTES_PER_SVD[head] * h["n"],
+                     "algorithmic_bytes_per_launch": h["bytes_per_svd"] * h["n"],
                      "pattern_ceiling_GBs": h["pattern_ceiling_GBs"],
                      "frac_of_pattern_ceiling": h["frac_of_pattern_ceiling"]},
         "cpu_baseline": cpu,

@@ -74,11 +74,18 @@ enum {
   SVD2_RESCUE_QUEUE = 8,    /* with RESCUE_FP64: flagged lanes are compacted into a
                                queue (one atomic per wavefront) and redone by a
                                second kernel; needs a workspace                     */
-  SVD2_RESCUE_SIGMA = 16    /* with RESCUE_FP64: on flagged lanes only sigma'_min is
+  SVD2_RESCUE_SIGMA = 16,   /* with RESCUE_FP64: on flagged lanes only sigma'_min is
                                recomputed, as |det(A^)| / sigma'_max in FP64 (the
                                product of the singular values is |det|); U, V and
                                sigma'_max keep their FP32 values.  Same relative
                                accuracy of sigma_min for a fraction of the FP64 work */
+  /* all four entry points: singular values only, the counterpart of the
+     values-only routine of section 2.  The last phase of section 4, the
+     assembly of U and V (eq. (29)), is skipped; the U and V pointers may be
+     NULL and are neither checked nor written.  smax, smin and s are bitwise
+     those of the same call without the flag (they do not depend on the
+     assembly), with every other flag including the rescues. */
+  SVD2_NO_UV = 32
 };
 
 /* Real FP64: a_ij in, u_ij, v_ij, smax, smin, s out (all length n). */
@@ -116,7 +123,7 @@ typedef struct {
   uint32_t *nrescued;
 } csvd2_args;
 
-/* Batched SVDs of n matrices (sections 2-7).  flags: SVD2_BACKSCALE_*.
+/* Batched SVDs of n matrices (sections 2-7).  flags: SVD2_BACKSCALE_* [| SVD2_NO_UV].
    Errors: SVD2_ERR_NULL/ALIGN/ALIAS/FLAGS before launch, SVD2_ERR_HIP if the
    launch fails. */
 svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream);
@@ -124,7 +131,8 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 
 /* FP32 form (the paper notes the method carries over to single precision,
    section 1; the tan 2phi clamp becomes sqrt(FLT_MAX), section 7).
-   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA].
+   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA]
+   [| SVD2_NO_UV].
    ws / ws_bytes: device workspace, at least svd2_workspace_bytes(n, flags)
    bytes (may be NULL/0 when that is 0).  With RESCUE_QUEUE, n must be below
    2^32 (SVD2_ERR_SIZE otherwise).  Calls sharing one workspace must not
@@ -142,7 +150,8 @@ size_t svd2_workspace_bytes(size_t n, unsigned flags);
    (2 uses 16-byte loads and stores when every array is 16-byte aligned).
    svd2_set_launch sets every element type; svd2_set_launch_kind one of them:
    kind 0 real FP64, 1 complex FP64, 2 real FP32, 3 complex FP32 (the
-   SVD2_KOG_* dtype codes).  Takes effect for later calls from any thread.
+   SVD2_KOG_* dtype codes), 4-7 the same with SVD2_NO_UV.  Takes effect for
+   later calls from any thread.
    SVD2_ERR_SIZE / SVD2_ERR_FLAGS for values out of range.
    svd2_get_launch reports the real-FP64 shape. */
 svd2_status svd2_set_launch(int block, int per_thread);
@@ -161,10 +170,11 @@ int svd2_last_hip_error(void);
    x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
 /* Memory-pattern probe, a diagnostic: the loads and stores of the batched
    kernel of element type `kind` (0 real FP64, 1 complex FP64, 2 real FP32,
-   3 complex FP32) with the same launch shape, but no SVD arithmetic (each
-   output = the sum of the inputs plus its index).  in/out: host arrays of
-   4 or 8 input and 11 or 19 output device pointers of n elements.  Its time
-   is the ceiling the memory system sets for that access pattern. */
+   3 complex FP32; 4-7 the same with SVD2_NO_UV) with the same launch shape,
+   but no SVD arithmetic (each output = the sum of the inputs plus its
+   index).  in/out: host arrays of 4 or 8 input and 11, 19 or (kinds 4-7) 3
+   output device pointers of n elements.  Its time is the ceiling the memory
+   system sets for that access pattern. */
 svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *const *out,
                               hipStream_t stream);
 

@@ -48,21 +48,27 @@ def _pick(res: dict, tiles) -> tuple:
     return min(near, key=lambda k: (tiles(k), res[k]))
 
 
-def tune_svd2(n: int, reps: int, rounds: int = 3) -> dict:
-    """Launch shape per element type, timed at the batch size of interest with
-    `rounds` interleaved passes over the candidates (the median of `reps`
-    launches each); the best minimum over rounds wins."""
+SVD2_KINDS = ["d", "z", "s", "c", "d_nouv", "z_nouv", "s_nouv", "c_nouv"]
+
+
+def tune_svd2(n: int, reps: int, rounds: int = 3, kinds=SVD2_KINDS) -> dict:
+    """Launch shape per element type (and per singular-values-only kernel,
+    kinds "*_nouv"), timed at the batch size of interest with `rounds`
+    interleaved passes over the candidates (the median of `reps` launches
+    each); the best minimum over rounds wins."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     from workloads import SEED_BASE, scaled_law, to_trains
     best = {}
     shapes = [(64, 1), (64, 2), (128, 1), (128, 2), (256, 1), (256, 2)]
-    for kind in "dzsc":
-        cplx = kind in "zc"
-        dt = np.float64 if kind in "dz" else np.float32
+    for kind in kinds:
+        cplx, nouv = kind[0] in "zc", kind.endswith("_nouv")
+        dt = np.float64 if kind[0] in "dz" else np.float32
         dev = [torch.from_numpy(t).cuda() for t in to_trains(scaled_law(n, SEED_BASE + 7, cplx, dtype=dt), dt)]
-        out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(19 if cplx else 11)]
-        flags = 0 if kind in "dz" else S.SVD2_RESCUE_FP64
+        out = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(3 if nouv else (19 if cplx else 11))]
+        flags = 0 if kind[0] in "dz" else S.SVD2_RESCUE_FP64
+        if nouv:
+            flags |= S.SVD2_NO_UV | (S.SVD2_RESCUE_SIGMA if flags else 0)
         res = {sh: [] for sh in shapes}
         for _ in range(rounds):
             for block, pt in shapes:
@@ -154,12 +160,29 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
+    ap.add_argument("--svd2-only", default=None, metavar="KINDS",
+                    help="tune only these batched-SVD kinds (comma list of " + ", ".join(SVD2_KINDS) +
+                         ") and merge them into the existing table")
     args = ap.parse_args()
     import torch
     from paper_2005_07403_amd import svd2 as S
     S.lib()
     assert torch.cuda.is_available()
     t0 = time.time()
+    if args.svd2_only:
+        kinds = args.svd2_only.split(",")
+        bad = [k for k in kinds if k not in SVD2_KINDS]
+        if bad:
+            raise SystemExit(f"unknown kinds {bad}")
+        tab = {}
+        if os.path.exists(args.out):
+            with open(args.out) as fh:
+                tab = json.load(fh)
+        tab.setdefault("svd2_launch", {}).update(tune_svd2(1 << 24, 20, kinds=kinds))
+        with open(args.out, "w") as fh:
+            json.dump(tab, fh, indent=1)
+        print(json.dumps(tab), flush=True)
+        return
     launch = tune_svd2(1 << (22 if args.quick else 24), 10 if args.quick else 20)
     orders = [64, 256, 1024, 4096] if args.quick else [32, 64, 128, 256, 512, 1024, 2048, 4096]
     rules = tune_kog(orders, 5 if args.quick else 10)

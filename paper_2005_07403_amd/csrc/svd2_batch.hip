@@ -23,8 +23,9 @@ namespace {
 
 thread_local int g_last_hip = 0;
 // launch shape per element type: 0 real FP64, 1 complex FP64, 2 real FP32, 3 complex FP32
-std::atomic<int> g_block[4] = {{256}, {256}, {256}, {256}};
-std::atomic<int> g_per_thread[4] = {{1}, {1}, {1}, {1}};
+// (+4: singular values only)
+std::atomic<int> g_block[8] = {{256}, {256}, {256}, {256}, {256}, {256}, {256}, {256}};
+std::atomic<int> g_per_thread[8] = {{1}, {1}, {1}, {1}, {1}, {1}, {1}, {1}};
 template <class T, bool CPLX> constexpr int kind_of() { return (sizeof(T) == 8 ? 0 : 2) + (CPLX ? 1 : 0); }
 
 template <class T, int NIN, int NOUT> struct KArgs {
@@ -61,12 +62,13 @@ __device__ __forceinline__ void load_lanes(const T *const (&in)[N], size_t k, in
   }
 }
 
-template <class T, int N, int PT>
+// outputs LO .. N-1 only (LO = N-3: sigma'_max, sigma'_min, s)
+template <class T, int N, int PT, int LO = 0>
 __device__ __forceinline__ void store_lanes(T *const (&out)[N], size_t k, int cnt, const T (&y)[PT][N]) {
   if (PT == 2 && cnt == 2) {
     typedef typename Vec2<T>::type V;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int i = LO; i < N; ++i) {
       V v;
       v.x = y[0][i];
       v.y = y[PT - 1][i];
@@ -77,7 +79,7 @@ __device__ __forceinline__ void store_lanes(T *const (&out)[N], size_t k, int cn
     for (int j = 0; j < PT; ++j)
       if (j < cnt) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) st_nt(out[i] + k + j, y[j][i]);
+        for (int i = LO; i < N; ++i) st_nt(out[i] + k + j, y[j][i]);
       }
   }
 }
@@ -88,13 +90,15 @@ __device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
 
 // ---------------------------------------------------------------------------
 // Main batched kernel.  RESCUE: 0 plain, 1 in-place FP64 rescue, 2 queue the
-// flagged lanes for svd2_rescue_kernel.
+// flagged lanes for svd2_rescue_kernel.  UV = false: singular values only; U
+// and V are neither stored nor, since nothing uses them, computed (the
+// assembly of eq. (29) and its FP64 counterpart in the rescue drop out).
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int PT, int RESCUE>
+template <class T, bool CPLX, int PT, int RESCUE, bool UV>
 __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                    int bs, uint32_t *nresc, uint32_t *queue,
                                                    uint32_t *qcount) {
-  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, LO = UV ? 0 : NOUT - 3;
   size_t k = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
   int cnt = (k < n) ? (int)((n - k < (size_t)PT) ? (n - k) : PT) : 0;
   T x[PT][NIN], y[PT][NOUT];
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
     fl[j] = false;
     if (j < cnt) fl[j] = one_matrix<T, CPLX, RESCUE>(x[j], y[j], bs);
   }
-  if (cnt > 0) store_lanes<T, NOUT, PT>(a.out, k, cnt, y);
+  if (cnt > 0) store_lanes<T, NOUT, PT, LO>(a.out, k, cnt, y);
   if constexpr (RESCUE != 0) {
 #pragma unroll
     for (int j = 0; j < PT; ++j) {
@@ -127,11 +131,11 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
 
 // Second pass for RESCUE == 2: redo each queued lane with the FP64 tail.  The
 // grid is fixed; every lane loops until the device-side count is exhausted.
-template <class T, bool CPLX, int TAIL>
+template <class T, bool CPLX, int TAIL, bool UV>
 __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                           int bs, const uint32_t *queue,
                                                           const uint32_t *qcount) {
-  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, LO = UV ? 0 : NOUT - 3;
   uint32_t total = *qcount;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     size_t k = queue[i];
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4,
     for (int e = 0; e < NIN; ++e) x[e] = a.in[e][k];
     one_matrix<T, CPLX, TAIL>(x, y, bs);
 #pragma unroll
-    for (int e = 0; e < NOUT; ++e) st_nt(a.out[e] + k, y[e]);
+    for (int e = LO; e < NOUT; ++e) st_nt(a.out[e] + k, y[e]);
   }
 }
 
@@ -200,11 +204,12 @@ svd2_status check_ptrs(size_t n, const T *const *in, int nin, T *const *out, int
   return SVD2_OK;
 }
 
+// every array the kernel touches 16-byte aligned (uv = false: U and V are not)
 template <class T, int NIN, int NOUT>
-bool all_aligned16(const KArgs<T, NIN, NOUT> &a) {
+bool all_aligned16(const KArgs<T, NIN, NOUT> &a, bool uv = true) {
   for (int i = 0; i < NIN; ++i)
     if ((uintptr_t)a.in[i] % 16) return false;
-  for (int i = 0; i < NOUT; ++i)
+  for (int i = uv ? 0 : NOUT - 3; i < NOUT; ++i)
     if ((uintptr_t)a.out[i] % 16) return false;
   return true;
 }
@@ -215,22 +220,29 @@ svd2_status hip_status(hipError_t e) {
   return SVD2_ERR_HIP;
 }
 
-template <class T, bool CPLX, int RESCUE>
+template <class T, bool CPLX, int RESCUE, bool UV>
 svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
                    uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
-  constexpr int kind = kind_of<T, CPLX>();
+  constexpr int kind = kind_of<T, CPLX>() + (UV ? 0 : 4);
   int block = g_block[kind].load(), pt = g_per_thread[kind].load();
-  if (pt == 2 && !all_aligned16(a)) pt = 1;
+  if (pt == 2 && !all_aligned16(a, UV)) pt = 1;
   size_t lanes = (n + pt - 1) / pt;
   size_t grid = (lanes + block - 1) / block;
   if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
   if (pt == 2)
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE>), dim3((unsigned)grid), dim3(block), 0, st,
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE, UV>), dim3((unsigned)grid), dim3(block), 0, st,
                        n, a, bs, nresc, queue, qcount);
   else
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE>), dim3((unsigned)grid), dim3(block), 0, st,
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE, UV>), dim3((unsigned)grid), dim3(block), 0, st,
                        n, a, bs, nresc, queue, qcount);
   return hip_status(hipGetLastError());
+}
+
+template <class T, bool CPLX, int RESCUE>
+svd2_status launch_uv(bool uv, size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
+                      uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
+  return uv ? launch<T, CPLX, RESCUE, true>(n, a, bs, nresc, queue, qcount, st)
+            : launch<T, CPLX, RESCUE, false>(n, a, bs, nresc, queue, qcount, st);
 }
 
 bool bad_bs_flags(unsigned flags) { return (flags & 3u) == 3u; }
@@ -240,11 +252,11 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
                      uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
   int bs = (int)(flags & 3u);
   bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE,
-       sigma = flags & SVD2_RESCUE_SIGMA;
-  if (!resc) return launch<T, CPLX, 0>(n, a, bs, nullptr, nullptr, nullptr, st);
+       sigma = flags & SVD2_RESCUE_SIGMA, uv = !(flags & SVD2_NO_UV);
+  if (!resc) return launch_uv<T, CPLX, 0>(uv, n, a, bs, nullptr, nullptr, nullptr, st);
   if (!queue) {
-    if (sigma) return launch<T, CPLX, 3>(n, a, bs, nresc, nullptr, nullptr, st);
-    return launch<T, CPLX, 1>(n, a, bs, nresc, nullptr, nullptr, st);
+    if (sigma) return launch_uv<T, CPLX, 3>(uv, n, a, bs, nresc, nullptr, nullptr, st);
+    return launch_uv<T, CPLX, 1>(uv, n, a, bs, nresc, nullptr, nullptr, st);
   }
   if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
   if (!ws) return SVD2_ERR_NULL;
@@ -255,12 +267,13 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, qcount);
   svd2_status s0 = hip_status(hipGetLastError());
   if (s0 != SVD2_OK) return s0;
-  svd2_status s1 = launch<T, CPLX, 2>(n, a, bs, nresc, q, qcount, st);
+  svd2_status s1 = launch_uv<T, CPLX, 2>(uv, n, a, bs, nresc, q, qcount, st);
   if (s1 != SVD2_OK) return s1;
-  if (sigma)
-    hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
-  else
-    hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1>), dim3(1024), dim3(256), 0, st, a, bs, q, qcount);
+  const dim3 g(1024), b(256);
+  if (sigma && uv) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3, true>), g, b, 0, st, a, bs, q, qcount);
+  else if (sigma) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3, false>), g, b, 0, st, a, bs, q, qcount);
+  else if (uv) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1, true>), g, b, 0, st, a, bs, q, qcount);
+  else hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1, false>), g, b, 0, st, a, bs, q, qcount);
   return hip_status(hipGetLastError());
 }
 
@@ -324,29 +337,31 @@ extern "C" {
 
 svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream) {
   if (!p) return SVD2_ERR_NULL;
-  if (flags & ~3u || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  if (flags & ~(3u | SVD2_NO_UV) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
   KArgs<double, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
                             {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
                              p->smax, p->smin, p->s}};
-  svd2_status st = check_ptrs<double>(n, a.in, 4, a.out, 11);
+  const bool uv = !(flags & SVD2_NO_UV);
+  svd2_status st = check_ptrs<double>(n, a.in, 4, a.out + (uv ? 0 : 8), uv ? 11 : 3);
   if (st != SVD2_OK || n == 0) return st;
-  return launch<double, false, 0>(n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+  return launch_uv<double, false, 0>(uv, n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
 }
 
 svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream_t stream) {
   if (!p) return SVD2_ERR_NULL;
-  if (flags & ~3u || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  if (flags & ~(3u | SVD2_NO_UV) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
   KArgs<double, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
                             {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
                              p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
                              p->smax, p->smin, p->s}};
-  svd2_status st = check_ptrs<double>(n, a.in, 8, a.out, 19);
+  const bool uv = !(flags & SVD2_NO_UV);
+  svd2_status st = check_ptrs<double>(n, a.in, 8, a.out + (uv ? 0 : 16), uv ? 19 : 3);
   if (st != SVD2_OK || n == 0) return st;
-  return launch<double, true, 0>(n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+  return launch_uv<double, true, 0>(uv, n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
 }
 
 static bool bad_fp32_flags(unsigned flags) {
-  if (flags & ~31u || bad_bs_flags(flags)) return true;
+  if (flags & ~(31u | SVD2_NO_UV) || bad_bs_flags(flags)) return true;
   if ((flags & (SVD2_RESCUE_QUEUE | SVD2_RESCUE_SIGMA)) && !(flags & SVD2_RESCUE_FP64)) return true;
   return false;
 }
@@ -358,7 +373,8 @@ svd2_status ssvd2_batch(size_t n, const ssvd2_args *p, unsigned flags, void *ws,
   KArgs<float, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
                            {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
                             p->smax, p->smin, p->s}};
-  svd2_status st = check_ptrs<float>(n, a.in, 4, a.out, 11);
+  const bool uv = !(flags & SVD2_NO_UV);
+  svd2_status st = check_ptrs<float>(n, a.in, 4, a.out + (uv ? 0 : 8), uv ? 11 : 3);
   if (st != SVD2_OK || n == 0) return st;
   return run_fp32<float, false>(n, a, flags, p->nrescued, ws, ws_bytes, stream);
 }
@@ -371,7 +387,8 @@ svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws,
                            {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
                             p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
                             p->smax, p->smin, p->s}};
-  svd2_status st = check_ptrs<float>(n, a.in, 8, a.out, 19);
+  const bool uv = !(flags & SVD2_NO_UV);
+  svd2_status st = check_ptrs<float>(n, a.in, 8, a.out + (uv ? 0 : 16), uv ? 19 : 3);
   if (st != SVD2_OK || n == 0) return st;
   return run_fp32<float, true>(n, a, flags, p->nrescued, ws, ws_bytes, stream);
 }
@@ -382,7 +399,7 @@ size_t svd2_workspace_bytes(size_t n, unsigned flags) {
 }
 
 svd2_status svd2_set_launch_kind(int kind, int block, int per_thread) {
-  if (kind < 0 || kind > 3) return SVD2_ERR_FLAGS;
+  if (kind < 0 || kind > 7) return SVD2_ERR_FLAGS;
   if (block < 64 || block > 256 || block % 64) return SVD2_ERR_SIZE;
   if (per_thread != 1 && per_thread != 2) return SVD2_ERR_SIZE;
   g_block[kind].store(block);
@@ -393,14 +410,14 @@ svd2_status svd2_set_launch_kind(int kind, int block, int per_thread) {
 svd2_status svd2_set_launch(int block, int per_thread) {
   if (block < 64 || block > 256 || block % 64) return SVD2_ERR_SIZE;
   if (per_thread != 1 && per_thread != 2) return SVD2_ERR_SIZE;
-  for (int k = 0; k < 4; ++k) svd2_set_launch_kind(k, block, per_thread);
+  for (int k = 0; k < 8; ++k) svd2_set_launch_kind(k, block, per_thread);
   return SVD2_OK;
 }
 
 void svd2_get_launch(int *block, int *per_thread) { svd2_get_launch_kind(0, block, per_thread); }
 
 void svd2_get_launch_kind(int kind, int *block, int *per_thread) {
-  if (kind < 0 || kind > 3) kind = 0;
+  if (kind < 0 || kind > 7) kind = 0;
   if (block) *block = g_block[kind].load();
   if (per_thread) *per_thread = g_per_thread[kind].load();
 }
@@ -429,6 +446,10 @@ svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *c
     case 1: return stream_probe<double, 8, 19>(n, in, out, stream, 1);
     case 2: return stream_probe<float, 4, 11>(n, in, out, stream, 2);
     case 3: return stream_probe<float, 8, 19>(n, in, out, stream, 3);
+    case 4: return stream_probe<double, 4, 3>(n, in, out, stream, 4);
+    case 5: return stream_probe<double, 8, 3>(n, in, out, stream, 5);
+    case 6: return stream_probe<float, 4, 3>(n, in, out, stream, 6);
+    case 7: return stream_probe<float, 8, 3>(n, in, out, stream, 7);
   }
   return SVD2_ERR_FLAGS;
 }

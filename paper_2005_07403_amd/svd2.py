@@ -22,6 +22,7 @@ SVD2_BACKSCALE_ALL = 2
 SVD2_RESCUE_FP64 = 4
 SVD2_RESCUE_QUEUE = 8
 SVD2_RESCUE_SIGMA = 16
+SVD2_NO_UV = 32
 
 _P = ctypes.c_void_p
 REAL_IN = ["a11", "a21", "a12", "a22"]
@@ -170,7 +171,8 @@ def svd2_get_launch() -> tuple:
     return b.value, p.value
 
 
-KIND = {"d": 0, "z": 1, "s": 2, "c": 3}
+# element type -> launch-shape kind; the "_nouv" kinds are the SVD2_NO_UV kernels
+KIND = {"d": 0, "z": 1, "s": 2, "c": 3, "d_nouv": 4, "z_nouv": 5, "s_nouv": 6, "c_nouv": 7}
 
 
 def svd2_set_launch_kind(kind: str, block: int, per_thread: int) -> None:
@@ -227,7 +229,8 @@ def svd2_stream_probe(kind: str, ins, outs, stream=None) -> None:
 def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
     """Batched SVD of SoA trains (list of 4 real or 8 re/im device tensors of
     one dtype, element order 11, 21, 12, 22).  Returns the list of output
-    trains (11 or 19 tensors: U, V, smax, smin, s) in the order of the C ABI."""
+    trains (11 or 19 tensors: U, V, smax, smin, s) in the order of the C ABI;
+    with SVD2_NO_UV only [smax, smin, s] (out, if given, holds those three)."""
     import torch
     trains = list(trains)
     cplx = len(trains) == 8
@@ -238,11 +241,15 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
     for t in trains:
         if t.dtype != dt or t.numel() != n or not t.is_cuda or not t.is_contiguous():
             raise ValueError("trains must be contiguous device tensors of one dtype and length")
-    nout = 19 if cplx else 11
+    nout = 3 if flags & SVD2_NO_UV else (19 if cplx else 11)
     if out is None:
         out = [torch.empty(n, dtype=dt, device=trains[0].device) for _ in range(nout)]
+    if len(out) != nout:
+        raise ValueError(f"expected {nout} output trains")
     ins = [t.data_ptr() for t in trains]
     outs = [t.data_ptr() for t in out]
+    if nout == 3:
+        outs = [0] * (16 if cplx else 8) + outs
     if dt == torch.float64:
         (zsvd2_batch if cplx else dsvd2_batch)(n, ins, outs, flags, stream)
     elif dt == torch.float32:

@@ -74,6 +74,32 @@ def test_argument_errors(fn, nin, nout):
     assert _call(fn, 10, ins, outs, flags=1 << 12) == 4
 
 
+@pytest.mark.parametrize("fn,nin,nuv", [(S.dsvd2_batch, 4, 8), (S.zsvd2_batch, 8, 16),
+                                        (S.ssvd2_batch, 4, 8), (S.csvd2_batch, 8, 16)])
+def test_singular_values_only_arguments(fn, nin, nuv):
+    """SVD2_NO_UV: U and V pointers may be NULL (or anything: they are neither
+    checked nor written); smax, smin, s are checked as without the flag."""
+    ins = _ptrs(nin)
+    sig = _ptrs(3, base=FAKE + (64 << 30))
+    f = S.SVD2_NO_UV
+    assert _call(fn, 0, ins, [0] * nuv + sig, flags=f) == 0
+    junk = [ins[0] + 1] * nuv  # misaligned and overlapping an input: ignored
+    assert _call(fn, 0, ins, junk + sig, flags=f) == 0
+    assert _call(fn, 10, ins, [0] * nuv + sig) == 1  # without the flag U and V are needed
+    assert _call(fn, 10, ins, [0] * nuv + [sig[0], 0, sig[2]], flags=f) == 1
+    assert _call(fn, 10, ins, [0] * nuv + [sig[0], sig[0] + 8, sig[2]], flags=f) == 3
+    assert _call(fn, 10, ins, [0] * nuv + [sig[0], sig[1] + 1, sig[2]], flags=f) == 2
+    assert _call(fn, 10, ins, [0] * nuv + [sig[0], ins[1], sig[2]], flags=f) == 3
+
+
+def test_singular_values_only_launch_kinds():
+    old = S.svd2_get_launch_kind("z_nouv")
+    S.svd2_set_launch_kind("z_nouv", 128, 2)
+    assert S.svd2_get_launch_kind("z_nouv") == (128, 2)
+    S.svd2_set_launch_kind("z_nouv", *old)
+    assert S.lib().svd2_set_launch_kind(8, 256, 1) == 4
+
+
 def test_fp64_rejects_fp32_flags():
     ins, outs = _ptrs(4), _ptrs(11, base=FAKE + (64 << 30))
     assert _call(S.dsvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_FP64) == 4

@@ -320,3 +320,47 @@ def test_fp32_full_size_2_26_sampled(cplx):
     ora, _ = oracle_outs(sub, cplx, np.float32, rescue=True)
     st = compare(gpu, ora, cplx, EPS[np.float32])
     assert st["bitwise_lanes"] == st["lanes"]
+
+
+# ---------------------------------------------------------------------------
+# singular values only (SVD2_NO_UV)
+# ---------------------------------------------------------------------------
+
+def _raw(a):
+    return np.ascontiguousarray(a).view(np.uint8)
+
+
+@pytest.mark.parametrize("pt", [1, 2])
+@pytest.mark.parametrize("kind,mode", [("d", "none"), ("d", "safe"), ("d", "all"), ("z", "none"),
+                                       ("z", "safe"), ("z", "all")] +
+                         [(k, m) for k in "sc" for m in RESCUE_MODES])
+def test_singular_values_only(kind, mode, pt):
+    """smax, smin and s of a NO_UV call are byte for byte those of the full
+    call (signed zeros included) and bitwise the oracle's; the rescued-lane
+    count is unchanged; U and V are not written (NULL pointers)."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    _set_launch(256, pt)
+    cplx, dtype = kind in "zc", np.float64 if kind in "dz" else np.float32
+    A = scaled_law((1 << 17) + 5, SEED_BASE + 60, cplx, dtype=dtype)
+    tr = to_trains(A, dtype)
+    dev = [torch.from_numpy(t).cuda() for t in tr]
+    if dtype == np.float64:
+        flags = {"none": 0, "safe": S.SVD2_BACKSCALE_SAFE, "all": S.SVD2_BACKSCALE_ALL}[mode]
+        rescue, backscale = False, mode
+    else:
+        flags, rescue, backscale = _fp32_flags(mode), _oracle_rescue(mode), "none"
+    c1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    full = S.svd2(dev, flags=flags, nrescued=c1 if dtype == np.float32 else None)
+    sig = S.svd2(dev, flags=flags | S.SVD2_NO_UV, nrescued=c2 if dtype == np.float32 else None)
+    torch.cuda.synchronize()
+    assert len(sig) == 3
+    k = 16 if cplx else 8
+    ora, flagged = oracle_outs(tr, cplx, dtype, rescue=rescue, backscale=backscale)
+    for j in range(3):
+        g, f = sig[j].cpu().numpy(), full[k + j].cpu().numpy()
+        assert np.array_equal(_raw(g), _raw(f)), (kind, mode, j)
+        assert same_bits(g, ora[k + j]).all(), (kind, mode, j)
+    if dtype == np.float32:
+        assert int(c1.item()) == int(c2.item()) == (int(flagged.sum()) if rescue else 0)
