@@ -178,6 +178,9 @@ def _kog_lib():
             getattr(L, f"oracle_kog_step_{s}").argtypes = [i, P, i, i]
             getattr(L, f"oracle_kog_solve_{s}").argtypes = [i, P, i, d, i, P, P, P]
             getattr(L, f"oracle_kog_solve_{s}").restype = i
+        for s in "ds":
+            getattr(L, f"oracle_kog_svd_{s}").argtypes = [i, P, i, P, i, P, i, P, i, d, i, P, P]
+            getattr(L, f"oracle_kog_svd_{s}").restype = i
         L.oracle_kog_norms_d.argtypes = [i, P, i, i, P, P]
         L.oracle_kog_norms_s.argtypes = [i, P, i, i, P, P]
         L._kog_ready = True
@@ -218,6 +221,26 @@ def kog_norms(A: np.ndarray):
         L.oracle_kog_norms_d(A.shape[0], buf.ctypes.data, A.shape[0], int(s == "z"),
                              ctypes.byref(off2), ctypes.byref(tot2))
     return off2.value, tot2.value
+
+
+def kog_svd(A: np.ndarray, tol: float = 1e-14, max_sweeps: int = 40) -> dict:
+    """SVD A_0 = U diag(sigma) V^* by the Kogbetliantz method with accumulated
+    transformations (at least one sweep; sigma descending, ties by index, U
+    and V columns permuted alike).  A (Fortran-ordered) is replaced by the
+    final iterate.  Returns status, sweeps, off_rel, U, V, sigma."""
+    N = A.shape[0]
+    buf, s = _kog_buf(A)
+    U = np.zeros((N, N), dtype=A.dtype, order="F")
+    V = np.zeros((N, N), dtype=A.dtype, order="F")
+    ub, _ = _kog_buf(U)
+    vb, _ = _kog_buf(V)
+    rdt = np.float64 if s in "dz" else np.float32
+    sig = np.zeros(N, dtype=rdt)
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    st = getattr(_kog_lib(), f"oracle_kog_svd_{'d' if s in 'dz' else 's'}")(
+        N, buf.ctypes.data, N, ub.ctypes.data, N, vb.ctypes.data, N, sig.ctypes.data, int(s in "zc"),
+        tol, max_sweeps, ctypes.byref(sw), ctypes.byref(off))
+    return dict(status=st, sweeps=sw.value, off_rel=off.value, U=U, V=V, sigma=sig)
 
 
 def kog_solve(A: np.ndarray, tol: float = 1e-14, max_sweeps: int = 40) -> dict:

@@ -14,6 +14,7 @@
 
 #include <cfloat>
 #include <algorithm>
+#include <vector>
 #include <cmath>
 #include <cstring>
 #include <omp.h>
@@ -701,7 +702,28 @@ template <class T, bool CPLX> struct Mat {
 
 template <class T> Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 
-template <class T, bool CPLX> void kog_step(int N, T *A, int lda, int t) {
+/* [x_.p, x_.q] <- [x_.p, x_.q] W for the 2x2 matrix W (rows i = 0 .. N-1):
+ * the column half of a step, also the accumulation of the transformations */
+template <class T, bool CPLX>
+void rotate_columns(int N, Mat<T, CPLX> &M, int p, int q, const Cx<T> (&w)[2][2]) {
+  for (int i = 0; i < N; ++i) {
+    Cx<T> c1 = M.get(i, p), c2 = M.get(i, q), o1, o2;
+    if (CPLX) {
+      o1 = cadd(cmul(c1, w[0][0]), cmul(c2, w[1][0]));
+      o2 = cadd(cmul(c1, w[0][1]), cmul(c2, w[1][1]));
+    } else {
+      o1 = {fmaT(c1.re, w[0][0].re, c2.re * w[1][0].re), T(0)};
+      o2 = {fmaT(c1.re, w[0][1].re, c2.re * w[1][1].re), T(0)};
+    }
+    M.set(i, p, o1); M.set(i, q, o2);
+  }
+}
+
+/* One parallel step t (section 1): the pivot SVDs, then A <- U_k^* A V_k for
+ * every pair.  With U and V given, also U <- U U_k and V <- V V_k, so that
+ * A_0 = U A V^* holds for the iterate A throughout. */
+template <class T, bool CPLX>
+void kog_step(int N, T *A, int lda, int t, T *U = nullptr, int ldu = 0, T *V = nullptr, int ldv = 0) {
   const int n = N / 2;
   Mat<T, CPLX> M{A, lda};
   int *pr = new int[2 * n];
@@ -729,19 +751,13 @@ template <class T, bool CPLX> void kog_step(int N, T *A, int lda, int t) {
     }
   }
   /* columns: [a_.p, a_.q] <- [a_.p, a_.q] V_l */
-  for (int l = 0; l < n; ++l) {
-    int p = pr[2 * l], q = pr[2 * l + 1];
-    const Rot<T> &r = R[l];
-    for (int i = 0; i < N; ++i) {
-      Cx<T> c1 = M.get(i, p), c2 = M.get(i, q), o1, o2;
-      if (CPLX) {
-        o1 = cadd(cmul(c1, r.v[0][0]), cmul(c2, r.v[1][0]));
-        o2 = cadd(cmul(c1, r.v[0][1]), cmul(c2, r.v[1][1]));
-      } else {
-        o1 = {fmaT(c1.re, r.v[0][0].re, c2.re * r.v[1][0].re), T(0)};
-        o2 = {fmaT(c1.re, r.v[0][1].re, c2.re * r.v[1][1].re), T(0)};
-      }
-      M.set(i, p, o1); M.set(i, q, o2);
+  for (int l = 0; l < n; ++l) rotate_columns<T, CPLX>(N, M, pr[2 * l], pr[2 * l + 1], R[l].v);
+  /* accumulated transformations */
+  if (U) {
+    Mat<T, CPLX> MU{U, ldu}, MV{V, ldv};
+    for (int l = 0; l < n; ++l) {
+      rotate_columns<T, CPLX>(N, MU, pr[2 * l], pr[2 * l + 1], R[l].u);
+      rotate_columns<T, CPLX>(N, MV, pr[2 * l], pr[2 * l + 1], R[l].v);
     }
   }
   /* pivot blocks become diag(sigma_max, sigma_min) */
@@ -768,7 +784,8 @@ template <class T, bool CPLX> void kog_norms(int N, const T *A, int lda, double 
 
 template <class T, bool CPLX>
 int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, double *off_rel,
-              double *history) {
+              double *history, T *U = nullptr, int ldu = 0, T *V = nullptr, int ldv = 0,
+              int min_sweeps = 0) {
   // Exact power-of-two scaling around the iteration (the idea of eq. (2)
   // applied to the whole matrix): E is the largest binary exponent among the
   // finite nonzero components, A is multiplied by 2^-E before the first
@@ -807,9 +824,9 @@ int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, dou
     double rel = nrm0 > 0 ? std::sqrt(off2) / nrm0 : 0.0;
     if (history) history[sw] = rel;
     if (off_rel) *off_rel = rel;
-    if (rel < tol || nrm0 == 0) { status = 0; break; }
+    if ((rel < tol || nrm0 == 0) && sw >= min_sweeps) { status = 0; break; }
     if (sw == max_sweeps) break;
-    for (int t = 0; t < N - 1; ++t) kog_step<T, CPLX>(N, A, lda, t);
+    for (int t = 0; t < N - 1; ++t) kog_step<T, CPLX>(N, A, lda, t, U, ldu, V, ldv);
     ++sw;
     kog_norms<T, CPLX>(N, A, lda, off2, tot2);
   }
@@ -818,9 +835,54 @@ int kog_solve(int N, T *A, int lda, double tol, int max_sweeps, int *sweeps, dou
   return status;
 }
 
+/* The SVD A_0 = U diag(sigma) V^* of a square matrix by the Kogbetliantz
+ * method (section 1): the iteration above with its transformations
+ * accumulated from U = V = I, and at least one sweep, so that every diagonal
+ * entry of the final iterate is a singular value of some pivot block (real,
+ * non-negative).  Then sigma = the diagonal in descending order (equal values
+ * by increasing index) and the columns of U and V permuted alike.  A keeps the
+ * final iterate.  max_sweeps >= 1. */
+template <class T, bool CPLX>
+int kog_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma, double tol, int max_sweeps,
+            int *sweeps, double *off_rel) {
+  const int nc = CPLX ? 2 : 1;
+  for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N * nc; ++i) {
+      U[(size_t)j * ldu * nc + i] = (i == j * nc) ? T(1) : T(0);
+      V[(size_t)j * ldv * nc + i] = (i == j * nc) ? T(1) : T(0);
+    }
+  int status = kog_solve<T, CPLX>(N, A, lda, tol, max_sweeps, sweeps, off_rel, nullptr, U, ldu, V, ldv, 1);
+  std::vector<int> perm(N);
+  std::vector<T> d(N);
+  for (int i = 0; i < N; ++i) { perm[i] = i; d[i] = A[(size_t)i * lda * nc + (size_t)i * nc]; }
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] > d[b]; });
+  std::vector<T> tmp((size_t)N * N * nc);
+  for (T *X : {U, V}) {
+    const int ld = X == U ? ldu : ldv;
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N * nc; ++i) tmp[(size_t)j * N * nc + i] = X[(size_t)j * ld * nc + i];
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N * nc; ++i) X[(size_t)j * ld * nc + i] = tmp[(size_t)perm[j] * N * nc + i];
+  }
+  for (int i = 0; i < N; ++i) sigma[i] = d[perm[i]];
+  return status;
+}
+
 } /* namespace */
 
 extern "C" {
+int oracle_kog_svd_d(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma,
+                     int cplx, double tol, int max_sweeps, int *sweeps, double *off_rel) {
+  if (max_sweeps < 1) return 6;
+  return cplx ? kog_svd<double, true>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel)
+              : kog_svd<double, false>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel);
+}
+int oracle_kog_svd_s(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma,
+                     int cplx, double tol, int max_sweeps, int *sweeps, double *off_rel) {
+  if (max_sweeps < 1) return 6;
+  return cplx ? kog_svd<float, true>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel)
+              : kog_svd<float, false>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel);
+}
 int oracle_kog_pairs(int N, int t, int *pairs) { kog_pairs(N, t, pairs); return 0; }
 int oracle_kog_step_d(int N, double *A, int lda, int t) { kog_step<double, false>(N, A, lda, t); return 0; }
 int oracle_kog_step_z(int N, double *A, int lda, int t) { kog_step<double, true>(N, A, lda, t); return 0; }

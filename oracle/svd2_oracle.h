@@ -132,6 +132,26 @@ int oracle_kog_solve_s(int N, float *A, int lda, double tol, int max_sweeps, int
                        double *off_rel, double *history);
 int oracle_kog_solve_c(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
                        double *off_rel, double *history);
+/* SVD A_0 = U diag(sigma) V^* with the transformations of every step
+ * accumulated (section 1: the iterate is updated by U_k^* from the left and
+ * V_k from the right, so A_0 = (prod U_k) A (prod V_k)^*): U = V = I, then
+ * each step also applies [x_.p, x_.q] <- [x_.p, x_.q] U_k to U and V_k to V,
+ * with the rounding order of the column half of the block update.  At least
+ * one sweep is done, so the final diagonal holds pivot singular values (real,
+ * >= 0); sigma = that diagonal in descending order, equal values by
+ * increasing index, and the columns of U and V permuted alike.  A keeps the
+ * final iterate; U, V are N x N column-major with leading dimensions ldu,
+ * ldv (complex interleaved); cplx selects complex data.  Returns 0, 7 (max
+ * sweeps reached) or 6 (max_sweeps < 1).  Pinned against the definition of
+ * the SVD and LAPACK: reconstruction and unitarity within a small multiple of
+ * S N^1.5 eps, sigma within 8 N eps sigma_max, singular vectors of separated
+ * singular values to 1e-11, exact signed permutations for a real diagonal
+ * matrix, the iterate equal to the solve's. */
+int oracle_kog_svd_d(int N, double *A, int lda, double *U, int ldu, double *V, int ldv,
+                     double *sigma, int cplx, double tol, int max_sweeps, int *sweeps,
+                     double *off_rel);
+int oracle_kog_svd_s(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma,
+                     int cplx, double tol, int max_sweeps, int *sweeps, double *off_rel);
 
 #ifdef __cplusplus
 }
