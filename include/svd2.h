@@ -330,7 +330,7 @@ svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_b
  * only); sigma_out: device, N elements of the real type; ws: device scratch
  * of kog_sigma_workspace_bytes(N, dtype) bytes, 256-byte aligned.  A,
  * sigma_out and ws must not overlap (SVD2_ERR_ALIAS).  Asynchronous on
- * `stream` (a device radix sort). */
+ * `stream` (a bitonic sorting network on the device). */
 size_t kog_sigma_workspace_bytes(int N, int dtype);
 svd2_status dkog_sigma(int N, const double *A, int lda, double *sigma_out, void *ws, size_t ws_bytes,
                        hipStream_t stream);
@@ -340,6 +340,45 @@ svd2_status skog_sigma(int N, const float *A, int lda, float *sigma_out, void *w
                        hipStream_t stream);
 svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *ws, size_t ws_bytes,
                        hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * SVD of a square matrix, A_0 = U diag(sigma) V^*, by the Kogbetliantz method
+ * with the transformations accumulated (section 1: each step updates the
+ * iterate by U_k^* from the left and V_k from the right, so with U <- U U_k
+ * and V <- V V_k from U = V = I the identity A_0 = U A V^* holds throughout).
+ * Each accumulation rotates the column pair (p, q) of U or V with the
+ * rounding order of the column half of the block update.  The iteration,
+ * ordering, stopping rule and scaling are those of *_solve, except that at
+ * least one sweep is always done, so every diagonal entry of the final
+ * iterate is a singular value of a pivot block (real, >= 0).  On return:
+ *   sigma[0..N): that diagonal in descending order, equal values by
+ *     increasing index (device, N elements of the real type);
+ *   U, V: N x N, column-major, leading dimensions ldu, ldv >= N (complex
+ *     interleaved), columns permuted alike, so A_0 ~ U diag(sigma) V^*;
+ *   A: the final iterate (unsorted).
+ * ws: kog_svd_workspace_bytes(N, dtype, flags) bytes, 256-byte aligned (the
+ * solve's workspace plus two N x N matrices and the sort keys).  A, U, V,
+ * sigma and ws must be pairwise disjoint (SVD2_ERR_ALIAS).  flags: 0 or
+ * SVD2_KOG_TWO_STEP (two steps per pass; U and V alternate with workspace
+ * copies like the iterate), SVD2_KOG_UNFUSED (one step per pass, U and V
+ * rotated in place) or SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH; anything else is
+ * SVD2_ERR_FLAGS.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
+ * SVD2_NOT_CONVERGED (outputs as above for the last iterate); synchronises
+ * `stream` like *_solve.
+ * ------------------------------------------------------------------------- */
+size_t kog_svd_workspace_bytes(int N, int dtype, unsigned flags);
+svd2_status dkog_svd(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma,
+                     double tol, int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes,
+                     unsigned flags, hipStream_t stream);
+svd2_status zkog_svd(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma,
+                     double tol, int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes,
+                     unsigned flags, hipStream_t stream);
+svd2_status skog_svd(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma,
+                     double tol, int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes,
+                     unsigned flags, hipStream_t stream);
+svd2_status ckog_svd(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma,
+                     double tol, int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes,
+                     unsigned flags, hipStream_t stream);
 
 /* last hipError_t seen by a Kogbetliantz entry point on this thread */
 int kog_last_hip_error(void);

@@ -286,6 +286,60 @@ __global__ __launch_bounds__(256) void kog_maxexp_final_kernel(int nparts, const
 }
 
 // ---------------------------------------------------------------------------
+// SVD entry points: U = V = I at the start; at the end sigma in descending
+// order (equal values by increasing index) and the columns of U and V
+// permuted alike
+// ---------------------------------------------------------------------------
+template <class T, bool CPLX> __global__ __launch_bounds__(256) void kog_eye_kernel(int N, Mat<T, CPLX> X) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < N; i += blockDim.x) X.st(i, j, Cx<T>{i == j ? T(1) : T(0), T(0)});
+}
+
+// keys[i] = a_ii (real and >= 0 after a sweep), idx[i] = i; -1 pads to P
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_svd_keys_kernel(int N, int P, Mat<T, CPLX> A, T *keys, int *idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  keys[i] = i < N ? A.ld(i, i).re : T(-1);
+  idx[i] = i;
+}
+
+// one compare-exchange stage (block size k, distance j) of a bitonic sort of
+// the pairs (key, index) into the order: key descending, then index ascending
+template <class T>
+__global__ __launch_bounds__(256) void kog_svd_bitonic_kernel(T *keys, int *idx, int P, int j, int k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const int l = i ^ j;
+  if (l <= i) return;
+  const T a = keys[i], b = keys[l];
+  const int ia = idx[i], ib = idx[l];
+  const bool l_first = b > a || (b == a && ib < ia);
+  if ((i & k) == 0 ? l_first : !l_first) {
+    keys[i] = b;
+    keys[l] = a;
+    idx[i] = ib;
+    idx[l] = ia;
+  }
+}
+
+// dst[:, j] = src[:, idx[j]]
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_gather_cols_kernel(int N, Mat<T, CPLX> src, Mat<T, CPLX> dst,
+                                                              const int *idx) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x) {
+    const int c = idx[j];
+    if ((unsigned)c >= (unsigned)N) continue;  // only a NaN diagonal (non-finite input) sorts padding here
+    for (int i = threadIdx.x; i < N; i += blockDim.x) dst.st(i, j, src.ld(i, c));
+  }
+}
+
+template <class T> __global__ __launch_bounds__(256) void kog_vec_copy_kernel(int N, const T *src, T *dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX> struct Ctx {
@@ -297,6 +351,11 @@ template <class T, bool CPLX> struct Ctx {
   char *ws;
   unsigned flags;
   hipStream_t st;
+  // SVD entry points: the accumulated transformations, rotated in place in
+  // (U, V) one step per pass, or alternating with (U2, V2) like the iterate
+  // two steps per pass
+  bool acc = false;
+  Mat<T, CPLX> U{}, V{}, U2{}, V2{};
 };
 
 template <class T, bool CPLX>
@@ -355,6 +414,27 @@ template <> svd2_status batch_svd<float, true>(const Ctx<float, true> &c) {
   return csvd2_batch(c.N / 2, &a, SVD2_BACKSCALE_ALL | SVD2_RESCUE_FP64, nullptr, 0, c.st);
 }
 
+// U <- U U_k, V <- V V_k for the pairs of step t (rotations in c.B), in place
+template <class T, bool CPLX>
+svd2_status accum_step(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &U, const Mat<T, CPLX> &V, int t) {
+  const int n = c.N / 2, rows = c.N < 256 ? c.N : 256, ppb = 256 / rows;
+  hipLaunchKernelGGL((kog_accum_kernel<T, CPLX>), dim3((n + ppb - 1) / ppb, 2), dim3(256), 0, c.st, c.N, U, V, t,
+                     c.B);
+  return hip_st(hipGetLastError());
+}
+
+// the same for steps t and t+1 (rotations in c.B and c.B1), from the buffer
+// pair that holds U and V (in_w: the workspace pair) into the other one
+constexpr int kAccSeg = 32;  // step-t+1 pairs per segment of the two-step accumulation
+template <class T, bool CPLX> svd2_status accum_two(const Ctx<T, CPLX> &c, bool in_w, int t) {
+  const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + kAccSeg - 1) / kAccSeg;
+  const Mat<T, CPLX> &U = in_w ? c.U2 : c.U, &V = in_w ? c.V2 : c.V;
+  const Mat<T, CPLX> &U2 = in_w ? c.U : c.U2, &V2 = in_w ? c.V : c.V2;
+  hipLaunchKernelGGL((kog_accum2_kernel<T, CPLX>), dim3(rb * nseg, 2), dim3(256), 0, c.st, c.N, U, V, U2, V2, t,
+                     c.B, c.B1, kAccSeg);
+  return hip_st(hipGetLastError());
+}
+
 template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, int t) {
   const int n = c.N / 2;
   hipLaunchKernelGGL((kog_gather_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, c.M,
@@ -367,7 +447,9 @@ template <class T, bool CPLX> svd2_status unfused_step(const Ctx<T, CPLX> &c, in
   dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
   hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, c.M, t, c.B,
                      r.kc, r.lc);
-  return hip_st(hipGetLastError());
+  s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && c.acc) s = accum_step<T, CPLX>(c, c.U, c.V, t);
+  return s;
 }
 
 template <class T, bool CPLX> int fused_grid(int N) {
@@ -465,7 +547,8 @@ template <class T, bool CPLX> TwoStepShape two_step_shape(int N) {
 
 // two steps t, t+1 from `cur` into `nxt`
 template <class T, bool CPLX>
-svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t) {
+svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t,
+                      bool in_w = false) {
   const int n = c.N / 2;
   hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, c.B,
                      c.B1);
@@ -475,11 +558,14 @@ svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<
   if (sh.ntiles <= 0) return SVD2_ERR_HIP;
   hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), dim3(sh.ntiles), dim3(64 * sh.wpg), sh.lds, c.st, c.N, cur,
                      nxt, t, c.B, c.B1, sh.wpg, sh.span, sh.lc, sh.gx, sh.ntiles);
-  return hip_st(hipGetLastError());
+  s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && c.acc) s = accum_two<T, CPLX>(c, in_w, t);
+  return s;
 }
 
 // one step t in place on `cur` (gather + SVD in one kernel, then the update)
-template <class T, bool CPLX> svd2_status one_step_on(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, int t) {
+template <class T, bool CPLX>
+svd2_status one_step_on(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, int t, bool in_w = false) {
   const int n = c.N / 2;
   hipLaunchKernelGGL((kog_pivot_kernel<T, CPLX>), dim3((n + 255) / 256), dim3(256), 0, c.st, c.N, cur, t, c.B);
   svd2_status s = hip_st(hipGetLastError());
@@ -487,7 +573,9 @@ template <class T, bool CPLX> svd2_status one_step_on(const Ctx<T, CPLX> &c, con
   TileRule r = rule_for(c.N);
   dim3 grid((n + r.kc - 1) / r.kc, (n + r.lc - 1) / r.lc);
   hipLaunchKernelGGL((kog_update_kernel<T, CPLX>), grid, dim3(kUpdBlock), 0, c.st, c.N, cur, t, c.B, r.kc, r.lc);
-  return hip_st(hipGetLastError());
+  s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && c.acc) s = accum_step<T, CPLX>(c, in_w ? c.U2 : c.U, in_w ? c.V2 : c.V, t);
+  return s;
 }
 
 // a sweep of the two-step mode; *in_w tells (and is updated with) which
@@ -497,10 +585,10 @@ template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, 
   int t = 0;
   for (; t + 1 < c.N - 1 && s == SVD2_OK; t += 2) {
     const Mat<T, CPLX> &cur = *in_w ? c.W : c.M, &nxt = *in_w ? c.M : c.W;
-    s = two_steps<T, CPLX>(c, cur, nxt, t);
+    s = two_steps<T, CPLX>(c, cur, nxt, t, *in_w);
     *in_w = !*in_w;
   }
-  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t);
+  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t, *in_w);
   return s;
 }
 
@@ -600,8 +688,11 @@ template <class T, bool CPLX> svd2_status graph_build(Ctx<T, CPLX> c, hipGraphEx
   return s;
 }
 
+// sweeps until off(A) < tol ||A_0||_F (and at least min_sweeps); *uv_in_w
+// (optional) tells whether the accumulated U, V ended in (U2, V2)
 template <class T, bool CPLX>
-svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, double *off_rel) {
+svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, double *off_rel,
+                  int min_sweeps = 0, bool *uv_in_w = nullptr) {
   if (max_sweeps < 0 || !(tol >= 0)) return SVD2_ERR_SIZE;
   hipGraphExec_t exec = nullptr;
   svd2_status s = SVD2_OK;
@@ -619,7 +710,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
   while (s == SVD2_OK) {
     double rel = nrm0 > 0 ? __builtin_sqrt(off2) / nrm0 : 0.0;
     if (off_rel) *off_rel = rel;
-    if (rel < tol || nrm0 == 0) {
+    if ((rel < tol || nrm0 == 0) && sw >= min_sweeps) {
       result = SVD2_OK;
       break;
     }
@@ -632,6 +723,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     if (s == SVD2_OK) s = check_abort<T, CPLX>(c);
     ++sw;
   }
+  if (uv_in_w) *uv_in_w = in_w;
   if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
   if (s == SVD2_OK && E != 0) s = scale_by<T, CPLX>(c, E);
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
@@ -685,6 +777,98 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
 }
 
 
+// workspace of the SVD entry points: the solve's, then the second U and V
+// buffers (N x N, lda N) and the sort keys and indices (next power of two)
+struct SvdLayout {
+  size_t u2, v2, keys, idx, total;
+  int P;
+};
+inline SvdLayout svd_layout(int N, size_t esz, bool cplx, bool two) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const Layout L = layout(N, esz, cplx);
+  const size_t mat = up((size_t)N * N * esz * (cplx ? 2 : 1));
+  SvdLayout S;
+  S.P = 1;
+  while (S.P < N) S.P <<= 1;
+  S.u2 = two ? L.total2 : L.total;
+  S.v2 = S.u2 + mat;
+  S.keys = S.v2 + mat;
+  S.idx = S.keys + up((size_t)S.P * esz);
+  S.total = S.idx + up((size_t)S.P * sizeof(int));
+  return S;
+}
+
+// the flags of the SVD entry points: 0 = two steps per pass
+inline unsigned svd_flags(unsigned flags) { return flags == 0 ? (unsigned)SVD2_KOG_TWO_STEP : flags; }
+
+template <class T, bool CPLX>
+svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma, double tol, int max_sweeps,
+                    int *sweeps, double *off_rel, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
+  flags = svd_flags(flags);
+  if (flags != SVD2_KOG_TWO_STEP && flags != SVD2_KOG_UNFUSED && flags != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))
+    return SVD2_ERR_FLAGS;
+  Ctx<T, CPLX> c;
+  svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
+  if (s != SVD2_OK) return s;
+  if (!U || !V || !sigma) return SVD2_ERR_NULL;
+  if (ldu < N || ldv < N || max_sweeps < 1) return SVD2_ERR_SIZE;
+  const size_t esz = sizeof(T) * (CPLX ? 2 : 1);
+  if ((uintptr_t)U % esz || (uintptr_t)V % esz || (uintptr_t)sigma % sizeof(T)) return SVD2_ERR_ALIGN;
+  const SvdLayout S = svd_layout(N, sizeof(T), CPLX, (flags & SVD2_KOG_TWO_STEP) != 0);
+  if (wsb < S.total) return SVD2_ERR_SIZE;
+  const uintptr_t r[5][2] = {{(uintptr_t)A, (uintptr_t)A + ((size_t)lda * (N - 1) + N) * esz},
+                             {(uintptr_t)U, (uintptr_t)U + ((size_t)ldu * (N - 1) + N) * esz},
+                             {(uintptr_t)V, (uintptr_t)V + ((size_t)ldv * (N - 1) + N) * esz},
+                             {(uintptr_t)sigma, (uintptr_t)sigma + (size_t)N * sizeof(T)},
+                             {(uintptr_t)ws, (uintptr_t)ws + S.total}};
+  for (int a = 0; a < 5; ++a)
+    for (int b = a + 1; b < 5; ++b)
+      if (r[a][0] < r[b][1] && r[b][0] < r[a][1]) return SVD2_ERR_ALIAS;
+  c.st = st;
+  c.acc = true;
+  c.U = Mat<T, CPLX>{U, (size_t)ldu};
+  c.V = Mat<T, CPLX>{V, (size_t)ldv};
+  c.U2 = Mat<T, CPLX>{(T *)(c.ws + S.u2), (size_t)N};
+  c.V2 = Mat<T, CPLX>{(T *)(c.ws + S.v2), (size_t)N};
+  const int grid = N < 4096 ? N : 4096;
+  hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.U);
+  hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.V);
+  s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  bool uv_in_w = false;
+  const svd2_status res = solve<T, CPLX>(c, tol, max_sweeps, sweeps, off_rel, 1, &uv_in_w);
+  if (res != SVD2_OK && res != SVD2_NOT_CONVERGED) return res;
+  // sort the diagonal with its indices
+  T *keys = (T *)(c.ws + S.keys);
+  int *idx = (int *)(c.ws + S.idx);
+  const dim3 pg((S.P + 255) / 256), blk(256);
+  hipLaunchKernelGGL((kog_svd_keys_kernel<T, CPLX>), pg, blk, 0, st, N, S.P, c.M, keys, idx);
+  s = hip_st(hipGetLastError());
+  for (int k = 2; k <= S.P && s == SVD2_OK; k <<= 1)
+    for (int j = k >> 1; j > 0 && s == SVD2_OK; j >>= 1) {
+      hipLaunchKernelGGL(kog_svd_bitonic_kernel<T>, pg, blk, 0, st, keys, idx, S.P, j, k);
+      s = hip_st(hipGetLastError());
+    }
+  // permuted columns into the caller's U and V (through the second buffers)
+  for (int m = 0; m < 2 && s == SVD2_OK; ++m) {
+    const Mat<T, CPLX> &X = m ? c.V : c.U, &X2 = m ? c.V2 : c.U2;
+    if (!uv_in_w) {
+      hipLaunchKernelGGL((kog_copy_kernel<T, CPLX>), dim3(grid), blk, 0, st, N, X, X2);
+      s = hip_st(hipGetLastError());
+    }
+    if (s == SVD2_OK) {
+      hipLaunchKernelGGL((kog_gather_cols_kernel<T, CPLX>), dim3(grid), blk, 0, st, N, X2, X, (const int *)idx);
+      s = hip_st(hipGetLastError());
+    }
+  }
+  if (s == SVD2_OK) {
+    hipLaunchKernelGGL(kog_vec_copy_kernel<T>, dim3((N + 255) / 256), blk, 0, st, N, (const T *)keys, sigma);
+    s = hip_st(hipGetLastError());
+  }
+  if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(st));
+  return s != SVD2_OK ? s : res;
+}
+
 }  // namespace
 
 // the last HIP error of a Kogbetliantz entry point defined in another file
@@ -706,6 +890,43 @@ size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags) {
 }
 
 size_t kog_workspace_bytes(int N, int dtype) { return kog_workspace_bytes_flags(N, dtype, 0); }
+
+size_t kog_svd_workspace_bytes(int N, int dtype, unsigned flags) {
+  if (N < 2 || N % 2 || N > (1 << 19)) return 0;
+  const bool two = (svd_flags(flags) & SVD2_KOG_TWO_STEP) != 0;
+  switch (dtype) {
+    case SVD2_KOG_F64: return svd_layout(N, 8, false, two).total;
+    case SVD2_KOG_C128: return svd_layout(N, 8, true, two).total;
+    case SVD2_KOG_F32: return svd_layout(N, 4, false, two).total;
+    case SVD2_KOG_C64: return svd_layout(N, 4, true, two).total;
+  }
+  return 0;
+}
+
+svd2_status dkog_svd(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma, double tol,
+                     int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes, unsigned flags,
+                     hipStream_t stream) {
+  return api_svd<double, false>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes,
+                                flags, stream);
+}
+svd2_status zkog_svd(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma, double tol,
+                     int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes, unsigned flags,
+                     hipStream_t stream) {
+  return api_svd<double, true>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes,
+                               flags, stream);
+}
+svd2_status skog_svd(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma, double tol,
+                     int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes, unsigned flags,
+                     hipStream_t stream) {
+  return api_svd<float, false>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes,
+                               flags, stream);
+}
+svd2_status ckog_svd(int N, float *A, int lda, float *U, int ldu, float *V, int ldv, float *sigma, double tol,
+                     int max_sweeps, int *sweeps, double *off_rel, void *ws, size_t ws_bytes, unsigned flags,
+                     hipStream_t stream) {
+  return api_svd<float, true>(N, A, lda, U, ldu, V, ldv, sigma, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes,
+                              flags, stream);
+}
 
 svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
                       hipStream_t stream) {

@@ -717,6 +717,136 @@ __device__ __forceinline__ void two_step_tile(char *kog_smem, int N, const Mat<T
 }
 
 
+// ---------------------------------------------------------------------------
+// Accumulated transformations (the SVD entry points).  Section 1 updates the
+// iterate by U_k^* from the left and V_k from the right, so with U <- U U_k
+// and V <- V V_k after every step A_0 = U A V^* holds throughout.  Each is a
+// rotation of the column pair (p, q) of U or V with the rounding order of the
+// column half of the block update.
+// ---------------------------------------------------------------------------
+template <class T> struct W4 {
+  Cx<T> w11, w21, w12, w22;
+};
+template <class T> __device__ __forceinline__ W4<T> w_of(const Rot<T> &r, bool v) {
+  return v ? W4<T>{r.v11, r.v21, r.v12, r.v22} : W4<T>{r.u11, r.u21, r.u12, r.u22};
+}
+
+// [c1, c2] <- [c1, c2] W
+template <class T, bool CPLX> __device__ __forceinline__ void rot_cols(const W4<T> &w, Cx<T> &c1, Cx<T> &c2) {
+  if constexpr (CPLX) {
+    const Cx<T> o1 = cadd(cmul(c1, w.w11), cmul(c2, w.w21));
+    const Cx<T> o2 = cadd(cmul(c1, w.w12), cmul(c2, w.w22));
+    c1 = o1;
+    c2 = o2;
+  } else {
+    const T o1 = vfma(c1.re, w.w11.re, c2.re * w.w21.re);
+    const T o2 = vfma(c1.re, w.w12.re, c2.re * w.w22.re);
+    c1.re = o1;
+    c2.re = o2;
+  }
+}
+
+// One step t in place: grid (ceil(n / ppb), 2), blockIdx.y = 0 rotates U by
+// the U_k, 1 rotates V by the V_k.  A workgroup of 256 threads takes ppb =
+// 256 / min(N, 256) column pairs; its lanes run down the rows of a pair, so a
+// wavefront reads and writes contiguous runs of both columns.
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V, int t,
+                                                        Bufs<T, CPLX> B) {
+  constexpr int G = 4;
+  const int n = N / 2, rows = N < 256 ? N : 256, ppb = 256 / rows;
+  const int slot = (int)threadIdx.x / rows, l = (int)blockIdx.x * ppb + slot;
+  if (slot >= ppb || l >= n) return;
+  const bool isv = blockIdx.y != 0;
+  const Mat<T, CPLX> X = isv ? V : U;
+  int a, b;
+  pair_ab(t, l, N - 1, a, b);
+  const int p = a < b ? a : b, q = a < b ? b : a;
+  const W4<T> w = w_of(load_rot<T, CPLX>(B, l), isv);
+  for (int i0 = (int)threadIdx.x % rows; i0 < N; i0 += G * rows) {
+    Cx<T> c1[G], c2[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g * rows;
+      if (i < N) {
+        c1[g] = X.ld(i, p);
+        c2[g] = X.ld(i, q);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g * rows;
+      if (i < N) {
+        rot_cols<T, CPLX>(w, c1[g], c2[g]);
+        X.st(i, p, c1[g]);
+        X.st(i, q, c2[g]);
+      }
+    }
+  }
+}
+
+// Two steps t, t+1 from (U, V) into (U2, V2), bitwise two single steps.
+// Pair j of step t has the columns x_j = (t + j) mod (N-1) and y_j = (t - j)
+// mod (N-1) (x_0 = t, y_0 = N-1); pair k of step t+1 is made of the rotated
+// columns f_k and g_k, where f_k = x_{k+1} (k < n-1) or y_{n-1} (k = n-1),
+// and g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one
+// row and walks the step-t pairs j in increasing order, keeping the last
+// three rotated pairs in registers; pair k is written at j = min(k+1, n-1).
+// Grid (row blocks of 256 x segments of seg output pairs, 2): a segment
+// re-walks the step-t pairs just before and after it, so the output is out of
+// place (a step-t column is read by two segments).
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_accum2_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
+                                                         Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
+                                                         Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int seg) {
+  const int n = N / 2, Mo = N - 1;
+  const int rb = (N + 255) / 256, nseg = (n + seg - 1) / seg;
+  const int blk = (int)blockIdx.x % rb, sg = (int)blockIdx.x / rb;
+  if (sg >= nseg) return;
+  const int i = blk * 256 + (int)threadIdx.x;
+  const bool live = i < N;
+  const bool isv = blockIdx.y != 0;
+  const Mat<T, CPLX> X = isv ? V : U, Y = isv ? V2 : U2;
+  const int k0 = sg * seg, k1 = k0 + seg < n ? k0 + seg : n;
+  const int jlo = k0 <= 1 ? 0 : k0 - 1, jhi = k1 < n - 1 ? k1 : n - 1;
+  // rotated (x_j, y_j) of the last three walked pairs: w0 = j, w1 = j-1, w2 = j-2
+  Cx<T> x0{}, y0{}, x1{}, y1{}, x2{}, y2{};
+  auto emit = [&](int k, Cx<T> f, Cx<T> g) {
+    int a, b;
+    pair_ab(t + 1, k, Mo, a, b);  // a holds f, b holds g
+    const W4<T> w = w_of(load_rot<T, CPLX>(B1, k), isv);
+    const bool fl = a > b;
+    Cx<T> c1 = fl ? g : f, c2 = fl ? f : g;
+    rot_cols<T, CPLX>(w, c1, c2);
+    if (live) {
+      Y.st(i, fl ? b : a, c1);
+      Y.st(i, fl ? a : b, c2);
+    }
+  };
+  for (int j = jlo; j <= jhi; ++j) {
+    int a, b;
+    pair_ab(t, j, Mo, a, b);  // a = x_j, b = y_j
+    const bool fl = a > b;
+    Cx<T> ca{}, cb{};
+    if (live) {
+      ca = X.ld(i, a);
+      cb = X.ld(i, b);
+    }
+    const W4<T> w = w_of(load_rot<T, CPLX>(B0, j), isv);
+    Cx<T> c1 = fl ? cb : ca, c2 = fl ? ca : cb;
+    rot_cols<T, CPLX>(w, c1, c2);
+    x2 = x1; y2 = y1;
+    x1 = x0; y1 = y0;
+    x0 = fl ? c2 : c1;
+    y0 = fl ? c1 : c2;
+    if (j >= 1) {
+      const int k = j - 1;
+      if (k >= k0 && k < k1) emit(k, x0, k == 0 ? y1 : (k == 1 ? x2 : y2));
+    }
+    if (j == n - 1 && n - 1 >= k0 && n - 1 < k1) emit(n - 1, y0, n - 1 == 1 ? x1 : y1);
+  }
+}
+
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_copy_kernel(int N, Mat<T, CPLX> src, Mat<T, CPLX> dst) {
   for (int j = blockIdx.x; j < N; j += gridDim.x)

@@ -62,7 +62,8 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
            "kog_batch_workspace_bytes_flags", "kog_sigma_workspace_bytes", "dkog_sigma", "zkog_sigma",
-           "skog_sigma", "ckog_sigma",
+           "skog_sigma", "ckog_sigma", "kog_svd_workspace_bytes", "dkog_svd", "zkog_svd", "skog_svd",
+           "ckog_svd",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -289,8 +290,11 @@ def _kog():
             getattr(L, f"{x}kog_solve").argtypes = [i, _P, i, d, i, _P, _P, _P, sz, ui, _P]
             getattr(L, f"{x}kog_norms").argtypes = [i, _P, i, _P, _P, _P, sz, _P]
             getattr(L, f"{x}kog_sigma").argtypes = [i, _P, i, _P, _P, sz, _P]
-            for f in ("step", "sweep", "solve", "norms", "sigma"):
+            getattr(L, f"{x}kog_svd").argtypes = [i, _P, i, _P, i, _P, i, _P, d, i, _P, _P, _P, sz, ui, _P]
+            for f in ("step", "sweep", "solve", "norms", "sigma", "svd"):
                 getattr(L, f"{x}kog_{f}").restype = i
+        L.kog_svd_workspace_bytes.argtypes = [i, i, ui]
+        L.kog_svd_workspace_bytes.restype = sz
         L.kog_sigma_workspace_bytes.argtypes = [i, i]
         L.kog_sigma_workspace_bytes.restype = sz
         L.kog_last_hip_error.restype = i
@@ -375,6 +379,36 @@ def kog_sigma(A, out=None, ws=None, stream=None):
     _kog_check(f"{k}kog_sigma", getattr(_kog(), f"{k}kog_sigma")(N, ptr, lda, out.data_ptr(), ws.data_ptr(),
                                                                   ws.numel(), _stream(stream)))
     return out
+
+
+def kog_svd_workspace_bytes(N: int, kind: str, flags: int = 0) -> int:
+    return int(_kog().kog_svd_workspace_bytes(N, KOG_DTYPE[kind], flags))
+
+
+def kog_svd(A, tol: float = 1e-14, max_sweeps: int = 40, U=None, V=None, sigma=None, ws=None,
+            flags: int = 0, stream=None) -> dict:
+    """SVD A_0 = U diag(sigma) V^* with the transformations accumulated; A is
+    replaced by the final iterate.  U, V (column-major, allocated if None)
+    and sigma (descending) are returned with status, sweeps, off_rel."""
+    import torch
+    k = kog_kind(A)
+    N, lda, ptr = _kog_args(A)
+    if U is None:
+        U = torch.empty((N, N), dtype=A.dtype, device=A.device).t()
+    if V is None:
+        V = torch.empty((N, N), dtype=A.dtype, device=A.device).t()
+    _, ldu, uptr = _kog_args(U)
+    _, ldv, vptr = _kog_args(V)
+    real = torch.float64 if k in "dz" else torch.float32
+    sigma = torch.empty(N, dtype=real, device=A.device) if sigma is None else sigma
+    if ws is None:
+        ws = torch.empty(kog_svd_workspace_bytes(N, k, flags), dtype=torch.uint8, device=A.device)
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    st = getattr(_kog(), f"{k}kog_svd")(N, ptr, lda, uptr, ldu, vptr, ldv, sigma.data_ptr(), tol, max_sweeps,
+                                        ctypes.byref(sw), ctypes.byref(off), ws.data_ptr(), ws.numel(), flags,
+                                        _stream(stream))
+    _kog_check(f"{k}kog_svd", st)
+    return dict(status=st, sweeps=sw.value, off_rel=off.value, U=U, V=V, sigma=sigma)
 
 
 def kog_norms(A, ws=None, stream=None):

@@ -179,6 +179,37 @@ def test_kog_argument_errors():
                         None) == 6                      # negative max_sweeps
 
 
+def test_kog_svd_argument_errors():
+    """The SVD entry points validate every pointer, size, flag and overlap
+    before any HIP call."""
+    import ctypes
+    L = S._kog()
+    N = 64
+    A, U, V, sig, ws = (FAKE + (i << 30) for i in range(5))
+    wsb = S.kog_svd_workspace_bytes(N, "z")
+    assert wsb >= S.kog_workspace_bytes(N, "z", S.SVD2_KOG_TWO_STEP) + 2 * N * N * 16
+    assert S.kog_svd_workspace_bytes(N, "z", S.SVD2_KOG_TWO_STEP) == wsb  # 0 means two steps per pass
+    assert S.kog_svd_workspace_bytes(N, "z", S.SVD2_KOG_UNFUSED) < wsb
+    assert S.kog_svd_workspace_bytes(63, "z") == 0
+    sw, off = ctypes.c_int(), ctypes.c_double()
+
+    def call(a=A, lda=N, u=U, ldu=N, v=V, ldv=N, s=sig, ms=40, w=ws, b=wsb, f=0):
+        return L.zkog_svd(N, a, lda, u, ldu, v, ldv, s, 1e-14, ms, ctypes.byref(sw), ctypes.byref(off), w, b,
+                          f, None)
+
+    assert call(u=0) == 1 and call(v=0) == 1 and call(s=0) == 1 and call(a=0) == 1
+    assert call(ldu=N - 1) == 6 and call(ldv=N - 1) == 6 and call(lda=N - 1) == 6
+    assert call(ms=0) == 6                               # at least one sweep
+    assert call(b=wsb - 1) == 6                          # workspace too small
+    assert call(u=U + 8) == 2 and call(s=sig + 4) == 2   # misaligned
+    assert call(v=U + 16) == 3                           # V overlaps U
+    assert call(s=A + 64) == 3                           # sigma inside A
+    assert call(u=ws + wsb - 64) == 3                    # U overlaps the workspace
+    assert call(f=S.SVD2_KOG_GRAPH) == 4                 # GRAPH without UNFUSED
+    assert call(f=S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_UNFUSED) == 4
+    assert call(f=8) == 4
+
+
 def test_kog_batch_argument_errors():
     import ctypes
     L = S._batch()
