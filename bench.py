@@ -197,9 +197,51 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
                         "sigma_max_abs_err_rel": float(np.max(np.abs(sig - s)) / s[0])}
         log(f"[bench] kog solve: {json.dumps(out['solve'])}")
         del G, ws
+    if solve:
+        out["svd"] = kog_svd_bench(A, s, G0, mat, steps, passes)
     del G0
     torch.cuda.empty_cache()
     return out
+
+
+def kog_svd_bench(A, s, G0, mat, steps, passes):
+    """The full SVD A_0 = U diag(sigma) V^* (transformations accumulated, two
+    steps per pass) on the one-problem workload: one sweep and a full solve,
+    sigma against the known singular values, and the residuals
+    ||A_0 - U S V^T||_F / ||A_0||_F and ||U^T U - I||_F computed on the GPU."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N = A.shape[0]
+    fl = S.SVD2_KOG_TWO_STEP
+    ws = torch.empty(S.kog_svd_workspace_bytes(N, "d", fl), dtype=torch.uint8, device="cuda")
+    # per sweep: the iterate once per pass (as the solve), U and V likewise
+    hbm = 3 * 2 * mat * (passes + (steps - 2 * passes))
+    res = {"mode": "two_step", "algorithmic_bytes_per_sweep": hbm}
+    G = G0.clone(memory_format=torch.preserve_format)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.kog_svd(G, tol=0.0, max_sweeps=1, ws=ws, flags=fl)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["one_sweep_s"] = el
+    res["hbm_GBs"] = hbm / el / 1e9
+    G = G0.clone(memory_format=torch.preserve_format)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = S.kog_svd(G, tol=1e-14, max_sweeps=60, ws=ws, flags=fl)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    U, V, sig = r["U"], r["V"], r["sigma"]
+    A0 = G0
+    rec = torch.linalg.norm(A0 - (U * sig) @ V.t().contiguous()) / torch.linalg.norm(A0)
+    orth = torch.linalg.norm(U.t().contiguous() @ U - torch.eye(N, dtype=U.dtype, device="cuda"))
+    res.update({"status": r["status"], "sweeps": r["sweeps"], "seconds": el, "sweeps_per_s": r["sweeps"] / el,
+                "sigma_max_abs_err_rel": float(np.max(np.abs(sig.cpu().numpy() - s)) / s[0]),
+                "residual_rel": float(rec), "orthogonality": float(orth)})
+    log(f"[bench] kog svd: {json.dumps(res)}")
+    del G, ws, U, V
+    torch.cuda.empty_cache()
+    return res
 
 
 def kog_batch_bench(nprob: int = 256):

@@ -425,13 +425,12 @@ svd2_status accum_step(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &U, const Mat<T
 
 // the same for steps t and t+1 (rotations in c.B and c.B1), from the buffer
 // pair that holds U and V (in_w: the workspace pair) into the other one
-constexpr int kAccSeg = 32;  // step-t+1 pairs per segment of the two-step accumulation
 template <class T, bool CPLX> svd2_status accum_two(const Ctx<T, CPLX> &c, bool in_w, int t) {
   const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + kAccSeg - 1) / kAccSeg;
   const Mat<T, CPLX> &U = in_w ? c.U2 : c.U, &V = in_w ? c.V2 : c.V;
   const Mat<T, CPLX> &U2 = in_w ? c.U : c.U2, &V2 = in_w ? c.V : c.V2;
   hipLaunchKernelGGL((kog_accum2_kernel<T, CPLX>), dim3(rb * nseg, 2), dim3(256), 0, c.st, c.N, U, V, U2, V2, t,
-                     c.B, c.B1, kAccSeg);
+                     c.B, c.B1);
   return hip_st(hipGetLastError());
 }
 

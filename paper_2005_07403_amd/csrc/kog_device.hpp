@@ -792,58 +792,90 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // and g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one
 // row and walks the step-t pairs j in increasing order, keeping the last
 // three rotated pairs in registers; pair k is written at j = min(k+1, n-1).
-// Grid (row blocks of 256 x segments of seg output pairs, 2): a segment
+// Grid (row blocks of 256 x segments of kAccSeg output pairs, 2): a segment
 // re-walks the step-t pairs just before and after it, so the output is out of
-// place (a step-t column is read by two segments).
+// place (a step-t column is read by two segments).  The segment's rotations
+// are staged in LDS first, and the walk goes in chunks of kAccChunk pairs
+// whose column loads are issued one chunk ahead (the loads cannot move past
+// the previous chunk's stores otherwise, and each would wait a full memory
+// round trip).
+constexpr int kAccSeg = 32, kAccChunk = 4;
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_accum2_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
                                                          Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
-                                                         Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, int seg) {
+                                                         Bufs<T, CPLX> B0, Bufs<T, CPLX> B1) {
+  constexpr int C = kAccChunk;
+  __shared__ W4<T> w0s[kAccSeg + 2], w1s[kAccSeg];
   const int n = N / 2, Mo = N - 1;
-  const int rb = (N + 255) / 256, nseg = (n + seg - 1) / seg;
+  const int rb = (N + 255) / 256, nseg = (n + kAccSeg - 1) / kAccSeg;
   const int blk = (int)blockIdx.x % rb, sg = (int)blockIdx.x / rb;
   if (sg >= nseg) return;
-  const int i = blk * 256 + (int)threadIdx.x;
+  const int tid = (int)threadIdx.x, i = blk * 256 + tid;
   const bool live = i < N;
   const bool isv = blockIdx.y != 0;
   const Mat<T, CPLX> X = isv ? V : U, Y = isv ? V2 : U2;
-  const int k0 = sg * seg, k1 = k0 + seg < n ? k0 + seg : n;
+  const int k0 = sg * kAccSeg, k1 = k0 + kAccSeg < n ? k0 + kAccSeg : n;
   const int jlo = k0 <= 1 ? 0 : k0 - 1, jhi = k1 < n - 1 ? k1 : n - 1;
+  if (tid < jhi - jlo + 1) w0s[tid] = w_of(load_rot<T, CPLX>(B0, jlo + tid), isv);
+  if (tid >= 128 && tid - 128 < k1 - k0) w1s[tid - 128] = w_of(load_rot<T, CPLX>(B1, k0 + tid - 128), isv);
+  __syncthreads();
   // rotated (x_j, y_j) of the last three walked pairs: w0 = j, w1 = j-1, w2 = j-2
   Cx<T> x0{}, y0{}, x1{}, y1{}, x2{}, y2{};
   auto emit = [&](int k, Cx<T> f, Cx<T> g) {
     int a, b;
     pair_ab(t + 1, k, Mo, a, b);  // a holds f, b holds g
-    const W4<T> w = w_of(load_rot<T, CPLX>(B1, k), isv);
+    const W4<T> w = w1s[k - k0];
     const bool fl = a > b;
-    Cx<T> c1 = fl ? g : f, c2 = fl ? f : g;
+    Cx<T> c1 = sel(fl, g, f), c2 = sel(fl, f, g);
     rot_cols<T, CPLX>(w, c1, c2);
     if (live) {
       Y.st(i, fl ? b : a, c1);
       Y.st(i, fl ? a : b, c2);
     }
   };
-  for (int j = jlo; j <= jhi; ++j) {
-    int a, b;
-    pair_ab(t, j, Mo, a, b);  // a = x_j, b = y_j
-    const bool fl = a > b;
-    Cx<T> ca{}, cb{};
-    if (live) {
-      ca = X.ld(i, a);
-      cb = X.ld(i, b);
+  auto load = [&](int jb, Cx<T> (&la)[C], Cx<T> (&lb)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = jb + c;
+      if (j <= jhi && live) {
+        int a, b;
+        pair_ab(t, j, Mo, a, b);
+        la[c] = X.ld(i, a);
+        lb[c] = X.ld(i, b);
+      }
     }
-    const W4<T> w = w_of(load_rot<T, CPLX>(B0, j), isv);
-    Cx<T> c1 = fl ? cb : ca, c2 = fl ? ca : cb;
-    rot_cols<T, CPLX>(w, c1, c2);
-    x2 = x1; y2 = y1;
-    x1 = x0; y1 = y0;
-    x0 = fl ? c2 : c1;
-    y0 = fl ? c1 : c2;
-    if (j >= 1) {
-      const int k = j - 1;
-      if (k >= k0 && k < k1) emit(k, x0, k == 0 ? y1 : (k == 1 ? x2 : y2));
+  };
+  auto walk = [&](int jb, const Cx<T> (&la)[C], const Cx<T> (&lb)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int j = jb + c;
+      if (j <= jhi) {
+        int a, b;
+        pair_ab(t, j, Mo, a, b);  // a = x_j, b = y_j
+        const bool fl = a > b;
+        Cx<T> c1 = sel(fl, lb[c], la[c]), c2 = sel(fl, la[c], lb[c]);
+        rot_cols<T, CPLX>(w0s[j - jlo], c1, c2);
+        x2 = x1; y2 = y1;
+        x1 = x0; y1 = y0;
+        x0 = sel(fl, c2, c1);
+        y0 = sel(fl, c1, c2);
+        if (j >= 1) {
+          const int k = j - 1;
+          if (k >= k0 && k < k1) emit(k, x0, sel(k == 0, y1, sel(k == 1, x2, y2)));
+        }
+        if (j == n - 1 && n - 1 >= k0 && n - 1 < k1) emit(n - 1, y0, sel(n - 1 == 1, x1, y1));
+      }
     }
-    if (j == n - 1 && n - 1 >= k0 && n - 1 < k1) emit(n - 1, y0, n - 1 == 1 ? x1 : y1);
+  };
+  Cx<T> pa[C], pb[C], qa[C], qb[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) pa[c] = pb[c] = qa[c] = qb[c] = Cx<T>{T(0), T(0)};
+  load(jlo, pa, pb);
+  for (int jb = jlo; jb <= jhi; jb += 2 * C) {
+    load(jb + C, qa, qb);
+    walk(jb, pa, pb);
+    load(jb + 2 * C, pa, pb);
+    walk(jb + C, qa, qb);
   }
 }
 
