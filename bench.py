@@ -335,7 +335,8 @@ def main():
                     help="run only the Kogbetliantz drivers named (comma list of fused, unfused, graph, "
                          "two_step), one sweep each, no solve; prints their JSON (for profiling runs)")
     ap.add_argument("--uv", choices=["both", "full", "nouv"], default="both",
-                    help="batched SVD: time the full kernels, the singular-values-only ones, or both")
+                    help="batched SVD: time only the default kernels (full), only the singular-values-only "
+                         "ones (nouv), or every variant (both)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -379,10 +380,13 @@ def main():
     F, NU = S.SVD2_RESCUE_FP64, S.SVD2_NO_UV
     fp32 = {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0,
             "RESCUE_FP64|SIGMA|NO_UV": F | S.SVD2_RESCUE_SIGMA | NU}
-    flagsets = {"d": {"": 0, "NO_UV": NU}, "z": {"": 0, "NO_UV": NU}, "s": fp32, "c": dict(fp32)}
-    if args.uv != "both":
+    SF = S.SVD2_SINE_FORM
+    flagsets = {"d": {"": 0, "NO_UV": NU, "SINE_FORM": SF}, "z": {"": 0, "NO_UV": NU, "SINE_FORM": SF},
+                "s": fp32, "c": dict(fp32)}
+    if args.uv != "both":  # one kernel per run (profiling): the default form, or singular values only
         keep_nouv = args.uv == "nouv"
-        flagsets = {v: {d: f for d, f in fs.items() if ("NO_UV" in d) == keep_nouv} for v, fs in flagsets.items()}
+        flagsets = {v: {d: f for d, f in fs.items() if ("NO_UV" in d) == keep_nouv and "SINE" not in d}
+                    for v, fs in flagsets.items()}
     results, inputs_z = {}, None
     # FP32 also at the precision form's own size (2^26: its inputs exceed the
     # 256 MB Infinity Cache, so they come from HBM on every launch)
@@ -400,6 +404,8 @@ def main():
                 key = v + tag
             elif nouv:
                 key = f"{v}{tag}_nouv"
+            elif desc == "SINE_FORM":
+                key = f"{v}{tag}_sine"
             else:
                 key = f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
             results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv)

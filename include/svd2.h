@@ -85,7 +85,17 @@ enum {
      NULL and are neither checked nor written.  smax, smin and s are bitwise
      those of the same call without the flag (they do not depend on the
      assembly), with every other flag including the rescues. */
-  SVD2_NO_UV = 32
+  SVD2_NO_UV = 32,
+  /* all four entry points: assemble U by the sine form of eq. (31), from
+     sin = cos * tan (section 7), instead of the tangent form of eq. (29) (the
+     default); V, sigma' and s are the same in both.  For the comparison of
+     section 8, whose pointwise routine assembles this way: with the products
+     cc = cos(a)cos(p), ss = sin(a)sin(p), cs = cos(a)sin(p), sc = sin(a)cos(p)
+     of the angles alpha (QR) and phi (triangular SVD), the elements of P_r^* U
+     are d_11 (cc - d^ ss), d_11 (cs + d^ sc), -d_22 (sc + d^ cs) and
+     d_22 (d^ cc - ss), each bracket one fma per part, each product by d_ii as
+     eq. (5).  Ignored with SVD2_NO_UV. */
+  SVD2_SINE_FORM = 64
 };
 
 /* Real FP64: a_ij in, u_ij, v_ij, smax, smin, s out (all length n). */
@@ -123,7 +133,8 @@ typedef struct {
   uint32_t *nrescued;
 } csvd2_args;
 
-/* Batched SVDs of n matrices (sections 2-7).  flags: SVD2_BACKSCALE_* [| SVD2_NO_UV].
+/* Batched SVDs of n matrices (sections 2-7).  flags: SVD2_BACKSCALE_* [| SVD2_NO_UV]
+   [| SVD2_SINE_FORM].
    Errors: SVD2_ERR_NULL/ALIGN/ALIAS/FLAGS before launch, SVD2_ERR_HIP if the
    launch fails. */
 svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream);
@@ -132,7 +143,8 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 /* FP32 form (the paper notes the method carries over to single precision,
    section 1; the tan 2phi clamp becomes sqrt(FLT_MAX), section 7).
    flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA]
-   [| SVD2_NO_UV].
+   [| SVD2_NO_UV] [| SVD2_SINE_FORM] (with the FP64 tail rescue the rescued lanes are
+   assembled in FP64 by the same form).
    ws / ws_bytes: device workspace, at least svd2_workspace_bytes(n, flags)
    bytes (may be NULL/0 when that is 0).  With RESCUE_QUEUE, n must be below
    2^32 (SVD2_ERR_SIZE otherwise).  Calls sharing one workspace must not

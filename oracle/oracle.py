@@ -120,9 +120,13 @@ def svd2(A: np.ndarray, dtype=np.float64, policy: str = "mirror", backscale: str
                 trains=outs, inputs=ins)
 
 
+SINE = 16  # ORACLE_SINE: U by the sine form of eq. (31)
+
+
 def run_trains(ins: list, cplx: bool, dtype, policy="mirror", backscale="none",
-               rescue=False, nthreads=0) -> tuple:
-    """Same as svd2 but on SoA trains directly; returns (outs, flagged)."""
+               rescue=False, nthreads=0, form="tangent") -> tuple:
+    """Same as svd2 but on SoA trains directly; returns (outs, flagged).
+    form: "tangent" (eq. (29)) or "sine" (eq. (31))."""
     dtype = np.dtype(dtype)
     n = ins[0].shape[0]
     nout = 19 if cplx else 11
@@ -130,12 +134,11 @@ def run_trains(ins: list, cplx: bool, dtype, policy="mirror", backscale="none",
     flagged = np.zeros(n, dtype=np.uint8)
     L = lib()
     pin, pout = _ptrs(ins), _ptrs(outs)
+    pol = POLICY[policy] | (SINE if form == "sine" else 0)
     if dtype == np.float64:
-        (L.oracle_zsvd2 if cplx else L.oracle_dsvd2)(n, pin, pout, POLICY[policy],
-                                                    BACKSCALE[backscale], nthreads)
+        (L.oracle_zsvd2 if cplx else L.oracle_dsvd2)(n, pin, pout, pol, BACKSCALE[backscale], nthreads)
     else:
-        (L.oracle_csvd2 if cplx else L.oracle_ssvd2)(n, pin, pout, POLICY[policy],
-                                                    BACKSCALE[backscale], int(rescue),
+        (L.oracle_csvd2 if cplx else L.oracle_ssvd2)(n, pin, pout, pol, BACKSCALE[backscale], int(rescue),
                                                     flagged.ctypes.data, nthreads)
     return outs, flagged
 

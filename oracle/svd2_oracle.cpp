@@ -34,13 +34,17 @@ namespace {
 template <class T> struct Lim;
 template <> struct Lim<double> {
   static constexpr int h = DBL_MAX_EXP - 3; /* 1021 */
+  static constexpr int pk = 128;            /* phase of a subnormal |z|: 2^pk z is normal */
   static double big() { return DBL_MAX; }
+  static double mn() { return DBL_MIN; }
   static double tm() { return DBL_TRUE_MIN; }
   static double f() { return 0x1.fffffffffffffp+511; }
 };
 template <> struct Lim<float> {
   static constexpr int h = FLT_MAX_EXP - 3; /* 125 */
+  static constexpr int pk = 64;
   static float big() { return FLT_MAX; }
+  static float mn() { return FLT_MIN; }
   static float tm() { return FLT_TRUE_MIN; }
   static float f() { return 0x1.fffffep+63f; }
 };
@@ -74,6 +78,7 @@ template <class T> T invsqrt_ref(T x) { return (T)(1 / sqrtq((__float128)x)); }
 
 template <class T> struct Prim {
   int policy;
+  bool sine = false; /* assemble U by eq. (31) instead of eq. (29) */
   T hyp(T a, T b) const { return policy == ORACLE_REF ? hypot_ref(a, b) : hypot_mirror(a, b); }
   T isq(T x) const { return policy == ORACLE_REF ? invsqrt_ref(x) : invsqrt_mirror(x); }
 };
@@ -103,9 +108,20 @@ template <class T> Cx<T> cmul(Cx<T> a, Cx<T> b) {
 template <class T> Cx<T> cmulc(Cx<T> a, Cx<T> b) {
   return {fmaT(a.re, b.re, a.im * b.im), fmaT(a.re, b.im, -(a.im * b.re))};
 }
-/* eq. (1): e^{i arg z} from z and |z|, without complex operations:
- * cos = copysign(min(|Re z|/|z|, 1), Re z), sin = Im z / max(|z|, TRUE_MIN). */
-template <class T> Cx<T> phase(Cx<T> z, T absz) {
+
+
+/* eq. (1): e^{i arg z} from z and |z| = P.hyp(Re z, Im z), without complex
+ * operations: cos = copysign(min(|Re z|/|z|, 1), Re z), sin = Im z /
+ * max(|z|, TRUE_MIN).  Reading: below the normal range the rounding error of
+ * |z| is no longer relative (z = (-4, 1) 2^-1074 gives |z| = 4 2^-1074 and the
+ * "phase" (-1, 1/4), whose modulus is not one, so U would not be unitary);
+ * there eq. (1) is applied to 2^k z instead, an exact scaling that leaves the
+ * phase unchanged.  Whenever |z| is normal the result is the literal one. */
+template <class T> Cx<T> phase(const Prim<T> &P, Cx<T> z, T absz) {
+  if (absz < Lim<T>::mn()) {
+    z = {std::ldexp(z.re, Lim<T>::pk), std::ldexp(z.im, Lim<T>::pk)};
+    absz = P.hyp(z.re, z.im);
+  }
   return {std::copysign(rmin(std::fabs(z.re) / absz, T(1)), z.re),
           z.im / rmax(absz, Lim<T>::tm())};
 }
@@ -154,6 +170,38 @@ template <class T> void triangular_svd(const Prim<T> &P, Mid<T> &m, T &smax, T &
   smin = (k * m.sec2phi) * m.r22;
 }
 
+/* ---------------------------------------------------------------------------
+ * The sine form of the assembly, eq. (31), for the comparison of section 8:
+ * sin(alpha) = cos(alpha) tan(alpha) and sin(phi) = cos(phi) tan(phi) (the
+ * relation section 7 gives), the four products cc = cos a cos p, ss = sin a
+ * sin p, cs = cos a sin p, sc = sin a cos p, one fma per element with the
+ * phase d^ (reading: eq. (31) fixes no operation order), then d_11 or d_22.
+ * tan(alpha) = -mt.  V is the same in both forms (cos psi tan psi is sin psi).
+ * ------------------------------------------------------------------------- */
+template <class W> struct SineW { W cc, ss, cs, sc; };
+template <class W> SineW<W> sine_products(W ca, W mt, W cphi, W tphi) {
+  W sa = ca * -mt, sphi = cphi * tphi;
+  return {ca * cphi, sa * sphi, ca * sphi, sa * cphi};
+}
+/* complex: P_r^* U before the row permutation */
+template <class W>
+void sine_u_cplx(const SineW<W> &q, Cx<W> dh, Cx<W> d1, Cx<W> d2, Cx<W> (&U)[2][2]) {
+  Cx<W> w11 = {fmaT(-dh.re, q.ss, q.cc), -(dh.im * q.ss)};
+  Cx<W> w12 = {fmaT(dh.re, q.sc, q.cs), dh.im * q.sc};
+  Cx<W> w21 = {fmaT(dh.re, q.cs, q.sc), dh.im * q.cs};
+  Cx<W> w22 = {fmaT(dh.re, q.cc, -q.ss), dh.im * q.cc};
+  Cx<W> p21 = cmul(d2, w21);
+  U[0][0] = cmul(d1, w11); U[0][1] = cmul(d1, w12);
+  U[1][0] = {-p21.re, -p21.im}; U[1][1] = cmul(d2, w22);
+}
+/* real: the phases are signs (neg1, neg2: d_11, d_22 = -1; dh = +-1) */
+template <class W> void sine_u_real(const SineW<W> &q, W dh, bool neg1, bool neg2, W (&U)[2][2]) {
+  W w11 = fmaT(-dh, q.ss, q.cc), w12 = fmaT(dh, q.sc, q.cs), w21 = fmaT(dh, q.cs, q.sc),
+    w22 = fmaT(dh, q.cc, -q.ss);
+  U[0][0] = neg1 ? -w11 : w11; U[0][1] = neg1 ? -w12 : w12;
+  U[1][0] = -(neg2 ? -w21 : w21); U[1][1] = neg2 ? -w22 : w22;
+}
+
 /* Section 2.1, eq. (2), Fig. 3: s and A^ = 2^s A over ncomp components. */
 template <class T> T scaling(const T *a, int ncomp, T *ah) {
   T s = Lim<T>::big();
@@ -190,8 +238,8 @@ template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
     for (int j = 0; j < 2; ++j) { std::swap(A[0][j], A[1][j]); std::swap(mag[0][j], mag[1][j]); }
   }
   /* D*, eq. (4), Fig. 7: a'''_i1 = |a''_i1|, a'''_i2 = conj(d_i) a''_i2 */
-  m.d1 = phase(A[0][0], mag[0][0]);
-  m.d2 = phase(A[1][0], mag[1][0]);
+  m.d1 = phase(P, A[0][0], mag[0][0]);
+  m.d2 = phase(P, A[1][0], mag[1][0]);
   T a311 = mag[0][0], a321 = mag[1][0];
   Cx<T> a312 = cmulc(m.d1, A[0][1]);
   Cx<T> a322 = cmulc(m.d2, A[1][1]);
@@ -203,12 +251,12 @@ template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
   Cx<T> r22pp = {m.ca * fmaT(-m.mt, a312.re, a322.re), m.ca * fmaT(-m.mt, a312.im, a322.im)};
   /* D~, eq. (8), Fig. 9: r12 = |r'_12|, r'_22 = r''_22 conj(e^{i arg r'_12}) */
   m.r12 = P.hyp(r12p.re, r12p.im);
-  m.e12 = phase(r12p, m.r12);
+  m.e12 = phase(P, r12p, m.r12);
   Cx<T> r22p = {fmaT(r22pp.re, m.e12.re, r22pp.im * m.e12.im),
                 fmaT(r22pp.im, m.e12.re, -(r22pp.re * m.e12.im))};
   /* D^, eq. (9), Fig. 9: r22 = |r'_22| */
   m.r22 = P.hyp(r22p.re, r22p.im);
-  m.dh = phase(r22p, m.r22);
+  m.dh = phase(P, r22p, m.r22);
   /* triangular SVD, eqs. (13)-(17) */
   triangular_svd(P, m, o.smax, o.smin);
   /* assembly of U and V, eq. (29) and its expansion (section 2.3).
@@ -221,6 +269,7 @@ template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
   Cx<T> p11 = cmul(m.d1, w11), p21 = cmul(m.d2, w21), p12 = cmul(m.d1, w12), p22 = cmul(m.d2, w22);
   Cx<T> U[2][2] = {{{C * p11.re, C * p11.im}, {C * p12.re, C * p12.im}},
                    {{-(C * p21.re), -(C * p21.im)}, {C * p22.re, C * p22.im}}};
+  if (P.sine) sine_u_cplx(sine_products(m.ca, m.mt, m.cphi, m.tphi), m.dh, m.d1, m.d2, U);
   if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); } /* P_r */
   /* V = cos(psi) P_c [[1, tan psi], [-d~ tan psi, d~]], d~ = conj(e12) */
   T ct = m.cpsi * m.tpsi;
@@ -281,6 +330,7 @@ template <class T> void dsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
     w22 = fmaT(m.mt, m.tphi, dh);
   T U[2][2] = {{C * (m.neg1 ? -w11 : w11), C * (m.neg1 ? -w12 : w12)},
                {-(C * (m.neg2 ? -w21 : w21)), C * (m.neg2 ? -w22 : w22)}};
+  if (P.sine) sine_u_real(sine_products(m.ca, m.mt, m.cphi, m.tphi), dh, m.neg1, m.neg2, U);
   if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); }
   T ct = m.cpsi * m.tpsi;
   T V[2][2] = {{m.cpsi, ct}, {m.negt ? ct : -ct, m.negt ? -m.cpsi : m.cpsi}};
@@ -365,7 +415,7 @@ template <bool CPLX> void rescue_sigma(const Mid<float> &m, Res<float> &o) {
   o.smin = (float)(ad / (double)o.smax);
 }
 
-template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
+template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o, bool sine = false) {
   Prim<double> P{ORACLE_MIRROR};
   const double one = 1.0;
   Cx<double> det = det_fp64<CPLX>(m);
@@ -380,7 +430,7 @@ template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
     r22p_re = sgn * (q.re / w.r11);
     r22p_im = sgn * (q.im / w.r11);
     w.r22 = P.hyp(r22p_re, r22p_im);
-    w.dh = phase(Cx<double>{r22p_re, r22p_im}, w.r22);
+    w.dh = phase(P, Cx<double>{r22p_re, r22p_im}, w.r22);
   } else {
     if (m.neg1 != m.neg2) sgn = -sgn;
     if (m.negt) sgn = -sgn;
@@ -403,6 +453,7 @@ template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
     Cx<double> p11 = cmul(d1, w11), p21 = cmul(d2, w21), p12 = cmul(d1, w12), p22 = cmul(d2, w22);
     U[0][0] = {C * p11.re, C * p11.im}; U[0][1] = {C * p12.re, C * p12.im};
     U[1][0] = {-(C * p21.re), -(C * p21.im)}; U[1][1] = {C * p22.re, C * p22.im};
+    if (sine) sine_u_cplx(sine_products(w.ca, w.mt, w.cphi, w.tphi), w.dh, d1, d2, U);
     V[0][0] = {w.cpsi, 0.0}; V[0][1] = {ct, 0.0};
     V[1][0] = {-(ct * e.re), ct * e.im}; V[1][1] = {w.cpsi * e.re, -(w.cpsi * e.im)};
   } else {
@@ -411,6 +462,11 @@ template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o) {
            w22 = fmaT(w.mt, w.tphi, dh);
     U[0][0] = {C * (m.neg1 ? -w11 : w11), 0.0}; U[0][1] = {C * (m.neg1 ? -w12 : w12), 0.0};
     U[1][0] = {-(C * (m.neg2 ? -w21 : w21)), 0.0}; U[1][1] = {C * (m.neg2 ? -w22 : w22), 0.0};
+    if (sine) {
+      double Ur[2][2];
+      sine_u_real(sine_products(w.ca, w.mt, w.cphi, w.tphi), dh, m.neg1, m.neg2, Ur);
+      for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) U[i][j] = {Ur[i][j], 0.0};
+    }
     V[0][0] = {w.cpsi, 0.0}; V[0][1] = {ct, 0.0};
     V[1][0] = {m.negt ? ct : -ct, 0.0}; V[1][1] = {m.negt ? -w.cpsi : w.cpsi, 0.0};
   }
@@ -465,7 +521,7 @@ void store(const Res<T> &o, T *const *out, size_t k) {
 template <class T, bool CPLX>
 void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int rescue,
            uint8_t *flagged, int nthreads) {
-  Prim<T> P{policy};
+  Prim<T> P{policy & ~ORACLE_SINE, (policy & ORACLE_SINE) != 0};
   if (nthreads <= 0) nthreads = omp_get_max_threads();
 #pragma omp parallel for schedule(static) num_threads(nthreads)
   for (long long kk = 0; kk < (long long)n; ++kk) {
@@ -477,7 +533,7 @@ void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int 
     if constexpr (std::is_same<T, float>::value) {
       if (rescue && near_degenerate(o.smax, o.smin)) {
         if (rescue == 2) rescue_sigma<CPLX>(m, o);
-        else rescue_fp64<CPLX>(m, o);
+        else rescue_fp64<CPLX>(m, o, P.sine);
         fl = true;
       }
     }

@@ -36,6 +36,13 @@ enum { ORACLE_REF = 0,    /* hypot and 1/sqrt correctly rounded via __float128 *
        ORACLE_MIRROR = 1  /* hypot = the division-based fallback of section 5,
                              invsqrt = 1/sqrt(x): two correctly rounded ops    */ };
 
+/* OR-ed into the policy argument of the batched entry points: assemble U by
+ * the sine form of eq. (31) (sin = cos * tan, section 7) instead of the
+ * tangent form of eq. (29); V is the same in both.  Pinned: the two forms give
+ * U within a few eps of each other (two formulas of one matrix) and the sine
+ * form's residual and orthogonality within 16 eps in binary128. */
+enum { ORACLE_SINE = 16 };
+
 /* backscale mode of eq. (28) */
 enum { ORACLE_BS_NONE = 0, /* write sigma' and s (the paper's default)          */
        ORACLE_BS_SAFE = 1, /* per lane, only if 2^-s sigma' is exact and finite */

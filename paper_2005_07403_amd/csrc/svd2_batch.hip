@@ -94,7 +94,7 @@ __device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
 // and V are neither stored nor, since nothing uses them, computed (the
 // assembly of eq. (29) and its FP64 counterpart in the rescue drop out).
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int PT, int RESCUE, bool UV>
+template <class T, bool CPLX, int PT, int RESCUE, bool UV, bool SINE>
 __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                    int bs, uint32_t *nresc, uint32_t *queue,
                                                    uint32_t *qcount) {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
 #pragma unroll
   for (int j = 0; j < PT; ++j) {
     fl[j] = false;
-    if (j < cnt) fl[j] = one_matrix<T, CPLX, RESCUE>(x[j], y[j], bs);
+    if (j < cnt) fl[j] = one_matrix<T, CPLX, RESCUE, SINE>(x[j], y[j], bs);
   }
   if (cnt > 0) store_lanes<T, NOUT, PT, LO>(a.out, k, cnt, y);
   if constexpr (RESCUE != 0) {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
 
 // Second pass for RESCUE == 2: redo each queued lane with the FP64 tail.  The
 // grid is fixed; every lane loops until the device-side count is exhausted.
-template <class T, bool CPLX, int TAIL, bool UV>
+template <class T, bool CPLX, int TAIL, bool UV, bool SINE>
 __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                           int bs, const uint32_t *queue,
                                                           const uint32_t *qcount) {
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void svd2_rescue_kernel(KArgs<T, CPLX ? 8 : 4,
     T x[NIN], y[NOUT];
 #pragma unroll
     for (int e = 0; e < NIN; ++e) x[e] = a.in[e][k];
-    one_matrix<T, CPLX, TAIL>(x, y, bs);
+    one_matrix<T, CPLX, TAIL, SINE>(x, y, bs);
 #pragma unroll
     for (int e = LO; e < NOUT; ++e) st_nt(a.out[e] + k, y[e]);
   }
@@ -220,7 +220,7 @@ svd2_status hip_status(hipError_t e) {
   return SVD2_ERR_HIP;
 }
 
-template <class T, bool CPLX, int RESCUE, bool UV>
+template <class T, bool CPLX, int RESCUE, bool UV, bool SINE>
 svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
                    uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
   constexpr int kind = kind_of<T, CPLX>() + (UV ? 0 : 4);
@@ -230,19 +230,31 @@ svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, in
   size_t grid = (lanes + block - 1) / block;
   if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
   if (pt == 2)
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE, UV>), dim3((unsigned)grid), dim3(block), 0, st,
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
                        n, a, bs, nresc, queue, qcount);
   else
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE, UV>), dim3((unsigned)grid), dim3(block), 0, st,
+    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
                        n, a, bs, nresc, queue, qcount);
   return hip_status(hipGetLastError());
 }
 
+// uv: U and V are wanted (else SVD2_NO_UV); sine: assembled by eq. (31)
 template <class T, bool CPLX, int RESCUE>
-svd2_status launch_uv(bool uv, size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
+svd2_status launch_uv(bool uv, bool sine, size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
                       uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
-  return uv ? launch<T, CPLX, RESCUE, true>(n, a, bs, nresc, queue, qcount, st)
-            : launch<T, CPLX, RESCUE, false>(n, a, bs, nresc, queue, qcount, st);
+  if (!uv) return launch<T, CPLX, RESCUE, false, false>(n, a, bs, nresc, queue, qcount, st);
+  return sine ? launch<T, CPLX, RESCUE, true, true>(n, a, bs, nresc, queue, qcount, st)
+              : launch<T, CPLX, RESCUE, true, false>(n, a, bs, nresc, queue, qcount, st);
+}
+
+// the second pass of the queued FP32 rescue
+template <class T, bool CPLX, int TAIL>
+void launch_rescue(bool uv, bool sine, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
+                   const uint32_t *q, const uint32_t *qcount, hipStream_t st) {
+  const dim3 g(1024), b(256);
+  if (!uv) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, TAIL, false, false>), g, b, 0, st, a, bs, q, qcount);
+  else if (sine) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, TAIL, true, true>), g, b, 0, st, a, bs, q, qcount);
+  else hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, TAIL, true, false>), g, b, 0, st, a, bs, q, qcount);
 }
 
 bool bad_bs_flags(unsigned flags) { return (flags & 3u) == 3u; }
@@ -252,11 +264,11 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
                      uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
   int bs = (int)(flags & 3u);
   bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE,
-       sigma = flags & SVD2_RESCUE_SIGMA, uv = !(flags & SVD2_NO_UV);
-  if (!resc) return launch_uv<T, CPLX, 0>(uv, n, a, bs, nullptr, nullptr, nullptr, st);
+       sigma = flags & SVD2_RESCUE_SIGMA, uv = !(flags & SVD2_NO_UV), sine = flags & SVD2_SINE_FORM;
+  if (!resc) return launch_uv<T, CPLX, 0>(uv, sine, n, a, bs, nullptr, nullptr, nullptr, st);
   if (!queue) {
-    if (sigma) return launch_uv<T, CPLX, 3>(uv, n, a, bs, nresc, nullptr, nullptr, st);
-    return launch_uv<T, CPLX, 1>(uv, n, a, bs, nresc, nullptr, nullptr, st);
+    if (sigma) return launch_uv<T, CPLX, 3>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
+    return launch_uv<T, CPLX, 1>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
   }
   if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
   if (!ws) return SVD2_ERR_NULL;
@@ -267,13 +279,10 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, qcount);
   svd2_status s0 = hip_status(hipGetLastError());
   if (s0 != SVD2_OK) return s0;
-  svd2_status s1 = launch_uv<T, CPLX, 2>(uv, n, a, bs, nresc, q, qcount, st);
+  svd2_status s1 = launch_uv<T, CPLX, 2>(uv, sine, n, a, bs, nresc, q, qcount, st);
   if (s1 != SVD2_OK) return s1;
-  const dim3 g(1024), b(256);
-  if (sigma && uv) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3, true>), g, b, 0, st, a, bs, q, qcount);
-  else if (sigma) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 3, false>), g, b, 0, st, a, bs, q, qcount);
-  else if (uv) hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1, true>), g, b, 0, st, a, bs, q, qcount);
-  else hipLaunchKernelGGL((svd2_rescue_kernel<T, CPLX, 1, false>), g, b, 0, st, a, bs, q, qcount);
+  if (sigma) launch_rescue<T, CPLX, 3>(uv, sine, a, bs, q, qcount, st);
+  else launch_rescue<T, CPLX, 1>(uv, sine, a, bs, q, qcount, st);
   return hip_status(hipGetLastError());
 }
 
@@ -337,19 +346,20 @@ extern "C" {
 
 svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream) {
   if (!p) return SVD2_ERR_NULL;
-  if (flags & ~(3u | SVD2_NO_UV) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  if (flags & ~(3u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
   KArgs<double, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
                             {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
                              p->smax, p->smin, p->s}};
   const bool uv = !(flags & SVD2_NO_UV);
   svd2_status st = check_ptrs<double>(n, a.in, 4, a.out + (uv ? 0 : 8), uv ? 11 : 3);
   if (st != SVD2_OK || n == 0) return st;
-  return launch_uv<double, false, 0>(uv, n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+  return launch_uv<double, false, 0>(uv, (flags & SVD2_SINE_FORM) != 0, n, a, (int)(flags & 3u), nullptr, nullptr,
+                                     nullptr, stream);
 }
 
 svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream_t stream) {
   if (!p) return SVD2_ERR_NULL;
-  if (flags & ~(3u | SVD2_NO_UV) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  if (flags & ~(3u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
   KArgs<double, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
                             {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
                              p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
@@ -357,11 +367,12 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
   const bool uv = !(flags & SVD2_NO_UV);
   svd2_status st = check_ptrs<double>(n, a.in, 8, a.out + (uv ? 0 : 16), uv ? 19 : 3);
   if (st != SVD2_OK || n == 0) return st;
-  return launch_uv<double, true, 0>(uv, n, a, (int)(flags & 3u), nullptr, nullptr, nullptr, stream);
+  return launch_uv<double, true, 0>(uv, (flags & SVD2_SINE_FORM) != 0, n, a, (int)(flags & 3u), nullptr, nullptr,
+                                    nullptr, stream);
 }
 
 static bool bad_fp32_flags(unsigned flags) {
-  if (flags & ~(31u | SVD2_NO_UV) || bad_bs_flags(flags)) return true;
+  if (flags & ~(31u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return true;
   if ((flags & (SVD2_RESCUE_QUEUE | SVD2_RESCUE_SIGMA)) && !(flags & SVD2_RESCUE_FP64)) return true;
   return false;
 }

@@ -28,12 +28,16 @@ template <> struct Fmt<double> {
   static constexpr int h = 1021;                        // DBL_MAX_EXP - 3
   static constexpr double big = 0x1.fffffffffffffp+1023; // DBL_MAX
   static constexpr double tm = 0x1p-1074;                // DBL_TRUE_MIN
+  static constexpr double mn = 0x1p-1022;                // DBL_MIN
+  static constexpr int pk = 128;                         // 2^pk |z| is normal for a subnormal |z|
   static constexpr double f = 0x1.fffffffffffffp+511;    // sqrt(DBL_MAX), Fig. 10
 };
 template <> struct Fmt<float> {
   static constexpr int h = 125;                          // FLT_MAX_EXP - 3
   static constexpr float big = 0x1.fffffep+127f;         // FLT_MAX
   static constexpr float tm = 0x1p-149f;                 // FLT_TRUE_MIN
+  static constexpr float mn = 0x1p-126f;                 // FLT_MIN
+  static constexpr int pk = 64;
   static constexpr float f = 0x1.fffffep+63f;            // sqrt(FLT_MAX) rounded down
 };
 
@@ -80,8 +84,16 @@ template <class T> __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
 template <class T> __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
   return {vfma(a.re, b.re, a.im * b.im), vfma(a.re, b.im, -(a.im * b.re))};
 }
-// eq. (1): e^{i arg z} from z and |z|
+// eq. (1): e^{i arg z} from z and |z| = hyp(Re z, Im z).  Below the normal
+// range the rounding error of |z| is no longer relative (z = (-4, 1) 2^-1074
+// gives |z| = 4 2^-1074 and a "phase" of modulus > 1, so U would not be
+// unitary); there eq. (1) is applied to 2^pk z, an exact scaling that leaves
+// the phase unchanged.  Whenever |z| is normal the result is the literal one.
 template <class T> __device__ __forceinline__ Cx<T> phase(Cx<T> z, T az) {
+  if (az < Fmt<T>::mn) {
+    z = Cx<T>{vldexp(z.re, Fmt<T>::pk), vldexp(z.im, Fmt<T>::pk)};
+    az = hyp(z.re, z.im);
+  }
   return {vcopysign(vmin(vabs(z.re) / az, T(1)), z.re), z.im / vmax(az, Fmt<T>::tm)};
 }
 
@@ -136,17 +148,41 @@ template <class T> struct RealRes {
   bool c, r, neg1, neg2, negt;
 };
 
-// eq. (29) expansion and the final row permutations, real case.
-template <class T, class W>
+// The sine form of the assembly, eq. (31) (SINE = true, flag SVD2_SINE_FORM):
+// sin(alpha) = cos(alpha) tan(alpha), sin(phi) = cos(phi) tan(phi) (section
+// 7), the products cc = cos a cos p, ss = sin a sin p, cs = cos a sin p,
+// sc = sin a cos p, one fma per element with the phase d^, then d_11 or d_22.
+// tan(alpha) = -mt.  V is the same in both forms (cos psi tan psi = sin psi).
+template <class W> struct SineW {
+  W cc, ss, cs, sc;
+};
+template <class W> __device__ __forceinline__ SineW<W> sine_products(W ca, W mt, const Tri<W> &t) {
+  const W sa = ca * -mt, sphi = t.cphi * t.tphi;
+  return SineW<W>{ca * t.cphi, sa * sphi, ca * sphi, sa * t.cphi};
+}
+
+// eq. (29) expansion (or eq. (31)) and the final row permutations, real case.
+template <class T, class W, bool SINE = false>
 __device__ __forceinline__ void real_assemble(const Tri<W> &t, W mt, W ca, bool negh, bool neg1,
                                               bool neg2, bool negt, bool c, bool r, T *u, T *v) {
   const W one = W(1);
   W C = ca * t.cphi, ta = -mt, tt = mt * t.tphi;
   W dh = negh ? -one : one;
-  W w11 = vfma(dh, tt, one), w21 = vfma(dh, t.tphi, ta), w12 = vfma(dh, ta, t.tphi),
-    w22 = vfma(mt, t.tphi, dh);
-  W U11 = C * flip(neg1, w11), U12 = C * flip(neg1, w12);
-  W U21 = -(C * flip(neg2, w21)), U22 = C * flip(neg2, w22);
+  W U11, U12, U21, U22;
+  if constexpr (SINE) {
+    const SineW<W> q = sine_products(ca, mt, t);
+    U11 = flip(neg1, vfma(-dh, q.ss, q.cc));
+    U12 = flip(neg1, vfma(dh, q.sc, q.cs));
+    U21 = -flip(neg2, vfma(dh, q.cs, q.sc));
+    U22 = flip(neg2, vfma(dh, q.cc, -q.ss));
+  } else {
+    W w11 = vfma(dh, tt, one), w21 = vfma(dh, t.tphi, ta), w12 = vfma(dh, ta, t.tphi),
+      w22 = vfma(mt, t.tphi, dh);
+    U11 = C * flip(neg1, w11);
+    U12 = C * flip(neg1, w12);
+    U21 = -(C * flip(neg2, w21));
+    U22 = C * flip(neg2, w22);
+  }
   W ct = t.cpsi * t.tpsi;
   W V11 = t.cpsi, V12 = ct, V21 = negt ? ct : -ct, V22 = flip(negt, t.cpsi);
   // P_r on the rows of U, P_c on the rows of V; element order 11, 21, 12, 22
@@ -156,7 +192,7 @@ __device__ __forceinline__ void real_assemble(const Tri<W> &t, W mt, W ca, bool 
   v[2] = (T)(c ? V22 : V12); v[3] = (T)(c ? V12 : V22);
 }
 
-template <class T>
+template <class T, bool SINE = false>
 __device__ __forceinline__ void real_lane(T a11, T a21, T a12, T a22, RealRes<T> &o) {
   const T one = T(1);
   // scaling (eq. (2), Fig. 3)
@@ -190,7 +226,7 @@ __device__ __forceinline__ void real_lane(T a11, T a21, T a12, T a22, RealRes<T>
   T r22 = vabs(r22p);
   Tri<T> t = tri_svd(r11, r12, r22);
   T u[4], v[4];
-  real_assemble<T, T>(t, mt, ca, negh, neg1, neg2, negt, c, r, u, v);
+  real_assemble<T, T, SINE>(t, mt, ca, negh, neg1, neg2, negt, c, r, u, v);
   o.u11 = u[0]; o.u21 = u[1]; o.u12 = u[2]; o.u22 = u[3];
   o.v11 = v[0]; o.v21 = v[1]; o.v12 = v[2]; o.v22 = v[3];
   o.smax = t.smax; o.smin = t.smin;
@@ -211,19 +247,35 @@ template <class T> struct CplxRes {
   bool c, r;
 };
 
-template <class T, class W>
+template <class T, class W, bool SINE = false>
 __device__ __forceinline__ void cplx_assemble(const Tri<W> &t, W mt, W ca, Cx<W> dh, Cx<W> d1,
                                               Cx<W> d2, Cx<W> e12, bool c, bool r, Cx<T> *u,
                                               Cx<T> *v) {
   const W one = W(1);
   W C = ca * t.cphi, ta = -mt, tt = mt * t.tphi;
-  Cx<W> w11 = {vfma(dh.re, tt, one), dh.im * tt};
-  Cx<W> w21 = {vfma(dh.re, t.tphi, ta), dh.im * t.tphi};
-  Cx<W> w12 = {vfma(dh.re, ta, t.tphi), dh.im * ta};
-  Cx<W> w22 = {vfma(mt, t.tphi, dh.re), dh.im};
-  Cx<W> p11 = cmul(d1, w11), p21 = cmul(d2, w21), p12 = cmul(d1, w12), p22 = cmul(d2, w22);
-  Cx<W> U11 = {C * p11.re, C * p11.im}, U12 = {C * p12.re, C * p12.im};
-  Cx<W> U21 = {-(C * p21.re), -(C * p21.im)}, U22 = {C * p22.re, C * p22.im};
+  Cx<W> U11, U12, U21, U22;
+  if constexpr (SINE) {
+    const SineW<W> q = sine_products(ca, mt, t);
+    const Cx<W> s11 = {vfma(-dh.re, q.ss, q.cc), -(dh.im * q.ss)};
+    const Cx<W> s12 = {vfma(dh.re, q.sc, q.cs), dh.im * q.sc};
+    const Cx<W> s21 = {vfma(dh.re, q.cs, q.sc), dh.im * q.cs};
+    const Cx<W> s22 = {vfma(dh.re, q.cc, -q.ss), dh.im * q.cc};
+    const Cx<W> p21 = cmul(d2, s21);
+    U11 = cmul(d1, s11);
+    U12 = cmul(d1, s12);
+    U21 = Cx<W>{-p21.re, -p21.im};
+    U22 = cmul(d2, s22);
+  } else {
+    Cx<W> w11 = {vfma(dh.re, tt, one), dh.im * tt};
+    Cx<W> w21 = {vfma(dh.re, t.tphi, ta), dh.im * t.tphi};
+    Cx<W> w12 = {vfma(dh.re, ta, t.tphi), dh.im * ta};
+    Cx<W> w22 = {vfma(mt, t.tphi, dh.re), dh.im};
+    Cx<W> p11 = cmul(d1, w11), p21 = cmul(d2, w21), p12 = cmul(d1, w12), p22 = cmul(d2, w22);
+    U11 = Cx<W>{C * p11.re, C * p11.im};
+    U12 = Cx<W>{C * p12.re, C * p12.im};
+    U21 = Cx<W>{-(C * p21.re), -(C * p21.im)};
+    U22 = Cx<W>{C * p22.re, C * p22.im};
+  }
   W ct = t.cpsi * t.tpsi;
   Cx<W> V11 = {t.cpsi, W(0)}, V12 = {ct, W(0)};
   Cx<W> V21 = {-(ct * e12.re), ct * e12.im}, V22 = {t.cpsi * e12.re, -(t.cpsi * e12.im)};
@@ -236,7 +288,7 @@ __device__ __forceinline__ void cplx_assemble(const Tri<W> &t, W mt, W ca, Cx<W>
 }
 
 // a[8] = a11r, a11i, a21r, a21i, a12r, a12i, a22r, a22i
-template <class T>
+template <class T, bool SINE = false>
 __device__ __forceinline__ void cplx_lane(const T *a, CplxRes<T> &o) {
   const T one = T(1);
   int s = scale_exp(a[0]);
@@ -279,7 +331,7 @@ __device__ __forceinline__ void cplx_lane(const T *a, CplxRes<T> &o) {
   T r22 = hyp(r22p.re, r22p.im);
   Cx<T> dh = phase(r22p, r22);
   Tri<T> t = tri_svd(r11, r12, r22);
-  cplx_assemble<T, T>(t, mt, ca, dh, d1, d2, e12, c, r, o.u, o.v);
+  cplx_assemble<T, T, SINE>(t, mt, ca, dh, d1, d2, e12, c, r, o.u, o.v);
   o.smax = t.smax; o.smin = t.smin;
   o.d1 = d1; o.d2 = d2; o.e12 = e12;
   o.r11 = r11; o.r12 = r12; o.mt = mt; o.ca = ca;
@@ -330,7 +382,7 @@ __device__ __forceinline__ void cplx_rescue_sigma(CplxRes<float> &o) {
   o.smin = (float)(hyp(det.re, det.im) / (double)o.smax);
 }
 
-__device__ __forceinline__ void real_rescue(RealRes<float> &o) {
+template <bool SINE = false> __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
   double det = (double)o.ah11 * (double)o.ah22 - (double)o.ah12 * (double)o.ah21;
   bool neg = (o.c != o.r) != ((o.neg1 != o.neg2) != o.negt);
   double r11 = o.r11;
@@ -339,15 +391,15 @@ __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
   double r22 = vabs(r22p);
   Tri<double> t = tri_svd(r11, (double)o.r12, r22);
   float u[4], v[4];
-  real_assemble<float, double>(t, (double)o.mt, (double)o.ca, negh, o.neg1, o.neg2, o.negt, o.c,
-                               o.r, u, v);
+  real_assemble<float, double, SINE>(t, (double)o.mt, (double)o.ca, negh, o.neg1, o.neg2, o.negt, o.c,
+                                     o.r, u, v);
   o.u11 = u[0]; o.u21 = u[1]; o.u12 = u[2]; o.u22 = u[3];
   o.v11 = v[0]; o.v21 = v[1]; o.v12 = v[2]; o.v22 = v[3];
   o.smax = (float)t.smax;
   o.smin = (float)t.smin;
 }
 
-__device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
+template <bool SINE = false> __device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
   Cx<double> det = cplx_det(o);
   double sgn = (o.c != o.r) ? -1.0 : 1.0;
   Cx<double> d1 = {o.d1.re, o.d1.im}, d2 = {o.d2.re, o.d2.im}, e = {o.e12.re, o.e12.im};
@@ -358,7 +410,7 @@ __device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
   double r22 = hyp(r22p.re, r22p.im);
   Cx<double> dh = phase(r22p, r22);
   Tri<double> t = tri_svd(r11, (double)o.r12, r22);
-  cplx_assemble<float, double>(t, (double)o.mt, (double)o.ca, dh, d1, d2, e, o.c, o.r, o.u, o.v);
+  cplx_assemble<float, double, SINE>(t, (double)o.mt, (double)o.ca, dh, d1, d2, e, o.c, o.r, o.u, o.v);
   o.smax = (float)t.smax;
   o.smin = (float)t.smin;
 }
@@ -387,16 +439,16 @@ template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &sm
 // RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only,
 // 3 in place (FP64 sigma_min quotient only)
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int RESCUE>
+template <class T, bool CPLX, int RESCUE, bool SINE = false>
 __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
   bool flagged = false;
   if constexpr (!CPLX) {
     RealRes<T> o;
-    real_lane<T>(x[0], x[1], x[2], x[3], o);
+    real_lane<T, SINE>(x[0], x[1], x[2], x[3], o);
     if constexpr (RESCUE != 0) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {
-        if (flagged) real_rescue(o);
+        if (flagged) real_rescue<SINE>(o);
       } else if constexpr (RESCUE == 3) {
         if (flagged) real_rescue_sigma(o);
       }
@@ -408,11 +460,11 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
     y[8] = smax; y[9] = smin; y[10] = sv;
   } else {
     CplxRes<T> o;
-    cplx_lane<T>(x, o);
+    cplx_lane<T, SINE>(x, o);
     if constexpr (RESCUE != 0) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {
-        if (flagged) cplx_rescue(o);
+        if (flagged) cplx_rescue<SINE>(o);
       } else if constexpr (RESCUE == 3) {
         if (flagged) cplx_rescue_sigma(o);
       }

@@ -68,6 +68,9 @@ def test_argument_errors(fn, nin, nout):
     # adjacent but disjoint ranges are fine (n = 0 avoids any launch)
     ok = [FAKE + i * 80 for i in range(nin + nout)]
     assert _call(fn, 0, ok[:nin], ok[nin:]) == 0
+    # the sine form of the assembly and singular values only are valid flags
+    assert _call(fn, 0, ins, outs, flags=S.SVD2_SINE_FORM) == 0
+    assert _call(fn, 0, ins, outs, flags=S.SVD2_SINE_FORM | S.SVD2_NO_UV) == 0
     # contradictory backscale flags
     assert _call(fn, 10, ins, outs, flags=3) == 4
     # unknown flag bits

@@ -364,3 +364,32 @@ def test_singular_values_only(kind, mode, pt):
         assert same_bits(g, ora[k + j]).all(), (kind, mode, j)
     if dtype == np.float32:
         assert int(c1.item()) == int(c2.item()) == (int(flagged.sum()) if rescue else 0)
+
+
+# ---------------------------------------------------------------------------
+# sine form of the assembly (SVD2_SINE_FORM, eq. (31))
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pt", [1, 2])
+@pytest.mark.parametrize("kind,mode", [("d", "none"), ("z", "none"), ("d", "safe"), ("z", "all")] +
+                         [(k, m) for k in "sc" for m in RESCUE_MODES])
+def test_sine_form_bitwise(kind, mode, pt):
+    """Every output of an SVD2_SINE_FORM call is bitwise the oracle's sine
+    form, in every backscale and rescue mode (the FP64 tail rescue assembles
+    in FP64 by the same form), both launch shapes."""
+    from paper_2005_07403_amd import svd2 as S
+    _set_launch(256, pt)
+    cplx, dtype = kind in "zc", np.float64 if kind in "dz" else np.float32
+    A = scaled_law((1 << 16) + 3, SEED_BASE + 65, cplx, dtype=dtype)
+    tr = to_trains(A, dtype)
+    if dtype == np.float64:
+        flags = {"none": 0, "safe": S.SVD2_BACKSCALE_SAFE, "all": S.SVD2_BACKSCALE_ALL}[mode]
+        rescue, backscale = False, mode
+        gpu = run_gpu(tr, flags=flags | S.SVD2_SINE_FORM)
+    else:
+        flags, rescue, backscale = _fp32_flags(mode), _oracle_rescue(mode), "none"
+        gpu, nres = run_gpu(tr, flags=flags | S.SVD2_SINE_FORM, nrescued=True)
+    ora, flagged = O.run_trains(tr, cplx, dtype, policy="mirror", backscale=backscale, rescue=rescue,
+                                form="sine")
+    for i, (g, o) in enumerate(zip(gpu, ora)):
+        assert same_bits(g, o).all(), (kind, mode, i, int((~same_bits(g, o)).sum()))

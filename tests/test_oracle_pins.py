@@ -433,3 +433,70 @@ def test_fp32_scaled_law_bounds(cplx, mode):
     s32 = np.array([float(backscaled(r, j)[0]) for j in range(0, 20000, 10)])
     nz = s64 > 0
     assert np.all(np.abs(s32[nz] - s64[nz]) <= 4 * EPS32 * s64[nz])
+
+
+# ---------------------------------------------------------------------------
+# The sine form of the assembly, eq. (31), against the tangent form, eq. (29)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+@pytest.mark.parametrize("law", ["scaled", "bits"])
+def test_sine_form_is_the_tangent_form(kind, law):
+    """Eqs. (29) and (31) are two formulas for the same U, written separately
+    (the sines from sin = cos * tan, section 7): on the same lanes they agree
+    within 4 eps entrywise (U's entries are at most 1 in magnitude); V, the
+    scaled singular values and s are bitwise the same; and the sine form's
+    rho, delta, eta (eqs. (33)-(35), binary128) stay within 16 eps.  A wrong
+    sign, a swapped product or a dropped phase in either formula breaks the
+    first check by orders of magnitude."""
+    from workloads import to_trains
+    cplx, dt = kind in "zc", (np.float64 if kind in "dz" else np.float32)
+    n = 1 << 15
+    if law == "bits":
+        if dt == np.float32:
+            pytest.skip("the random-bit law is the FP64 workload")
+        A = random_bits(n, 811, cplx)
+    else:
+        A = scaled_law(n, 812, cplx, dtype=dt)
+    tr = to_trains(A, dt)
+    resc = dt == np.float32
+    ot, ft = O.run_trains(tr, cplx, dt, rescue=resc)
+    os_, fs = O.run_trains(tr, cplx, dt, rescue=resc, form="sine")
+    assert np.array_equal(ft, fs)
+    k = 16 if cplx else 8
+    eps = float(np.finfo(dt).eps)
+    for i in range(k // 2):
+        d = np.abs(ot[i].astype(np.float64) - os_[i].astype(np.float64))
+        assert np.nanmax(d) <= 4 * eps, (i, np.nanmax(d) / eps)
+    for i in range(k // 2, k + 3):
+        assert np.array_equal(ot[i], os_[i], equal_nan=True), i
+    met = O.metrics(tr, os_, cplx)
+    for key in ("rho", "delta", "eta"):
+        assert np.nanmax(met[key]) <= 16 * eps, (key, np.nanmax(met[key]) / eps)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_subnormal_phase_keeps_u_unitary(dt):
+    """A complex pivot whose modulus is subnormal after the scaling of eq. (2)
+    (here a_21 = (-4 + i) 2^-1074 beside a_11 = 2^1021, which the scaling
+    leaves unchanged): eq. (1) taken literally gives the "phase" (-1, 1/4) of
+    modulus 1.03 and a U that is 2^-4 away from unitary; the phase is taken of
+    an exactly rescaled z, so U is unitary to rounding (delta <= 16 eps) and
+    the residual stays small.  The second lane is one found that way in the
+    seeded +-m 2^e workload (r'_22 subnormal after the QR step)."""
+    from workloads import to_trains
+    tiny = np.ldexp(1.0, -1074 if dt == np.float64 else -149)
+    big = np.ldexp(1.0, 1021 if dt == np.float64 else 125)
+    lanes = [[big, (-4 + 1j) * tiny, 0.0, 0.0]]
+    if dt == np.float64:
+        h = [float.fromhex(x) for x in ("-0x1.8f3ff0bbc6878p-114", "0x1.b7b4128a87457p-115", "0x0.0p+0",
+                                        "0x0.0p+0", "0x1.da9c4603b1d54p-561", "0x1.44b5677d98d6fp+972",
+                                        "0x1.3f8a762830dd4p-36", "-0x1.cc6cffd77a71fp-496")]
+        lanes.append([h[0] + 1j * h[1], h[2] + 1j * h[3], h[4] + 1j * h[5], h[6] + 1j * h[7]])
+    A = np.array(lanes, dtype=np.complex128).T.astype(np.complex128 if dt == np.float64 else np.complex64)
+    tr = to_trains(A, dt)
+    eps = float(np.finfo(dt).eps)
+    for form in ("tangent", "sine"):
+        out, _ = O.run_trains(tr, True, dt, form=form)
+        met = O.metrics(tr, out, True)
+        assert np.max(met["delta"]) <= 16 * eps, (form, met["delta"] / eps)
+        assert np.max(met["rho"]) <= 16 * eps, (form, met["rho"] / eps)
