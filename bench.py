@@ -35,6 +35,7 @@ BYTES_PER_SVD_NOUV = {"d": 56, "z": 88, "s": 28, "c": 44}
 # launch shape (threads per block, matrices per lane) used by the benchmark
 DEFAULT_LAUNCH = {"d": (256, 1), "z": (64, 2), "s": (256, 1), "c": (256, 1),
                   "d_nouv": (256, 1), "z_nouv": (256, 1), "s_nouv": (256, 1), "c_nouv": (256, 1)}
+WARM_S = 0.1  # minimum warm-up per timed variant, seconds
 KERNEL_SOURCES = ["paper_2005_07403_amd/csrc/svd2_batch.hip", "paper_2005_07403_amd/csrc/svd2_lane.hpp"]
 
 
@@ -79,8 +80,18 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
     res = {}
 
     def timed(fn):
+        # W warm-up steps, and at least WARM_S of warm-up in all, so that the
+        # GPU's clocks have left the idle state they drop to while the host
+        # generates inputs (otherwise whichever variant is timed first reads
+        # several percent slow)
+        t0 = time.perf_counter()
         for _ in range(warmup):
             fn()
+        torch.cuda.synchronize()
+        while time.perf_counter() - t0 < WARM_S:
+            for _ in range(8):
+                fn()
+            torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
         torch.cuda.synchronize()
@@ -214,8 +225,11 @@ def kog_svd_bench(A, s, G0, mat, steps, passes):
     N = A.shape[0]
     fl = S.SVD2_KOG_TWO_STEP
     ws = torch.empty(S.kog_svd_workspace_bytes(N, "d", fl), dtype=torch.uint8, device="cuda")
-    # per sweep: the iterate once per pass (as the solve), U and V likewise
-    hbm = 3 * 2 * mat * (passes + (steps - 2 * passes))
+    # per sweep: the iterate read and written once per pass of two steps (and
+    # for the odd last step); U and V once per four steps (pairs of passes),
+    # once for an unpaired last pass and once for the last step
+    single = steps - 2 * passes
+    hbm = 2 * mat * (passes + single) + 2 * 2 * mat * (passes // 2 + passes % 2 + single)
     res = {"mode": "two_step", "algorithmic_bytes_per_sweep": hbm}
     G = G0.clone(memory_format=torch.preserve_format)
     torch.cuda.synchronize()

@@ -369,10 +369,12 @@ svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *w
  *     interleaved), columns permuted alike, so A_0 ~ U diag(sigma) V^*;
  *   A: the final iterate (unsorted).
  * ws: kog_svd_workspace_bytes(N, dtype, flags) bytes, 256-byte aligned (the
- * solve's workspace plus two N x N matrices and the sort keys).  A, U, V,
+ * solve's workspace plus two N x N matrices, the sort keys and, two steps per
+ * pass, two more rotation sets).  A, U, V,
  * sigma and ws must be pairwise disjoint (SVD2_ERR_ALIAS).  flags: 0 or
- * SVD2_KOG_TWO_STEP (two steps per pass; U and V alternate with workspace
- * copies like the iterate), SVD2_KOG_UNFUSED (one step per pass, U and V
+ * SVD2_KOG_TWO_STEP (two steps per pass over A; U and V are taken four steps
+ * further per pass after every second pass, alternating with workspace
+ * copies), SVD2_KOG_UNFUSED (one step per pass, U and V
  * rotated in place) or SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH; anything else is
  * SVD2_ERR_FLAGS.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
  * SVD2_NOT_CONVERGED (outputs as above for the last iterate); synchronises

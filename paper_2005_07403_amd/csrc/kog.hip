@@ -356,6 +356,7 @@ template <class T, bool CPLX> struct Ctx {
   // two steps per pass
   bool acc = false;
   Mat<T, CPLX> U{}, V{}, U2{}, V2{};
+  Bufs<T, CPLX> B2{}, B3{};  // two steps per pass: the rotations of every second pass
 };
 
 template <class T, bool CPLX>
@@ -423,14 +424,18 @@ svd2_status accum_step(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &U, const Mat<T
   return hip_st(hipGetLastError());
 }
 
-// the same for steps t and t+1 (rotations in c.B and c.B1), from the buffer
-// pair that holds U and V (in_w: the workspace pair) into the other one
-template <class T, bool CPLX> svd2_status accum_two(const Ctx<T, CPLX> &c, bool in_w, int t) {
-  const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + kAccSeg - 1) / kAccSeg;
+// S steps t .. t+S-1 (rotations in sets[0 .. S-1]), from the buffer pair
+// that holds U and V (in_w: the workspace pair) into the other one
+template <class T, bool CPLX, int S>
+svd2_status accum_s(const Ctx<T, CPLX> &c, bool in_w, int t, const Bufs<T, CPLX> *sets) {
+  constexpr int SEG = AccShape<CPLX>::seg;
+  const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + SEG - 1) / SEG;
   const Mat<T, CPLX> &U = in_w ? c.U2 : c.U, &V = in_w ? c.V2 : c.V;
   const Mat<T, CPLX> &U2 = in_w ? c.U : c.U2, &V2 = in_w ? c.V : c.V2;
-  hipLaunchKernelGGL((kog_accum2_kernel<T, CPLX>), dim3(rb * nseg, 2), dim3(256), 0, c.st, c.N, U, V, U2, V2, t,
-                     c.B, c.B1);
+  AccSets<T, CPLX> R{};
+  for (int L = 0; L < S; ++L) R.b[L] = sets[L];
+  hipLaunchKernelGGL((kog_accum_s_kernel<T, CPLX, S>), dim3(rb * nseg, 2), dim3(256), 0, c.st, c.N, U, V, U2, V2,
+                     t, R);
   return hip_st(hipGetLastError());
 }
 
@@ -547,19 +552,16 @@ template <class T, bool CPLX> TwoStepShape two_step_shape(int N) {
 // two steps t, t+1 from `cur` into `nxt`
 template <class T, bool CPLX>
 svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t,
-                      bool in_w = false) {
+                      const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1) {
   const int n = c.N / 2;
-  hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, c.B,
-                     c.B1);
+  hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   const TwoStepShape sh = two_step_shape<T, CPLX>(c.N);
   if (sh.ntiles <= 0) return SVD2_ERR_HIP;
   hipLaunchKernelGGL((kog_two_step_kernel<T, CPLX>), dim3(sh.ntiles), dim3(64 * sh.wpg), sh.lds, c.st, c.N, cur,
-                     nxt, t, c.B, c.B1, sh.wpg, sh.span, sh.lc, sh.gx, sh.ntiles);
-  s = hip_st(hipGetLastError());
-  if (s == SVD2_OK && c.acc) s = accum_two<T, CPLX>(c, in_w, t);
-  return s;
+                     nxt, t, B0, B1, sh.wpg, sh.span, sh.lc, sh.gx, sh.ntiles);
+  return hip_st(hipGetLastError());
 }
 
 // one step t in place on `cur` (gather + SVD in one kernel, then the update)
@@ -578,16 +580,32 @@ svd2_status one_step_on(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, int t, b
 }
 
 // a sweep of the two-step mode; *in_w tells (and is updated with) which
-// buffer holds the iterate (false: the caller's A, true: the workspace copy)
-template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, bool *in_w) {
+// buffer holds the iterate (false: the caller's A, true: the workspace copy),
+// *uv_in the same for the accumulated U and V.  With accumulation the passes
+// alternate between the rotation sets (B, B1) and (B2, B3), and after every
+// second pass one kernel takes U and V four steps further; an odd last pass
+// gets a two-step accumulation, and the sweep's last single step an in-place
+// one.
+template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, bool *in_w, bool *uv_in) {
   svd2_status s = SVD2_OK;
   int t = 0;
-  for (; t + 1 < c.N - 1 && s == SVD2_OK; t += 2) {
+  for (int p = 0; t + 1 < c.N - 1 && s == SVD2_OK; t += 2, ++p) {
     const Mat<T, CPLX> &cur = *in_w ? c.W : c.M, &nxt = *in_w ? c.M : c.W;
-    s = two_steps<T, CPLX>(c, cur, nxt, t, *in_w);
+    const bool odd = c.acc && (p & 1);
+    s = two_steps<T, CPLX>(c, cur, nxt, t, odd ? c.B2 : c.B, odd ? c.B3 : c.B1);
     *in_w = !*in_w;
+    if (s != SVD2_OK || !c.acc) continue;
+    if (odd) {
+      const Bufs<T, CPLX> sets[4] = {c.B, c.B1, c.B2, c.B3};
+      s = accum_s<T, CPLX, 4>(c, *uv_in, t - 2, sets);
+      *uv_in = !*uv_in;
+    } else if (t + 3 >= c.N - 1) {
+      const Bufs<T, CPLX> sets[2] = {c.B, c.B1};
+      s = accum_s<T, CPLX, 2>(c, *uv_in, t, sets);
+      *uv_in = !*uv_in;
+    }
   }
-  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t, *in_w);
+  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t, *uv_in);
   return s;
 }
 
@@ -599,8 +617,8 @@ template <class T, bool CPLX> svd2_status copy_back(const Ctx<T, CPLX> &c) {
 
 template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
   if (c.flags & SVD2_KOG_TWO_STEP) {
-    bool in_w = false;
-    svd2_status s = sweep_two_step<T, CPLX>(c, &in_w);
+    bool in_w = false, uv_in = false;
+    svd2_status s = sweep_two_step<T, CPLX>(c, &in_w, &uv_in);
     if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
     return s;
   }
@@ -697,7 +715,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
   svd2_status s = SVD2_OK;
   if (c.flags & SVD2_KOG_GRAPH) s = graph_build<T, CPLX>(c, &exec);
   const bool two = c.flags & SVD2_KOG_TWO_STEP;
-  bool in_w = false;
+  bool in_w = false, uv_in = false;
   double off2 = 0, tot2 = 0, nrm0 = 0;
   int sw = 0, E = 0;
   if (s == SVD2_OK) s = max_exponent<T, CPLX>(c, E);
@@ -715,14 +733,14 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     }
     if (sw == max_sweeps) break;
     if (exec) s = hip_st(hipGraphLaunch(exec, c.st));
-    else if (two) s = sweep_two_step<T, CPLX>(c, &in_w);
+    else if (two) s = sweep_two_step<T, CPLX>(c, &in_w, &uv_in);
     else s = sweep<T, CPLX>(c);
     if (s == SVD2_OK) s = norms_async<T, CPLX>(c, in_w);
     if (s == SVD2_OK) s = read_norms<T, CPLX>(c, off2, tot2);
     if (s == SVD2_OK) s = check_abort<T, CPLX>(c);
     ++sw;
   }
-  if (uv_in_w) *uv_in_w = in_w;
+  if (uv_in_w) *uv_in_w = uv_in;
   if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
   if (s == SVD2_OK && E != 0) s = scale_by<T, CPLX>(c, E);
   if (s == SVD2_OK) s = hip_st(hipStreamSynchronize(c.st));
@@ -777,15 +795,17 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
 
 
 // workspace of the SVD entry points: the solve's, then the second U and V
-// buffers (N x N, lda N) and the sort keys and indices (next power of two)
+// buffers (N x N, lda N), the sort keys and indices (next power of two) and,
+// two steps per pass, two more rotation sets
 struct SvdLayout {
-  size_t u2, v2, keys, idx, total;
+  size_t u2, v2, keys, idx, b2, b3, total;
   int P;
 };
 inline SvdLayout svd_layout(int N, size_t esz, bool cplx, bool two) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const Layout L = layout(N, esz, cplx);
   const size_t mat = up((size_t)N * N * esz * (cplx ? 2 : 1));
+  const size_t set = (cplx ? 27 : 15) * up((size_t)(N / 2) * esz);
   SvdLayout S;
   S.P = 1;
   while (S.P < N) S.P <<= 1;
@@ -793,8 +813,19 @@ inline SvdLayout svd_layout(int N, size_t esz, bool cplx, bool two) {
   S.v2 = S.u2 + mat;
   S.keys = S.v2 + mat;
   S.idx = S.keys + up((size_t)S.P * esz);
-  S.total = S.idx + up((size_t)S.P * sizeof(int));
+  S.b2 = S.idx + up((size_t)S.P * sizeof(int));
+  S.b3 = S.b2 + (two ? set : 0);
+  S.total = S.b3 + (two ? set : 0);
   return S;
+}
+
+// a rotation set (pivot and SVD arrays, as make_bufs lays them out) at base
+template <class T, bool CPLX> Bufs<T, CPLX> bufs_at(char *base, int N) {
+  const size_t arr = ((size_t)(N / 2) * sizeof(T) + 255) & ~size_t(255);
+  Bufs<T, CPLX> b;
+  for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + i * arr);
+  for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + (Bufs<T, CPLX>::NIN + i) * arr);
+  return b;
 }
 
 // the flags of the SVD entry points: 0 = two steps per pass
@@ -829,6 +860,8 @@ svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma
   c.V = Mat<T, CPLX>{V, (size_t)ldv};
   c.U2 = Mat<T, CPLX>{(T *)(c.ws + S.u2), (size_t)N};
   c.V2 = Mat<T, CPLX>{(T *)(c.ws + S.v2), (size_t)N};
+  c.B2 = bufs_at<T, CPLX>(c.ws + S.b2, N);
+  c.B3 = bufs_at<T, CPLX>(c.ws + S.b3, N);
   const int grid = N < 4096 ? N : 4096;
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.U);
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.V);

@@ -785,87 +785,133 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
   }
 }
 
-// Two steps t, t+1 from (U, V) into (U2, V2), bitwise two single steps.
-// Pair j of step t has the columns x_j = (t + j) mod (N-1) and y_j = (t - j)
-// mod (N-1) (x_0 = t, y_0 = N-1); pair k of step t+1 is made of the rotated
-// columns f_k and g_k, where f_k = x_{k+1} (k < n-1) or y_{n-1} (k = n-1),
-// and g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one
-// row and walks the step-t pairs j in increasing order, keeping the last
-// three rotated pairs in registers; pair k is written at j = min(k+1, n-1).
-// Grid (row blocks of 256 x segments of kAccSeg output pairs, 2): a segment
-// re-walks the step-t pairs just before and after it, so the output is out of
-// place (a step-t column is read by two segments).  The segment's rotations
-// are staged in LDS first, and the walk goes in chunks of kAccChunk pairs
-// whose column loads are issued one chunk ahead (the loads cannot move past
-// the previous chunk's stores otherwise, and each would wait a full memory
-// round trip).
-constexpr int kAccSeg = 32, kAccChunk = 4;
-template <class T, bool CPLX>
-__global__ __launch_bounds__(256) void kog_accum2_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
-                                                         Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
-                                                         Bufs<T, CPLX> B0, Bufs<T, CPLX> B1) {
-  constexpr int C = kAccChunk;
-  __shared__ W4<T> w0s[kAccSeg + 2], w1s[kAccSeg];
-  const int n = N / 2, Mo = N - 1;
-  const int rb = (N + 255) / 256, nseg = (n + kAccSeg - 1) / kAccSeg;
+// S consecutive steps t .. t+S-1 of the accumulation from (U, V) into
+// (U2, V2), bitwise S single steps.  Pair j of step tau has the columns
+// x_j = (tau + j) mod (N-1) and y_j = (tau - j) mod (N-1) (x_0 = tau,
+// y_0 = N-1); pair k of step tau+1 is made of the rotated columns f_k and g_k
+// of step tau, where f_k = x_{k+1} (k < n-1) or y_{n-1} (k = n-1), and
+// g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one row.
+// Level L of a cascade receives the pairs of step t+L in increasing order,
+// rotates each, keeps the last three in registers and hands pair k of step
+// t+L+1 to level L+1 as soon as its second input is there (at j = min(k+1,
+// n-1)); the last level rotates and writes.  Level L only takes the pairs in
+// its range [lo_L, hi_L]: the last level's is the workgroup's segment of
+// output pairs, and each level's range is what the next one needs.
+// Grid (row blocks of 256 x segments, 2): segments re-walk a few pairs at
+// their edges, so the output is out of place.  The rotations of every level
+// are staged in LDS first, and the level-0 column loads go in chunks issued
+// one chunk ahead (the loads cannot move past the previous chunk's stores
+// otherwise).  Segment and chunk lengths as measured best at N = 4096 with
+// four levels: 64 and 2 for real, 32 and 2 for complex data (the complex
+// kernel holds twice the registers per value and runs at half the occupancy).
+constexpr int kAccMaxS = 4;
+template <bool CPLX> struct AccShape {
+  static constexpr int seg = CPLX ? 32 : 64, chunk = 2;
+};
+template <class T, bool CPLX> struct AccSets {
+  Bufs<T, CPLX> b[kAccMaxS];  // the rotations of steps t, t+1, ...
+};
+template <class T> struct AccWin {
+  Cx<T> x0, y0, x1, y1, x2, y2;
+};
+
+template <class T, bool CPLX, int S> struct AccWalk {
+  int n, Mo, t, i;
+  bool live;
+  Mat<T, CPLX> Y;
+  int lo[S], hi[S];
+  const W4<T> *w[S];
+  AccWin<T> win[S > 1 ? S - 1 : 1];
+
+  template <int L> __device__ __forceinline__ void feed(int j, Cx<T> x, Cx<T> y) {
+    if (j < lo[L] || j > hi[L]) return;
+    int a, b;
+    pair_ab(t + L, j, Mo, a, b);  // a holds x, b holds y
+    const bool fl = a > b;
+    Cx<T> c1 = sel(fl, y, x), c2 = sel(fl, x, y);
+    rot_cols<T, CPLX>(w[L][j - lo[L]], c1, c2);
+    const Cx<T> rx = sel(fl, c2, c1), ry = sel(fl, c1, c2);
+    if constexpr (L == S - 1) {
+      if (live) {
+        Y.st(i, a, rx);
+        Y.st(i, b, ry);
+      }
+    } else {
+      AccWin<T> &W = win[L];
+      W.x2 = W.x1;
+      W.y2 = W.y1;
+      W.x1 = W.x0;
+      W.y1 = W.y0;
+      W.x0 = rx;
+      W.y0 = ry;
+      if (j >= 1) {
+        const int k = j - 1;
+        feed<L + 1>(k, W.x0, sel(k == 0, W.y1, sel(k == 1, W.x2, W.y2)));
+      }
+      if (j == n - 1) feed<L + 1>(n - 1, W.y0, sel(n - 1 == 1, W.x1, W.y1));
+    }
+  }
+};
+
+template <class T, bool CPLX, int S>
+__global__ __launch_bounds__(256) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
+                                                          Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
+                                                          AccSets<T, CPLX> R) {
+  static_assert(S >= 2 && S <= kAccMaxS, "levels");
+  constexpr int SEG = AccShape<CPLX>::seg, C = AccShape<CPLX>::chunk, WMAX = S * SEG + 2 * S * S;
+  __shared__ W4<T> ws[WMAX];
+  const int n = N / 2;
+  const int rb = (N + 255) / 256, nseg = (n + SEG - 1) / SEG;
   const int blk = (int)blockIdx.x % rb, sg = (int)blockIdx.x / rb;
   if (sg >= nseg) return;
-  const int tid = (int)threadIdx.x, i = blk * 256 + tid;
-  const bool live = i < N;
+  const int tid = (int)threadIdx.x;
   const bool isv = blockIdx.y != 0;
-  const Mat<T, CPLX> X = isv ? V : U, Y = isv ? V2 : U2;
-  const int k0 = sg * kAccSeg, k1 = k0 + kAccSeg < n ? k0 + kAccSeg : n;
-  const int jlo = k0 <= 1 ? 0 : k0 - 1, jhi = k1 < n - 1 ? k1 : n - 1;
-  if (tid < jhi - jlo + 1) w0s[tid] = w_of(load_rot<T, CPLX>(B0, jlo + tid), isv);
-  if (tid >= 128 && tid - 128 < k1 - k0) w1s[tid - 128] = w_of(load_rot<T, CPLX>(B1, k0 + tid - 128), isv);
+  const Mat<T, CPLX> X = isv ? V : U;
+  AccWalk<T, CPLX, S> A;
+  A.n = n;
+  A.Mo = N - 1;
+  A.t = t;
+  A.i = blk * 256 + tid;
+  A.live = A.i < N;
+  A.Y = isv ? V2 : U2;
+  const int k0 = sg * SEG, k1 = k0 + SEG < n ? k0 + SEG : n;
+  A.lo[S - 1] = k0;
+  A.hi[S - 1] = k1 - 1;
+#pragma unroll
+  for (int L = S - 2; L >= 0; --L) {
+    A.lo[L] = A.lo[L + 1] <= 1 ? 0 : A.lo[L + 1] - 1;
+    A.hi[L] = A.hi[L + 1] + 1 < n - 1 ? A.hi[L + 1] + 1 : n - 1;
+  }
+  int base[S + 1];
+  base[0] = 0;
+#pragma unroll
+  for (int L = 0; L < S; ++L) base[L + 1] = base[L] + (A.hi[L] - A.lo[L] + 1);
+#pragma unroll
+  for (int L = 0; L < S; ++L) {
+    for (int q = tid; q < A.hi[L] - A.lo[L] + 1; q += 256)
+      ws[base[L] + q] = w_of(load_rot<T, CPLX>(R.b[L], A.lo[L] + q), isv);
+    A.w[L] = ws + base[L];
+  }
   __syncthreads();
-  // rotated (x_j, y_j) of the last three walked pairs: w0 = j, w1 = j-1, w2 = j-2
-  Cx<T> x0{}, y0{}, x1{}, y1{}, x2{}, y2{};
-  auto emit = [&](int k, Cx<T> f, Cx<T> g) {
-    int a, b;
-    pair_ab(t + 1, k, Mo, a, b);  // a holds f, b holds g
-    const W4<T> w = w1s[k - k0];
-    const bool fl = a > b;
-    Cx<T> c1 = sel(fl, g, f), c2 = sel(fl, f, g);
-    rot_cols<T, CPLX>(w, c1, c2);
-    if (live) {
-      Y.st(i, fl ? b : a, c1);
-      Y.st(i, fl ? a : b, c2);
-    }
-  };
+#pragma unroll
+  for (int L = 0; L < S - 1; ++L) A.win[L] = AccWin<T>{};
+  const int jlo = A.lo[0], jhi = A.hi[0];
   auto load = [&](int jb, Cx<T> (&la)[C], Cx<T> (&lb)[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int j = jb + c;
-      if (j <= jhi && live) {
+      if (j <= jhi && A.live) {
         int a, b;
-        pair_ab(t, j, Mo, a, b);
-        la[c] = X.ld(i, a);
-        lb[c] = X.ld(i, b);
+        pair_ab(t, j, A.Mo, a, b);
+        la[c] = X.ld(A.i, a);
+        lb[c] = X.ld(A.i, b);
       }
     }
   };
   auto walk = [&](int jb, const Cx<T> (&la)[C], const Cx<T> (&lb)[C]) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int j = jb + c;
-      if (j <= jhi) {
-        int a, b;
-        pair_ab(t, j, Mo, a, b);  // a = x_j, b = y_j
-        const bool fl = a > b;
-        Cx<T> c1 = sel(fl, lb[c], la[c]), c2 = sel(fl, la[c], lb[c]);
-        rot_cols<T, CPLX>(w0s[j - jlo], c1, c2);
-        x2 = x1; y2 = y1;
-        x1 = x0; y1 = y0;
-        x0 = sel(fl, c2, c1);
-        y0 = sel(fl, c1, c2);
-        if (j >= 1) {
-          const int k = j - 1;
-          if (k >= k0 && k < k1) emit(k, x0, sel(k == 0, y1, sel(k == 1, x2, y2)));
-        }
-        if (j == n - 1 && n - 1 >= k0 && n - 1 < k1) emit(n - 1, y0, sel(n - 1 == 1, x1, y1));
-      }
-    }
+    for (int c = 0; c < C; ++c)
+      if (jb + c <= jhi) A.template feed<0>(jb + c, la[c], lb[c]);
   };
   Cx<T> pa[C], pb[C], qa[C], qb[C];
 #pragma unroll
