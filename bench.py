@@ -142,6 +142,62 @@ def cpu_baseline(variant: str, trains_np, budget_s: float = 12.0):
                        f"({'complex' if cplx else 'real'} {dtype.name}), {t_total:.1f} s")
 
 
+def cpu_details(trains_z, trains_d, nthreads, budget_s: float = 1.5):
+    """Further oracle timings for context: one thread and all threads, real
+    and complex FP64, the MIRROR policy (what the GPU computes) and the REF
+    policy (hypot and 1/sqrt through binary128), each on a leading sample of
+    the batch repeated for about budget_s."""
+    import oracle.oracle as O
+    out = {}
+    for name, tr, cplx in (("z", trains_z, True), ("d", trains_d, False)):
+        for pol in ("mirror", "ref"):
+            for th in (1, nthreads):
+                if pol == "ref" and th == 1:
+                    continue
+                n = min(tr[0].shape[0], (1 << 20) if th > 1 else (1 << 17))
+                sub = [t[:n] for t in tr]
+                reps, el = 0, 0.0
+                while el < budget_s and reps < 50:
+                    t0 = time.perf_counter()
+                    O.run_trains(sub, cplx, np.float64, policy=pol, nthreads=th)
+                    el += time.perf_counter() - t0
+                    reps += 1
+                out[f"{name}_{pol}_{th}t"] = {"SVDs_per_s": reps * n / el, "sample": f"{reps} x {n} matrices"}
+    return out
+
+
+def cpu_kog(order: int = 4096, steps: int = 4, small: int = 256):
+    """The oracle's Kogbetliantz (single-threaded plain loops) on the host:
+    seconds per step at the benchmark order over a few steps, extrapolated to
+    a sweep of order - 1 steps (an extrapolation, stated as such), and a full
+    solve at a small order, timed beside the GPU's two-step solve of it."""
+    import torch
+    import oracle.oracle as O
+    from paper_2005_07403_amd import svd2 as S
+    from workloads import SEED_BASE, kog_matrix
+    A = np.asfortranarray(kog_matrix(order, SEED_BASE + 3, cond=1e12))
+    t0 = time.perf_counter()
+    for t in range(steps):
+        O.kog_step(A, t)
+    per_step = (time.perf_counter() - t0) / steps
+    B = np.asfortranarray(kog_matrix(small, SEED_BASE + 5, cond=1e12))
+    G = torch.from_numpy(B.copy(order="F")).cuda()
+    t0 = time.perf_counter()
+    ro = O.kog_solve(B, tol=1e-14)
+    cpu_s = time.perf_counter() - t0
+    S.kog_solve(G.clone(memory_format=torch.preserve_format), tol=1e-14, flags=S.SVD2_KOG_TWO_STEP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rg = S.kog_solve(G, tol=1e-14, flags=S.SVD2_KOG_TWO_STEP)
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - t0
+    return {"cores": 1, "kind": "oracle", "order": order, "seconds_per_step": per_step,
+            "seconds_per_sweep_extrapolated": per_step * (order - 1),
+            "sample": f"{steps} steps at order {order}",
+            "full_solve": {"order": small, "sweeps": ro["sweeps"], "cpu_seconds": cpu_s,
+                           "gpu_two_step_seconds": gpu_s, "gpu_sweeps": rg["sweeps"]}}
+
+
 def read_traffic(kernel_key: str):
     """HBM bytes per dispatch from the committed rocprofv3 --pmc summary, or
     None when the kernel sources changed since it was taken."""
@@ -215,7 +271,7 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
     return out
 
 
-def kog_svd_bench(A, s, G0, mat, steps, passes):
+def kog_svd_bench(A, s, G0, mat, steps, passes, full: bool = True):
     """The full SVD A_0 = U diag(sigma) V^* (transformations accumulated, two
     steps per pass) on the one-problem workload: one sweep and a full solve,
     sigma against the known singular values, and the residuals
@@ -239,6 +295,9 @@ def kog_svd_bench(A, s, G0, mat, steps, passes):
     el = time.perf_counter() - t0
     res["one_sweep_s"] = el
     res["hbm_GBs"] = hbm / el / 1e9
+    if not full:
+        del G, ws
+        return res
     G = G0.clone(memory_format=torch.preserve_format)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -323,7 +382,8 @@ def summarize(variant, r, pattern, flags_desc="", nouv=False):
     pms = float(np.mean(pattern["kernel_ms"]))
     pgbs = bps * n / (pms * 1e-3) / 1e9
     return dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
-                kernel_ms_min=float(np.min(r["kernel_ms"])), algorithmic_GBs=gbs,
+                kernel_ms_min=float(np.min(r["kernel_ms"])), kernel_ms_median=float(np.median(r["kernel_ms"])),
+                algorithmic_GBs=gbs,
                 hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=bps,
                 pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
 
@@ -351,6 +411,9 @@ def main():
     ap.add_argument("--uv", choices=["both", "full", "nouv"], default="both",
                     help="batched SVD: time only the default kernels (full), only the singular-values-only "
                          "ones (nouv), or every variant (both)")
+    ap.add_argument("--kog-svd-only", action="store_true",
+                    help="run only one sweep of the Kogbetliantz SVD with U and V (two steps per pass); "
+                         "prints its JSON (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -385,6 +448,14 @@ def main():
         out = kog_bench(args.kog_order, sweeps=1, solve=False, only=args.kog_only.split(","))
         print(json.dumps(out), flush=True)
         return
+    if args.kog_svd_only:
+        from workloads import SEED_BASE, kog_matrix
+        A, sig = kog_matrix(args.kog_order, SEED_BASE + 3, cond=1e12, return_sigma=True)
+        steps = args.kog_order - 1
+        out = kog_svd_bench(A, sig, torch.from_numpy(A).cuda(), args.kog_order ** 2 * 8, steps,
+                            (steps - 1) // 2, full=False)
+        print(json.dumps(out), flush=True)
+        return
     if args.kog_batch_only:
         out = kog_batch_bench(args.kog_batch)
         print(json.dumps({k: v for k, v in out.items() if k != "problems"}), flush=True)
@@ -401,7 +472,7 @@ def main():
         keep_nouv = args.uv == "nouv"
         flagsets = {v: {d: f for d, f in fs.items() if ("NO_UV" in d) == keep_nouv and "SINE" not in d}
                     for v, fs in flagsets.items()}
-    results, inputs_z = {}, None
+    results, inputs_z, inputs_d = {}, None, None
     # FP32 also at the precision form's own size (2^26: its inputs exceed the
     # 256 MB Infinity Cache, so they come from HBM on every launch)
     runs = [(v, args.n, "") for v in variants]
@@ -424,8 +495,10 @@ def main():
                 key = f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
             results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv)
             log(f"[bench] {key}: {json.dumps(results[key])}")
-        if v == "z":
+        if v == "z" and not tag:
             inputs_z = tr
+        elif v == "d" and not tag:
+            inputs_d = tr
         else:
             del tr
 
@@ -446,6 +519,12 @@ def main():
         log("[bench] CPU baseline (oracle) ...")
         cpu = cpu_baseline("z", inputs_z)
         log(f"[bench] cpu: {json.dumps(cpu)}")
+        if inputs_d is not None:
+            cpu["details"] = cpu_details(inputs_z, inputs_d, cpu["cores"])
+            log(f"[bench] cpu details: {json.dumps(cpu['details'])}")
+        if kog is not None:
+            kog["cpu_baseline"] = cpu_kog(args.kog_order)
+            log(f"[bench] kog cpu: {json.dumps(kog['cpu_baseline'])}")
     traffic = read_traffic(f"svd2_{head}")
     dtype_name = {"d": "f64", "z": "f64", "s": "f32", "c": "f32"}[head[0]]
     line = {
