@@ -404,7 +404,8 @@ svd2_status kog_set_fused_blocks_per_cu(int per_cu);
    first rule i with N <= max_order[i] applies; a tile covers kc[i] row pairs
    (64, 128 or 256) and lc[i] column pairs (1..4096) on one 256-thread
    workgroup.  max_order must increase.  count == 0 restores the default
-   (kc 256, lc 8 for every order).  Host arrays, copied.  Affects later calls. */
+   (kc 256, lc 8 for every order).  Host arrays, copied; safe to call while
+   other threads launch; affects later calls. */
 svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, const int *lc);
 
 /* Workgroup shapes of the two-step kernel (SVD2_KOG_TWO_STEP), by order: the
@@ -413,7 +414,8 @@ svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, c
  * [2, 64] fixes the column pairs each wavefront writes; lc[i] in [-3, 0]
  * sizes the column split so that the grid fills 1 - lc[i] whole rounds of
  * the workgroups the GPU holds at once.  count = 0 restores the default
- * (4, 8).  Host state, not thread-safe against concurrent launches. */
+ * (4, 8).  Host arrays, copied; safe to call while other threads launch
+ * (the tables are guarded); affects later calls. */
 svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *wpg, const int *lc);
 
 #ifdef __cplusplus

@@ -23,6 +23,8 @@
 // persistent cooperative kernel that runs all steps of a sweep with two grid
 // barriers per step, and two steps per pass over the matrix (kog_device.hpp).
 // The uneven multi-problem batch is in kog_batch.hip.
+#include <atomic>
+#include <mutex>
 #include <stdint.h>
 #include <string.h>
 
@@ -31,11 +33,16 @@
 namespace kog {
 
 thread_local int g_kog_hip = 0;
-int g_fused_per_cu = 1;  // co-resident workgroups per CU used by the fused kernel
+std::atomic<int> g_fused_per_cu{1};  // co-resident workgroups per CU used by the fused kernel
+
+// tile-shape tables, set by kog_set_tile_rules / kog_set_two_step_tiles from
+// any thread and read at every launch: guarded by one mutex
+std::mutex g_rules_mu;
 TileRule g_rules[kMaxRules] = {default_rule()};
 int g_nrules = 1;
 
 TileRule rule_for(int N) {
+  std::lock_guard<std::mutex> lock(g_rules_mu);
   for (int i = 0; i < g_nrules; ++i)
     if (N <= g_rules[i].max_order) return g_rules[i];
   return default_rule();
@@ -46,6 +53,7 @@ TileRule default_rule2() { return TileRule{0x7fffffff, 4, 8}; }
 TileRule g_rules2[kMaxRules] = {default_rule2()};
 int g_nrules2 = 1;
 TileRule rule2_for(int N) {
+  std::lock_guard<std::mutex> lock(g_rules_mu);
   for (int i = 0; i < g_nrules2; ++i)
     if (N <= g_rules2[i].max_order) return g_rules2[i];
   return default_rule2();
@@ -468,7 +476,8 @@ template <class T, bool CPLX> int fused_grid(int N) {
     per = p;
     cus = c;
   }
-  int want = g_fused_per_cu < per ? g_fused_per_cu : per;
+  const int fpc = g_fused_per_cu.load();
+  int want = fpc < per ? fpc : per;
   int max_blocks = cus * want;
   const int n = N / 2;
   TileRule r = rule_for(N);
@@ -1038,6 +1047,7 @@ svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, c
     if (lc[i] < 1 || lc[i] > 4096 || max_order[i] < 2) return SVD2_ERR_SIZE;
     if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
   }
+  std::lock_guard<std::mutex> lock(g_rules_mu);
   for (int i = 0; i < count; ++i) g_rules[i] = TileRule{max_order[i], kc[i], lc[i]};
   g_nrules = count;
   if (count == 0) {
@@ -1055,6 +1065,7 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
     if (lc[i] < -3 || lc[i] == 1 || lc[i] > 64 || max_order[i] < 2) return SVD2_ERR_SIZE;
     if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
   }
+  std::lock_guard<std::mutex> lock(g_rules_mu);
   for (int i = 0; i < count; ++i) g_rules2[i] = TileRule{max_order[i], wpg[i], lc[i]};
   g_nrules2 = count;
   if (count == 0) {
@@ -1066,7 +1077,7 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
 
 svd2_status kog_set_fused_blocks_per_cu(int per_cu) {
   if (per_cu < 1 || per_cu > 16) return SVD2_ERR_SIZE;
-  g_fused_per_cu = per_cu;
+  g_fused_per_cu.store(per_cu);
   return SVD2_OK;
 }
 
