@@ -132,3 +132,34 @@ def test_svd_order_1030_two_step_equals_one_step(kind):
     bound = 4 * r1["sweeps"] * N ** 1.5 * EPS[kind]
     assert float(rec) <= bound and float(orth) <= bound
     assert np.all(np.diff(s1) <= 0)
+
+
+@pytest.mark.slow
+def test_svd_full_order_4096():
+    """The benchmark's SVD (order 4096, real FP64, sigma from 1 to 1e-12, tuned
+    launch shapes): two steps per pass (U and V four steps per pass) bitwise
+    equal to one step per pass, which matches the oracle bitwise at the orders
+    the oracle can run; U diag(sigma) V^T reproduces A_0 and U, V are
+    orthogonal within 4 S N^1.5 eps; sigma matches the construction within
+    8 N eps."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    S.apply_tuning()
+    N = 4096
+    A, sig0 = kog_matrix(N, SEED_BASE + 3, cond=1e12, return_sigma=True)
+    A = np.asfortranarray(A)
+    r1, A1, U1, V1, s1 = _run(A.copy(order="F"), "d", "two", max_sweeps=60)
+    r2, A2, U2, V2, s2 = _run(A.copy(order="F"), "d", "unfused", max_sweeps=60)
+    assert r1["status"] == r2["status"] == 0 and r1["sweeps"] == r2["sweeps"]
+    for x, y in ((A1, A2), (U1, U2), (V1, V2), (s1, s2)):
+        assert np.array_equal(_bits(x), _bits(y))
+    eps, S_ = 2.0 ** -52, r1["sweeps"]
+    Ug, Vg, sg = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (U1, V1, s1))
+    A0 = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    rec = float(torch.linalg.norm(A0 - (Ug * sg) @ Vg.t().contiguous()) / torch.linalg.norm(A0))
+    I = torch.eye(N, dtype=torch.float64, device="cuda")
+    bound = 4 * S_ * N ** 1.5 * eps
+    assert rec <= bound
+    assert float(torch.linalg.norm(Ug.t().contiguous() @ Ug - I)) <= bound
+    assert float(torch.linalg.norm(Vg.t().contiguous() @ Vg - I)) <= bound
+    assert np.max(np.abs(s1 - sig0)) <= 8 * N * eps * sig0[0]
