@@ -419,8 +419,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the batched SVD shards trivially by contiguous chunks; see DESIGN.md)",
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported (the batched SVD "
+              "would shard by contiguous chunks of the batch, one per GPU, with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 
