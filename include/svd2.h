@@ -175,11 +175,6 @@ void svd2_get_launch_kind(int kind, int *block, int *per_thread);
 const char *svd2_status_string(svd2_status st);
 int svd2_last_hip_error(void);
 
-/* Conformance probe of the device primitives the kernels use (correct
-   rounding of /, sqrt, fma, ldexp; frexp exponents of subnormals; NaN
-   handling of fmin/fmax), for tests.  op: 0 div, 1 sqrt, 2 fma, 3 ldexp(x,
-   (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y).
-   x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
 /* Memory-pattern probe, a diagnostic: the loads and stores of the batched
    kernel of element type `kind` (0 real FP64, 1 complex FP64, 2 real FP32,
    3 complex FP32; 4-7 the same with SVD2_NO_UV) with the same launch shape,
@@ -190,6 +185,11 @@ int svd2_last_hip_error(void);
 svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *const *out,
                               hipStream_t stream);
 
+/* Conformance probe of the device primitives the kernels use (correct
+   rounding of /, sqrt, fma, ldexp; frexp exponents of subnormals; NaN
+   handling of fmin/fmax), for tests.  op: 0 div, 1 sqrt, 2 fma, 3 ldexp(x,
+   (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y).
+   x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
 svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y,
                            const double *z, double *out, hipStream_t stream);
 svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
