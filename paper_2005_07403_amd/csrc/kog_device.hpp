@@ -827,10 +827,22 @@ template <class T, bool CPLX, int S> struct AccWalk {
     if (j < lo[L] || j > hi[L]) return;
     int a, b;
     pair_ab(t + L, j, Mo, a, b);  // a holds x, b holds y
-    const bool fl = a > b;
-    Cx<T> c1 = sel(fl, y, x), c2 = sel(fl, x, y);
-    rot_cols<T, CPLX>(w[L][j - lo[L]], c1, c2);
-    const Cx<T> rx = sel(fl, c2, c1), ry = sel(fl, c1, c2);
+    // the orientation is uniform over the wavefront: a branch, whose two
+    // sides write rx and ry directly, costs less than selecting the operands
+    // and the results (8 v_cndmask per real rotation)
+    Cx<T> rx, ry;
+    const W4<T> &wl = w[L][j - lo[L]];
+    if (a > b) {
+      Cx<T> c1 = y, c2 = x;
+      rot_cols<T, CPLX>(wl, c1, c2);
+      ry = c1;
+      rx = c2;
+    } else {
+      Cx<T> c1 = x, c2 = y;
+      rot_cols<T, CPLX>(wl, c1, c2);
+      rx = c1;
+      ry = c2;
+    }
     if constexpr (L == S - 1) {
       if (live) {
         Y.st(i, a, rx);
