@@ -792,7 +792,7 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // of step tau, where f_k = x_{k+1} (k < n-1) or y_{n-1} (k = n-1), and
 // g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one row.
 // Level L of a cascade receives the pairs of step t+L in increasing order,
-// rotates each, keeps the last three in registers and hands pair k of step
+// rotates each, keeps the y columns of the last three in registers and hands pair k of step
 // t+L+1 to level L+1 as soon as its second input is there (at j = min(k+1,
 // n-1)); the last level rotates and writes.  Level L only takes the pairs in
 // its range [lo_L, hi_L]: the last level's is the workgroup's segment of
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // one chunk ahead (the loads cannot move past the previous chunk's stores
 // otherwise).  Segment and chunk lengths as measured best at N = 4096 with
 // four levels: 64 and 2 for real, 32 and 2 for complex data (the complex
-// kernel holds twice the registers per value and runs at half the occupancy).
+// kernel holds twice the registers per value).
 constexpr int kAccMaxS = 4;
 template <bool CPLX> struct AccShape {
   static constexpr int seg = CPLX ? 32 : 64, chunk = 2;
@@ -811,8 +811,9 @@ template <bool CPLX> struct AccShape {
 template <class T, bool CPLX> struct AccSets {
   Bufs<T, CPLX> b[kAccMaxS];  // the rotations of steps t, t+1, ...
 };
+// a level's delay line of rotated y columns (see AccWalk::feed)
 template <class T> struct AccWin {
-  Cx<T> x0, y0, x1, y1, x2, y2;
+  Cx<T> y0, y1, y2;
 };
 
 template <class T, bool CPLX, int S> struct AccWalk {
@@ -849,24 +850,25 @@ template <class T, bool CPLX, int S> struct AccWalk {
         Y.st(i, b, ry);
       }
     } else {
+      // Pair k of the next step takes f_k = x_{k+1} (the x just rotated, at
+      // j = k+1) and g_k = y_{k-1} for k >= 2, y_0 for k = 0, x_0 for k = 1.
+      // Pair 0 enters the delay line as y_0 then x_0, so g_k is always the
+      // entry two pairs back, and g_{n-1} of the last pair one back.
       AccWin<T> &W = win[L];
-      W.x2 = W.x1;
       W.y2 = W.y1;
-      W.x1 = W.x0;
-      W.y1 = W.y0;
-      W.x0 = rx;
-      W.y0 = ry;
-      if (j >= 1) {
-        const int k = j - 1;
-        feed<L + 1>(k, W.x0, sel(k == 0, W.y1, sel(k == 1, W.x2, W.y2)));
-      }
-      if (j == n - 1) feed<L + 1>(n - 1, W.y0, sel(n - 1 == 1, W.x1, W.y1));
+      W.y1 = sel(j == 0, ry, W.y0);
+      W.y0 = sel(j == 0, rx, ry);
+      if (j >= 1) feed<L + 1>(j - 1, rx, W.y2);
+      if (j == n - 1) feed<L + 1>(n - 1, ry, W.y1);
     }
   }
 };
 
+// The register cap of 4 waves per SIMD (128 VGPRs) binds only the complex
+// FP64 walk (133 VGPRs uncapped, 4 spilled when capped), which then holds a
+// third more waves and runs a sweep 4 % faster at N = 4096.
 template <class T, bool CPLX, int S>
-__global__ __launch_bounds__(256) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
                                                           Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
                                                           AccSets<T, CPLX> R) {
   static_assert(S >= 2 && S <= kAccMaxS, "levels");
