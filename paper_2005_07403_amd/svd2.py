@@ -114,6 +114,11 @@ def _check(fn: str, st: int) -> None:
         raise Svd2Error(fn, st, lib().svd2_last_hip_error() if st == 5 else 0)
 
 
+def _nbytes(t) -> int:
+    """Size in bytes of a caller's device buffer (any dtype)."""
+    return t.numel() * t.element_size()
+
+
 def _stream(stream) -> int:
     if stream is None:
         import torch
@@ -258,8 +263,10 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
         wsb = svd2_workspace_bytes(n, flags)
         if wsb and ws is None:
             ws = torch.empty(wsb, dtype=torch.uint8, device=trains[0].device)
+        # the library checks the size the caller's buffer really has
+        ws_bytes = 0 if ws is None else _nbytes(ws)
         (csvd2_batch if cplx else ssvd2_batch)(
-            n, ins, outs, flags, 0 if ws is None else ws.data_ptr(), wsb,
+            n, ins, outs, flags, 0 if ws is None else ws.data_ptr(), ws_bytes,
             0 if nrescued is None else nrescued.data_ptr(), stream)
     else:
         raise TypeError(dt)
@@ -341,7 +348,7 @@ def kog_step(A, t: int, ws=None, flags: int = 0, stream=None) -> None:
     N, lda, ptr = _kog_args(A)
     ws = kog_workspace(A) if ws is None else ws
     _kog_check(f"{k}kog_step", getattr(_kog(), f"{k}kog_step")(N, ptr, lda, t, ws.data_ptr(),
-                                                              ws.numel(), flags, _stream(stream)))
+                                                              _nbytes(ws), flags, _stream(stream)))
 
 
 def kog_sweep(A, ws=None, flags: int = 0, stream=None) -> None:
@@ -349,7 +356,7 @@ def kog_sweep(A, ws=None, flags: int = 0, stream=None) -> None:
     N, lda, ptr = _kog_args(A)
     ws = kog_workspace(A, flags) if ws is None else ws
     _kog_check(f"{k}kog_sweep", getattr(_kog(), f"{k}kog_sweep")(N, ptr, lda, ws.data_ptr(),
-                                                                ws.numel(), flags, _stream(stream)))
+                                                                _nbytes(ws), flags, _stream(stream)))
 
 
 def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int = 0,
@@ -360,7 +367,7 @@ def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int =
     ws = kog_workspace(A, flags) if ws is None else ws
     sw, off = ctypes.c_int(), ctypes.c_double()
     st = getattr(_kog(), f"{k}kog_solve")(N, ptr, lda, tol, max_sweeps, ctypes.byref(sw),
-                                          ctypes.byref(off), ws.data_ptr(), ws.numel(), flags,
+                                          ctypes.byref(off), ws.data_ptr(), _nbytes(ws), flags,
                                           _stream(stream))
     _kog_check(f"{k}kog_solve", st)
     return dict(status=st, sweeps=sw.value, off_rel=off.value)
@@ -378,7 +385,7 @@ def kog_sigma(A, out=None, ws=None, stream=None):
         ws = torch.empty(max(int(_kog().kog_sigma_workspace_bytes(N, KOG_DTYPE[k])), 1), dtype=torch.uint8,
                          device=A.device)
     _kog_check(f"{k}kog_sigma", getattr(_kog(), f"{k}kog_sigma")(N, ptr, lda, out.data_ptr(), ws.data_ptr(),
-                                                                  ws.numel(), _stream(stream)))
+                                                                  _nbytes(ws), _stream(stream)))
     return out
 
 
@@ -406,7 +413,7 @@ def kog_svd(A, tol: float = 1e-14, max_sweeps: int = 40, U=None, V=None, sigma=N
         ws = torch.empty(kog_svd_workspace_bytes(N, k, flags), dtype=torch.uint8, device=A.device)
     sw, off = ctypes.c_int(), ctypes.c_double()
     st = getattr(_kog(), f"{k}kog_svd")(N, ptr, lda, uptr, ldu, vptr, ldv, sigma.data_ptr(), tol, max_sweeps,
-                                        ctypes.byref(sw), ctypes.byref(off), ws.data_ptr(), ws.numel(), flags,
+                                        ctypes.byref(sw), ctypes.byref(off), ws.data_ptr(), _nbytes(ws), flags,
                                         _stream(stream))
     _kog_check(f"{k}kog_svd", st)
     return dict(status=st, sweeps=sw.value, off_rel=off.value, U=U, V=V, sigma=sigma)
@@ -418,7 +425,7 @@ def kog_norms(A, ws=None, stream=None):
     ws = kog_workspace(A) if ws is None else ws
     o, t = ctypes.c_double(), ctypes.c_double()
     _kog_check(f"{k}kog_norms", getattr(_kog(), f"{k}kog_norms")(
-        N, ptr, lda, ctypes.byref(o), ctypes.byref(t), ws.data_ptr(), ws.numel(), _stream(stream)))
+        N, ptr, lda, ctypes.byref(o), ctypes.byref(t), ws.data_ptr(), _nbytes(ws), _stream(stream)))
     return o.value, t.value
 
 
@@ -490,7 +497,7 @@ def kog_batch_solve(mats, tols, max_sweeps=40, flags: int = 0, ws=None, stream=N
     wsb = int(L.kog_batch_workspace_bytes_flags(n, probs, flags))
     if ws is None:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=mats[0].device)
-    st = L.kog_batch_solve(n, probs, ws.data_ptr(), ws.numel(), flags, _stream(stream))
+    st = L.kog_batch_solve(n, probs, ws.data_ptr(), _nbytes(ws), flags, _stream(stream))
     _kog_check("kog_batch_solve", st)
     return [dict(status=probs[i].status, sweeps=probs[i].sweeps, off_rel=probs[i].off_rel)
             for i in range(n)]

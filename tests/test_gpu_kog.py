@@ -281,3 +281,27 @@ def test_solve_tiny_and_huge_matrices(kind, k, mode):
     assert r["status"] == ro["status"] == r1["status"] == 0
     assert r["sweeps"] == ro["sweeps"] == r1["sweeps"] > 0
     assert _same(G.cpu().numpy(), A)
+
+
+@pytest.mark.parametrize("kind", ["d", "c"])
+def test_caller_workspace_in_bytes(kind):
+    """The binding passes a caller's workspace at its size in bytes whatever
+    its dtype: 8 bytes short of kog_workspace_bytes is refused before any
+    launch (the matrix untouched), and the exact size gives the solve of a
+    workspace the binding allocates, bit for bit."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N, flags = 64, S.SVD2_KOG_TWO_STEP
+    A = _make(N, kind, SEED_BASE + 360)
+    need = S.kog_workspace_bytes(N, kind, flags)
+    assert need % 8 == 0
+    G = _dev(A)
+    with pytest.raises(S.Svd2Error) as err:
+        S.kog_solve(G, ws=torch.empty(need // 8 - 1, dtype=torch.float64, device="cuda"), flags=flags)
+    assert err.value.status == 6
+    assert _same(G.cpu().numpy(), A)
+    r1 = S.kog_solve(G, flags=flags)
+    G2 = _dev(A)
+    r2 = S.kog_solve(G2, ws=torch.empty(need // 8, dtype=torch.float64, device="cuda"), flags=flags)
+    torch.cuda.synchronize()
+    assert r1["sweeps"] == r2["sweeps"] and _same(G.cpu().numpy(), G2.cpu().numpy())

@@ -296,6 +296,31 @@ def test_fp32_rescue_near_singular(cplx):
         _check(A, np.float32, flags=_fp32_flags(mode), rescue=_oracle_rescue(mode))
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fp32_caller_workspace(cplx):
+    """A workspace the caller passes in is checked at the size it really has:
+    one byte short of svd2_workspace_bytes is refused before anything runs,
+    and a buffer of exactly that size in another dtype gives the same bits as
+    the one the binding allocates."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    from tests.gpu_util import to_dev
+    n = 4099
+    dev = to_dev(to_trains(scaled_law(n, SEED_BASE + 51, cplx, dtype=np.float32), np.float32))
+    fl = _fp32_flags("queue")
+    need = S.svd2_workspace_bytes(n, fl)
+    assert need % 4 == 0
+    ref = [o.cpu() for o in S.svd2(dev, flags=fl)]
+    short = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.Svd2Error) as err:
+        S.svd2(dev, flags=fl, ws=short)
+    assert err.value.status == 6
+    exact = torch.empty(need // 4, dtype=torch.int32, device="cuda")
+    got = [o.cpu() for o in S.svd2(dev, flags=fl, ws=exact)]
+    for a, b in zip(ref, got):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("cplx", [False, True])
 def test_fp32_full_size_2_26_sampled(cplx):
