@@ -115,7 +115,10 @@ def _check(fn: str, st: int) -> None:
 
 
 def _nbytes(t) -> int:
-    """Size in bytes of a caller's device buffer (any dtype)."""
+    """Size in bytes of a caller's device buffer (any dtype); a host tensor
+    is refused, since the kernels would dereference its address."""
+    if not t.is_cuda:
+        raise ValueError("workspace buffers must be device tensors")
     return t.numel() * t.element_size()
 
 
@@ -253,6 +256,10 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
         out = [torch.empty(n, dtype=dt, device=trains[0].device) for _ in range(nout)]
     if len(out) != nout:
         raise ValueError(f"expected {nout} output trains")
+    for i, t in enumerate(out):
+        _like(t, f"output train {i}", dt, trains[0].device, n)
+    if nrescued is not None and (not nrescued.is_cuda or nrescued.element_size() != 4 or nrescued.numel() < 1):
+        raise ValueError("nrescued: expected a device tensor of 32-bit integers")
     ins = [t.data_ptr() for t in trains]
     outs = [t.data_ptr() for t in out]
     if nout == 3:
@@ -331,10 +338,19 @@ def kog_workspace_bytes(N: int, kind: str, flags: int = 0) -> int:
 def _kog_args(A):
     """A: (N, N) device tensor stored column-major (A.t() contiguous, or a
     Fortran-ordered view).  Returns N, lda, data pointer."""
+    if not A.is_cuda:
+        raise ValueError("the matrix must be a device tensor")
     N = A.shape[0]
     if A.dim() != 2 or A.shape[1] != N or A.stride(0) != 1:
         raise ValueError("A must be a square column-major device tensor (stride(0) == 1)")
     return N, A.stride(1), A.data_ptr()
+
+
+def _like(t, name: str, dtype, device, numel: int) -> None:
+    """A caller's output tensor must have the element type, device and size
+    the library will write (it cannot check them itself)."""
+    if t.dtype != dtype or t.device != device or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of at least {numel} elements on {device}")
 
 
 def kog_workspace(A, flags: int = 0):
@@ -381,6 +397,7 @@ def kog_sigma(A, out=None, ws=None, stream=None):
     N, lda, ptr = _kog_args(A)
     real = torch.float64 if k in "dz" else torch.float32
     out = torch.empty(N, dtype=real, device=A.device) if out is None else out
+    _like(out, "out", real, A.device, N)
     if ws is None:
         ws = torch.empty(max(int(_kog().kog_sigma_workspace_bytes(N, KOG_DTYPE[k])), 1), dtype=torch.uint8,
                          device=A.device)
@@ -405,10 +422,14 @@ def kog_svd(A, tol: float = 1e-14, max_sweeps: int = 40, U=None, V=None, sigma=N
         U = torch.empty((N, N), dtype=A.dtype, device=A.device).t()
     if V is None:
         V = torch.empty((N, N), dtype=A.dtype, device=A.device).t()
+    for X, name in ((U, "U"), (V, "V")):
+        if X.dtype != A.dtype or X.device != A.device or tuple(X.shape) != (N, N):
+            raise ValueError(f"{name}: expected an {N}x{N} {A.dtype} tensor on {A.device}")
     _, ldu, uptr = _kog_args(U)
     _, ldv, vptr = _kog_args(V)
     real = torch.float64 if k in "dz" else torch.float32
     sigma = torch.empty(N, dtype=real, device=A.device) if sigma is None else sigma
+    _like(sigma, "sigma", real, A.device, N)
     if ws is None:
         ws = torch.empty(kog_svd_workspace_bytes(N, k, flags), dtype=torch.uint8, device=A.device)
     sw, off = ctypes.c_int(), ctypes.c_double()

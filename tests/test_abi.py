@@ -275,3 +275,18 @@ def test_kog_sigma_argument_errors():
     assert call(100, A, 100, out, ws + 8, wsb) == 2       # misaligned workspace
     assert call(100, A, 100, A + 800, ws, wsb) == 3       # output inside the matrix
     assert call(100, A, 100, out, out + 256, wsb) == 3    # workspace overlaps the output
+
+
+def test_binding_refuses_host_tensors():
+    """The binding only hands device addresses to the library: host matrices,
+    trains and workspaces are refused before any library call."""
+    import torch
+    A = torch.zeros((8, 8), dtype=torch.float64).t()
+    for call in (lambda: S.kog_solve(A), lambda: S.kog_svd(A), lambda: S.kog_sigma(A),
+                 lambda: S.kog_batch_solve([A], 1e-14)):
+        with pytest.raises(ValueError, match="device tensor"):
+            call()
+    with pytest.raises(ValueError, match="device tensors"):
+        S.svd2([torch.zeros(16, dtype=torch.float64) for _ in range(4)])
+    with pytest.raises(ValueError, match="device tensors"):
+        S._nbytes(torch.zeros(16, dtype=torch.uint8))

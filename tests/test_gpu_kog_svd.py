@@ -134,6 +134,35 @@ def test_svd_order_1030_two_step_equals_one_step(kind):
     assert np.all(np.diff(s1) <= 0)
 
 
+def test_svd_caller_outputs_checked():
+    """U, V and sigma supplied by the caller must have A's order, element type
+    and device, since the library writes N x N and N elements of that type;
+    a mismatch raises before anything is launched and leaves A as it was.
+    The same holds for kog_sigma's and svd2's output tensors."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    N = 16
+    A = np.asfortranarray(kog_matrix(N, SEED_BASE + 370, cond=1e4))
+    G = _dev(A)
+    bad = [dict(U=torch.empty((N, N), dtype=torch.float32, device="cuda").t()),
+           dict(V=torch.empty((N - 2, N - 2), dtype=torch.float64, device="cuda").t()),
+           dict(sigma=torch.empty(N - 1, dtype=torch.float64, device="cuda")),
+           dict(sigma=torch.empty(N, dtype=torch.float32, device="cuda"))]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            S.kog_svd(G, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(G.cpu().numpy(), A)
+    with pytest.raises(ValueError):
+        S.kog_sigma(G, out=torch.empty(N - 1, dtype=torch.float64, device="cuda"))
+    trains = [torch.zeros(64, dtype=torch.float64, device="cuda") for _ in range(4)]
+    outs = [torch.empty(64, dtype=torch.float64, device="cuda") for _ in range(10)]
+    with pytest.raises(ValueError):
+        S.svd2(trains, out=outs + [torch.empty(32, dtype=torch.float64, device="cuda")])
+    with pytest.raises(ValueError):
+        S.svd2(trains, out=outs + [torch.empty(64, dtype=torch.float32, device="cuda")])
+
+
 @pytest.mark.slow
 def test_svd_full_order_4096():
     """The benchmark's SVD (order 4096, real FP64, sigma from 1 to 1e-12, tuned
