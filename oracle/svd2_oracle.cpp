@@ -211,6 +211,52 @@ template <class T> T scaling(const T *a, int ncomp, T *ah) {
 }
 
 /* ---------------------------------------------------------------------------
+ * Assembly of U and V, eq. (29) and its expansion (section 2.3), or eq. (31)
+ * with P.sine, then the row permutations P_r (U) and P_c (V).  Reads alpha
+ * (ca, mt), the angles phi and psi (tphi, cphi, tpsi, cpsi) and the phases of
+ * m; C = cos(alpha) cos(phi), t = -tan(alpha) tan(phi), tan(alpha) = -mt.
+ * V = cos(psi) P_c [[1, tan psi], [-d~ tan psi, d~]], d~ = conj(e12).
+ * ------------------------------------------------------------------------- */
+template <class T> void assemble_cplx(const Prim<T> &P, const Mid<T> &m, Res<T> &o) {
+  const T one = T(1);
+  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
+  Cx<T> w11 = {fmaT(m.dh.re, t, one), m.dh.im * t};
+  Cx<T> w21 = {fmaT(m.dh.re, m.tphi, ta), m.dh.im * m.tphi};
+  Cx<T> w12 = {fmaT(m.dh.re, ta, m.tphi), m.dh.im * ta};
+  Cx<T> w22 = {fmaT(m.mt, m.tphi, m.dh.re), m.dh.im};
+  Cx<T> p11 = cmul(m.d1, w11), p21 = cmul(m.d2, w21), p12 = cmul(m.d1, w12), p22 = cmul(m.d2, w22);
+  Cx<T> U[2][2] = {{{C * p11.re, C * p11.im}, {C * p12.re, C * p12.im}},
+                   {{-(C * p21.re), -(C * p21.im)}, {C * p22.re, C * p22.im}}};
+  if (P.sine) sine_u_cplx(sine_products(m.ca, m.mt, m.cphi, m.tphi), m.dh, m.d1, m.d2, U);
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); } /* P_r */
+  T ct = m.cpsi * m.tpsi;
+  Cx<T> V[2][2] = {{{m.cpsi, T(0)}, {ct, T(0)}},
+                   {{-(ct * m.e12.re), ct * m.e12.im}, {m.cpsi * m.e12.re, -(m.cpsi * m.e12.im)}}};
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); } /* P_c */
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) { o.u[i][j] = U[i][j]; o.v[i][j] = V[i][j]; }
+}
+
+/* the real case: the phases are the signs neg1, neg2, negt and dh = +-1 */
+template <class T> void assemble_real(const Prim<T> &P, const Mid<T> &m, Res<T> &o) {
+  const T one = T(1);
+  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
+  T dh = m.dh.re;
+  T w11 = fmaT(dh, t, one), w21 = fmaT(dh, m.tphi, ta), w12 = fmaT(dh, ta, m.tphi),
+    w22 = fmaT(m.mt, m.tphi, dh);
+  T U[2][2] = {{C * (m.neg1 ? -w11 : w11), C * (m.neg1 ? -w12 : w12)},
+               {-(C * (m.neg2 ? -w21 : w21)), C * (m.neg2 ? -w22 : w22)}};
+  if (P.sine) sine_u_real(sine_products(m.ca, m.mt, m.cphi, m.tphi), dh, m.neg1, m.neg2, U);
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); }
+  T ct = m.cpsi * m.tpsi;
+  T V[2][2] = {{m.cpsi, ct}, {m.negt ? ct : -ct, m.negt ? -m.cpsi : m.cpsi}};
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); }
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
+    o.u[i][j] = {U[i][j], T(0)};
+    o.v[i][j] = {V[i][j], T(0)};
+  }
+}
+
+/* ---------------------------------------------------------------------------
  * Complex case, one matrix.  a[8] = a11r,a11i,a21r,a21i,a12r,a12i,a22r,a22i.
  * ------------------------------------------------------------------------- */
 template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T> &m) {
@@ -259,24 +305,7 @@ template <class T> void zsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
   m.dh = phase(P, r22p, m.r22);
   /* triangular SVD, eqs. (13)-(17) */
   triangular_svd(P, m, o.smax, o.smin);
-  /* assembly of U and V, eq. (29) and its expansion (section 2.3).
-   * C = cos(alpha) cos(phi), t = -tan(alpha) tan(phi), tan(alpha) = -mt. */
-  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
-  Cx<T> w11 = {fmaT(m.dh.re, t, one), m.dh.im * t};
-  Cx<T> w21 = {fmaT(m.dh.re, m.tphi, ta), m.dh.im * m.tphi};
-  Cx<T> w12 = {fmaT(m.dh.re, ta, m.tphi), m.dh.im * ta};
-  Cx<T> w22 = {fmaT(m.mt, m.tphi, m.dh.re), m.dh.im};
-  Cx<T> p11 = cmul(m.d1, w11), p21 = cmul(m.d2, w21), p12 = cmul(m.d1, w12), p22 = cmul(m.d2, w22);
-  Cx<T> U[2][2] = {{{C * p11.re, C * p11.im}, {C * p12.re, C * p12.im}},
-                   {{-(C * p21.re), -(C * p21.im)}, {C * p22.re, C * p22.im}}};
-  if (P.sine) sine_u_cplx(sine_products(m.ca, m.mt, m.cphi, m.tphi), m.dh, m.d1, m.d2, U);
-  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); } /* P_r */
-  /* V = cos(psi) P_c [[1, tan psi], [-d~ tan psi, d~]], d~ = conj(e12) */
-  T ct = m.cpsi * m.tpsi;
-  Cx<T> V[2][2] = {{{m.cpsi, T(0)}, {ct, T(0)}},
-                   {{-(ct * m.e12.re), ct * m.e12.im}, {m.cpsi * m.e12.re, -(m.cpsi * m.e12.im)}}};
-  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); } /* P_c */
-  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) { o.u[i][j] = U[i][j]; o.v[i][j] = V[i][j]; }
+  assemble_cplx(P, m, o);
   o.s = m.s;
 }
 
@@ -324,21 +353,7 @@ template <class T> void dsvd2_one(const Prim<T> &P, const T *a, Res<T> &o, Mid<T
   m.dh = {m.negh ? -one : one, T(0)};
   m.r22 = std::fabs(r22p);
   triangular_svd(P, m, o.smax, o.smin);
-  T C = m.ca * m.cphi, ta = -m.mt, t = m.mt * m.tphi;
-  T dh = m.dh.re;
-  T w11 = fmaT(dh, t, one), w21 = fmaT(dh, m.tphi, ta), w12 = fmaT(dh, ta, m.tphi),
-    w22 = fmaT(m.mt, m.tphi, dh);
-  T U[2][2] = {{C * (m.neg1 ? -w11 : w11), C * (m.neg1 ? -w12 : w12)},
-               {-(C * (m.neg2 ? -w21 : w21)), C * (m.neg2 ? -w22 : w22)}};
-  if (P.sine) sine_u_real(sine_products(m.ca, m.mt, m.cphi, m.tphi), dh, m.neg1, m.neg2, U);
-  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); }
-  T ct = m.cpsi * m.tpsi;
-  T V[2][2] = {{m.cpsi, ct}, {m.negt ? ct : -ct, m.negt ? -m.cpsi : m.cpsi}};
-  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); }
-  for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) {
-    o.u[i][j] = {U[i][j], T(0)};
-    o.v[i][j] = {V[i][j], T(0)};
-  }
+  assemble_real(P, m, o);
   o.s = m.s;
 }
 
