@@ -113,7 +113,7 @@ def svd2(A: np.ndarray, dtype=np.float64, policy: str = "mirror", backscale: str
         f(n, pin, pout, pol, bs, int(rescue), flagged.ctypes.data, nthreads)
     else:
         raise ValueError(dtype)
-    # rescue: False/0 none, True/1 FP64 tail, 2 sigma quotient only
+    # rescue: False/0 none, True/1 FP64 tail, 2 sigma quotient only, 3 FP64 triangle + FP32 assembly
     k = 16 if cplx else 8
     return dict(U=join(outs[0:k // 2], cplx), V=join(outs[k // 2:k], cplx),
                 smax=outs[k], smin=outs[k + 1], s=outs[k + 2], flagged=flagged,

@@ -430,12 +430,14 @@ template <bool CPLX> void rescue_sigma(const Mid<float> &m, Res<float> &o) {
   o.smin = (float)(ad / (double)o.smax);
 }
 
-template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o, bool sine = false) {
-  Prim<double> P{ORACLE_MIRROR};
+/* The FP64 half shared by the two rescues below: r'_22 from det(A^), D^ of
+   eq. (9) and the triangular SVD of eqs. (13)-(17) in FP64, from the FP32
+   r11, r12, alpha and phases of m.  w receives mt, ca, the angles and D^. */
+template <bool CPLX> void fp64_triangle(const Prim<double> &P, const Mid<float> &m, Mid<double> &w,
+                                        double &smax, double &smin) {
   const double one = 1.0;
   Cx<double> det = det_fp64<CPLX>(m);
   double sgn = (m.c != m.r) ? -one : one;
-  Mid<double> w{};
   w.r11 = m.r11; w.r12 = m.r12; w.mt = m.mt; w.ca = m.ca;
   double r22p_re, r22p_im;
   if (CPLX) {
@@ -454,8 +456,36 @@ template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o, bool s
     w.r22 = std::fabs(r22p_re);
     w.dh = {w.negh ? -one : one, 0.0};
   }
-  double smax, smin;
   triangular_svd(P, w, smax, smin);
+}
+
+/* The middle rescue: FP64 only up to the triangular SVD (the steps whose
+   stability the near-singular case needs: r'_22 and with it sigma'_min, and
+   the rotation angles phi and psi), whose tangents, cosines and phase d^ are
+   rounded to FP32; U and V are then assembled in FP32 by the plain lane's
+   formulas, with the FP32 alpha and phases. */
+template <bool CPLX> void rescue_tri(const Mid<float> &m, Res<float> &o, bool sine = false) {
+  Prim<double> P{ORACLE_MIRROR};
+  Mid<double> w{};
+  double smax, smin;
+  fp64_triangle<CPLX>(P, m, w, smax, smin);
+  Mid<float> f = m;
+  f.tphi = (float)w.tphi; f.cphi = (float)w.cphi;
+  f.tpsi = (float)w.tpsi; f.cpsi = (float)w.cpsi;
+  f.dh = {(float)w.dh.re, (float)w.dh.im};
+  f.negh = w.negh;
+  Prim<float> P32{ORACLE_MIRROR, sine};
+  if (CPLX) assemble_cplx(P32, f, o); else assemble_real(P32, f, o);
+  o.smax = (float)smax;
+  o.smin = (float)smin;
+}
+
+template <bool CPLX> void rescue_fp64(const Mid<float> &m, Res<float> &o, bool sine = false) {
+  Prim<double> P{ORACLE_MIRROR};
+  const double one = 1.0;
+  Mid<double> w{};
+  double smax, smin;
+  fp64_triangle<CPLX>(P, m, w, smax, smin);
   double C = w.ca * w.cphi, ta = -w.mt, t = w.mt * w.tphi;
   Cx<double> U[2][2], V[2][2];
   double ct = w.cpsi * w.tpsi;
@@ -548,6 +578,7 @@ void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int 
     if constexpr (std::is_same<T, float>::value) {
       if (rescue && near_degenerate(o.smax, o.smin)) {
         if (rescue == 2) rescue_sigma<CPLX>(m, o);
+        else if (rescue == 3) rescue_tri<CPLX>(m, o, P.sine);
         else rescue_fp64<CPLX>(m, o, P.sine);
         fl = true;
       }
@@ -680,6 +711,8 @@ int oracle_trace_s(const float *a, int cplx, int policy, int rescue, double *tra
   if (rescue && near_degenerate(o.smax, o.smin)) {
     if (rescue == 2) {
       if (cplx) rescue_sigma<true>(m, o); else rescue_sigma<false>(m, o);
+    } else if (rescue == 3) {
+      if (cplx) rescue_tri<true>(m, o); else rescue_tri<false>(m, o);
     } else {
       if (cplx) rescue_fp64<true>(m, o); else rescue_fp64<false>(m, o);
     }

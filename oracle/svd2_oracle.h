@@ -52,7 +52,10 @@ enum { ORACLE_BS_NONE = 0, /* write sigma' and s (the paper's default)          
  * rescue (float only): 0 = plain FP32 algorithm; 1 = recompute R's (2,2)
  * entry from det(A^) in FP64 on lanes with smin' < 2^-20 smax', then run the
  * triangular SVD and the assembly of U, V in FP64 for those lanes; 2 = on
- * those lanes only smin' = |det(A^)| / smax' in FP64 (U, V stay FP32).
+ * those lanes only smin' = |det(A^)| / smax' in FP64 (U, V stay FP32); 3 = on
+ * those lanes R's (2,2) entry, its phase and the triangular SVD in FP64, whose
+ * tangents, cosines, phase and sigma' are rounded to FP32, and U, V assembled
+ * in FP32 from them by the plain formulas.
  * flagged (optional, may be NULL): per-lane 0/1 marks of rescued lanes.
  * nthreads <= 0: use the OpenMP default.  Returns 0. */
 int oracle_dsvd2(size_t n, const double *const *in, double *const *out,

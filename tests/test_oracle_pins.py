@@ -386,7 +386,7 @@ def test_fp32_closed_form_exhaustive_real():
         assert abs(smin - ns) / xs <= 4 * EPS32
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_fp32_rescue_restores_relative_sigma_min(cplx, mode):
     """On near-singular FP32 inputs the plain FP32 sigma_min is only accurate
@@ -419,7 +419,7 @@ def test_fp32_rescue_restores_relative_sigma_min(cplx, mode):
         assert met[key].max() <= 16 * EPS32, (key, met[key].max() / EPS32)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_fp32_scaled_law_bounds(cplx, mode):
     A = scaled_law(20000, 24, cplx, dtype=np.float32)
@@ -433,6 +433,40 @@ def test_fp32_scaled_law_bounds(cplx, mode):
     s32 = np.array([float(backscaled(r, j)[0]) for j in range(0, 20000, 10)])
     nz = s64 > 0
     assert np.all(np.abs(s32[nz] - s64[nz]) <= 4 * EPS32 * s64[nz])
+
+
+@pytest.mark.parametrize("form", ["tangent", "sine"])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fp32_middle_rescue_against_fp64_tail(cplx, form):
+    """The middle rescue (mode 3) runs the same FP64 triangular SVD as the
+    FP64 tail (mode 1) and only assembles U, V in FP32 from its rounded
+    angles: sigma' and s must be bitwise mode 1's, U and V within 4 eps32 of
+    mode 1's (assembled in FP64, rounded once), and every unflagged lane
+    bitwise the plain FP32 result.  Swapped or unrounded angles, a dropped
+    phase or the FP32 r'_22 in place of the FP64 one break one of these."""
+    from workloads import to_trains
+    rng = np.random.default_rng(29)
+    n = 4000
+    u = rng.standard_normal((2, n)) + (1j * rng.standard_normal((2, n)) if cplx else 0)
+    v = rng.standard_normal((2, n)) + (1j * rng.standard_normal((2, n)) if cplx else 0)
+    near = np.stack([u[0] * np.conj(v[0]), u[1] * np.conj(v[0]), u[0] * np.conj(v[1]),
+                     u[1] * np.conj(v[1])]) + 3e-8 * rng.standard_normal((4, n))
+    dt = np.complex64 if cplx else np.float32
+    A = np.concatenate([near.astype(dt), scaled_law(n, 30, cplx, dtype=np.float32)], axis=1)
+    tr = to_trains(A, np.float32)
+    o0, f0 = O.run_trains(tr, cplx, np.float32, rescue=0, form=form)
+    o1, f1 = O.run_trains(tr, cplx, np.float32, rescue=1, form=form)
+    o3, f3 = O.run_trains(tr, cplx, np.float32, rescue=3, form=form)
+    assert np.array_equal(f1, f3) and f3.sum() > n // 2
+    k = 16 if cplx else 8
+    for i in range(k, k + 3):
+        assert np.array_equal(o1[i], o3[i], equal_nan=True), i
+    fl = f3.astype(bool)
+    for i in range(k):
+        d = np.abs(o3[i][fl].astype(np.float64) - o1[i][fl].astype(np.float64))
+        assert d.max() <= 4 * EPS32, (i, d.max() / EPS32)
+        assert np.array_equal(o3[i][~fl], o0[i][~fl]), i
+    assert any(not np.array_equal(o3[i][fl], o1[i][fl]) for i in range(k))  # a different assembly
 
 
 # ---------------------------------------------------------------------------
