@@ -463,7 +463,8 @@ def main():
 
     variants = [args.only] if args.only else ["z", "d", "s", "c"]
     F, NU = S.SVD2_RESCUE_FP64, S.SVD2_NO_UV
-    fp32 = {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA, "none": 0,
+    fp32 = {"RESCUE_FP64": F, "RESCUE_FP64|SIGMA": F | S.SVD2_RESCUE_SIGMA,
+            "RESCUE_FP64|TRI": F | S.SVD2_RESCUE_TRI, "none": 0,
             "RESCUE_FP64|SIGMA|NO_UV": F | S.SVD2_RESCUE_SIGMA | NU}
     SF = S.SVD2_SINE_FORM
     flagsets = {"d": {"": 0, "NO_UV": NU, "SINE_FORM": SF}, "z": {"": 0, "NO_UV": NU, "SINE_FORM": SF},
@@ -491,6 +492,8 @@ def main():
                 key = f"{v}{tag}_nouv"
             elif desc == "SINE_FORM":
                 key = f"{v}{tag}_sine"
+            elif "TRI" in desc:
+                key = f"{v}{tag}_tri"
             else:
                 key = f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
             results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv)

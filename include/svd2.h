@@ -79,6 +79,14 @@ enum {
                                product of the singular values is |det|); U, V and
                                sigma'_max keep their FP32 values.  Same relative
                                accuracy of sigma_min for a fraction of the FP64 work */
+  /* with RESCUE_FP64, instead of SVD2_RESCUE_SIGMA: on flagged lanes FP64 is
+     used only up to the triangular SVD -- the (2,2) entry of R from det(A^)
+     (and with it sigma'_min), its phase D^ (eq. (9)) and the rotation angles
+     phi, psi with sigma' (eqs. (13)-(17)) -- whose tangents, cosines and phase
+     are rounded to FP32 and assembled into U and V in FP32 by eq. (29) (or
+     eq. (31)), as on an unflagged lane.  sigma' and s are bitwise those of the
+     FP64 tail; U and V are within a few FP32 ulps of them. */
+  SVD2_RESCUE_TRI = 128,
   /* all four entry points: singular values only, the counterpart of the
      values-only routine of section 2.  The last phase of section 4, the
      assembly of U and V (eq. (29)), is skipped; the U and V pointers may be
@@ -142,7 +150,8 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 
 /* FP32 form (the paper notes the method carries over to single precision,
    section 1; the tan 2phi clamp becomes sqrt(FLT_MAX), section 7).
-   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA]
+   flags: SVD2_BACKSCALE_* | SVD2_RESCUE_FP64 [| SVD2_RESCUE_QUEUE] [| SVD2_RESCUE_SIGMA or
+   SVD2_RESCUE_TRI]
    [| SVD2_NO_UV] [| SVD2_SINE_FORM] (with the FP64 tail rescue the rescued lanes are
    assembled in FP64 by the same form).
    ws / ws_bytes: device workspace, at least svd2_workspace_bytes(n, flags)

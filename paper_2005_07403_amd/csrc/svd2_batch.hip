@@ -90,7 +90,8 @@ __device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
 
 // ---------------------------------------------------------------------------
 // Main batched kernel.  RESCUE: 0 plain, 1 in-place FP64 rescue, 2 queue the
-// flagged lanes for svd2_rescue_kernel.  UV = false: singular values only; U
+// flagged lanes for svd2_rescue_kernel, 3 and 4 the in-place sigma-quotient
+// and middle rescues.  UV = false: singular values only; U
 // and V are neither stored nor, since nothing uses them, computed (the
 // assembly of eq. (29) and its FP64 counterpart in the rescue drop out).
 // ---------------------------------------------------------------------------
@@ -264,10 +265,12 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
                      uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
   int bs = (int)(flags & 3u);
   bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE,
-       sigma = flags & SVD2_RESCUE_SIGMA, uv = !(flags & SVD2_NO_UV), sine = flags & SVD2_SINE_FORM;
+       sigma = flags & SVD2_RESCUE_SIGMA, tri = flags & SVD2_RESCUE_TRI, uv = !(flags & SVD2_NO_UV),
+       sine = flags & SVD2_SINE_FORM;
   if (!resc) return launch_uv<T, CPLX, 0>(uv, sine, n, a, bs, nullptr, nullptr, nullptr, st);
   if (!queue) {
     if (sigma) return launch_uv<T, CPLX, 3>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
+    if (tri) return launch_uv<T, CPLX, 4>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
     return launch_uv<T, CPLX, 1>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
   }
   if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
@@ -282,6 +285,7 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
   svd2_status s1 = launch_uv<T, CPLX, 2>(uv, sine, n, a, bs, nresc, q, qcount, st);
   if (s1 != SVD2_OK) return s1;
   if (sigma) launch_rescue<T, CPLX, 3>(uv, sine, a, bs, q, qcount, st);
+  else if (tri) launch_rescue<T, CPLX, 4>(uv, sine, a, bs, q, qcount, st);
   else launch_rescue<T, CPLX, 1>(uv, sine, a, bs, q, qcount, st);
   return hip_status(hipGetLastError());
 }
@@ -372,8 +376,10 @@ svd2_status zsvd2_batch(size_t n, const zsvd2_args *p, unsigned flags, hipStream
 }
 
 static bool bad_fp32_flags(unsigned flags) {
-  if (flags & ~(31u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return true;
-  if ((flags & (SVD2_RESCUE_QUEUE | SVD2_RESCUE_SIGMA)) && !(flags & SVD2_RESCUE_FP64)) return true;
+  if (flags & ~(31u | SVD2_NO_UV | SVD2_SINE_FORM | SVD2_RESCUE_TRI) || bad_bs_flags(flags)) return true;
+  if ((flags & (SVD2_RESCUE_QUEUE | SVD2_RESCUE_SIGMA | SVD2_RESCUE_TRI)) && !(flags & SVD2_RESCUE_FP64))
+    return true;
+  if ((flags & SVD2_RESCUE_SIGMA) && (flags & SVD2_RESCUE_TRI)) return true;
   return false;
 }
 

@@ -382,14 +382,38 @@ __device__ __forceinline__ void cplx_rescue_sigma(CplxRes<float> &o) {
   o.smin = (float)(hyp(det.re, det.im) / (double)o.smax);
 }
 
-template <bool SINE = false> __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
+// the FP64 half of the two rescues below: r'_22 from det(A^), D^ (eq. (9))
+// and the triangular SVD (eqs. (13)-(17)) in FP64
+__device__ __forceinline__ Tri<double> real_triangle64(const RealRes<float> &o, bool &negh) {
   double det = (double)o.ah11 * (double)o.ah22 - (double)o.ah12 * (double)o.ah21;
   bool neg = (o.c != o.r) != ((o.neg1 != o.neg2) != o.negt);
   double r11 = o.r11;
   double r22p = flip(neg, det / r11);
-  bool negh = vsignbit(r22p);
+  negh = vsignbit(r22p);
   double r22 = vabs(r22p);
-  Tri<double> t = tri_svd(r11, (double)o.r12, r22);
+  return tri_svd(r11, (double)o.r12, r22);
+}
+
+__device__ __forceinline__ Tri<float> round_tri(const Tri<double> &t) {
+  return Tri<float>{(float)t.tphi, (float)t.cphi, (float)t.tpsi, (float)t.cpsi, (float)t.smax, (float)t.smin};
+}
+
+// the middle rescue: FP64 up to the triangular SVD, its angles rounded to
+// FP32, U and V by the FP32 assembly (the plain lane's formulas)
+template <bool SINE = false> __device__ __forceinline__ void real_rescue_tri(RealRes<float> &o) {
+  bool negh;
+  const Tri<float> t = round_tri(real_triangle64(o, negh));
+  float u[4], v[4];
+  real_assemble<float, float, SINE>(t, o.mt, o.ca, negh, o.neg1, o.neg2, o.negt, o.c, o.r, u, v);
+  o.u11 = u[0]; o.u21 = u[1]; o.u12 = u[2]; o.u22 = u[3];
+  o.v11 = v[0]; o.v21 = v[1]; o.v12 = v[2]; o.v22 = v[3];
+  o.smax = t.smax;
+  o.smin = t.smin;
+}
+
+template <bool SINE = false> __device__ __forceinline__ void real_rescue(RealRes<float> &o) {
+  bool negh;
+  const Tri<double> t = real_triangle64(o, negh);
   float u[4], v[4];
   real_assemble<float, double, SINE>(t, (double)o.mt, (double)o.ca, negh, o.neg1, o.neg2, o.negt, o.c,
                                      o.r, u, v);
@@ -399,7 +423,7 @@ template <bool SINE = false> __device__ __forceinline__ void real_rescue(RealRes
   o.smin = (float)t.smin;
 }
 
-template <bool SINE = false> __device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
+__device__ __forceinline__ Tri<double> cplx_triangle64(const CplxRes<float> &o, Cx<double> &dh) {
   Cx<double> det = cplx_det(o);
   double sgn = (o.c != o.r) ? -1.0 : 1.0;
   Cx<double> d1 = {o.d1.re, o.d1.im}, d2 = {o.d2.re, o.d2.im}, e = {o.e12.re, o.e12.im};
@@ -408,8 +432,23 @@ template <bool SINE = false> __device__ __forceinline__ void cplx_rescue(CplxRes
   double r11 = o.r11;
   Cx<double> r22p = {sgn * (q.re / r11), sgn * (q.im / r11)};
   double r22 = hyp(r22p.re, r22p.im);
-  Cx<double> dh = phase(r22p, r22);
-  Tri<double> t = tri_svd(r11, (double)o.r12, r22);
+  dh = phase(r22p, r22);
+  return tri_svd(r11, (double)o.r12, r22);
+}
+
+template <bool SINE = false> __device__ __forceinline__ void cplx_rescue_tri(CplxRes<float> &o) {
+  Cx<double> dh;
+  const Tri<float> t = round_tri(cplx_triangle64(o, dh));
+  const Cx<float> dhf = {(float)dh.re, (float)dh.im};
+  cplx_assemble<float, float, SINE>(t, o.mt, o.ca, dhf, o.d1, o.d2, o.e12, o.c, o.r, o.u, o.v);
+  o.smax = t.smax;
+  o.smin = t.smin;
+}
+
+template <bool SINE = false> __device__ __forceinline__ void cplx_rescue(CplxRes<float> &o) {
+  Cx<double> dh;
+  const Tri<double> t = cplx_triangle64(o, dh);
+  Cx<double> d1 = {o.d1.re, o.d1.im}, d2 = {o.d2.re, o.d2.im}, e = {o.e12.re, o.e12.im};
   cplx_assemble<float, double, SINE>(t, (double)o.mt, (double)o.ca, dh, d1, d2, e, o.c, o.r, o.u, o.v);
   o.smax = (float)t.smax;
   o.smin = (float)t.smin;
@@ -437,7 +476,8 @@ template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &sm
 // ---------------------------------------------------------------------------
 // one matrix: inputs x[NIN] -> outputs y[NOUT]; returns the rescue flag
 // RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only,
-// 3 in place (FP64 sigma_min quotient only)
+// 3 in place (FP64 sigma_min quotient only), 4 in place (FP64 up to the
+// triangular SVD, FP32 assembly)
 // ---------------------------------------------------------------------------
 template <class T, bool CPLX, int RESCUE, bool SINE = false>
 __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
@@ -451,6 +491,8 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
         if (flagged) real_rescue<SINE>(o);
       } else if constexpr (RESCUE == 3) {
         if (flagged) real_rescue_sigma(o);
+      } else if constexpr (RESCUE == 4) {
+        if (flagged) real_rescue_tri<SINE>(o);
       }
     }
     y[0] = o.u11; y[1] = o.u21; y[2] = o.u12; y[3] = o.u22;
@@ -467,6 +509,8 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
         if (flagged) cplx_rescue<SINE>(o);
       } else if constexpr (RESCUE == 3) {
         if (flagged) cplx_rescue_sigma(o);
+      } else if constexpr (RESCUE == 4) {
+        if (flagged) cplx_rescue_tri<SINE>(o);
       }
     }
 #pragma unroll

@@ -24,6 +24,7 @@ SVD2_RESCUE_QUEUE = 8
 SVD2_RESCUE_SIGMA = 16
 SVD2_NO_UV = 32
 SVD2_SINE_FORM = 64
+SVD2_RESCUE_TRI = 128
 
 _P = ctypes.c_void_p
 REAL_IN = ["a11", "a21", "a12", "a22"]

@@ -113,6 +113,11 @@ def test_fp32_queue_needs_rescue_and_workspace():
     assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_QUEUE) == 4
     assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_SIGMA) == 4
     assert _call(S.dsvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_SIGMA) == 4
+    # the middle rescue: needs RESCUE_FP64, excludes RESCUE_SIGMA, FP32 only
+    assert _call(S.ssvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_TRI) == 4
+    assert _call(S.ssvd2_batch, 10, ins, outs,
+                 flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA | S.SVD2_RESCUE_TRI) == 4
+    assert _call(S.dsvd2_batch, 10, ins, outs, flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_TRI) == 4
     # queue without workspace
     assert _call(S.ssvd2_batch, 10, ins, outs,
                  flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE) == 1

@@ -55,7 +55,7 @@ def test_tangent_and_sine_form_accuracy(cplx, law):
     print(f"tangent smaller / sine smaller: rho {wins[0]}, delta {wins[1]}, eta {wins[2]}")
 
 
-@pytest.mark.parametrize("mode", ["none", "fp64_tail", "sigma_quotient"])
+@pytest.mark.parametrize("mode", ["none", "fp64_tail", "sigma_quotient", "fp64_triangle"])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_fp32_form_error_against_fp64(cplx, mode):
     """The FP32 form on the GPU against the FP64 oracle run on the exact
@@ -79,7 +79,8 @@ def test_fp32_form_error_against_fp64(cplx, mode):
     A = scaled_law(n, SEED_BASE + 950 + (1 if cplx else 0), cplx, dtype=np.float32)
     tr32 = to_trains(A, np.float32)
     flags = {"none": 0, "fp64_tail": S.SVD2_RESCUE_FP64,
-             "sigma_quotient": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA}[mode]
+             "sigma_quotient": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA,
+             "fp64_triangle": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_TRI}[mode]
     dev = [torch.from_numpy(t).cuda() for t in tr32]
     out = [o.cpu().numpy() for o in S.svd2(dev, flags=flags)]
     torch.cuda.synchronize()

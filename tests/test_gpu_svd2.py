@@ -258,7 +258,7 @@ def test_complex_full_size_2_24():
 # FP32 form and the FP64 rescue
 # ---------------------------------------------------------------------------
 
-RESCUE_MODES = ["plain", "inplace", "queue", "sigma", "sigma_queue"]
+RESCUE_MODES = ["plain", "inplace", "queue", "sigma", "sigma_queue", "tri", "tri_queue"]
 
 
 def _fp32_flags(mode):
@@ -266,11 +266,15 @@ def _fp32_flags(mode):
     return {"plain": 0, "inplace": S.SVD2_RESCUE_FP64,
             "queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE,
             "sigma": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA,
-            "sigma_queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA | S.SVD2_RESCUE_QUEUE}[mode]
+            "sigma_queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_SIGMA | S.SVD2_RESCUE_QUEUE,
+            "tri": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_TRI,
+            "tri_queue": S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_TRI | S.SVD2_RESCUE_QUEUE}[mode]
 
 
 def _oracle_rescue(mode):
-    return 0 if mode == "plain" else (2 if mode.startswith("sigma") else 1)
+    if mode == "plain":
+        return 0
+    return 2 if mode.startswith("sigma") else (3 if mode.startswith("tri") else 1)
 
 
 @pytest.mark.parametrize("cplx", [False, True])
