@@ -6,10 +6,13 @@ whose real and imaginary parts are +-m 2^e (m ~ U[1,2), e ~ U{-1000..1000})
 with 1 % special lanes, in SoA layout resident in HBM.  One step = one
 zsvd2_batch call over the whole batch.  value = SVDs per second.
 
-The same line carries the other forms of the metric (real FP64, real and
-complex FP32 with the FP64 rescue, at n = 2^24; the Kogbetliantz solver when
-built), the roofline of the dominant kernel measured with HIP events on the
-launch stream, and the CPU oracle timed on this host as a baseline.
+The same line carries the other forms of the metric (real FP64; the
+singular-values-only and sine-form variants; real and complex FP32 without a
+rescue and with each FP64 rescue -- the FP64 tail, the sigma quotient and the
+FP64 triangle -- at n = 2^24 and at n = 2^26; the Kogbetliantz solver, its SVD
+with U and V and the uneven batch), the roofline of the dominant kernel
+measured with HIP events on the launch stream, and the CPU oracle timed on
+this host as a baseline.
 """
 from __future__ import annotations
 
