@@ -6,13 +6,18 @@ whose real and imaginary parts are +-m 2^e (m ~ U[1,2), e ~ U{-1000..1000})
 with 1 % special lanes, in SoA layout resident in HBM.  One step = one
 zsvd2_batch call over the whole batch.  value = SVDs per second.
 
-The same line carries the other forms of the metric (real FP64; the
-singular-values-only and sine-form variants; real and complex FP32 without a
-rescue and with each FP64 rescue -- the FP64 tail, the sigma quotient and the
-FP64 triangle -- at n = 2^24 and at n = 2^26; the Kogbetliantz solver, its SVD
-with U and V and the uneven batch), the roofline of the dominant kernel
-measured with HIP events on the launch stream, and the CPU oracle timed on
-this host as a baseline.
+The same line carries the other forms of the metric, one entry each
+([SVDs/s, fraction of 8 TB/s, fraction of the VALU issue peak]): real FP64;
+the singular-values-only and sine-form variants; real and complex FP32
+without a rescue and with each FP64 rescue -- the FP64 tail, the sigma
+quotient and the FP64 triangle -- at n = 2^24 and at n = 2^26, with the
+fraction of lanes each rescue took.  Then the Kogbetliantz solver (sweeps/s of
+each driver, a full solve, the SVD with U and V) and the uneven batch, the
+roofline of the dominant kernel measured with HIP events on the launch
+stream, and the CPU oracle timed on this host as a baseline, together with a
+comparison of the GPU's outputs with the oracle's on a sample of lanes.  The
+line stays under 4 KB; the full result (every launch figure, every problem of
+the uneven batch) goes to stderr before it, and to --detail-out.
 """
 from __future__ import annotations
 
@@ -62,14 +67,16 @@ def make_inputs(variant: str, n: int, seed_off: int = 1):
     return to_trains(A, dtype)
 
 
-def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
+def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets, sample=None):
     """Time `steps` batched calls on inputs resident in HBM, once per flag set
     in `flagsets` (same inputs).  Returns {flags: dict} with the wall-clock
     time of the timed region and the per-launch kernel time from HIP events
     recorded on the launch stream; the memory-pattern probe (same loads and
     stores, no arithmetic) is timed the same way under key 'pattern', and
     under 'pattern_nouv' for the singular-values-only pattern when a flag set
-    has SVD2_NO_UV."""
+    has SVD2_NO_UV.  FP32 flag sets with a rescue also get the count of
+    rescued lanes (one extra call); with `sample` (lane indices) the outputs
+    of the first flag set on those lanes come back as host arrays."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     S.svd2_set_launch_kind(variant, *DEFAULT_LAUNCH[variant])
@@ -107,6 +114,7 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
         t1 = time.perf_counter()
         return dict(n=n, wall_s=t1 - t0, kernel_ms=[a.elapsed_time(b) for a, b in ev])
 
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
     for flags in flagsets:
         ws = None
         wsb = S.svd2_workspace_bytes(n, flags) if dev[0].dtype == torch.float32 else 0
@@ -114,10 +122,24 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets):
             ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
         o = sig if flags & S.SVD2_NO_UV else out
         res[flags] = timed(lambda: S.svd2(dev, flags=flags, out=o, ws=ws))
+        if flags & S.SVD2_RESCUE_FP64:
+            # one more call, outside the timed region, counting the rescued lanes
+            cnt.zero_()
+            S.svd2(dev, flags=flags, out=o, ws=ws, nrescued=cnt)
+            res[flags]["rescued"] = int(cnt.item())
+    if sample is not None:
+        # outputs of the default call on a sample of lanes, for the comparison
+        # with the oracle in the CPU-baseline leg
+        wsb = S.svd2_workspace_bytes(n, flagsets[0]) if dev[0].dtype == torch.float32 else 0
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda") if wsb else None
+        S.svd2(dev, flags=flagsets[0], out=out, ws=ws)
+        idx = torch.from_numpy(sample).cuda()
+        res["sample_out"] = [o.index_select(0, idx).cpu().numpy() for o in out]
+        res["sample_flags"] = flagsets[0]
     res["pattern"] = timed(lambda: S.svd2_stream_probe(variant, dev, out))
     if any(f & S.SVD2_NO_UV for f in flagsets):
         res["pattern_nouv"] = timed(lambda: S.svd2_stream_probe(variant + "_nouv", dev, sig))
-    del dev, out
+    del dev, out, cnt
     torch.cuda.empty_cache()
     return res
 
@@ -127,11 +149,7 @@ def cpu_baseline(variant: str, trains_np, budget_s: float = 12.0):
     import oracle.oracle as O
     cplx = len(trains_np) == 8
     dtype = trains_np[0].dtype
-    nthreads = os.cpu_count() or 1
-    try:
-        nthreads = len(os.sched_getaffinity(0))
-    except AttributeError:
-        pass
+    nthreads = host_threads()
     n = trains_np[0].shape[0]
     reps, t_total = 0, 0.0
     while t_total < budget_s and reps < 50:
@@ -143,6 +161,75 @@ def cpu_baseline(variant: str, trains_np, budget_s: float = 12.0):
     return dict(value=reps * n / t_total, unit="SVDs/s", cores=nthreads, kind="oracle",
                 sample=f"{reps} pass(es) over the same {n}-matrix batch "
                        f"({'complex' if cplx else 'real'} {dtype.name}), {t_total:.1f} s")
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def rescue_mode(flags: int) -> int:
+    """the oracle's rescue argument for an FP32 flag set: 0 none, 1 the FP64
+    tail, 2 the sigma quotient, 3 the FP64 triangle"""
+    if not flags & 4:
+        return 0
+    return 2 if flags & 16 else (3 if flags & 128 else 1)
+
+
+def oracle_check(ins, gpu_out, flags: int) -> dict:
+    """The GPU's outputs on a sample of lanes beside the oracle's on the same
+    lanes: s compared bitwise, sigma'_max and sigma'_min in ulps, U and V in
+    eps (absolute; their entries are bounded by one), the count of lanes equal
+    in every bit, and the accuracy of the GPU's results by eqs. (33)-(35)
+    (rho, delta, eta computed by the oracle in binary128; maxima in eps of the
+    element type)."""
+    import oracle.oracle as O
+    cplx = len(ins) == 8
+    dtype = ins[0].dtype
+    it = np.int64 if dtype == np.float64 else np.int32
+    outs, _ = O.run_trains(ins, cplx, dtype, policy="mirror", rescue=rescue_mode(flags),
+                           nthreads=host_threads())
+    k = 16 if cplx else 8
+    eps = float(np.finfo(dtype).eps)
+
+    def ulps(a, b):
+        ia, ib = a.view(it).astype(np.int64), b.view(it).astype(np.int64)
+        m = np.int64((1 << (8 * a.itemsize - 1)) - 1)
+        ia = np.where(ia < 0, -(ia & m), ia)
+        ib = np.where(ib < 0, -(ib & m), ib)
+        return int(np.max(np.abs(ia - ib), initial=0))
+
+    same = np.ones(ins[0].shape[0], dtype=bool)
+    for g, o in zip(gpu_out, outs):
+        same &= (g.view(it) == o.view(it)) | ((g == 0) & (o == 0))
+    met = O.metrics(ins, gpu_out, cplx, nthreads=host_threads())
+    uv = max(float(np.max(np.abs(gpu_out[i].astype(np.float64) - outs[i]))) for i in range(k))
+    return {"lanes": int(ins[0].shape[0]), "bitwise_lanes": int(same.sum()),
+            "s_equal": bool(np.array_equal(gpu_out[k + 2].view(it), outs[k + 2].view(it))),
+            "smax_ulp": ulps(gpu_out[k], outs[k]), "smin_ulp": ulps(gpu_out[k + 1], outs[k + 1]),
+            "uv_max_abs_eps": uv / eps,
+            "rho_eps": float(np.nanmax(met["rho"])) / eps, "delta_eps": float(np.nanmax(met["delta"])) / eps,
+            "eta_eps": float(np.nanmax(met["eta"])) / eps}
+
+
+def cpu_upcast(trains32, budget_s: float = 1.5) -> dict:
+    """The FP64 oracle on the exact FP64 upcast of an FP32 batch (a leading
+    sample), on every host core: what a CPU would take to reach the FP32
+    form's results through FP64."""
+    import oracle.oracle as O
+    cplx = len(trains32) == 8
+    n = min(trains32[0].shape[0], 1 << 20)
+    sub = [t[:n].astype(np.float64) for t in trains32]
+    th = host_threads()
+    reps, el = 0, 0.0
+    while el < budget_s and reps < 50:
+        t0 = time.perf_counter()
+        O.run_trains(sub, cplx, np.float64, policy="mirror", nthreads=th)
+        el += time.perf_counter() - t0
+        reps += 1
+    return {"SVDs_per_s": reps * n / el, "sample": f"{reps} x {n} matrices", "threads": th}
 
 
 def cpu_details(trains_z, trains_d, nthreads, budget_s: float = 1.5):
@@ -213,6 +300,34 @@ def read_traffic(kernel_key: str):
     if not m or not b or m.group(1) != source_hash():
         return None
     return float(b.group(1))
+
+
+# issue rate of the vector ALUs: a wave64 instruction occupies a 16-lane SIMD
+# for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_SIMDS, VALU_CLOCK_HZ, VALU_CYCLES_PER_INSTR = 1024, 2.4e9, 4
+
+
+def read_valu_table():
+    """VALU instructions per matrix for each variant, from the committed
+    rocprofv3 --pmc summary (SQ_INSTS_VALU per launch x 64 / n), or {} when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "svd2_valu.md")
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha:\s*(\w+)", txt)
+    t = re.search(r"valu_instr_per_matrix:\s*(\{.*\})", txt)
+    if not m or not t or m.group(1) != source_hash():
+        return {}
+    return json.loads(t.group(1))
+
+
+def valu_frac(instr_per_matrix, n: int, kernel_ms: float):
+    """fraction of the VALU issue peak a launch of n matrices used"""
+    if instr_per_matrix is None:
+        return None
+    cycles = instr_per_matrix * n / 64 * VALU_CYCLES_PER_INSTR
+    return cycles / (kernel_ms * 1e-3 * VALU_CLOCK_HZ * VALU_SIMDS)
 
 
 def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
@@ -376,7 +491,7 @@ def kog_batch_bench(nprob: int = 256):
     return out
 
 
-def summarize(variant, r, pattern, flags_desc="", nouv=False):
+def summarize(variant, r, pattern, flags_desc="", nouv=False, valu_per_matrix=None):
     n = r["n"]
     bps = (BYTES_PER_SVD_NOUV if nouv else BYTES_PER_SVD)[variant]
     kms = float(np.mean(r["kernel_ms"]))
@@ -384,11 +499,96 @@ def summarize(variant, r, pattern, flags_desc="", nouv=False):
     gbs = bps * n / (kms * 1e-3) / 1e9
     pms = float(np.mean(pattern["kernel_ms"]))
     pgbs = bps * n / (pms * 1e-3) / 1e9
-    return dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
-                kernel_ms_min=float(np.min(r["kernel_ms"])), kernel_ms_median=float(np.median(r["kernel_ms"])),
-                algorithmic_GBs=gbs,
-                hbm_frac=gbs / HBM_PEAK_GBS, bytes_per_svd=bps,
-                pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
+    vf = valu_frac(valu_per_matrix, n, kms)
+    hf = gbs / HBM_PEAK_GBS
+    out = dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
+               kernel_ms_min=float(np.min(r["kernel_ms"])), kernel_ms_median=float(np.median(r["kernel_ms"])),
+               algorithmic_GBs=gbs,
+               hbm_frac=hf, bytes_per_svd=bps, valu_instr_per_matrix=valu_per_matrix, valu_frac=vf,
+               bound="valu" if vf is not None and vf > hf else "hbm",
+               pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
+    if "rescued" in r:
+        out["rescued"] = r["rescued"]
+        out["rescued_frac"] = r["rescued"] / n
+    return out
+
+
+def r4(x):
+    """four significant digits (None stays None)"""
+    if x is None:
+        return None
+    if isinstance(x, bool) or isinstance(x, int):
+        return x
+    return float(f"{x:.4g}")
+
+
+def headline(full: dict) -> dict:
+    """The one JSON line bench.py prints last on stdout, kept under 4 KB: the
+    headline metric with its roofline and CPU baseline, one entry per variant
+    ([SVDs/s, fraction of 8 TB/s, fraction of the VALU issue peak or null]),
+    the rescued-lane fraction of each FP32 rescue variant, and the
+    Kogbetliantz figures.  Per-problem and per-launch detail stays in `full`."""
+    h = full["variants"][full["head"]]
+    line = {k: full[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                  "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
+    line["value"] = r4(line["value"])
+    line["ms_per_step"] = r4(line["ms_per_step"])
+    rl = dict(full["roofline"])
+    line["roofline"] = {k: (r4(v) if isinstance(v, float) else v) for k, v in rl.items()}
+    cpu = full.get("cpu_baseline")
+    if cpu is not None:
+        c = {k: cpu[k] for k in ("unit", "cores", "kind", "sample")}
+        c["value"] = r4(cpu["value"])
+        if "upcast" in cpu:
+            c["fp32_via_fp64_upcast_SVDs_per_s"] = {k: r4(v["SVDs_per_s"]) for k, v in cpu["upcast"].items()}
+        if "check" in cpu:
+            c["gpu_vs_oracle_sample"] = {k: {kk: r4(vv) for kk, vv in v.items()} for k, v in cpu["check"].items()}
+        line["cpu_baseline"] = c
+    else:
+        line["cpu_baseline"] = None
+    line["variants_fields"] = ["SVDs/s", "hbm_frac", "valu_frac"]
+    line["variants"] = {k: [r4(v["svds_per_s"]), r4(v["hbm_frac"]), r4(v.get("valu_frac"))]
+                        for k, v in full["variants"].items()}
+    resc = {k: r4(v["rescued_frac"]) for k, v in full["variants"].items() if "rescued_frac" in v}
+    if resc:
+        line["rescued_frac"] = resc
+    kog = full.get("kogbetliantz")
+    if kog:
+        k = {"order": kog["order"], "sweeps_per_s": {m: r4(kog[m]["sweeps_per_s"]) for m in
+                                                      ("two_step", "unfused", "graph", "fused") if m in kog}}
+        if "solve" in kog:
+            s = kog["solve"]
+            k["solve"] = {"mode": s["mode"], "sweeps": s["sweeps"], "seconds": r4(s["seconds"]),
+                          "off_rel": r4(s["off_rel"]), "sigma_err_rel": r4(s["sigma_max_abs_err_rel"])}
+        if "svd" in kog and "seconds" in kog["svd"]:
+            s = kog["svd"]
+            k["svd"] = {"sweeps": s["sweeps"], "seconds": r4(s["seconds"]), "residual_rel": r4(s["residual_rel"]),
+                        "orthogonality": r4(s["orthogonality"])}
+        if "cpu_baseline" in kog:
+            k["cpu_oracle_s_per_sweep_extrapolated"] = r4(kog["cpu_baseline"]["seconds_per_sweep_extrapolated"])
+        line["kogbetliantz"] = k
+    kb = full.get("kogbetliantz_batch")
+    if kb:
+        line["kogbetliantz_batch"] = {
+            "nprob": kb["nprob"], "seconds": r4(kb["seconds"]), "converged": kb["converged"],
+            "problem_sweeps_per_s": r4(kb["problem_sweeps_per_s"]),
+            "one_step_per_pass_seconds": r4(kb["one_step_per_pass"]["seconds"]),
+            "max_sigma_err_rel_c128": r4(kb["max_sigma_err_rel_c128"]),
+            "max_sigma_err_rel_f32": r4(kb["max_sigma_err_rel_f32"])}
+    line["kernel_source_sha"] = full["kernel_source_sha"]
+    return line
+
+
+def emit(full: dict, detail_out=None) -> None:
+    """Everything, per launch and per problem, as one line on stderr (and in
+    detail_out if given); then the compact headline as the last line on
+    stdout."""
+    detail = json.dumps(full)
+    log(f"[bench] detail: {detail}")
+    if detail_out:
+        with open(detail_out, "w") as fh:
+            fh.write(detail + "\n")
+    print(json.dumps(headline(full), separators=(",", ":")), flush=True)
 
 
 def main():
@@ -417,6 +617,8 @@ def main():
     ap.add_argument("--kog-svd-only", action="store_true",
                     help="run only one sweep of the Kogbetliantz SVD with U and V (two steps per pass); "
                          "prints its JSON (for profiling runs)")
+    ap.add_argument("--detail-out", default=None, metavar="PATH",
+                    help="also write the full result (every launch figure, every uneven-batch problem) to PATH")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -477,6 +679,9 @@ def main():
         flagsets = {v: {d: f for d, f in fs.items() if ("NO_UV" in d) == keep_nouv and "SINE" not in d}
                     for v, fs in flagsets.items()}
     results, inputs_z, inputs_d = {}, None, None
+    checks_in, checks_out, lead32 = {}, {}, {}
+    valu_tab = read_valu_table()
+    do_cpu = not args.no_cpu_baseline
     # FP32 also at the precision form's own size (2^26: its inputs exceed the
     # 256 MB Infinity Cache, so they come from HBM on every launch)
     runs = [(v, args.n, "") for v in variants]
@@ -485,8 +690,18 @@ def main():
     for v, n, tag in runs:
         log(f"[bench] generating {v} inputs n={n}")
         tr = make_inputs(v, n)
+        # lanes compared with the oracle in the CPU-baseline leg: a seeded
+        # sample of the timed batch (special lanes included at their rate)
+        sample = None
+        if do_cpu and not tag:
+            sample = np.sort(np.random.default_rng(20050740).choice(n, size=min(n, 1 << 16), replace=False))
         log(f"[bench] timing {v}{tag}: warmup {args.warmup}, steps {args.steps}")
-        r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()))
+        r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()), sample=sample)
+        if sample is not None:
+            checks_in[v] = [np.ascontiguousarray(t[sample]) for t in tr]
+            checks_out[v] = (r["sample_out"], r["sample_flags"])
+            if v in ("s", "c"):
+                lead32[v] = [t[: 1 << 20].copy() for t in tr]
         for desc, fl in flagsets[v].items():
             nouv = "NO_UV" in desc
             if desc in ("", "RESCUE_FP64"):
@@ -499,7 +714,8 @@ def main():
                 key = f"{v}{tag}_tri"
             else:
                 key = f"{v}{tag}_{'sigma' if 'SIGMA' in desc else 'norescue'}"
-            results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv)
+            results[key] = summarize(v, r[fl], r["pattern_nouv" if nouv else "pattern"], desc, nouv,
+                                     valu_tab.get(key.replace("26", "")))
             log(f"[bench] {key}: {json.dumps(results[key])}")
         if v == "z" and not tag:
             inputs_z = tr
@@ -521,19 +737,25 @@ def main():
     h = results[head]
     steps = args.steps
     cpu = None
-    if not args.no_cpu_baseline and inputs_z is not None:
+    if do_cpu and inputs_z is not None:
         log("[bench] CPU baseline (oracle) ...")
         cpu = cpu_baseline("z", inputs_z)
         log(f"[bench] cpu: {json.dumps(cpu)}")
         if inputs_d is not None:
             cpu["details"] = cpu_details(inputs_z, inputs_d, cpu["cores"])
             log(f"[bench] cpu details: {json.dumps(cpu['details'])}")
+        cpu["upcast"] = {v: cpu_upcast(tr) for v, tr in lead32.items()}
+        log(f"[bench] cpu, FP32 batches through the FP64 oracle on the upcast: {json.dumps(cpu['upcast'])}")
+        cpu["check"] = {v: oracle_check(checks_in[v], *checks_out[v]) for v in checks_in}
+        log(f"[bench] GPU against the oracle on sampled lanes: {json.dumps(cpu['check'])}")
         if kog is not None:
             kog["cpu_baseline"] = cpu_kog(args.kog_order)
             log(f"[bench] kog cpu: {json.dumps(kog['cpu_baseline'])}")
+    del inputs_z, inputs_d, checks_in, checks_out, lead32
     traffic = read_traffic(f"svd2_{head}")
     dtype_name = {"d": "f64", "z": "f64", "s": "f32", "c": "f32"}[head[0]]
-    line = {
+    full = {
+        "head": head,
         "metric": METRIC,
         "value": h["svds_per_s"],
         "unit": "SVDs/s",
@@ -559,6 +781,7 @@ def main():
                      "unit": "GB/s", "frac": h["hbm_frac"],
                      "traffic": traffic, "traffic_unit": "bytes per launch",
                      "algorithmic_bytes_per_launch": h["bytes_per_svd"] * h["n"],
+                     "kernel_ms": h["kernel_ms"], "valu_frac": h["valu_frac"],
                      "pattern_ceiling_GBs": h["pattern_ceiling_GBs"],
                      "frac_of_pattern_ceiling": h["frac_of_pattern_ceiling"]},
         "cpu_baseline": cpu,
@@ -567,7 +790,10 @@ def main():
         "kogbetliantz_batch": kog_batch,
         "kernel_source_sha": source_hash(),
     }
-    print(json.dumps(line), flush=True)
+    del results, kog, kog_batch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    emit(full, args.detail_out)
 
 
 if __name__ == "__main__":
