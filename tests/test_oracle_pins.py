@@ -534,3 +534,79 @@ def test_subnormal_phase_keeps_u_unitary(dt):
         met = O.metrics(tr, out, True)
         assert np.max(met["delta"]) <= 16 * eps, (form, met["delta"] / eps)
         assert np.max(met["rho"]) <= 16 * eps, (form, met["rho"] / eps)
+
+
+# ---------------------------------------------------------------------------
+# FP32 rescue: which lanes are near-degenerate
+# ---------------------------------------------------------------------------
+
+def _flag_rule_cases(cplx):
+    """Matrices whose singular values are exact in FP32 (diagonal and
+    anti-diagonal, entries times 1, i, -1 or -i, magnitudes 2^e and 2^e b) with
+    b = sigma_min / sigma_max placed on both sides of 2^-20 down to one FP32
+    ulp, plus the zero matrix, exactly rank-one ones and well-conditioned ones.
+    Returns the (4, n) matrices and the exact ratio b (Fraction) per lane."""
+    two20 = Fraction(1, 1 << 20)
+    ratios = [two20, Fraction(1), Fraction(1, 2), two20 * 2, Fraction(0)]
+    for k in range(1, 24):
+        ratios += [two20 * (1 - Fraction(1, 1 << k)), two20 * (1 + Fraction(1, 1 << k))]
+    ratios.append(two20 * (1 - Fraction(1, 1 << 24)))  # 1 - 2^-24 is representable too
+    phases = [1, 1j, -1, -1j] if cplx else [1, -1]
+    cols, bs = [], []
+    for e in (-100, -40, 0, 37, 120):  # both singular values stay in the normal range
+        big = 2.0 ** e
+        for b in ratios:
+            small = float(b) * big
+            assert Fraction(np.float32(small).item()) == b * Fraction(big)  # exact in FP32
+            for i, (p1, p2) in enumerate(itertools.product(phases, repeat=2)):
+                x, y = p1 * big, p2 * small
+                shape = i % 4
+                if shape == 0:
+                    m = (x, 0, 0, y)      # diag(x, y)
+                elif shape == 1:
+                    m = (y, 0, 0, x)      # diag(y, x): the column pivot swaps
+                elif shape == 2:
+                    m = (0, x, y, 0)      # [[0, y], [x, 0]]
+                else:
+                    m = (0, y, x, 0)
+                cols.append(m)
+                bs.append(b)
+    zero = (0, 0, 0, 0)
+    cols.append(zero)
+    bs.append(None)
+    A = np.array(cols, dtype=np.complex64 if cplx else np.float32).T
+    if not cplx:
+        A = A.real.astype(np.float32)
+    return A, bs
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_fp32_rescue_flags_exactly_below_2_to_minus_20(cplx, mode):
+    """The precision form rescues a lane iff sigma_min / sigma_max < 2^-20
+    (the near-degenerate rule of the FP32 form).  On matrices whose singular
+    values are exact in FP32 the ratio is known exactly, so the flag must be
+    set on every lane with ratio below 2^-20 (down to one ulp below) and on
+    exactly rank-one lanes, and on no other lane: not at 2^-20 itself, not one
+    ulp above, not on well-conditioned lanes and not on the zero matrix.  A
+    wrong exponent, a <= for <, or a rule that flags every lane fails here.
+    The same marks come back from the per-matrix trace."""
+    from workloads import to_trains
+    A, bs = _flag_rule_cases(cplx)
+    tr = to_trains(A, np.float32)
+    outs, flagged = O.run_trains(tr, cplx, np.float32, policy="mirror", rescue=mode)
+    k = 16 if cplx else 8
+    want = np.array([b is not None and b < Fraction(1, 1 << 20) for b in bs])
+    got = flagged.astype(bool)
+    assert np.array_equal(got, want), (np.nonzero(got != want)[0][:10], [bs[i] for i in np.nonzero(got != want)[0][:10]])
+    # the singular values of these lanes are exact in FP32, rescued or not
+    s = outs[k + 2].astype(np.int64)
+    nz = np.array([b is not None for b in bs])
+    smax = np.ldexp(outs[k].astype(np.float64), -s)
+    smin = np.ldexp(outs[k + 1].astype(np.float64), -s)
+    for i in np.nonzero(nz)[0]:
+        assert Fraction(smin[i]) == bs[i] * Fraction(smax[i]), i
+    # the per-matrix trace takes the same decision
+    for i in list(range(0, len(bs), 37)) + [len(bs) - 1]:
+        a = np.stack([t[i] for t in tr])
+        assert bool(O.trace(a, cplx, np.float32, rescue=mode)["rescued"]) == want[i], i
