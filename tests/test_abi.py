@@ -295,3 +295,19 @@ def test_binding_refuses_host_tensors():
         S.svd2([torch.zeros(16, dtype=torch.float64) for _ in range(4)])
     with pytest.raises(ValueError, match="device tensors"):
         S._nbytes(torch.zeros(16, dtype=torch.uint8))
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present: the launch would run on it")
+def test_launch_without_a_device_reports_the_hip_error():
+    """With no GPU, a well-formed call passes every argument check, its launch
+    fails, and the entry point returns SVD2_ERR_HIP with the HIP error
+    (hipErrorNoDevice) kept for svd2_last_hip_error; nothing is dereferenced
+    on the host (the addresses are fake device addresses)."""
+    L = S.lib()
+    for fn, nin, nout in ((S.dsvd2_batch, 4, 11), (S.zsvd2_batch, 8, 19), (S.csvd2_batch, 8, 19)):
+        ins, outs = _ptrs(nin), _ptrs(nout, base=FAKE + (64 << 30))
+        with pytest.raises(S.Svd2Error) as ei:
+            fn(10, ins, outs, 0, stream=0)
+        assert ei.value.status == 5
+        assert L.svd2_last_hip_error() == 100  # hipErrorNoDevice
+        assert "hipError 100" in str(ei.value)
