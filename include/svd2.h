@@ -262,7 +262,10 @@ size_t kog_workspace_bytes(int N, int dtype);
 /* the same for the given flags (SVD2_KOG_TWO_STEP adds N^2 elements) */
 size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags);
 
-/* one step t (0 <= t < N-1) */
+/* one step t (0 <= t < N-1); flags 0 (fused kernel) or SVD2_KOG_UNFUSED.
+   With SVD2_KOG_TWO_STEP (alone): steps t and t+1 (0 <= t, t+1 < N-1) in one
+   two-step pass into the workspace matrix, which is then copied back into A
+   (workspace of kog_workspace_bytes_flags(N, dtype, SVD2_KOG_TWO_STEP)). */
 svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
                       hipStream_t stream);
 svd2_status zkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,

@@ -761,11 +761,17 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
 template <class T, bool CPLX>
 svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
   Ctx<T, CPLX> c;
-  if (flags & (SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;  // solve/sweep modes
+  if (flags & SVD2_KOG_GRAPH) return SVD2_ERR_FLAGS;  // graph replay is a solve-only mode
   svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
   if (s != SVD2_OK) return s;
-  if (t < 0 || t >= N - 1) return SVD2_ERR_SIZE;
   c.st = st;
+  if (c.flags & SVD2_KOG_TWO_STEP) {
+    // steps t and t+1 in one pass into the workspace matrix, then copied back
+    if (t < 0 || t + 1 >= N - 1) return SVD2_ERR_SIZE;
+    s = two_steps<T, CPLX>(c, c.M, c.W, t, c.B, c.B1);
+    return s != SVD2_OK ? s : copy_back<T, CPLX>(c);
+  }
+  if (t < 0 || t >= N - 1) return SVD2_ERR_SIZE;
   return (c.flags & SVD2_KOG_UNFUSED) ? unfused_step<T, CPLX>(c, t) : fused_steps<T, CPLX>(c, t, t + 1);
 }
 
@@ -1007,6 +1013,7 @@ svd2_status dkog_solve(int N, double *A, int lda, double tol, int max_sweeps, in
                        double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
   return api_solve<double, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
 }
+
 svd2_status zkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
                        double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
   return api_solve<double, true>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);

@@ -56,7 +56,8 @@ int main(void) {
   CHECK(kog_sigma_workspace_bytes(64, SVD2_KOG_F32) > 0);
   CHECK(dkog_solve(64, NULL, 64, 1e-14, 40, NULL, NULL, NULL, 0, 0, st) == SVD2_ERR_NULL);
   CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_UNFUSED, st) == SVD2_ERR_NULL);
-  CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_TWO_STEP, st) == SVD2_ERR_FLAGS);
+  CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_TWO_STEP, st) == SVD2_ERR_NULL);
+  CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_TWO_STEP | SVD2_KOG_GRAPH, st) == SVD2_ERR_FLAGS);
   CHECK(skog_sweep(64, NULL, 64, NULL, 0, SVD2_KOG_GRAPH, st) == SVD2_ERR_FLAGS);
   CHECK(ckog_svd(64, NULL, 64, NULL, 64, NULL, 64, NULL, 1e-7, 40, NULL, NULL, NULL, 0, 0, st) ==
         SVD2_ERR_NULL);

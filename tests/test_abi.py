@@ -174,13 +174,16 @@ def test_kog_argument_errors():
     assert call(64, A, 64, 0, ws, wsb, 2) == 4          # GRAPH without UNFUSED
     assert call(64, A, 64, 0, ws, wsb, 3) == 4          # GRAPH is solve-only
     assert L.dkog_sweep(64, A, 64, ws, wsb, 3, None) == 4
-    assert call(64, A, 64, 0, ws, wsb, 4) == 4          # TWO_STEP is a sweep/solve mode
+    assert call(64, A, 64, 0, ws, wsb, 4) == 6          # TWO_STEP step: no room for the matrix buffer
+    assert call(64, A, 64, 0, ws, wsb, 5) == 4          # TWO_STEP with UNFUSED
     assert L.dkog_sweep(64, A, 64, ws, wsb, 5, None) == 4   # TWO_STEP with UNFUSED
     assert L.dkog_sweep(64, A, 64, ws, wsb, 4, None) == 6   # too small for the matrix buffer
     ws2 = S.kog_workspace_bytes(64, "d", S.SVD2_KOG_TWO_STEP)
     assert ws2 >= wsb + 64 * 64 * 8
     assert S.kog_workspace_bytes(64, "z", S.SVD2_KOG_TWO_STEP) >= 64 * 64 * 16
     assert L.dkog_sweep(64, A, 64, A + 512, ws2, 4, None) == 3  # overlap
+    assert call(64, A, 64, 62, ws, ws2, 4) == 6         # two steps from t = N-2 run past the sweep
+    assert call(64, A, 64, -1, ws, ws2, 4) == 6
     assert call(64, A, 64, 63, ws, wsb, 0) == 6         # step out of range
     sw, off = ctypes.c_int(), ctypes.c_double()
     assert L.dkog_solve(64, A, 64, 1e-14, -1, ctypes.byref(sw), ctypes.byref(off), ws, wsb, 0,

@@ -94,20 +94,30 @@ def test_sweep_entry_point_and_norms():
     assert abs(off2 - o2) <= 1e-12 * t2 and abs(tot2 - t2) <= 1e-12 * t2
 
 
-def test_full_order_4096_first_steps():
+@pytest.mark.parametrize("mode", ["two_step", "unfused", "fused"])
+def test_full_order_4096_first_steps(mode):
     """The one-problem workload (real FP64, N = 4096, sigma geometric from 1
-    to 1e-12): the first two fused steps are bitwise the oracle's."""
+    to 1e-12) in the tile shapes the benchmark times (the autotuner's table):
+    steps 0-3 as two two-step passes, or as four unfused or fused steps, are
+    bitwise the oracle's after steps 1 and 3."""
     import torch
     from paper_2005_07403_amd import svd2 as S
+    S.apply_tuning()
     N = 4096
     A = kog_matrix(N, SEED_BASE + 3, cond=1e12)
     G = _dev(A)
-    ws = S.kog_workspace(G)
-    for t in range(2):
-        S.kog_step(G, t, ws=ws)
-        O.kog_step(A, t)
-    torch.cuda.synchronize()
-    assert _same(G.cpu().numpy(), A)
+    flags = {"two_step": S.SVD2_KOG_TWO_STEP, "unfused": S.SVD2_KOG_UNFUSED, "fused": 0}[mode]
+    ws = S.kog_workspace(G, flags)
+    for t0 in (0, 2):
+        if mode == "two_step":
+            S.kog_step(G, t0, ws=ws, flags=flags)
+        else:
+            for t in (t0, t0 + 1):
+                S.kog_step(G, t, ws=ws, flags=flags)
+        for t in (t0, t0 + 1):
+            O.kog_step(A, t)
+        torch.cuda.synchronize()
+        assert _same(G.cpu().numpy(), A), (mode, t0)
 
 
 @pytest.mark.slow
@@ -144,6 +154,25 @@ def test_two_step_sweep_bitwise(kind, N):
             O.kog_step(A, t)
         torch.cuda.synchronize()
         assert _same(G.cpu().numpy(), A), (kind, N)
+
+
+@pytest.mark.parametrize("kind", ["d", "z", "s", "c"])
+@pytest.mark.parametrize("N", [4, 6, 130])
+def test_two_step_single_pass_bitwise(kind, N):
+    """One two-step pass through the step entry point (steps t, t+1, copied
+    back into A), at the first and the last pair of steps of a sweep,
+    bitwise equal to two oracle steps each."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    A = _make(N, kind, SEED_BASE + 360 + N)
+    G = _dev(A)
+    ws = S.kog_workspace(G, S.SVD2_KOG_TWO_STEP)
+    for t in sorted({0, N - 3}):
+        S.kog_step(G, t, ws=ws, flags=S.SVD2_KOG_TWO_STEP)
+        O.kog_step(A, t)
+        O.kog_step(A, t + 1)
+        torch.cuda.synchronize()
+        assert _same(G.cpu().numpy(), A), (kind, N, t)
 
 
 @pytest.mark.parametrize("kind", ["d", "z", "s", "c"])

@@ -242,16 +242,30 @@ def test_lane_isolation_nonfinite():
     compare(gpu, ora, True, EPS[np.float64], lanes=ok)
 
 
-@pytest.mark.slow
-def test_complex_full_size_2_24():
-    """The full complex workload: n = 2^24, +-m 2^e, e in [-1000, 1000], 1 %
-    special lanes, in the launch shape the benchmark times.  All lanes are
-    compared with the oracle."""
+def _bench_shape(kind):
+    """Set and return the launch shape the benchmark times for `kind`: the
+    autotuner's table when present (bench.py loads it), else its default."""
     from bench import DEFAULT_LAUNCH
-    _set_launch(*DEFAULT_LAUNCH["z"])
-    A = scaled_law(1 << 24, SEED_BASE + 1, True)
+    from paper_2005_07403_amd import svd2 as S
+    tab = S.apply_tuning() or {}
+    shape = tuple(int(x) for x in tab.get("svd2_launch", {}).get(kind, DEFAULT_LAUNCH[kind]))
+    S.svd2_set_launch_kind(kind, *shape)
+    assert tuple(S.svd2_get_launch_kind(kind)) == shape
+    return shape
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["z", "d"])
+def test_full_size_2_24_in_the_benchmark_shape(kind):
+    """The full FP64 workloads the benchmark times: n = 2^24 matrices, +-m 2^e,
+    e in [-1000, 1000], 1 % special lanes, complex (the headline) and real,
+    in the launch shape the benchmark uses.  Every lane is compared with the
+    oracle."""
+    shape = _bench_shape(kind)
+    A = scaled_law(1 << 24, SEED_BASE + 1, kind == "z")
     st = _check(A, np.float64, metrics=False)
     assert st["lanes"] == 1 << 24
+    print(f"{kind} n=2^24 shape {shape}: {st}")
 
 
 # ---------------------------------------------------------------------------
