@@ -293,6 +293,24 @@ svd2_status skog_solve(int N, float *A, int lda, double tol, int max_sweeps, int
                        double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
 svd2_status ckog_solve(int N, float *A, int lda, double tol, int max_sweeps, int *sweeps,
                        double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream);
+/* dkog_solve without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid hipMalloc).  The library calls no hipMalloc, hipFree or other
+ * allocating routine: the workspace is a 2 MiB array that the library's code
+ * object holds on every GPU it runs on, until the process ends.
+ *  - Arguments and results as dkog_solve; flags: 0 (fused) or
+ *    SVD2_KOG_UNFUSED only (SVD2_ERR_FLAGS otherwise: the hipGraph mode
+ *    allocates its graph and the two-step mode needs an N x N buffer).
+ *  - N is limited by the array: kog_workspace_bytes(N, SVD2_KOG_F64) must not
+ *    exceed 2 MiB, i.e. N <= 30272 (SVD2_ERR_SIZE otherwise, before any HIP
+ *    call).
+ *  - Every call on one GPU shares that GPU's array, and the array keeps the
+ *    last call's contents (each call overwrites what it reads, so nothing
+ *    carries over).  Calls that overlap in time on one GPU -- from several
+ *    host threads or on several streams -- race on the array and give
+ *    undefined results; serialise them. */
+svd2_status dkog_solve_noalloc(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                               double *off_rel, unsigned flags, hipStream_t stream);
 /* off(A)^2 and ||A||_F^2 accumulated in FP64 (host outputs; synchronises) */
 svd2_status dkog_norms(int N, const double *A, int lda, double *off2, double *tot2, void *ws,
                        size_t ws_bytes, hipStream_t stream);

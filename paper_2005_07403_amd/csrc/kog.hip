@@ -918,6 +918,38 @@ svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma
 
 }  // namespace
 
+// Workspace of dkog_solve_noalloc: one copy of this array per GPU, allocated
+// with the code object when it is loaded on that GPU and held until the
+// process ends.  Host code never uses its name as an address: the device
+// address comes from hipGetSymbolAddress, once per device (noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = size_t(2) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// the device address of `scratch` on the current device, looked up on the
+// first call on each device
+svd2_status noalloc_scratch(void **out) {
+  int dev = 0;
+  svd2_status s = hip_st(hipGetDevice(&dev));
+  if (s != SVD2_OK) return s;
+  if (dev < 0 || dev >= kMaxScratchDevices) return SVD2_ERR_SIZE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    s = hip_st(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (s != SVD2_OK) return s;
+    if (!p || (uintptr_t)p % 256) return SVD2_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SVD2_OK;
+}
+}  // namespace
+
 // the last HIP error of a Kogbetliantz entry point defined in another file
 void kog_note_hip_error(int e) { g_kog_hip = e; }
 
@@ -1012,6 +1044,20 @@ svd2_status ckog_sweep(int N, float *A, int lda, void *ws, size_t ws_bytes, unsi
 svd2_status dkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
                        double *off_rel, void *ws, size_t ws_bytes, unsigned flags, hipStream_t stream) {
   return api_solve<double, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, ws_bytes, flags, stream);
+}
+
+svd2_status dkog_solve_noalloc(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,
+                               double *off_rel, unsigned flags, hipStream_t stream) {
+  // argument checks first, so that a rejected call makes no HIP call at all
+  if (!A) return SVD2_ERR_NULL;
+  if (flags & ~(unsigned)SVD2_KOG_UNFUSED) return SVD2_ERR_FLAGS;
+  if (N < 2 || N % 2 || lda < N) return SVD2_ERR_SIZE;
+  if (kog_workspace_bytes(N, SVD2_KOG_F64) > kNoAllocScratchBytes) return SVD2_ERR_SIZE;
+  void *ws = nullptr;
+  svd2_status s = noalloc_scratch(&ws);
+  if (s != SVD2_OK) return s;
+  return api_solve<double, false>(N, A, lda, tol, max_sweeps, sweeps, off_rel, ws, kNoAllocScratchBytes, flags,
+                                  stream);
 }
 
 svd2_status zkog_solve(int N, double *A, int lda, double tol, int max_sweeps, int *sweeps,

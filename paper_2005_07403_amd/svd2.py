@@ -65,7 +65,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
            "kog_batch_workspace_bytes_flags", "kog_sigma_workspace_bytes", "dkog_sigma", "zkog_sigma",
            "skog_sigma", "ckog_sigma", "kog_svd_workspace_bytes", "dkog_svd", "zkog_svd", "skog_svd",
-           "ckog_svd",
+           "ckog_svd", "dkog_solve_noalloc",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -316,6 +316,8 @@ def _kog():
         L.kog_last_hip_error.restype = i
         L.kog_set_fused_blocks_per_cu.argtypes = [i]
         L.kog_set_fused_blocks_per_cu.restype = i
+        L.dkog_solve_noalloc.argtypes = [i, _P, i, d, i, _P, _P, ui, _P]
+        L.dkog_solve_noalloc.restype = i
         _kog_ready = True
     return L
 
@@ -387,6 +389,21 @@ def kog_solve(A, tol: float = 1e-14, max_sweeps: int = 40, ws=None, flags: int =
                                           ctypes.byref(off), ws.data_ptr(), _nbytes(ws), flags,
                                           _stream(stream))
     _kog_check(f"{k}kog_solve", st)
+    return dict(status=st, sweeps=sw.value, off_rel=off.value)
+
+
+def kog_solve_noalloc(A, tol: float = 1e-14, max_sweeps: int = 40, flags: int = 0,
+                      stream=None) -> dict:
+    """kog_solve of a real FP64 matrix with the library's own fixed device
+    workspace (no allocation by the library or here).  flags: 0 (fused) or
+    SVD2_KOG_UNFUSED.  Returns status, sweeps, off_rel."""
+    if kog_kind(A) != "d":
+        raise ValueError("kog_solve_noalloc takes a real float64 matrix")
+    N, lda, ptr = _kog_args(A)
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    st = _kog().dkog_solve_noalloc(N, ptr, lda, tol, max_sweeps, ctypes.byref(sw), ctypes.byref(off), flags,
+                                   _stream(stream))
+    _kog_check("dkog_solve_noalloc", st)
     return dict(status=st, sweeps=sw.value, off_rel=off.value)
 
 

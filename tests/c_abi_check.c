@@ -55,6 +55,11 @@ int main(void) {
   CHECK(kog_svd_workspace_bytes(64, SVD2_KOG_C128, 0) > kog_workspace_bytes(64, SVD2_KOG_C128));
   CHECK(kog_sigma_workspace_bytes(64, SVD2_KOG_F32) > 0);
   CHECK(dkog_solve(64, NULL, 64, 1e-14, 40, NULL, NULL, NULL, 0, 0, st) == SVD2_ERR_NULL);
+  CHECK(dkog_solve_noalloc(64, NULL, 64, 1e-14, 40, NULL, NULL, 0, st) == SVD2_ERR_NULL);
+  CHECK(dkog_solve_noalloc(30274, (double *)(uintptr_t)4096, 30274, 1e-14, 40, NULL, NULL, 0, st) ==
+        SVD2_ERR_SIZE);
+  CHECK(dkog_solve_noalloc(64, (double *)(uintptr_t)4096, 64, 1e-14, 40, NULL, NULL, SVD2_KOG_GRAPH | 1, st) ==
+        SVD2_ERR_FLAGS);
   CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_UNFUSED, st) == SVD2_ERR_NULL);
   CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_TWO_STEP, st) == SVD2_ERR_NULL);
   CHECK(zkog_step(64, NULL, 64, 0, NULL, 0, SVD2_KOG_TWO_STEP | SVD2_KOG_GRAPH, st) == SVD2_ERR_FLAGS);

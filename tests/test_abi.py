@@ -190,6 +190,27 @@ def test_kog_argument_errors():
                         None) == 6                      # negative max_sweeps
 
 
+def test_kog_solve_noalloc_argument_errors():
+    """The solve on the library's fixed workspace checks its arguments before
+    any HIP call: NULL matrix, modes that would need an allocation, and
+    orders whose workspace exceeds the fixed 2 MiB."""
+    import ctypes
+    L = S._kog()
+    A = FAKE
+    sw, off = ctypes.c_int(), ctypes.c_double()
+    call = lambda N, a, lda, f: L.dkog_solve_noalloc(N, a, lda, 1e-14, 40, ctypes.byref(sw),
+                                                     ctypes.byref(off), f, None)
+    assert call(64, 0, 64, 0) == 1                      # NULL matrix
+    for f in (2, 3, 4, 5, 8):                           # GRAPH, TWO_STEP, unknown
+        assert call(64, A, 64, f) == 4, f
+    assert call(63, A, 64, 0) == 6                      # odd order
+    assert call(64, A, 63, 0) == 6                      # lda < N
+    lim = max(N for N in range(30000, 30600, 2) if S.kog_workspace_bytes(N, "d") <= 2 << 20)
+    assert lim == 30272                                 # the limit the header states
+    assert call(lim + 2, A, lim + 2, 0) == 6            # workspace beyond the fixed array
+    assert call(1 << 20, A, 1 << 20, 1) == 6
+
+
 def test_kog_svd_argument_errors():
     """The SVD entry points validate every pointer, size, flag and overlap
     before any HIP call."""
