@@ -197,7 +197,10 @@ svd2_status svd2_stream_probe(int kind, size_t n, const void *const *in, void *c
 /* Conformance probe of the device primitives the kernels use (correct
    rounding of /, sqrt, fma, ldexp; frexp exponents of subnormals; NaN
    handling of fmin/fmax), for tests.  op: 0 div, 1 sqrt, 2 fma, 3 ldexp(x,
-   (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y).
+   (int)y), 4 frexp exponent of x (as a value), 5 fmin(x,y), 6 fmax(x,y),
+   7 the kernels' square root for arguments x >= 1, 8 their reciprocal 1/x for
+   x >= 1 with a normal result (ops 7 and 8 must equal ops 1 and 0 on that
+   domain; y and z are unused by ops 1, 4, 7 and 8 and may be NULL).
    x, y, z, out: device arrays of n doubles (FP64) or floats (FP32). */
 svd2_status svd2_probe_f64(int op, size_t n, const double *x, const double *y,
                            const double *z, double *out, hipStream_t stream);

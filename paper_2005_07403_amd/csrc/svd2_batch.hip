@@ -167,7 +167,9 @@ __global__ __launch_bounds__(256) void probe_kernel(int op, size_t n, const T *x
     case 3: r = vldexp(x[i], (int)y[i]); break;
     case 4: r = (T)vfrexp_exp(x[i]); break;
     case 5: r = vmin(x[i], y[i]); break;
-    default: r = vmax(x[i], y[i]); break;
+    case 6: r = vmax(x[i], y[i]); break;
+    case 7: r = vsqrt_ge1(x[i]); break;
+    default: r = vrcp_ge1(x[i]); break;
   }
   out[i] = r;
 }
@@ -293,8 +295,8 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
 template <class T>
 svd2_status probe(int op, size_t n, const T *x, const T *y, const T *z, T *out,
                          hipStream_t stream) {
-  if (op < 0 || op > 6) return SVD2_ERR_FLAGS;
-  if (!x || !out || (!y && op != 1 && op != 4) || (!z && op == 2)) return SVD2_ERR_NULL;
+  if (op < 0 || op > 8) return SVD2_ERR_FLAGS;
+  if (!x || !out || (!y && op != 1 && op != 4 && op < 7) || (!z && op == 2)) return SVD2_ERR_NULL;
   if (n == 0) return SVD2_OK;
   size_t grid = (n + 255) / 256;
   if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;

@@ -66,13 +66,63 @@ __device__ __forceinline__ bool vsignbit(float a) { return __builtin_signbit(a);
 // negate when the flag is set (an XOR of the sign bit)
 template <class T> __device__ __forceinline__ T flip(bool neg, T a) { return neg ? -a : a; }
 
+// Correctly rounded sqrt(x) and 1/x on the arguments the pipeline gives them.
+// Every square root here is of a sum 1 + t^2 (t finite: q in [0, 1] in hyp,
+// the tangents of eqs. (7), (15), (16)), so x >= 1, and every reciprocal is of
+// such a root, so x is in [1, 2^64] (FP32) or [1, 2^512] (FP64) and 1/x is
+// normal.  On that domain the general sequences need neither their range
+// reduction of tiny arguments nor their fix-ups of 0, inf and NaN, which
+// leaves
+//  - FP32 sqrt: the hardware estimate s, then whichever of s - ulp, s,
+//    s + ulp the signs of the exact residuals x - (s -+ ulp) s select;
+//  - FP64 sqrt: the hardware reciprocal-root estimate y, g = x y, h = y/2,
+//    one coupled Newton step on (g, h), then two corrections
+//    g += (x - g^2) h;
+//  - 1/x: the hardware reciprocal estimate r, Newton steps on r, and the
+//    quotient q = r corrected by q += (1 - x q) r, twice.
+// These are the operations the compiler's own correctly rounded sqrt and
+// division perform on that domain, so the results are the correctly rounded
+// ones bit for bit (checked by the primitive probe: FP32 on every argument of
+// the domain, FP64 on samples).  Non-finite inputs give unspecified lanes
+// anyway, as with the general sequences.
+__device__ __forceinline__ float vsqrt_ge1(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sd = __builtin_bit_cast(float, __builtin_bit_cast(int, s) - 1);
+  const float su = __builtin_bit_cast(float, __builtin_bit_cast(int, s) + 1);
+  const float rd = vfma(-sd, s, x), ru = vfma(-su, s, x);
+  const float t = (rd <= 0.0f) ? sd : s;
+  return (ru > 0.0f) ? su : t;
+}
+__device__ __forceinline__ double vsqrt_ge1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = y * 0.5;
+  const double e = vfma(-h, g, 0.5);
+  g = vfma(g, e, g);
+  h = vfma(h, e, h);
+  g = vfma(vfma(-g, g, x), h, g);
+  return vfma(vfma(-g, g, x), h, g);
+}
+__device__ __forceinline__ float vrcp_ge1(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  r = vfma(vfma(-x, r, 1.0f), r, r);
+  float q = vfma(vfma(-x, r, 1.0f), r, r);
+  return vfma(vfma(-x, q, 1.0f), r, q);
+}
+__device__ __forceinline__ double vrcp_ge1(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = vfma(r, vfma(-x, r, 1.0), r);
+  r = vfma(r, vfma(-x, r, 1.0), r);
+  return vfma(vfma(-x, r, 1.0), r, r);
+}
+
 template <class T> __device__ __forceinline__ T hyp(T a, T b) {
   T x = vabs(a), y = vabs(b);
   T hi = vmax(x, y), lo = vmin(x, y);
   T q = lo / vmax(hi, Fmt<T>::tm);
-  return hi * vsqrt(vfma(q, q, T(1)));
+  return hi * vsqrt_ge1(vfma(q, q, T(1)));
 }
-template <class T> __device__ __forceinline__ T rsq(T x) { return T(1) / vsqrt(x); }
+// invsqrt(x) = 1/sqrt(x) (two correctly rounded operations); x >= 1 at every use
+template <class T> __device__ __forceinline__ T rsq(T x) { return vrcp_ge1(vsqrt_ge1(x)); }
 
 template <class T> struct Cx { T re, im; };
 
@@ -125,7 +175,7 @@ template <class T> __device__ __forceinline__ Tri<T> tri_svd(T r11, T r12, T r22
   T den = vfma(x - y, x + y, one);
   T t2 = -vmin(vmax(num / den, zero), Fmt<T>::f);
   Tri<T> o;
-  o.tphi = t2 / (one + vsqrt(vfma(t2, t2, one)));
+  o.tphi = t2 / (one + vsqrt_ge1(vfma(t2, t2, one)));
   T sec2phi = vfma(o.tphi, o.tphi, one);
   o.cphi = rsq(sec2phi);
   o.tpsi = vfma(y, o.tphi, -x);

@@ -136,6 +136,86 @@ def test_primitives_correctly_rounded(dtype):
     assert np.all(o8.cpu().numpy() == 2.0)
 
 
+def _bits_equal_dev(a, b):
+    import torch
+    ia = a.view(torch.int32 if a.dtype == torch.float32 else torch.int64)
+    ib = b.view(torch.int32 if b.dtype == torch.float32 else torch.int64)
+    return bool(torch.equal(ia, ib))
+
+
+def test_sqrt_and_reciprocal_on_their_domain_fp32_every_argument():
+    """The kernels' square root (every x in [1, FLT_MAX]) and reciprocal (every
+    x in [1, 2^126), where 1/x is normal) are bitwise the correctly rounded
+    sqrt and division of the same device (themselves checked against numpy
+    above), on every FP32 argument of those domains."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    chunk = 1 << 26
+    for op, ref_op, lo, hi in ((7, 1, 0x3F800000, 0x7F7FFFFF), (8, 0, 0x3F800000, 0x7E7FFFFF)):
+        base = lo
+        while base <= hi:
+            m = min(chunk, hi - base + 1)
+            x = torch.arange(base, base + m, dtype=torch.int64, device="cuda").to(torch.int32).view(torch.float32)
+            got, want = torch.empty_like(x), torch.empty_like(x)
+            S.svd2_probe(op, x, None, None, got)
+            if ref_op == 1:
+                S.svd2_probe(1, x, None, None, want)
+            else:
+                S.svd2_probe(0, torch.ones_like(x), x, None, want)
+            torch.cuda.synchronize()
+            assert _bits_equal_dev(got, want), (op, hex(base))
+            base += m
+    # and against numpy on a sample of each domain
+    rng = np.random.default_rng(SEED_BASE + 77)
+    xs = rng.integers(0x3F800000, 0x7F7FFFFF, 1 << 16, dtype=np.int64).astype(np.int32).view(np.float32)
+    tx = torch.from_numpy(xs).cuda()
+    out = torch.empty_like(tx)
+    S.svd2_probe(7, tx, None, None, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), np.sqrt(xs))
+    xr = rng.integers(0x3F800000, 0x7E7FFFFF, 1 << 16, dtype=np.int64).astype(np.int32).view(np.float32)
+    tx = torch.from_numpy(xr).cuda()
+    S.svd2_probe(8, tx, None, None, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), np.float32(1) / xr)
+
+
+def test_sqrt_and_reciprocal_on_their_domain_fp64_sampled():
+    """The FP64 square root on x >= 1 and reciprocal on [1, 2^1022] against
+    the device's correctly rounded sqrt and division and numpy: random
+    exponents and mantissas, the neighbourhoods of exact squares (where the
+    rounding of sqrt is decided), powers of two and their neighbours."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    rng = np.random.default_rng(SEED_BASE + 78)
+    n = 1 << 22
+    m = rng.integers(0, 1 << 52, n, dtype=np.int64)
+    e = rng.integers(1023, 2046, n, dtype=np.int64)           # exponents 0 .. 1022
+    x = ((e << 52) | m).view(np.float64)
+    r = rng.integers(1 << 26, 1 << 27, n // 4, dtype=np.int64).astype(np.float64)
+    sq = r * r                                                 # exact squares (< 2^54)
+    sq = sq[sq < 2.0 ** 53]
+    near = np.concatenate([np.nextafter(sq, 0), sq, np.nextafter(sq, np.inf)])
+    p2 = np.ldexp(1.0, np.arange(0, 1023))
+    x = np.concatenate([x, near, p2, np.nextafter(p2, np.inf), np.nextafter(p2[1:], 0),
+                        1.0 + np.arange(1, 4096) * np.finfo(np.float64).eps])
+    tx = torch.from_numpy(x).cuda()
+    got, want = torch.empty_like(tx), torch.empty_like(tx)
+    S.svd2_probe(7, tx, None, None, got)
+    S.svd2_probe(1, tx, None, None, want)
+    torch.cuda.synchronize()
+    assert _bits_equal_dev(got, want)
+    assert np.array_equal(got.cpu().numpy(), np.sqrt(x))
+    xr = x[x <= 2.0 ** 1022]
+    tx = torch.from_numpy(xr).cuda()
+    got, want = torch.empty_like(tx), torch.empty_like(tx)
+    S.svd2_probe(8, tx, None, None, got)
+    S.svd2_probe(0, torch.ones_like(tx), tx, None, want)
+    torch.cuda.synchronize()
+    assert _bits_equal_dev(got, want)
+    assert np.array_equal(got.cpu().numpy(), 1.0 / xr)
+
+
 # ---------------------------------------------------------------------------
 # FP64 parity
 # ---------------------------------------------------------------------------
