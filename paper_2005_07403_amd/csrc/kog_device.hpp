@@ -470,6 +470,10 @@ __device__ __forceinline__ void pivots2_one(int N, const Mat<T, CPLX> &M, int t,
 // outputs are written after a barrier.  Only the workgroup's outer edges read
 // a column pair outside their own outputs.
 constexpr int kShiftOut = 62;
+// Column blocks the two-step walk loads ahead: 3 (real N = 4096 FP64: 32.4 ->
+// 32.0 us per step against 1), except complex FP64, whose larger blocks would
+// spill at the batch kernel's register cap and cost more than they gain.
+template <class T, bool CPLX> constexpr int two_step_depth() { return (CPLX && sizeof(T) == 8) ? 1 : 3; }
 
 // value select (a ternary on lvalues would select addresses and spill)
 template <class T> __device__ __forceinline__ Cx<T> sel(bool c, Cx<T> x, Cx<T> y) {
@@ -655,10 +659,16 @@ __device__ __forceinline__ void two_step_tile_r(char *kog_smem, int N, T *__rest
   };
   ColPair<T> prev1P{zero, zero}, prev1Q{zero, zero}, prev2m{zero, zero}, firstc{zero, zero};
   if (has) {
-    Blk nx = load_blk(aw);  // the block of the next iteration is in flight
+    // the blocks of the next D iterations are in flight
+    constexpr int D = two_step_depth<T, CPLX>();
+    Blk q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = aw + d <= bw ? load_blk(aw + d) : Blk{zero, zero, zero, zero};
     for (int jj = aw; jj <= bw; ++jj) {
-      const Blk a = nx;
-      if (jj < bw) nx = load_blk(jj + 1);
+      const Blk a = q[0];
+#pragma unroll
+      for (int d = 0; d + 1 < D; ++d) q[d] = q[d + 1];
+      if (jj + D <= bw) q[D - 1] = load_blk(jj + D);
       // step t on the block (j, jj), in (p, q) order
       int Pc, Qc;
       rows_at(t, jj, Mo, Pc, Qc);

@@ -42,15 +42,30 @@ template <> struct Vec2<float> { typedef f2v type; };
 template <class T> __device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
 // ---------------------------------------------------------------------------
-// loads / stores of PT consecutive matrices per lane
+// loads / stores of PT consecutive matrices per lane (PT = 2: 16-byte
+// accesses; the host launches that form on an even count only).  k is the
+// matrix index within one launch, whose arrays span at most kChunkBytes, so
+// every access is an array base (the same for the whole grid, held in scalar
+// registers) plus one 32-bit byte offset shared by all arrays: no per-array
+// 64-bit address arithmetic on the vector ALUs.
 // ---------------------------------------------------------------------------
+constexpr size_t kChunkBytes = size_t(1) << 30;
+
+template <class P> __device__ __forceinline__ const P *at(const P *base, uint32_t off) {
+  return reinterpret_cast<const P *>(reinterpret_cast<const char *>(base) + off);
+}
+template <class P> __device__ __forceinline__ P *at(P *base, uint32_t off) {
+  return reinterpret_cast<P *>(reinterpret_cast<char *>(base) + off);
+}
+
 template <class T, int N, int PT>
-__device__ __forceinline__ void load_lanes(const T *const (&in)[N], size_t k, int cnt, T (&x)[PT][N]) {
-  if (PT == 2 && cnt == 2) {
+__device__ __forceinline__ void load_lanes(const T *const (&in)[N], uint32_t k, int cnt, T (&x)[PT][N]) {
+  const uint32_t off = k * (uint32_t)sizeof(T);
+  if constexpr (PT == 2) {
     typedef typename Vec2<T>::type V;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      V v = *reinterpret_cast<const V *>(in[i] + k);
+      V v = *at(reinterpret_cast<const V *>(in[i]), off);
       x[0][i] = v.x;
       x[PT - 1][i] = v.y;
     }
@@ -58,28 +73,29 @@ __device__ __forceinline__ void load_lanes(const T *const (&in)[N], size_t k, in
 #pragma unroll
     for (int j = 0; j < PT; ++j)
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[j][i] = (j < cnt) ? in[i][k + j] : T(0);
+      for (int i = 0; i < N; ++i) x[j][i] = (j < cnt) ? at(in[i], off)[j] : T(0);
   }
 }
 
 // outputs LO .. N-1 only (LO = N-3: sigma'_max, sigma'_min, s)
 template <class T, int N, int PT, int LO = 0>
-__device__ __forceinline__ void store_lanes(T *const (&out)[N], size_t k, int cnt, const T (&y)[PT][N]) {
-  if (PT == 2 && cnt == 2) {
+__device__ __forceinline__ void store_lanes(T *const (&out)[N], uint32_t k, int cnt, const T (&y)[PT][N]) {
+  const uint32_t off = k * (uint32_t)sizeof(T);
+  if constexpr (PT == 2) {
     typedef typename Vec2<T>::type V;
 #pragma unroll
     for (int i = LO; i < N; ++i) {
       V v;
       v.x = y[0][i];
       v.y = y[PT - 1][i];
-      st_nt(reinterpret_cast<V *>(out[i] + k), v);
+      st_nt(at(reinterpret_cast<V *>(out[i]), off), v);
     }
   } else {
 #pragma unroll
     for (int j = 0; j < PT; ++j)
       if (j < cnt) {
 #pragma unroll
-        for (int i = LO; i < N; ++i) st_nt(out[i] + k + j, y[j][i]);
+        for (int i = LO; i < N; ++i) st_nt(at(out[i], off) + j, y[j][i]);
       }
   }
 }
@@ -95,13 +111,16 @@ __device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
 // and V are neither stored nor, since nothing uses them, computed (the
 // assembly of eq. (29) and its FP64 counterpart in the rescue drop out).
 // ---------------------------------------------------------------------------
+// One launch covers the n matrices of one chunk (at most kChunkBytes per
+// array); k0 is the chunk's first matrix in the whole batch (queue entries
+// are whole-batch indices).
 template <class T, bool CPLX, int PT, int RESCUE, bool UV, bool SINE>
-__global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
+__global__ __launch_bounds__(256) void svd2_kernel(uint32_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
                                                    int bs, uint32_t *nresc, uint32_t *queue,
-                                                   uint32_t *qcount) {
+                                                   uint32_t *qcount, uint32_t k0) {
   constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, LO = UV ? 0 : NOUT - 3;
-  size_t k = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
-  int cnt = (k < n) ? (int)((n - k < (size_t)PT) ? (n - k) : PT) : 0;
+  const uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  int cnt = (k < n) ? (int)((n - k < (uint32_t)PT) ? (n - k) : PT) : 0;
   T x[PT][NIN], y[PT][NOUT];
   bool fl[PT];
   if (cnt > 0) load_lanes<T, NIN, PT>(a.in, k, cnt, x);
@@ -124,7 +143,7 @@ __global__ __launch_bounds__(256) void svd2_kernel(size_t n, KArgs<T, CPLX ? 8 :
         unsigned base = 0;
         if (lane == first) base = atomicAdd(qcount, total);
         base = __shfl(base, (int)first);
-        if (fl[j]) queue[base + lane_prefix(m)] = (uint32_t)(k + j);
+        if (fl[j]) queue[base + lane_prefix(m)] = k0 + k + (uint32_t)j;
       }
     }
   }
@@ -227,18 +246,33 @@ template <class T, bool CPLX, int RESCUE, bool UV, bool SINE>
 svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
                    uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
   constexpr int kind = kind_of<T, CPLX>() + (UV ? 0 : 4);
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11;
+  constexpr size_t chunk = kChunkBytes / sizeof(T);  // matrices per launch (even)
   int block = g_block[kind].load(), pt = g_per_thread[kind].load();
   if (pt == 2 && !all_aligned16(a, UV)) pt = 1;
-  size_t lanes = (n + pt - 1) / pt;
-  size_t grid = (lanes + block - 1) / block;
-  if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
-  if (pt == 2)
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
-                       n, a, bs, nresc, queue, qcount);
-  else
-    hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
-                       n, a, bs, nresc, queue, qcount);
-  return hip_status(hipGetLastError());
+  // launches of m matrices from matrix c0 on: two matrices per lane over an
+  // even count, one per lane for the rest
+  auto go = [&](size_t c0, size_t m, int p) {
+    KArgs<T, NIN, NOUT> ac = a;
+    for (int i = 0; i < NIN; ++i) ac.in[i] = a.in[i] + c0;
+    for (int i = 0; i < NOUT; ++i) ac.out[i] = a.out[i] + c0;
+    const size_t grid = (m / p + block - 1) / block;
+    if (p == 2)
+      hipLaunchKernelGGL((svd2_kernel<T, CPLX, 2, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
+                         (uint32_t)m, ac, bs, nresc, queue, qcount, (uint32_t)c0);
+    else
+      hipLaunchKernelGGL((svd2_kernel<T, CPLX, 1, RESCUE, UV, SINE>), dim3((unsigned)grid), dim3(block), 0, st,
+                         (uint32_t)m, ac, bs, nresc, queue, qcount, (uint32_t)c0);
+    return hip_status(hipGetLastError());
+  };
+  for (size_t c0 = 0; c0 < n; c0 += chunk) {
+    const size_t m = n - c0 < chunk ? n - c0 : chunk;
+    const size_t m2 = pt == 2 ? m & ~size_t(1) : 0;
+    svd2_status s = m2 ? go(c0, m2, 2) : SVD2_OK;
+    if (s == SVD2_OK && m > m2) s = go(c0 + m2, m - m2, 1);
+    if (s != SVD2_OK) return s;
+  }
+  return SVD2_OK;
 }
 
 // uv: U and V are wanted (else SVD2_NO_UV); sine: assembled by eq. (31)
@@ -311,9 +345,9 @@ svd2_status probe(int op, size_t n, const T *x, const T *y, const T *z, T *out,
 // arithmetic (each output = sum of the inputs + its index), same launch shape
 // ---------------------------------------------------------------------------
 template <class T, int NIN, int NOUT, int PT>
-__global__ __launch_bounds__(256) void stream_probe_kernel(size_t n, KArgs<T, NIN, NOUT> a) {
-  size_t k = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * PT;
-  int cnt = (k < n) ? (int)((n - k < (size_t)PT) ? (n - k) : PT) : 0;
+__global__ __launch_bounds__(256) void stream_probe_kernel(uint32_t n, KArgs<T, NIN, NOUT> a) {
+  const uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * PT;
+  int cnt = (k < n) ? (int)((n - k < (uint32_t)PT) ? (n - k) : PT) : 0;
   if (cnt == 0) return;
   T x[PT][NIN], y[PT][NOUT];
   load_lanes<T, NIN, PT>(a.in, k, cnt, x);
@@ -337,13 +371,28 @@ svd2_status stream_probe(size_t n, const void *const *in, void *const *out, hipS
   if (s != SVD2_OK || n == 0) return s;
   int block = g_block[kind].load(), pt = g_per_thread[kind].load();
   if (pt == 2 && !all_aligned16(a)) pt = 1;
-  size_t lanes = (n + pt - 1) / pt, grid = (lanes + block - 1) / block;
-  if (grid > 0x7fffffffu) return SVD2_ERR_SIZE;
-  if (pt == 2)
-    hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 2>), dim3((unsigned)grid), dim3(block), 0, st, n, a);
-  else
-    hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 1>), dim3((unsigned)grid), dim3(block), 0, st, n, a);
-  return hip_status(hipGetLastError());
+  constexpr size_t chunk = kChunkBytes / sizeof(T);
+  auto go = [&](size_t c0, size_t m, int p) {
+    KArgs<T, NIN, NOUT> ac = a;
+    for (int i = 0; i < NIN; ++i) ac.in[i] = a.in[i] + c0;
+    for (int i = 0; i < NOUT; ++i) ac.out[i] = a.out[i] + c0;
+    const size_t grid = (m / p + block - 1) / block;
+    if (p == 2)
+      hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 2>), dim3((unsigned)grid), dim3(block), 0, st,
+                         (uint32_t)m, ac);
+    else
+      hipLaunchKernelGGL((stream_probe_kernel<T, NIN, NOUT, 1>), dim3((unsigned)grid), dim3(block), 0, st,
+                         (uint32_t)m, ac);
+    return hip_status(hipGetLastError());
+  };
+  for (size_t c0 = 0; c0 < n; c0 += chunk) {
+    const size_t m = n - c0 < chunk ? n - c0 : chunk;
+    const size_t m2 = pt == 2 ? m & ~size_t(1) : 0;
+    svd2_status s = m2 ? go(c0, m2, 2) : SVD2_OK;
+    if (s == SVD2_OK && m > m2) s = go(c0 + m2, m - m2, 1);
+    if (s != SVD2_OK) return s;
+  }
+  return SVD2_OK;
 }
 
 }  // namespace

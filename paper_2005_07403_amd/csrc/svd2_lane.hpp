@@ -151,6 +151,10 @@ template <class T> __device__ __forceinline__ Cx<T> phase(Cx<T> z, T az) {
 // Section 2.1, eq. (2), Fig. 3.  s = min over components of h - exp2(x), with
 // zero components ignored; all-zero -> s = BIG.  Kept as an int (sentinel
 // INT_MAX for BIG); ldexp(0, INT_MAX) = 0, so the scaling needs no branch.
+// exp2 (the frexp exponent, true also for subnormals) never decreases as |x|
+// grows, so the minimum is taken at the component of largest magnitude:
+// s = scale_exp(max |x|), one exponent instead of one per component (a zero
+// component never attains the maximum unless all are zero).
 // ---------------------------------------------------------------------------
 constexpr int kSBig = 0x7fffffff;
 template <class T> __device__ __forceinline__ int scale_exp(T x) {
@@ -246,7 +250,7 @@ template <class T, bool SINE = false>
 __device__ __forceinline__ void real_lane(T a11, T a21, T a12, T a22, RealRes<T> &o) {
   const T one = T(1);
   // scaling (eq. (2), Fig. 3)
-  int s = min(min(scale_exp(a11), scale_exp(a21)), min(scale_exp(a12), scale_exp(a22)));
+  int s = scale_exp(vmax(vmax(vabs(a11), vabs(a21)), vmax(vabs(a12), vabs(a22))));
   T b11 = vldexp(a11, s), b21 = vldexp(a21, s), b12 = vldexp(a12, s), b22 = vldexp(a22, s);
   o.s = s;
   o.ah11 = b11; o.ah21 = b21; o.ah12 = b12; o.ah22 = b22;
@@ -341,9 +345,10 @@ __device__ __forceinline__ void cplx_assemble(const Tri<W> &t, W mt, W ca, Cx<W>
 template <class T, bool SINE = false>
 __device__ __forceinline__ void cplx_lane(const T *a, CplxRes<T> &o) {
   const T one = T(1);
-  int s = scale_exp(a[0]);
+  T amax = vabs(a[0]);
 #pragma unroll
-  for (int i = 1; i < 8; ++i) s = min(s, scale_exp(a[i]));
+  for (int i = 1; i < 8; ++i) amax = vmax(amax, vabs(a[i]));
+  const int s = scale_exp(amax);
   o.s = s;
   Cx<T> b11 = {vldexp(a[0], s), vldexp(a[1], s)}, b21 = {vldexp(a[2], s), vldexp(a[3], s)};
   Cx<T> b12 = {vldexp(a[4], s), vldexp(a[5], s)}, b22 = {vldexp(a[6], s), vldexp(a[7], s)};

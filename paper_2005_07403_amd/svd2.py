@@ -78,6 +78,10 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing; build it with "
                                "python paper_2005_07403_amd/build.py (no CPU fallback exists)")
+        # torch first: its HIP runtime must be the process's one, which the
+        # library then shares (loaded the other way round, the library's calls
+        # report hipErrorNoDevice once torch has initialised the GPU)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         sz, ui, i = ctypes.c_size_t, ctypes.c_uint, ctypes.c_int
         L.dsvd2_batch.argtypes = [sz, ctypes.POINTER(dsvd2_args), ui, _P]

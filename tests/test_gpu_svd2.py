@@ -445,6 +445,46 @@ def test_fp32_full_size_2_26_sampled(cplx):
     assert st["bitwise_lanes"] == st["lanes"]
 
 
+@pytest.mark.slow
+def test_fp32_batch_over_several_launches():
+    """A batch longer than one launch's span (2^30 bytes per array, 2^28
+    FP32 matrices): n = 2^28 + 3 real FP32 matrices, two matrices per lane
+    with a one-matrix tail.  The lanes around the boundary between launches
+    and a random sample elsewhere are bitwise the oracle's; the queued rescue
+    (whole-batch queue indices) gives byte for byte the in-place rescue's
+    outputs and the same rescued-lane count."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    S.svd2_set_launch_kind("s", 256, 2)
+    n = (1 << 28) + 3
+    A = scaled_law(n, SEED_BASE + 61, False, dtype=np.float32)
+    tr = to_trains(A)
+    del A
+    dev = [torch.from_numpy(t).cuda() for t in tr]
+    cnt1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cnt2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out1 = S.svd2(dev, flags=S.SVD2_RESCUE_FP64, nrescued=cnt1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(SEED_BASE + 62)
+    idx = np.unique(np.concatenate([np.arange((1 << 28) - 300, n), np.arange(0, 64),
+                                    rng.choice(n, 1 << 18, replace=False)]))
+    tidx = torch.from_numpy(idx).cuda()
+    gpu = [o[tidx].cpu().numpy() for o in out1]
+    sub = [np.ascontiguousarray(t[idx]) for t in tr]
+    ora, _ = oracle_outs(sub, False, np.float32, rescue=True)
+    st = compare(gpu, ora, False, EPS[np.float32])
+    assert st["bitwise_lanes"] == st["lanes"], st
+    del gpu
+    ws = torch.empty(S.svd2_workspace_bytes(n, S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE), dtype=torch.uint8,
+                     device="cuda")
+    out2 = S.svd2(dev, flags=S.SVD2_RESCUE_FP64 | S.SVD2_RESCUE_QUEUE, ws=ws, nrescued=cnt2)
+    torch.cuda.synchronize()
+    assert int(cnt1.item()) == int(cnt2.item()) > 0
+    for a, b in zip(out1, out2):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    S.svd2_set_launch(256, 1)
+
+
 # ---------------------------------------------------------------------------
 # singular values only (SVD2_NO_UV)
 # ---------------------------------------------------------------------------
