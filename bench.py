@@ -389,6 +389,45 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
     return out
 
 
+def barrier_bench():
+    """What a grid barrier of the fused Kogbetliantz kernel costs: cooperative
+    launches of 1, 2 and 4 workgroups per CU that pass 0 or 1000 barriers and
+    do nothing else (median of HIP-event times on the launch stream), beside
+    the cost of a plain kernel launch (100 back-to-back launches of the small
+    memory-pattern probe)."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    ws = torch.empty(256 + 4096 * 64, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def median_ms(fn, reps=15):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"cus": cus, "workgroup_threads": 256}
+    for per in (1, 2, 4):
+        blocks = per * cus
+        t0 = median_ms(lambda: S.kog_barrier_probe(0, blocks, ws))
+        t1 = median_ms(lambda: S.kog_barrier_probe(1000, blocks, ws))
+        out[f"blocks_{blocks}"] = {"empty_launch_us": t0 * 1e3, "us_per_barrier": (t1 - t0)}
+        log(f"[bench] barrier, {blocks} workgroups: {json.dumps(out[f'blocks_{blocks}'])}")
+    x = [torch.ones(256, dtype=torch.float64, device="cuda") for _ in range(8)]
+    y = [torch.empty(256, dtype=torch.float64, device="cuda") for _ in range(19)]
+    t2 = median_ms(lambda: [S.svd2_stream_probe("z", x, y) for _ in range(100)])
+    out["plain_launch_us"] = t2 / 100 * 1e3
+    log(f"[bench] plain launch: {out['plain_launch_us']:.2f} us")
+    return out
+
+
 def kog_svd_bench(A, s, G0, mat, steps, passes, full: bool = True):
     """The full SVD A_0 = U diag(sigma) V^* (transformations accumulated, two
     steps per pass) on the one-problem workload: one sweep and a full solve,
@@ -621,6 +660,8 @@ def main():
                     help="also write the full result (every launch figure, every uneven-batch problem) to PATH")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--barrier-probe", action="store_true",
+                    help="time the fused Kogbetliantz kernel's grid barrier alone; prints its JSON")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -649,6 +690,9 @@ def main():
         log("copy calibration: 3 copies of 1 GiB done")
         return
 
+    if args.barrier_probe:
+        print(json.dumps(barrier_bench()), flush=True)
+        return
     if args.kog_only:
         out = kog_bench(args.kog_order, sweeps=1, solve=False, only=args.kog_only.split(","))
         print(json.dumps(out), flush=True)
@@ -796,5 +840,15 @@ def main():
     emit(full, args.detail_out)
 
 
+def child_processes() -> int:
+    """processes this one started that are still there (there should be none)"""
+    try:
+        import psutil
+        return len(psutil.Process().children(recursive=True))
+    except Exception:
+        return -1
+
+
 if __name__ == "__main__":
     main()
+    log(f"[bench] child processes left: {child_processes()}")

@@ -197,6 +197,15 @@ __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX
   }
 }
 
+// Diagnostic: nbar grid barriers and nothing else, with the fused kernel's
+// barrier and workgroup size; its time per barrier is what each of the fused
+// kernel's two barriers per step costs.
+__global__ __launch_bounds__(kUpdBlock) void kog_barrier_probe_kernel(Bar *bar, unsigned *flags, int nbar) {
+  unsigned epoch = 0;
+  for (int i = 0; i < nbar; ++i)
+    if (!grid_sync(bar, flags, gridDim.x, epoch)) return;
+}
+
 __global__ void kog_bar_reset_kernel(Bar *bar, unsigned *flags, int nflags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
@@ -1126,6 +1135,29 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
     g_nrules2 = 1;
   }
   return SVD2_OK;
+}
+
+svd2_status kog_barrier_probe(int nbar, int blocks, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!ws) return SVD2_ERR_NULL;
+  if (nbar < 0 || blocks < 1 || blocks > kMaxFusedBlocks) return SVD2_ERR_SIZE;
+  if (ws_bytes < 256 + (size_t)kMaxFusedBlocks * 64) return SVD2_ERR_SIZE;
+  if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
+  int dev = 0, cus = 0, per = 0;
+  svd2_status s = hip_st(hipGetDevice(&dev));
+  if (s == SVD2_OK) s = hip_st(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (s == SVD2_OK)
+    s = hip_st(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kog_barrier_probe_kernel, kUpdBlock,
+                                                            0));
+  if (s != SVD2_OK) return s;
+  if ((long)blocks > (long)per * cus) return SVD2_ERR_SIZE;  // not all co-resident
+  Bar *bar = (Bar *)ws;
+  unsigned *flags = (unsigned *)((char *)ws + 256);
+  hipLaunchKernelGGL(kog_bar_reset_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bar, flags, blocks);
+  s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  void *args[] = {&bar, &flags, &nbar};
+  return hip_st(hipLaunchCooperativeKernel((const void *)kog_barrier_probe_kernel, dim3(blocks), dim3(kUpdBlock), args,
+                                           0, stream));
 }
 
 svd2_status kog_set_fused_blocks_per_cu(int per_cu) {

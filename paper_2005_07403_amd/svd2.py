@@ -65,7 +65,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
            "kog_batch_workspace_bytes_flags", "kog_sigma_workspace_bytes", "dkog_sigma", "zkog_sigma",
            "skog_sigma", "ckog_sigma", "kog_svd_workspace_bytes", "dkog_svd", "zkog_svd", "skog_svd",
-           "ckog_svd", "dkog_solve_noalloc",
+           "ckog_svd", "dkog_solve_noalloc", "kog_barrier_probe",
            "svd2_set_launch", "svd2_get_launch", "svd2_set_launch_kind", "svd2_get_launch_kind",
            "svd2_status_string", "svd2_last_hip_error",
            "svd2_probe_f64", "svd2_probe_f32", "svd2_stream_probe"]
@@ -322,6 +322,8 @@ def _kog():
         L.kog_set_fused_blocks_per_cu.restype = i
         L.dkog_solve_noalloc.argtypes = [i, _P, i, d, i, _P, _P, ui, _P]
         L.dkog_solve_noalloc.restype = i
+        L.kog_barrier_probe.argtypes = [i, i, _P, sz, _P]
+        L.kog_barrier_probe.restype = i
         _kog_ready = True
     return L
 
@@ -409,6 +411,13 @@ def kog_solve_noalloc(A, tol: float = 1e-14, max_sweeps: int = 40, flags: int = 
                                    _stream(stream))
     _kog_check("dkog_solve_noalloc", st)
     return dict(status=st, sweeps=sw.value, off_rel=off.value)
+
+
+def kog_barrier_probe(nbar: int, blocks: int, ws, stream=None) -> None:
+    """Diagnostic: one cooperative launch of `blocks` workgroups passing nbar
+    grid barriers (ws: a device uint8 tensor of >= 256 + 4096 * 64 bytes)."""
+    _kog_check("kog_barrier_probe", _kog().kog_barrier_probe(nbar, blocks, ws.data_ptr(), _nbytes(ws),
+                                                             _stream(stream)))
 
 
 def kog_sigma(A, out=None, ws=None, stream=None):

@@ -211,6 +211,18 @@ def test_kog_solve_noalloc_argument_errors():
     assert call(1 << 20, A, 1 << 20, 1) == 6
 
 
+def test_kog_barrier_probe_argument_errors():
+    """The barrier probe checks its arguments before any HIP call."""
+    L = S._kog()
+    ws, wsb = FAKE, 256 + 4096 * 64
+    assert L.kog_barrier_probe(10, 256, 0, wsb, None) == 1       # NULL workspace
+    assert L.kog_barrier_probe(-1, 256, ws, wsb, None) == 6      # negative count
+    assert L.kog_barrier_probe(10, 0, ws, wsb, None) == 6        # no workgroups
+    assert L.kog_barrier_probe(10, 4097, ws, wsb, None) == 6     # beyond the barrier's slots
+    assert L.kog_barrier_probe(10, 256, ws, wsb - 1, None) == 6  # short workspace
+    assert L.kog_barrier_probe(10, 256, ws + 8, wsb, None) == 2  # misaligned workspace
+
+
 def test_kog_svd_argument_errors():
     """The SVD entry points validate every pointer, size, flag and overlap
     before any HIP call."""

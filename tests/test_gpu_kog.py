@@ -334,3 +334,18 @@ def test_caller_workspace_in_bytes(kind):
     r2 = S.kog_solve(G2, ws=torch.empty(need // 8, dtype=torch.float64, device="cuda"), flags=flags)
     torch.cuda.synchronize()
     assert r1["sweeps"] == r2["sweeps"] and _same(G.cpu().numpy(), G2.cpu().numpy())
+
+
+def test_barrier_probe_completes():
+    """The grid-barrier probe (a cooperative launch that passes barriers and
+    does nothing else) completes for 1 and 2 workgroups per CU, and refuses
+    more workgroups than the GPU holds at once."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    ws = torch.empty(256 + 4096 * 64, dtype=torch.uint8, device="cuda")
+    for blocks in (cus, 2 * cus):
+        S.kog_barrier_probe(50, blocks, ws)
+        torch.cuda.synchronize()
+    with pytest.raises(S.Svd2Error):
+        S.kog_barrier_probe(1, 4096 + 1, ws)
