@@ -643,6 +643,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kog", action="store_true", help="skip the Kogbetliantz measurement")
     ap.add_argument("--kog-order", type=int, default=4096)
+    ap.add_argument("--kog-sweeps", type=int, default=1,
+                    help="sweeps timed per driver with --kog-only (from the same starting matrix)")
+    ap.add_argument("--kog-fused-per-cu", type=int, default=None,
+                    help="workgroups per CU of the fused Kogbetliantz kernel (1-16; default: the library's)")
     ap.add_argument("--no-kog-batch", action="store_true", help="skip the uneven Kogbetliantz batch")
     ap.add_argument("--kog-batch", type=int, default=256, help="problems in the uneven batch")
     ap.add_argument("--kog-batch-only", action="store_true",
@@ -690,11 +694,14 @@ def main():
         log("copy calibration: 3 copies of 1 GiB done")
         return
 
+    if args.kog_fused_per_cu is not None and S._kog().kog_set_fused_blocks_per_cu(args.kog_fused_per_cu) != 0:
+        print(f"bench.py: --kog-fused-per-cu {args.kog_fused_per_cu} is out of range (1-16)", file=sys.stderr)
+        sys.exit(2)
     if args.barrier_probe:
         print(json.dumps(barrier_bench()), flush=True)
         return
     if args.kog_only:
-        out = kog_bench(args.kog_order, sweeps=1, solve=False, only=args.kog_only.split(","))
+        out = kog_bench(args.kog_order, sweeps=args.kog_sweeps, solve=False, only=args.kog_only.split(","))
         print(json.dumps(out), flush=True)
         return
     if args.kog_svd_only:

@@ -436,11 +436,16 @@ svd2_status kog_set_fused_blocks_per_cu(int per_cu);
 /* Diagnostic: one cooperative launch of `blocks` workgroups of the fused
    kernel's size that pass nbar grid barriers (the fused kernel's barrier) and
    do nothing else, so that (time - time with nbar = 0) / nbar is the cost of
-   one barrier.  ws: device, >= 256 + 4096 * 64 bytes, 256-byte aligned.
+   one barrier.  violations: optional device counter (the caller zeroes it);
+   when not NULL the barrier is checked by its epoch counters -- after barrier
+   e every workgroup reads every workgroup's published epoch, which must be at
+   least e -- and each one found behind, and each aborted wait, adds 1 (0 for
+   a correct barrier).  ws: device, >= 256 + 4096 * 64 bytes, 256-byte aligned.
    SVD2_ERR_SIZE if blocks exceeds 4096 or what the GPU holds at once, nbar < 0
    or ws_bytes is short.  Asynchronous on `stream`; spins are bounded as in the
    fused kernel. */
-svd2_status kog_barrier_probe(int nbar, int blocks, void *ws, size_t ws_bytes, hipStream_t stream);
+svd2_status kog_barrier_probe(int nbar, int blocks, unsigned *violations, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
 /* Update-tile shapes by order (set by the autotuner): for an order N the
    first rule i with N <= max_order[i] applies; a tile covers kc[i] row pairs
    (64, 128 or 256) and lc[i] column pairs (1..4096) on one 256-thread

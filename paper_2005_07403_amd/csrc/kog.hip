@@ -199,11 +199,26 @@ __global__ __launch_bounds__(kUpdBlock) void kog_fused_kernel(int N, Mat<T, CPLX
 
 // Diagnostic: nbar grid barriers and nothing else, with the fused kernel's
 // barrier and workgroup size; its time per barrier is what each of the fused
-// kernel's two barriers per step costs.
-__global__ __launch_bounds__(kUpdBlock) void kog_barrier_probe_kernel(Bar *bar, unsigned *flags, int nbar) {
+// kernel's two barriers per step costs.  With `violations`, the barrier is
+// also checked by its epochs: after barrier e every workgroup reads every
+// workgroup's published epoch, which must already be >= e (a workgroup that
+// had not arrived would show e - 1), and counts those that are not; an
+// aborted wait counts once more.
+__global__ __launch_bounds__(kUpdBlock) void kog_barrier_probe_kernel(Bar *bar, unsigned *flags, int nbar,
+                                                                       unsigned *violations) {
   unsigned epoch = 0;
-  for (int i = 0; i < nbar; ++i)
-    if (!grid_sync(bar, flags, gridDim.x, epoch)) return;
+  for (int i = 0; i < nbar; ++i) {
+    if (!grid_sync(bar, flags, gridDim.x, epoch)) {
+      if (violations && threadIdx.x == 0) atomicAdd(violations, 1u);
+      return;
+    }
+    if (violations) {
+      unsigned late = 0;
+      for (unsigned g = threadIdx.x; g < gridDim.x; g += blockDim.x)
+        late += __hip_atomic_load(&flags[16 * g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch ? 1u : 0u;
+      if (late) atomicAdd(violations, late);
+    }
+  }
 }
 
 __global__ void kog_bar_reset_kernel(Bar *bar, unsigned *flags, int nflags) {
@@ -1137,7 +1152,8 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
   return SVD2_OK;
 }
 
-svd2_status kog_barrier_probe(int nbar, int blocks, void *ws, size_t ws_bytes, hipStream_t stream) {
+svd2_status kog_barrier_probe(int nbar, int blocks, unsigned *violations, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
   if (!ws) return SVD2_ERR_NULL;
   if (nbar < 0 || blocks < 1 || blocks > kMaxFusedBlocks) return SVD2_ERR_SIZE;
   if (ws_bytes < 256 + (size_t)kMaxFusedBlocks * 64) return SVD2_ERR_SIZE;
@@ -1155,7 +1171,7 @@ svd2_status kog_barrier_probe(int nbar, int blocks, void *ws, size_t ws_bytes, h
   hipLaunchKernelGGL(kog_bar_reset_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bar, flags, blocks);
   s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
-  void *args[] = {&bar, &flags, &nbar};
+  void *args[] = {&bar, &flags, &nbar, &violations};
   return hip_st(hipLaunchCooperativeKernel((const void *)kog_barrier_probe_kernel, dim3(blocks), dim3(kUpdBlock), args,
                                            0, stream));
 }

@@ -322,7 +322,7 @@ def _kog():
         L.kog_set_fused_blocks_per_cu.restype = i
         L.dkog_solve_noalloc.argtypes = [i, _P, i, d, i, _P, _P, ui, _P]
         L.dkog_solve_noalloc.restype = i
-        L.kog_barrier_probe.argtypes = [i, i, _P, sz, _P]
+        L.kog_barrier_probe.argtypes = [i, i, _P, _P, sz, _P]
         L.kog_barrier_probe.restype = i
         _kog_ready = True
     return L
@@ -413,10 +413,15 @@ def kog_solve_noalloc(A, tol: float = 1e-14, max_sweeps: int = 40, flags: int = 
     return dict(status=st, sweeps=sw.value, off_rel=off.value)
 
 
-def kog_barrier_probe(nbar: int, blocks: int, ws, stream=None) -> None:
+def kog_barrier_probe(nbar: int, blocks: int, ws, violations=None, stream=None) -> None:
     """Diagnostic: one cooperative launch of `blocks` workgroups passing nbar
-    grid barriers (ws: a device uint8 tensor of >= 256 + 4096 * 64 bytes)."""
-    _kog_check("kog_barrier_probe", _kog().kog_barrier_probe(nbar, blocks, ws.data_ptr(), _nbytes(ws),
+    grid barriers (ws: a device uint8 tensor of >= 256 + 4096 * 64 bytes);
+    violations (optional device int32 tensor of one element, zeroed by the
+    caller) receives the count of epoch-check failures."""
+    v = 0 if violations is None else violations.data_ptr()
+    if violations is not None:
+        _like(violations, "violations", violations.dtype, violations.device, 1)
+    _kog_check("kog_barrier_probe", _kog().kog_barrier_probe(nbar, blocks, v, ws.data_ptr(), _nbytes(ws),
                                                              _stream(stream)))
 
 

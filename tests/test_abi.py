@@ -215,12 +215,12 @@ def test_kog_barrier_probe_argument_errors():
     """The barrier probe checks its arguments before any HIP call."""
     L = S._kog()
     ws, wsb = FAKE, 256 + 4096 * 64
-    assert L.kog_barrier_probe(10, 256, 0, wsb, None) == 1       # NULL workspace
-    assert L.kog_barrier_probe(-1, 256, ws, wsb, None) == 6      # negative count
-    assert L.kog_barrier_probe(10, 0, ws, wsb, None) == 6        # no workgroups
-    assert L.kog_barrier_probe(10, 4097, ws, wsb, None) == 6     # beyond the barrier's slots
-    assert L.kog_barrier_probe(10, 256, ws, wsb - 1, None) == 6  # short workspace
-    assert L.kog_barrier_probe(10, 256, ws + 8, wsb, None) == 2  # misaligned workspace
+    assert L.kog_barrier_probe(10, 256, None, 0, wsb, None) == 1       # NULL workspace
+    assert L.kog_barrier_probe(-1, 256, None, ws, wsb, None) == 6      # negative count
+    assert L.kog_barrier_probe(10, 0, None, ws, wsb, None) == 6        # no workgroups
+    assert L.kog_barrier_probe(10, 4097, None, ws, wsb, None) == 6     # beyond the barrier's slots
+    assert L.kog_barrier_probe(10, 256, None, ws, wsb - 1, None) == 6  # short workspace
+    assert L.kog_barrier_probe(10, 256, None, ws + 8, wsb, None) == 2  # misaligned workspace
 
 
 def test_kog_svd_argument_errors():

@@ -336,16 +336,24 @@ def test_caller_workspace_in_bytes(kind):
     assert r1["sweeps"] == r2["sweeps"] and _same(G.cpu().numpy(), G2.cpu().numpy())
 
 
-def test_barrier_probe_completes():
-    """The grid-barrier probe (a cooperative launch that passes barriers and
-    does nothing else) completes for 1 and 2 workgroups per CU, and refuses
-    more workgroups than the GPU holds at once."""
+def test_barrier_probe_epochs():
+    """The fused kernel's grid barrier, checked by its epoch counters in the
+    barrier probe: after each of 200 barriers every workgroup sees every
+    other's epoch at the barrier's (no workgroup released early, no wait
+    aborted), for 1, 2 and 4 workgroups per CU; a barrier-free launch and a
+    grid larger than the barrier's slots are handled."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     ws = torch.empty(256 + 4096 * 64, dtype=torch.uint8, device="cuda")
-    for blocks in (cus, 2 * cus):
-        S.kog_barrier_probe(50, blocks, ws)
+    viol = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for blocks in (cus, 2 * cus, 4 * cus):
+        viol.zero_()
+        S.kog_barrier_probe(200, blocks, ws, violations=viol)
         torch.cuda.synchronize()
+        assert int(viol.item()) == 0, blocks
+    S.kog_barrier_probe(0, cus, ws, violations=viol)
+    torch.cuda.synchronize()
+    assert int(viol.item()) == 0
     with pytest.raises(S.Svd2Error):
         S.kog_barrier_probe(1, 4096 + 1, ws)
