@@ -78,13 +78,15 @@ template <class T> __device__ __forceinline__ T flip(bool neg, T a) { return neg
 //  - FP64 sqrt: the hardware reciprocal-root estimate y, g = x y, h = y/2,
 //    one coupled Newton step on (g, h), then two corrections
 //    g += (x - g^2) h;
-//  - 1/x: the hardware reciprocal estimate r, Newton steps on r, and the
-//    quotient q = r corrected by q += (1 - x q) r, twice.
-// These are the operations the compiler's own correctly rounded sqrt and
-// division perform on that domain, so the results are the correctly rounded
-// ones bit for bit (checked by the primitive probe: FP32 on every argument of
-// the domain, FP64 on samples).  Non-finite inputs give unspecified lanes
-// anyway, as with the general sequences.
+//  - 1/x in FP64: the hardware reciprocal estimate r, Newton steps on r, and
+//    the quotient q = r corrected by q += (1 - x q) r;
+//  - 1/x in FP32: see vrcp_ge1 below.
+// The square roots and the FP64 reciprocal are the operations the compiler's
+// own correctly rounded sqrt and division perform on that domain, so the
+// results are the correctly rounded ones bit for bit (checked by the
+// primitive probe: FP32 on every argument of the domain, FP64 on samples).
+// Non-finite inputs give unspecified lanes anyway, as with the general
+// sequences.
 __device__ __forceinline__ float vsqrt_ge1(float x) {
   const float s = __builtin_amdgcn_sqrtf(x);
   const float sd = __builtin_bit_cast(float, __builtin_bit_cast(int, s) - 1);
@@ -102,11 +104,14 @@ __device__ __forceinline__ double vsqrt_ge1(double x) {
   g = vfma(vfma(-g, g, x), h, g);
   return vfma(vfma(-g, g, x), h, g);
 }
+// FP32 reciprocal through FP64: the hardware FP64 reciprocal estimate of x
+// after one Newton step, rounded to FP32.  Its relative error (about 2^-48.7
+// at worst over all FP32 x) is no proof of correct rounding by itself, so
+// the domain is settled by enumeration: the probe compares it with the
+// correctly rounded division 1/x on every FP32 x in [1, 2^126).
 __device__ __forceinline__ float vrcp_ge1(float x) {
-  float r = __builtin_amdgcn_rcpf(x);
-  r = vfma(vfma(-x, r, 1.0f), r, r);
-  float q = vfma(vfma(-x, r, 1.0f), r, r);
-  return vfma(vfma(-x, q, 1.0f), r, q);
+  const double d = x, r = __builtin_amdgcn_rcp(d);
+  return (float)vfma(r, vfma(-d, r, 1.0), r);
 }
 __device__ __forceinline__ double vrcp_ge1(double x) {
   double r = __builtin_amdgcn_rcp(x);
