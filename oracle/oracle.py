@@ -46,6 +46,10 @@ def lib():
             f.restype = ctypes.c_int
         _lib.oracle_trace_d.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         _lib.oracle_trace_s.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        for name in ("oracle_urv_d", "oracle_urv_s"):
+            f = getattr(_lib, name)
+            f.argtypes = [ctypes.c_size_t, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int]
+            f.restype = ctypes.c_int
         for name in ("oracle_metrics_d", "oracle_metrics_s"):
             f = getattr(_lib, name)
             f.argtypes = [ctypes.c_size_t, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int]
@@ -258,3 +262,29 @@ def kog_solve(A: np.ndarray, tol: float = 1e-14, max_sweeps: int = 40) -> dict:
     sig = np.sort(np.abs(np.diag(A)).astype(np.float64))[::-1]
     return dict(status=st, sweeps=sw.value, off_rel=off.value, history=hist[: sw.value + 1],
                 sigma=sig)
+
+
+def urv(A: np.ndarray, dtype=np.float64, policy: str = "mirror", nthreads: int = 0,
+        cplx: bool | None = None) -> dict:
+    """Phase outputs of the URV factorization (section 2.2, eqs. (9) and (11)):
+    R = [[r11, r12], [0, r22]] of the scaled matrix A^ = 2^s A and its unitary
+    factors, A^ = U_+ R V_+^*.  Same pipeline and arguments as svd2().
+    Returns dict(r11, r12, r22, Up=(4, n), Vp=(4, n), trains=list of the
+    output arrays in the order r11, r12, r22, U_+, V_+)."""
+    if cplx is None:
+        cplx = bool(np.iscomplexobj(A))
+    dtype = np.dtype(dtype)
+    if cplx and not np.iscomplexobj(A):
+        A = A.astype(np.complex128 if dtype == np.float64 else np.complex64)
+    n = A.shape[1]
+    ins = split(A, dtype)
+    nf = 19 if cplx else 11
+    outs = [np.empty(n, dtype=dtype) for _ in range(nf)]
+    L = lib()
+    f = L.oracle_urv_d if dtype == np.float64 else L.oracle_urv_s
+    if dtype not in (np.float64, np.float32):
+        raise ValueError(dtype)
+    f(n, int(cplx), _ptrs(ins), _ptrs(outs), POLICY[policy], nthreads)
+    k = 8 if cplx else 4
+    return dict(r11=outs[0], r12=outs[1], r22=outs[2], Up=join(outs[3:3 + k], cplx),
+                Vp=join(outs[3 + k:3 + 2 * k], cplx), trains=outs)

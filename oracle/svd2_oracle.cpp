@@ -589,6 +589,47 @@ void batch(size_t n, const T *const *in, T *const *out, int policy, int bs, int 
   }
 }
 
+/* ---------------------------------------------------------------------------
+ * Phase outputs of section 2.2: R of eq. (9) and U_+ = P_r D Q_alpha D^,
+ * V_+ = P_c D~ of eq. (11), in the operation order stated in the header.
+ * ------------------------------------------------------------------------- */
+template <class T> Cx<T> rscale(Cx<T> z, T a) { return {z.re * a, z.im * a}; }
+
+template <class T, bool CPLX> void urv_one(const Mid<T> &m, T *const *f, size_t k) {
+  const T one = T(1), zero = T(0);
+  const T sa = m.ca * m.mt;
+  const Cx<T> d1dh = cmul(m.d1, m.dh), d2dh = cmul(m.d2, m.dh);
+  Cx<T> U[2][2] = {{rscale(m.d1, m.ca), rscale(d1dh, sa)}, {rscale(m.d2, sa), rscale(d2dh, m.ca)}};
+  U[0][1] = {-U[0][1].re, -U[0][1].im};
+  if (m.r) { std::swap(U[0][0], U[1][0]); std::swap(U[0][1], U[1][1]); } /* P_r */
+  Cx<T> V[2][2] = {{{one, zero}, {zero, zero}}, {{zero, zero}, {m.e12.re, -m.e12.im}}};
+  if (m.c) { std::swap(V[0][0], V[1][0]); std::swap(V[0][1], V[1][1]); } /* P_c */
+  f[0][k] = m.r11; f[1][k] = m.r12; f[2][k] = m.r22;
+  const int ii[4] = {0, 1, 0, 1}, jj[4] = {0, 0, 1, 1}; /* element order 11, 21, 12, 22 */
+  for (int e = 0; e < 4; ++e) {
+    if (CPLX) {
+      f[3 + 2 * e][k] = U[ii[e]][jj[e]].re; f[4 + 2 * e][k] = U[ii[e]][jj[e]].im;
+      f[11 + 2 * e][k] = V[ii[e]][jj[e]].re; f[12 + 2 * e][k] = V[ii[e]][jj[e]].im;
+    } else {
+      f[3 + e][k] = U[ii[e]][jj[e]].re;
+      f[7 + e][k] = V[ii[e]][jj[e]].re;
+    }
+  }
+}
+
+template <class T, bool CPLX>
+void urv_batch(size_t n, const T *const *in, T *const *f, int policy, int nthreads) {
+  Prim<T> P{policy & ~ORACLE_SINE, false};
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+  for (long long kk = 0; kk < (long long)n; ++kk) {
+    Res<T> o;
+    Mid<T> m{};
+    run_one<T, CPLX>(P, in, (size_t)kk, o, m);
+    urv_one<T, CPLX>(m, f, (size_t)kk);
+  }
+}
+
 template <class T> void fill_trace(const Mid<T> &m, const Res<T> &o, double *tr) {
   double v[ORACLE_TRACE_LEN] = {(double)m.s, (double)m.c, (double)m.r, (double)m.r11,
       (double)m.r12, (double)m.r22, (double)m.mt, (double)m.ca, (double)m.x, (double)m.y,
@@ -693,6 +734,19 @@ int oracle_ssvd2(size_t n, const float *const *in, float *const *out, int policy
 int oracle_csvd2(size_t n, const float *const *in, float *const *out, int policy,
                  int backscale_mode, int rescue, uint8_t *flagged, int nthreads) {
   batch<float, true>(n, in, out, policy, backscale_mode, rescue, flagged, nthreads);
+  return 0;
+}
+
+int oracle_urv_d(size_t n, int cplx, const double *const *in, double *const *f, int policy,
+                 int nthreads) {
+  if (cplx) urv_batch<double, true>(n, in, f, policy, nthreads);
+  else urv_batch<double, false>(n, in, f, policy, nthreads);
+  return 0;
+}
+int oracle_urv_s(size_t n, int cplx, const float *const *in, float *const *f, int policy,
+                 int nthreads) {
+  if (cplx) urv_batch<float, true>(n, in, f, policy, nthreads);
+  else urv_batch<float, false>(n, in, f, policy, nthreads);
   return 0;
 }
 

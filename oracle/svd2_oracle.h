@@ -78,6 +78,29 @@ int oracle_csvd2(size_t n, const float *const *in, float *const *out,
  * 21 rescued (float only) */
 #define ORACLE_TRACE_LEN 22
 int oracle_trace_d(const double *a, int cplx, int policy, double *trace);
+
+/* Phase outputs of the URV factorization, section 2.2 (section 4: the output
+ * of a phase may be written alongside the final results, in the same
+ * layout), for the same pipeline as oracle_dsvd2 ... oracle_csvd2:
+ *   R = [[r11, r12], [0, r22]] of eq. (9), real, of A^ = 2^s A;
+ *   U_+ = P_r D Q_alpha D^ and V_+ = P_c D~, the unitary factors of eq. (11)
+ *   (A^ = U_+ R V_+^*), with D = diag(d1, d2) the conjugate of D* (eq. (4)),
+ *   Q_alpha = cos(alpha) [[1, -mt], [mt, 1]] (eq. (6), tan(alpha) = -mt),
+ *   D^ = diag(1, dh) (dh = e^{i arg r'_22}, eq. (9)) and D~ = diag(1,
+ *   conj(e12)) (e12 = e^{i arg r'_12}, eq. (8)); in the real case d1, d2, dh
+ *   and e12 are the signs +-1 of eq. (10).
+ * Reading (the paper gives no operation order for U_+): with ca = cos(alpha)
+ * and sa = ca * mt (one rounding), before the row swap P_r
+ *   u11 = d1 ca, u21 = d2 sa, u12 = -((d1 dh) sa), u22 = (d2 dh) ca,
+ * each real-by-complex product one rounding per part and d1 dh, d2 dh by
+ * eq. (5); V_+ before the row swap P_c is [[1, 0], [0, conj(e12)]] exactly.
+ * f: r11, r12, r22, then U_+ and V_+ in the element order of U and V
+ * (11 arrays real, 19 complex).  FP32: the FP32 pipeline's values (no rescue
+ * is applied to them).  Returns 0. */
+int oracle_urv_d(size_t n, int cplx, const double *const *in, double *const *f, int policy,
+                 int nthreads);
+int oracle_urv_s(size_t n, int cplx, const float *const *in, float *const *f, int policy,
+                 int nthreads);
 int oracle_trace_s(const float *a, int cplx, int policy, int rescue, double *trace);
 
 /* Error metrics of section 8, eqs. (32)-(35), per lane, in __float128.
