@@ -67,7 +67,7 @@ def make_inputs(variant: str, n: int, seed_off: int = 1):
     return to_trains(A, dtype)
 
 
-def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets, sample=None):
+def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets, sample=None, urv=False):
     """Time `steps` batched calls on inputs resident in HBM, once per flag set
     in `flagsets` (same inputs).  Returns {flags: dict} with the wall-clock
     time of the timed region and the per-launch kernel time from HIP events
@@ -76,7 +76,9 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets, sam
     under 'pattern_nouv' for the singular-values-only pattern when a flag set
     has SVD2_NO_UV.  FP32 flag sets with a rescue also get the count of
     rescued lanes (one extra call); with `sample` (lane indices) the outputs
-    of the first flag set on those lanes come back as host arrays."""
+    of the first flag set on those lanes come back as host arrays.  With urv
+    the call with the phase outputs (R, U_+, V_+; default flags) is timed as
+    well, under key 'urv'."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     S.svd2_set_launch_kind(variant, *DEFAULT_LAUNCH[variant])
@@ -127,6 +129,10 @@ def time_variant(variant: str, trains_np, steps: int, warmup: int, flagsets, sam
             cnt.zero_()
             S.svd2(dev, flags=flags, out=o, ws=ws, nrescued=cnt)
             res[flags]["rescued"] = int(cnt.item())
+    if urv:
+        f = [torch.empty(n, dtype=dev[0].dtype, device="cuda") for _ in range(nout)]
+        res["urv"] = timed(lambda: S.svd2(dev, flags=0, out=out, urv=f))
+        del f
     if sample is not None:
         # outputs of the default call on a sample of lanes, for the comparison
         # with the oracle in the CPU-baseline leg
@@ -530,14 +536,17 @@ def kog_batch_bench(nprob: int = 256):
     return out
 
 
-def summarize(variant, r, pattern, flags_desc="", nouv=False, valu_per_matrix=None):
+def summarize(variant, r, pattern, flags_desc="", nouv=False, valu_per_matrix=None, bps=None):
     n = r["n"]
-    bps = (BYTES_PER_SVD_NOUV if nouv else BYTES_PER_SVD)[variant]
+    if bps is None:
+        bps = (BYTES_PER_SVD_NOUV if nouv else BYTES_PER_SVD)[variant]
     kms = float(np.mean(r["kernel_ms"]))
     wall_ms = r["wall_s"] * 1e3 / len(r["kernel_ms"])
     gbs = bps * n / (kms * 1e-3) / 1e9
-    pms = float(np.mean(pattern["kernel_ms"]))
-    pgbs = bps * n / (pms * 1e-3) / 1e9
+    pgbs = None
+    if pattern is not None:
+        pms = float(np.mean(pattern["kernel_ms"]))
+        pgbs = bps * n / (pms * 1e-3) / 1e9
     vf = valu_frac(valu_per_matrix, n, kms)
     hf = gbs / HBM_PEAK_GBS
     out = dict(n=n, svds_per_s=n / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kms,
@@ -545,7 +554,8 @@ def summarize(variant, r, pattern, flags_desc="", nouv=False, valu_per_matrix=No
                algorithmic_GBs=gbs,
                hbm_frac=hf, bytes_per_svd=bps, valu_instr_per_matrix=valu_per_matrix, valu_frac=vf,
                bound="valu" if vf is not None and vf > hf else "hbm",
-               pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=gbs / pgbs, flags=flags_desc)
+               pattern_ceiling_GBs=pgbs, frac_of_pattern_ceiling=None if pgbs is None else gbs / pgbs,
+               flags=flags_desc)
     if "rescued" in r:
         out["rescued"] = r["rescued"]
         out["rescued_frac"] = r["rescued"] / n
@@ -747,7 +757,13 @@ def main():
         if do_cpu and not tag:
             sample = np.sort(np.random.default_rng(20050740).choice(n, size=min(n, 1 << 16), replace=False))
         log(f"[bench] timing {v}{tag}: warmup {args.warmup}, steps {args.steps}")
-        r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()), sample=sample)
+        urv = v in ("z", "d") and not tag and args.uv == "both"
+        r = time_variant(v, tr, args.steps, args.warmup, list(flagsets[v].values()), sample=sample, urv=urv)
+        if urv:
+            # the phase outputs add R, U_+ and V_+: 11 (real) or 19 (complex) arrays
+            results[f"{v}_urv"] = summarize(v, r["urv"], None, "phase outputs R, U+, V+", False, None,
+                                            bps=BYTES_PER_SVD[v] + 8 * (19 if v == "z" else 11))
+            log(f"[bench] {v}_urv: {json.dumps(results[v + '_urv'])}")
         if sample is not None:
             checks_in[v] = [np.ascontiguousarray(t[sample]) for t in tr]
             checks_out[v] = (r["sample_out"], r["sample_flags"])

@@ -166,6 +166,57 @@ svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws,
 /* Workspace needed by the FP32 entry points: 0 unless SVD2_RESCUE_QUEUE. */
 size_t svd2_workspace_bytes(size_t n, unsigned flags);
 
+/* Phase outputs of the URV factorization (section 2.2), written beside the
+   final results in the same layout (section 4 allows the output of a phase
+   to be kept this way): the real upper-triangular factor
+   R = [[r11, r12], [0, r22]] of eq. (9), r11 >= max(r12, r22) >= 0, and the
+   unitary factors of eq. (11), A^ = 2^s A = U_+ R V_+^*, with
+   U_+ = P_r D Q_alpha D^ and V_+ = P_c D~:
+     D = diag(d1, d2), the conjugate of D* of eq. (4) (signs in the real case);
+     Q_alpha = cos(alpha) [[1, tan(alpha)], [-tan(alpha), 1]] of eqs. (6)-(7);
+     D^ = diag(1, e^{i arg r'_22}) of eq. (9), D~ = diag(1, e^{-i arg r'_12})
+     of eq. (8).
+   Operation order (the paper gives none for U_+): with ca = cos(alpha) and
+   sa = ca * (-tan(alpha)), one rounding, the rows of U_+ before the swap P_r
+   are [d1 ca, -((d1 dh) sa)] and [d2 sa, (d2 dh) ca], dh = D^_22, each
+   product rounded once per part (d1 dh by eq. (5)); V_+ is [[1, 0], [0, D~_22]]
+   before the swap P_c (exact).  R, U_+ and V_+ are those of the scaled matrix,
+   so the backscale flags are refused (SVD2_ERR_FLAGS): s is always returned.
+   r11, r12, r22 are required; the U_+ and V_+ pointers are all given or all
+   NULL (then only R is written).  Every other flag, pointer rule and error is
+   that of the plain entry point; the main outputs are bitwise those of the
+   plain call.  FP32: R, U_+ and V_+ are the FP32 pipeline's values on every
+   lane (the rescues recompute later phases only). */
+typedef struct {
+  double *r11, *r12, *r22;
+  double *u11, *u21, *u12, *u22;
+  double *v11, *v21, *v12, *v22;
+} dsvd2_urv;
+typedef struct {
+  double *r11, *r12, *r22;
+  double *u11r, *u11i, *u21r, *u21i, *u12r, *u12i, *u22r, *u22i;
+  double *v11r, *v11i, *v21r, *v21i, *v12r, *v12i, *v22r, *v22i;
+} zsvd2_urv;
+typedef struct {
+  float *r11, *r12, *r22;
+  float *u11, *u21, *u12, *u22;
+  float *v11, *v21, *v12, *v22;
+} ssvd2_urv;
+typedef struct {
+  float *r11, *r12, *r22;
+  float *u11r, *u11i, *u21r, *u21i, *u12r, *u12i, *u22r, *u22i;
+  float *v11r, *v11i, *v21r, *v21i, *v12r, *v12i, *v22r, *v22i;
+} csvd2_urv;
+
+svd2_status dsvd2_batch_urv(size_t n, const dsvd2_args *p, const dsvd2_urv *f, unsigned flags,
+                            hipStream_t stream);
+svd2_status zsvd2_batch_urv(size_t n, const zsvd2_args *p, const zsvd2_urv *f, unsigned flags,
+                            hipStream_t stream);
+svd2_status ssvd2_batch_urv(size_t n, const ssvd2_args *p, const ssvd2_urv *f, unsigned flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+svd2_status csvd2_batch_urv(size_t n, const csvd2_args *p, const csvd2_urv *f, unsigned flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+
 /* Launch shape of the batched kernels (set by the autotuner).  block: threads
    per workgroup, 64, 128, 192 or 256; per_thread: matrices per lane, 1 or 2
    (2 uses 16-byte loads and stores when every array is 16-byte aligned).

@@ -14,6 +14,7 @@
 
 #include <atomic>
 #include <stdint.h>
+#include <string.h>
 
 #include "svd2_lane.hpp"
 
@@ -104,6 +105,26 @@ __device__ __forceinline__ unsigned lane_prefix(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// the flagged lanes of one matrix per lane (every lane of the wavefront
+// calls it): their count is added to nresc (one atomic per wavefront) and,
+// for RESCUE == 2, their batch indices idx are appended to the queue
+template <int RESCUE>
+__device__ __forceinline__ void note_flagged(bool fl, uint32_t idx, uint32_t *nresc, uint32_t *queue,
+                                             uint32_t *qcount) {
+  const uint64_t m = __ballot(fl);
+  if (m == 0) return;
+  const unsigned total = (unsigned)__popcll(m);
+  const unsigned lane = __lane_id();
+  const unsigned first = (unsigned)__ffsll((unsigned long long)m) - 1;
+  if (nresc && lane == first) atomicAdd(nresc, total);
+  if constexpr (RESCUE == 2) {
+    unsigned base = 0;
+    if (lane == first) base = atomicAdd(qcount, total);
+    base = __shfl(base, (int)first);
+    if (fl) queue[base + lane_prefix(m)] = idx;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Main batched kernel.  RESCUE: 0 plain, 1 in-place FP64 rescue, 2 queue the
 // flagged lanes for svd2_rescue_kernel, 3 and 4 the in-place sigma-quotient
@@ -132,21 +153,38 @@ __global__ __launch_bounds__(256) void svd2_kernel(uint32_t n, KArgs<T, CPLX ? 8
   if (cnt > 0) store_lanes<T, NOUT, PT, LO>(a.out, k, cnt, y);
   if constexpr (RESCUE != 0) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) {
-      uint64_t m = __ballot(fl[j]);
-      if (m == 0) continue;
-      unsigned total = (unsigned)__popcll(m);
-      unsigned lane = __lane_id();
-      unsigned first = (unsigned)__ffsll((unsigned long long)m) - 1;
-      if (nresc && lane == first) atomicAdd(nresc, total);
-      if constexpr (RESCUE == 2) {
-        unsigned base = 0;
-        if (lane == first) base = atomicAdd(qcount, total);
-        base = __shfl(base, (int)first);
-        if (fl[j]) queue[base + lane_prefix(m)] = k0 + k + (uint32_t)j;
-      }
-    }
+    for (int j = 0; j < PT; ++j) note_flagged<RESCUE>(fl[j], k0 + k + (uint32_t)j, nresc, queue, qcount);
   }
+}
+
+// the phase-output arrays: r11, r12, r22, then U_+ and V_+ (11 real, 19 complex)
+template <class T, int N> struct OutArgs {
+  T *out[N];
+};
+template <bool CPLX> constexpr int urv_count() { return CPLX ? 19 : 11; }
+
+// The batched kernel with the phase outputs of the URV factorization
+// (section 2.2, written beside the final results as section 4 allows): the
+// outputs of svd2_kernel, and in f the factor R (UPV = false) or R, U_+ and
+// V_+ (UPV = true).  One matrix per lane.
+template <class T, bool CPLX, int RESCUE, bool UV, bool SINE, bool UPV>
+__global__ __launch_bounds__(256) void svd2_urv_kernel(uint32_t n, KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> a,
+                                                       OutArgs<T, urv_count<CPLX>()> f, int bs, uint32_t *nresc,
+                                                       uint32_t *queue, uint32_t *qcount, uint32_t k0) {
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, LO = UV ? 0 : NOUT - 3;
+  constexpr int NF = UPV ? urv_count<CPLX>() : 3;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  bool fl = false;
+  if (k < n) {
+    T x[1][NIN], y[1][NOUT], fv[urv_count<CPLX>()];
+    load_lanes<T, NIN, 1>(a.in, k, 1, x);
+    fl = one_matrix<T, CPLX, RESCUE, SINE, UPV ? 2 : 1>(x[0], y[0], bs, fv);
+    store_lanes<T, NOUT, 1, LO>(a.out, k, 1, y);
+    const uint32_t off = k * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) st_nt(at(f.out[i], off), fv[i]);
+  }
+  if constexpr (RESCUE != 0) note_flagged<RESCUE>(fl, k0 + k, nresc, queue, qcount);
 }
 
 // Second pass for RESCUE == 2: redo each queued lane with the FP64 tail.  The
@@ -212,7 +250,7 @@ svd2_status check_ptrs(size_t n, const T *const *in, int nin, T *const *out, int
     if ((uintptr_t)out[i] % sizeof(T)) return SVD2_ERR_ALIGN;
   if (n > SIZE_MAX / sizeof(T)) return SVD2_ERR_SIZE;
   const size_t bytes = n * sizeof(T);
-  Span sp[27 + 8];
+  Span sp[19 + 19];
   int m = 0;
   for (int i = 0; i < nout; ++i) sp[m++] = {(uintptr_t)out[i], (uintptr_t)out[i] + bytes};
   for (int i = 0; i < m; ++i)
@@ -275,10 +313,51 @@ svd2_status launch(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, in
   return SVD2_OK;
 }
 
-// uv: U and V are wanted (else SVD2_NO_UV); sine: assembled by eq. (31)
+// the phase-output form: one matrix per lane, launches of at most
+// kChunkBytes per array as above
+template <class T, bool CPLX, int RESCUE, bool UV, bool SINE, bool UPV>
+svd2_status launch_urv(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a,
+                       const OutArgs<T, urv_count<CPLX>()> &f, int bs, uint32_t *nresc, uint32_t *queue,
+                       uint32_t *qcount, hipStream_t st) {
+  constexpr int kind = kind_of<T, CPLX>() + (UV ? 0 : 4);
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, NF = urv_count<CPLX>();
+  constexpr size_t chunk = kChunkBytes / sizeof(T);
+  const int block = g_block[kind].load();
+  for (size_t c0 = 0; c0 < n; c0 += chunk) {
+    const size_t m = n - c0 < chunk ? n - c0 : chunk;
+    KArgs<T, NIN, NOUT> ac = a;
+    OutArgs<T, NF> fc = f;
+    for (int i = 0; i < NIN; ++i) ac.in[i] = a.in[i] + c0;
+    for (int i = 0; i < NOUT; ++i) ac.out[i] = a.out[i] ? a.out[i] + c0 : nullptr;
+    for (int i = 0; i < NF; ++i) fc.out[i] = f.out[i] ? f.out[i] + c0 : nullptr;
+    const size_t grid = (m + block - 1) / block;
+    hipLaunchKernelGGL((svd2_urv_kernel<T, CPLX, RESCUE, UV, SINE, UPV>), dim3((unsigned)grid), dim3(block), 0, st,
+                       (uint32_t)m, ac, fc, bs, nresc, queue, qcount, (uint32_t)c0);
+    svd2_status s = hip_status(hipGetLastError());
+    if (s != SVD2_OK) return s;
+  }
+  return SVD2_OK;
+}
+
+template <class T, bool CPLX, int RESCUE, bool UPV>
+svd2_status launch_urv_uv(bool uv, bool sine, size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a,
+                          const OutArgs<T, urv_count<CPLX>()> &f, int bs, uint32_t *nresc, uint32_t *queue,
+                          uint32_t *qcount, hipStream_t st) {
+  if (!uv) return launch_urv<T, CPLX, RESCUE, false, false, UPV>(n, a, f, bs, nresc, queue, qcount, st);
+  return sine ? launch_urv<T, CPLX, RESCUE, true, true, UPV>(n, a, f, bs, nresc, queue, qcount, st)
+              : launch_urv<T, CPLX, RESCUE, true, false, UPV>(n, a, f, bs, nresc, queue, qcount, st);
+}
+
+// uv: U and V are wanted (else SVD2_NO_UV); sine: assembled by eq. (31);
+// f: the phase outputs (R, and U_+, V_+ with upv), or none
 template <class T, bool CPLX, int RESCUE>
 svd2_status launch_uv(bool uv, bool sine, size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, int bs,
-                      uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st) {
+                      uint32_t *nresc, uint32_t *queue, uint32_t *qcount, hipStream_t st,
+                      const OutArgs<T, urv_count<CPLX>()> *f = nullptr, bool upv = false) {
+  if (f) {
+    return upv ? launch_urv_uv<T, CPLX, RESCUE, true>(uv, sine, n, a, *f, bs, nresc, queue, qcount, st)
+               : launch_urv_uv<T, CPLX, RESCUE, false>(uv, sine, n, a, *f, bs, nresc, queue, qcount, st);
+  }
   if (!uv) return launch<T, CPLX, RESCUE, false, false>(n, a, bs, nresc, queue, qcount, st);
   return sine ? launch<T, CPLX, RESCUE, true, true>(n, a, bs, nresc, queue, qcount, st)
               : launch<T, CPLX, RESCUE, true, false>(n, a, bs, nresc, queue, qcount, st);
@@ -298,16 +377,17 @@ bool bad_bs_flags(unsigned flags) { return (flags & 3u) == 3u; }
 
 template <class T, bool CPLX>
 svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, unsigned flags,
-                     uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st) {
+                     uint32_t *nresc, void *ws, size_t ws_bytes, hipStream_t st,
+                     const OutArgs<T, urv_count<CPLX>()> *f = nullptr, bool upv = false) {
   int bs = (int)(flags & 3u);
   bool resc = flags & SVD2_RESCUE_FP64, queue = flags & SVD2_RESCUE_QUEUE,
        sigma = flags & SVD2_RESCUE_SIGMA, tri = flags & SVD2_RESCUE_TRI, uv = !(flags & SVD2_NO_UV),
        sine = flags & SVD2_SINE_FORM;
-  if (!resc) return launch_uv<T, CPLX, 0>(uv, sine, n, a, bs, nullptr, nullptr, nullptr, st);
+  if (!resc) return launch_uv<T, CPLX, 0>(uv, sine, n, a, bs, nullptr, nullptr, nullptr, st, f, upv);
   if (!queue) {
-    if (sigma) return launch_uv<T, CPLX, 3>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
-    if (tri) return launch_uv<T, CPLX, 4>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
-    return launch_uv<T, CPLX, 1>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st);
+    if (sigma) return launch_uv<T, CPLX, 3>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st, f, upv);
+    if (tri) return launch_uv<T, CPLX, 4>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st, f, upv);
+    return launch_uv<T, CPLX, 1>(uv, sine, n, a, bs, nresc, nullptr, nullptr, st, f, upv);
   }
   if (n >= 0xffffffffull) return SVD2_ERR_SIZE;
   if (!ws) return SVD2_ERR_NULL;
@@ -318,7 +398,7 @@ svd2_status run_fp32(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, 
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, st, qcount);
   svd2_status s0 = hip_status(hipGetLastError());
   if (s0 != SVD2_OK) return s0;
-  svd2_status s1 = launch_uv<T, CPLX, 2>(uv, sine, n, a, bs, nresc, q, qcount, st);
+  svd2_status s1 = launch_uv<T, CPLX, 2>(uv, sine, n, a, bs, nresc, q, qcount, st, f, upv);
   if (s1 != SVD2_OK) return s1;
   if (sigma) launch_rescue<T, CPLX, 3>(uv, sine, a, bs, q, qcount, st);
   else if (tri) launch_rescue<T, CPLX, 4>(uv, sine, a, bs, q, qcount, st);
@@ -395,9 +475,81 @@ svd2_status stream_probe(size_t n, const void *const *in, void *const *out, hipS
   return SVD2_OK;
 }
 
+// the phase-output struct of an entry point as an OutArgs: R required, U_+
+// and V_+ all given (upv) or all NULL
+template <class T, int NF> svd2_status urv_args(T *const (&p)[NF], OutArgs<T, NF> &f, bool &upv) {
+  int given = 0;
+  for (int i = 0; i < NF; ++i) {
+    f.out[i] = p[i];
+    if (i >= 3 && p[i]) ++given;
+  }
+  if (!p[0] || !p[1] || !p[2]) return SVD2_ERR_NULL;
+  if (given != 0 && given != NF - 3) return SVD2_ERR_NULL;
+  upv = given != 0;
+  return SVD2_OK;
+}
+
+// outputs of one call for the alias and alignment checks: the used outputs of
+// the args struct, then the used phase outputs
+template <class T, int NOUT, int NF>
+int gather_outputs(T *const (&out)[NOUT], bool uv, const OutArgs<T, NF> &f, bool upv, T *(&all)[NOUT + NF]) {
+  int m = 0;
+  for (int i = uv ? 0 : NOUT - 3; i < NOUT; ++i) all[m++] = out[i];
+  for (int i = 0; i < (upv ? NF : 3); ++i) all[m++] = f.out[i];
+  return m;
+}
+
+template <class T, bool CPLX, class FS>
+svd2_status urv_prepare(size_t n, const KArgs<T, CPLX ? 8 : 4, CPLX ? 19 : 11> &a, const FS *fs, unsigned flags,
+                        OutArgs<T, urv_count<CPLX>()> &f, bool &upv) {
+  constexpr int NIN = CPLX ? 8 : 4, NOUT = CPLX ? 19 : 11, NF = urv_count<CPLX>();
+  if (!fs) return SVD2_ERR_NULL;
+  // R, U_+ and V_+ belong to 2^s A: s must be returned, so no backscale
+  if (flags & 3u) return SVD2_ERR_FLAGS;
+  T *p[NF];
+  static_assert(sizeof(FS) == NF * sizeof(T *), "phase-output struct layout");
+  memcpy(p, fs, sizeof p);
+  svd2_status st = urv_args<T, NF>(p, f, upv);
+  if (st != SVD2_OK) return st;
+  T *all[NOUT + NF];
+  const int m = gather_outputs<T, NOUT, NF>(a.out, !(flags & SVD2_NO_UV), f, upv, all);
+  return check_ptrs<T>(n, a.in, NIN, all, m);
+}
+
 }  // namespace
 
 extern "C" {
+
+svd2_status dsvd2_batch_urv(size_t n, const dsvd2_args *p, const dsvd2_urv *fs, unsigned flags,
+                            hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (flags & ~(3u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<double, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
+                            {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
+                             p->smax, p->smin, p->s}};
+  OutArgs<double, 11> f;
+  bool upv = false;
+  svd2_status st = urv_prepare<double, false>(n, a, fs, flags, f, upv);
+  if (st != SVD2_OK || n == 0) return st;
+  return launch_uv<double, false, 0>(!(flags & SVD2_NO_UV), (flags & SVD2_SINE_FORM) != 0, n, a, 0, nullptr,
+                                     nullptr, nullptr, stream, &f, upv);
+}
+
+svd2_status zsvd2_batch_urv(size_t n, const zsvd2_args *p, const zsvd2_urv *fs, unsigned flags,
+                            hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (flags & ~(3u | SVD2_NO_UV | SVD2_SINE_FORM) || bad_bs_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<double, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
+                            {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
+                             p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
+                             p->smax, p->smin, p->s}};
+  OutArgs<double, 19> f;
+  bool upv = false;
+  svd2_status st = urv_prepare<double, true>(n, a, fs, flags, f, upv);
+  if (st != SVD2_OK || n == 0) return st;
+  return launch_uv<double, true, 0>(!(flags & SVD2_NO_UV), (flags & SVD2_SINE_FORM) != 0, n, a, 0, nullptr,
+                                    nullptr, nullptr, stream, &f, upv);
+}
 
 svd2_status dsvd2_batch(size_t n, const dsvd2_args *p, unsigned flags, hipStream_t stream) {
   if (!p) return SVD2_ERR_NULL;
@@ -459,6 +611,35 @@ svd2_status csvd2_batch(size_t n, const csvd2_args *p, unsigned flags, void *ws,
   svd2_status st = check_ptrs<float>(n, a.in, 8, a.out + (uv ? 0 : 16), uv ? 19 : 3);
   if (st != SVD2_OK || n == 0) return st;
   return run_fp32<float, true>(n, a, flags, p->nrescued, ws, ws_bytes, stream);
+}
+
+svd2_status ssvd2_batch_urv(size_t n, const ssvd2_args *p, const ssvd2_urv *fs, unsigned flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (bad_fp32_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<float, 4, 11> a = {{p->a11, p->a21, p->a12, p->a22},
+                           {p->u11, p->u21, p->u12, p->u22, p->v11, p->v21, p->v12, p->v22,
+                            p->smax, p->smin, p->s}};
+  OutArgs<float, 11> f;
+  bool upv = false;
+  svd2_status st = urv_prepare<float, false>(n, a, fs, flags, f, upv);
+  if (st != SVD2_OK || n == 0) return st;
+  return run_fp32<float, false>(n, a, flags, p->nrescued, ws, ws_bytes, stream, &f, upv);
+}
+
+svd2_status csvd2_batch_urv(size_t n, const csvd2_args *p, const csvd2_urv *fs, unsigned flags, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  if (!p) return SVD2_ERR_NULL;
+  if (bad_fp32_flags(flags)) return SVD2_ERR_FLAGS;
+  KArgs<float, 8, 19> a = {{p->a11r, p->a11i, p->a21r, p->a21i, p->a12r, p->a12i, p->a22r, p->a22i},
+                           {p->u11r, p->u11i, p->u21r, p->u21i, p->u12r, p->u12i, p->u22r, p->u22i,
+                            p->v11r, p->v11i, p->v21r, p->v21i, p->v12r, p->v12i, p->v22r, p->v22i,
+                            p->smax, p->smin, p->s}};
+  OutArgs<float, 19> f;
+  bool upv = false;
+  svd2_status st = urv_prepare<float, true>(n, a, fs, flags, f, upv);
+  if (st != SVD2_OK || n == 0) return st;
+  return run_fp32<float, true>(n, a, flags, p->nrescued, ws, ws_bytes, stream, &f, upv);
 }
 
 size_t svd2_workspace_bytes(size_t n, unsigned flags) {

@@ -205,6 +205,9 @@ template <class T> struct RealRes {
   // kept for the FP64 rescue of FP32 lanes
   T ah11, ah21, ah12, ah22, r11, r12, mt, ca;
   bool c, r, neg1, neg2, negt;
+  // kept for the phase outputs
+  T r22;
+  bool negh;
 };
 
 // The sine form of the assembly, eq. (31) (SINE = true, flag SVD2_SINE_FORM):
@@ -291,6 +294,7 @@ __device__ __forceinline__ void real_lane(T a11, T a21, T a12, T a22, RealRes<T>
   o.smax = t.smax; o.smin = t.smin;
   o.r11 = r11; o.r12 = r12; o.mt = mt; o.ca = ca;
   o.c = c; o.r = r; o.neg1 = neg1; o.neg2 = neg2; o.negt = negt;
+  o.r22 = r22; o.negh = negh;
 }
 
 // ---------------------------------------------------------------------------
@@ -304,6 +308,9 @@ template <class T> struct CplxRes {
   Cx<T> d1, d2, e12;
   T r11, r12, mt, ca;
   bool c, r;
+  // kept for the phase outputs
+  T r22;
+  Cx<T> dh;
 };
 
 template <class T, class W, bool SINE = false>
@@ -396,6 +403,7 @@ __device__ __forceinline__ void cplx_lane(const T *a, CplxRes<T> &o) {
   o.d1 = d1; o.d2 = d2; o.e12 = e12;
   o.r11 = r11; o.r12 = r12; o.mt = mt; o.ca = ca;
   o.c = c; o.r = r;
+  o.r22 = r22; o.dh = dh;
 }
 
 // ---------------------------------------------------------------------------
@@ -534,17 +542,63 @@ template <class T> __device__ __forceinline__ T backscale(int mode, int s, T &sm
 }
 
 // ---------------------------------------------------------------------------
+// Phase outputs of the URV factorization (section 2.2; section 4 allows the
+// output of a phase to be written beside the final results): f = r11, r12,
+// r22 of eq. (9), then, with UPV, U_+ = P_r D Q_alpha D^ and V_+ = P_c D~ of
+// eq. (11) in the element order of U and V.  With D = diag(d1, d2), Q_alpha =
+// cos(alpha) [[1, -mt], [mt, 1]] and D^ = diag(1, dh), before the row swap
+// u11 = d1 ca, u21 = d2 sa, u12 = -((d1 dh) sa), u22 = (d2 dh) ca, sa = ca mt
+// (one rounding per product, d1 dh by eq. (5)); V_+ is [[1, 0], [0,
+// conj(e12)]] before the row swap.  In the real case the phases are the signs
+// of eq. (10), so the products are exact sign changes.
+// ---------------------------------------------------------------------------
+template <class T, bool UPV> __device__ __forceinline__ void real_urv(const RealRes<T> &o, T *f) {
+  f[0] = o.r11; f[1] = o.r12; f[2] = o.r22;
+  if constexpr (UPV) {
+    const T sa = o.ca * o.mt, one = T(1), zero = T(0);
+    const T u11 = flip(o.neg1, o.ca), u21 = flip(o.neg2, sa);
+    const T u12 = -flip(o.neg1 != o.negh, sa), u22 = flip(o.neg2 != o.negh, o.ca);
+    f[3] = o.r ? u21 : u11; f[4] = o.r ? u11 : u21;
+    f[5] = o.r ? u22 : u12; f[6] = o.r ? u12 : u22;
+    const T v22 = o.negt ? -one : one;
+    f[7] = o.c ? zero : one; f[8] = o.c ? one : zero;
+    f[9] = o.c ? v22 : zero; f[10] = o.c ? zero : v22;
+  }
+}
+
+template <class T, bool UPV> __device__ __forceinline__ void cplx_urv(const CplxRes<T> &o, T *f) {
+  f[0] = o.r11; f[1] = o.r12; f[2] = o.r22;
+  if constexpr (UPV) {
+    const T sa = o.ca * o.mt, one = T(1), zero = T(0);
+    const Cx<T> d1dh = cmul(o.d1, o.dh), d2dh = cmul(o.d2, o.dh);
+    const Cx<T> u11 = {o.d1.re * o.ca, o.d1.im * o.ca}, u21 = {o.d2.re * sa, o.d2.im * sa};
+    const Cx<T> u12 = {-(d1dh.re * sa), -(d1dh.im * sa)}, u22 = {d2dh.re * o.ca, d2dh.im * o.ca};
+    const Cx<T> U[4] = {o.r ? u21 : u11, o.r ? u11 : u21, o.r ? u22 : u12, o.r ? u12 : u22};
+    const Cx<T> e1 = {one, zero}, e0 = {zero, zero}, v22 = {o.e12.re, -o.e12.im};
+    const Cx<T> V[4] = {o.c ? e0 : e1, o.c ? e1 : e0, o.c ? v22 : e0, o.c ? e0 : v22};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      f[3 + 2 * e] = U[e].re; f[4 + 2 * e] = U[e].im;
+      f[11 + 2 * e] = V[e].re; f[12 + 2 * e] = V[e].im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // one matrix: inputs x[NIN] -> outputs y[NOUT]; returns the rescue flag
 // RESCUE: 0 none, 1 in place (FP64 tail on flagged lanes), 2 flag only,
 // 3 in place (FP64 sigma_min quotient only), 4 in place (FP64 up to the
 // triangular SVD, FP32 assembly)
 // ---------------------------------------------------------------------------
-template <class T, bool CPLX, int RESCUE, bool SINE = false>
-__device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
+// URV (phase outputs into f): 0 none, 1 R, 2 R, U_+ and V_+; the FP32 lanes
+// give the FP32 pipeline's values (the rescue recomputes none of them)
+template <class T, bool CPLX, int RESCUE, bool SINE = false, int URV = 0>
+__device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs, T *f = nullptr) {
   bool flagged = false;
   if constexpr (!CPLX) {
     RealRes<T> o;
     real_lane<T, SINE>(x[0], x[1], x[2], x[3], o);
+    if constexpr (URV != 0) real_urv<T, URV == 2>(o, f);
     if constexpr (RESCUE != 0) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {
@@ -563,6 +617,7 @@ __device__ __forceinline__ bool one_matrix(const T *x, T *y, int bs) {
   } else {
     CplxRes<T> o;
     cplx_lane<T, SINE>(x, o);
+    if constexpr (URV != 0) cplx_urv<T, URV == 2>(o, f);
     if constexpr (RESCUE != 0) {
       flagged = near_degenerate(o.smax, o.smin);
       if constexpr (RESCUE == 1) {

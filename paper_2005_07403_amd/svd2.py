@@ -49,6 +49,21 @@ class csvd2_args(ctypes.Structure):
     _fields_ = [(k, _P) for k in CPLX_IN + CPLX_OUT] + [("nrescued", _P)]
 
 
+REAL_URV = ["r11", "r12", "r22"] + REAL_OUT[:8]
+CPLX_URV = ["r11", "r12", "r22"] + CPLX_OUT[:16]
+
+
+class dsvd2_urv(ctypes.Structure):
+    _fields_ = [(k, _P) for k in REAL_URV]
+
+
+class zsvd2_urv(ctypes.Structure):
+    _fields_ = [(k, _P) for k in CPLX_URV]
+
+
+ssvd2_urv, csvd2_urv = dsvd2_urv, zsvd2_urv
+
+
 class Svd2Error(RuntimeError):
     def __init__(self, fn: str, status: int, hip: int = 0):
         super().__init__(f"{fn}: {STATUS.get(status, status)}" + (f" (hipError {hip})" if hip else ""))
@@ -58,6 +73,7 @@ class Svd2Error(RuntimeError):
 _lib = None
 
 EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_workspace_bytes",
+           "dsvd2_batch_urv", "zsvd2_batch_urv", "ssvd2_batch_urv", "csvd2_batch_urv",
            "kog_workspace_bytes", "dkog_step", "zkog_step", "skog_step", "ckog_step", "dkog_sweep",
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
@@ -88,7 +104,14 @@ def lib() -> ctypes.CDLL:
         L.zsvd2_batch.argtypes = [sz, ctypes.POINTER(zsvd2_args), ui, _P]
         L.ssvd2_batch.argtypes = [sz, ctypes.POINTER(ssvd2_args), ui, _P, sz, _P]
         L.csvd2_batch.argtypes = [sz, ctypes.POINTER(csvd2_args), ui, _P, sz, _P]
-        for f in ("dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch"):
+        L.dsvd2_batch_urv.argtypes = [sz, ctypes.POINTER(dsvd2_args), ctypes.POINTER(dsvd2_urv), ui, _P]
+        L.zsvd2_batch_urv.argtypes = [sz, ctypes.POINTER(zsvd2_args), ctypes.POINTER(zsvd2_urv), ui, _P]
+        L.ssvd2_batch_urv.argtypes = [sz, ctypes.POINTER(ssvd2_args), ctypes.POINTER(ssvd2_urv), ui, _P, sz,
+                                      _P]
+        L.csvd2_batch_urv.argtypes = [sz, ctypes.POINTER(csvd2_args), ctypes.POINTER(csvd2_urv), ui, _P, sz,
+                                      _P]
+        for f in ("dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "dsvd2_batch_urv",
+                  "zsvd2_batch_urv", "ssvd2_batch_urv", "csvd2_batch_urv"):
             getattr(L, f).restype = i
         L.svd2_workspace_bytes.argtypes = [sz, ui]
         L.svd2_workspace_bytes.restype = sz
@@ -172,6 +195,34 @@ def csvd2_batch(n: int, ins, outs, flags: int = 0, ws: int = 0, ws_bytes: int = 
                                             _stream(stream)))
 
 
+def dsvd2_batch_urv(n: int, ins, outs, f, flags: int = 0, stream=None) -> None:
+    a = _fill(dsvd2_args, REAL_IN + REAL_OUT, list(ins) + list(outs))
+    u = _fill(dsvd2_urv, REAL_URV, list(f))
+    _check("dsvd2_batch_urv", lib().dsvd2_batch_urv(n, ctypes.byref(a), ctypes.byref(u), flags, _stream(stream)))
+
+
+def zsvd2_batch_urv(n: int, ins, outs, f, flags: int = 0, stream=None) -> None:
+    a = _fill(zsvd2_args, CPLX_IN + CPLX_OUT, list(ins) + list(outs))
+    u = _fill(zsvd2_urv, CPLX_URV, list(f))
+    _check("zsvd2_batch_urv", lib().zsvd2_batch_urv(n, ctypes.byref(a), ctypes.byref(u), flags, _stream(stream)))
+
+
+def ssvd2_batch_urv(n: int, ins, outs, f, flags: int = 0, ws: int = 0, ws_bytes: int = 0,
+                    nrescued: int = 0, stream=None) -> None:
+    a = _fill(ssvd2_args, REAL_IN + REAL_OUT, list(ins) + list(outs), {"nrescued": nrescued})
+    u = _fill(ssvd2_urv, REAL_URV, list(f))
+    _check("ssvd2_batch_urv", lib().ssvd2_batch_urv(n, ctypes.byref(a), ctypes.byref(u), flags, ws, ws_bytes,
+                                                    _stream(stream)))
+
+
+def csvd2_batch_urv(n: int, ins, outs, f, flags: int = 0, ws: int = 0, ws_bytes: int = 0,
+                    nrescued: int = 0, stream=None) -> None:
+    a = _fill(csvd2_args, CPLX_IN + CPLX_OUT, list(ins) + list(outs), {"nrescued": nrescued})
+    u = _fill(csvd2_urv, CPLX_URV, list(f))
+    _check("csvd2_batch_urv", lib().csvd2_batch_urv(n, ctypes.byref(a), ctypes.byref(u), flags, ws, ws_bytes,
+                                                    _stream(stream)))
+
+
 def svd2_workspace_bytes(n: int, flags: int) -> int:
     return int(lib().svd2_workspace_bytes(n, flags))
 
@@ -241,11 +292,14 @@ def svd2_stream_probe(kind: str, ins, outs, stream=None) -> None:
 # tensor convenience: allocate outputs with torch and call the entry point
 # ---------------------------------------------------------------------------
 
-def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
+def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None, urv=None):
     """Batched SVD of SoA trains (list of 4 real or 8 re/im device tensors of
     one dtype, element order 11, 21, 12, 22).  Returns the list of output
     trains (11 or 19 tensors: U, V, smax, smin, s) in the order of the C ABI;
-    with SVD2_NO_UV only [smax, smin, s] (out, if given, holds those three)."""
+    with SVD2_NO_UV only [smax, smin, s] (out, if given, holds those three).
+    urv: a list of device trains for the phase outputs of the URV
+    factorization (the *_batch_urv entry points): 3 (R only) or 11 / 19
+    (R, U_+, V_+); then (out, urv) is returned."""
     import torch
     trains = list(trains)
     cplx = len(trains) == 8
@@ -269,20 +323,33 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None):
     outs = [t.data_ptr() for t in out]
     if nout == 3:
         outs = [0] * (16 if cplx else 8) + outs
+    fp = None
+    if urv is not None:
+        nf = 19 if cplx else 11
+        if len(urv) not in (3, nf):
+            raise ValueError(f"expected 3 or {nf} phase-output trains")
+        for i, t in enumerate(urv):
+            _like(t, f"phase-output train {i}", dt, trains[0].device, n)
+        fp = [t.data_ptr() for t in urv] + [0] * (nf - len(urv))
     if dt == torch.float64:
-        (zsvd2_batch if cplx else dsvd2_batch)(n, ins, outs, flags, stream)
+        if fp is None:
+            (zsvd2_batch if cplx else dsvd2_batch)(n, ins, outs, flags, stream)
+        else:
+            (zsvd2_batch_urv if cplx else dsvd2_batch_urv)(n, ins, outs, fp, flags, stream)
     elif dt == torch.float32:
         wsb = svd2_workspace_bytes(n, flags)
         if wsb and ws is None:
             ws = torch.empty(wsb, dtype=torch.uint8, device=trains[0].device)
         # the library checks the size the caller's buffer really has
         ws_bytes = 0 if ws is None else _nbytes(ws)
-        (csvd2_batch if cplx else ssvd2_batch)(
-            n, ins, outs, flags, 0 if ws is None else ws.data_ptr(), ws_bytes,
-            0 if nrescued is None else nrescued.data_ptr(), stream)
+        wsp, nr = 0 if ws is None else ws.data_ptr(), 0 if nrescued is None else nrescued.data_ptr()
+        if fp is None:
+            (csvd2_batch if cplx else ssvd2_batch)(n, ins, outs, flags, wsp, ws_bytes, nr, stream)
+        else:
+            (csvd2_batch_urv if cplx else ssvd2_batch_urv)(n, ins, outs, fp, flags, wsp, ws_bytes, nr, stream)
     else:
         raise TypeError(dt)
-    return out
+    return out if urv is None else (out, urv)
 
 
 # ---------------------------------------------------------------------------

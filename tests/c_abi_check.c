@@ -33,6 +33,19 @@ int main(void) {
   CHECK(ssvd2_batch(16, &s, SVD2_RESCUE_SIGMA, NULL, 0, st) == SVD2_ERR_FLAGS);
   CHECK(ssvd2_batch(16, &s, SVD2_RESCUE_FP64 | SVD2_RESCUE_SIGMA | SVD2_RESCUE_TRI, NULL, 0, st) ==
         SVD2_ERR_FLAGS);
+  /* phase outputs: missing structs or arrays, backscale refused */
+  {
+    dsvd2_urv df = {0};
+    zsvd2_urv zf = {0};
+    ssvd2_urv sf = {0};
+    csvd2_urv cf = {0};
+    CHECK(dsvd2_batch_urv(16, &d, NULL, 0, st) == SVD2_ERR_NULL);
+    CHECK(dsvd2_batch_urv(16, &d, &df, 0, st) == SVD2_ERR_NULL);
+    CHECK(zsvd2_batch_urv(16, &z, &zf, SVD2_BACKSCALE_SAFE, st) == SVD2_ERR_FLAGS);
+    CHECK(ssvd2_batch_urv(16, &s, &sf, SVD2_RESCUE_FP64, NULL, 0, st) == SVD2_ERR_NULL);
+    CHECK(csvd2_batch_urv(16, &c, &cf, SVD2_RESCUE_FP64 | SVD2_BACKSCALE_ALL, NULL, 0, st) == SVD2_ERR_FLAGS);
+    CHECK(csvd2_batch_urv(0, &c, &cf, SVD2_RESCUE_SIGMA, NULL, 0, st) == SVD2_ERR_FLAGS);
+  }
   /* workspace queries and launch shapes */
   CHECK(svd2_workspace_bytes(1000, SVD2_RESCUE_FP64) == 0);
   CHECK(svd2_workspace_bytes(1000, SVD2_RESCUE_FP64 | SVD2_RESCUE_QUEUE) >= 1000 * sizeof(uint32_t));

@@ -95,6 +95,56 @@ def test_singular_values_only_arguments(fn, nin, nuv):
     assert _call(fn, 10, ins, [0] * nuv + [sig[0], ins[1], sig[2]], flags=f) == 3
 
 
+def _call_urv(fn, n, ins, outs, f, flags=0, **kw):
+    try:
+        fn(n, ins, outs, f, flags, stream=0, **kw)
+    except S.Svd2Error as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("fn,nin,nout", [(S.dsvd2_batch_urv, 4, 11), (S.zsvd2_batch_urv, 8, 19),
+                                         (S.ssvd2_batch_urv, 4, 11), (S.csvd2_batch_urv, 8, 19)])
+def test_phase_output_arguments(fn, nin, nout):
+    """The *_batch_urv entry points: R required, U_+ and V_+ all or none,
+    no backscale, the phase outputs in the alias and alignment checks."""
+    ins, outs = _ptrs(nin), _ptrs(nout, base=FAKE + (64 << 30))
+    f = _ptrs(nout, base=FAKE + (128 << 30))
+    r_only = f[:3] + [0] * (nout - 3)
+    assert _call_urv(fn, 0, ins, outs, f) == 0
+    assert _call_urv(fn, 0, ins, outs, r_only) == 0
+    assert _call_urv(fn, 0, ins, [0] * (nout - 3) + outs[-3:], r_only, flags=S.SVD2_NO_UV) == 0
+    assert _call_urv(fn, 0, ins, outs, f, flags=S.SVD2_SINE_FORM) == 0
+    for i in range(3):  # R is required
+        bad = list(f)
+        bad[i] = 0
+        assert _call_urv(fn, 10, ins, outs, bad) == 1
+    bad = list(f)
+    bad[5] = 0  # U_+ / V_+ partly given
+    assert _call_urv(fn, 10, ins, outs, bad) == 1
+    # the backscale flags are refused: R, U_+ and V_+ belong to 2^s A
+    assert _call_urv(fn, 10, ins, outs, f, flags=S.SVD2_BACKSCALE_SAFE) == 4
+    assert _call_urv(fn, 10, ins, outs, f, flags=S.SVD2_BACKSCALE_ALL) == 4
+    assert _call_urv(fn, 10, ins, outs, f, flags=1 << 12) == 4
+    bad = list(f)
+    bad[1] += 1  # misaligned R
+    assert _call_urv(fn, 10, ins, outs, bad) == 2
+    bad = list(f)
+    bad[nout - 1] = ins[0]  # V_+ over an input
+    assert _call_urv(fn, 10, ins, outs, bad) == 3
+    bad = list(f)
+    bad[2] = outs[4] + 8  # R over an output
+    assert _call_urv(fn, 10, ins, outs, bad) == 3
+    bad = r_only[:]
+    bad[0] = bad[1]  # two phase outputs on one array
+    assert _call_urv(fn, 10, ins, outs, bad) == 3
+    # NULL structs
+    L = S.lib()
+    raw = getattr(L, fn.__name__)
+    args = (10, None, None, 0, None) if fn.__name__[0] in "dz" else (10, None, None, 0, None, 0, None)
+    assert raw(*args) == 1
+
+
 def test_singular_values_only_launch_kinds():
     old = S.svd2_get_launch_kind("z_nouv")
     S.svd2_set_launch_kind("z_nouv", 128, 2)
