@@ -340,8 +340,8 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
     """Kogbetliantz on the one-problem workload: real FP64, A = Q1 diag(s) Q2^T
     with s geometric from 1 to 1e-12.  Sweeps/s of each driver, timed over
     `sweeps` sweeps from the same matrix: the fused persistent kernel, the
-    unfused gather -> SVD -> update chain, its hipGraph replay, and two steps
-    per pass over the matrix; then a full solve with the fastest."""
+    unfused gather -> SVD -> update chain, its hipGraph replay, and two or
+    three steps per pass over the matrix; then a full solve with the fastest."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     from workloads import SEED_BASE, kog_matrix
@@ -353,12 +353,14 @@ def kog_bench(order: int, sweeps: int = 2, solve: bool = True, only=None):
     # the single-step drivers; one per pass of two steps (plus the odd last
     # step) for the two-step driver
     passes = (steps - 1) // 2 if steps > 1 else 0
+    passes3 = steps // 3  # three-step passes, then a two-step pass or a single step for the rest
     hbm_sweep = {"fused": 2 * mat * steps, "unfused": 2 * mat * steps, "graph": 2 * mat * steps,
-                 "two_step": 2 * mat * (passes + (steps - 2 * passes))}
+                 "two_step": 2 * mat * (passes + (steps - 2 * passes)),
+                 "three_step": 2 * mat * (passes3 + (1 if steps % 3 else 0))}
     out = {"order": order, "dtype": "f64", "steps_per_sweep": steps,
            "algorithmic_bytes_per_step": 2 * mat}
     modes = {"fused": 0, "unfused": S.SVD2_KOG_UNFUSED, "graph": S.SVD2_KOG_UNFUSED | S.SVD2_KOG_GRAPH,
-             "two_step": S.SVD2_KOG_TWO_STEP}
+             "two_step": S.SVD2_KOG_TWO_STEP, "three_step": S.SVD2_KOG_THREE_STEP}
     if only:
         modes = {m: modes[m] for m in only}
     for name, fl in modes.items():
@@ -604,7 +606,7 @@ def headline(full: dict) -> dict:
     kog = full.get("kogbetliantz")
     if kog:
         k = {"order": kog["order"], "sweeps_per_s": {m: r4(kog[m]["sweeps_per_s"]) for m in
-                                                      ("two_step", "unfused", "graph", "fused") if m in kog}}
+                                                      ("three_step", "two_step", "unfused", "graph", "fused") if m in kog}}
         if "solve" in kog:
             s = kog["solve"]
             k["solve"] = {"mode": s["mode"], "sweeps": s["sweeps"], "seconds": r4(s["seconds"]),

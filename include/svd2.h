@@ -308,18 +308,30 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  * before the matrix is read; every entry is computed with the operations of
  * the single-step update (bitwise the same result) and the matrix is read and
  * written once per two steps.  The result is always returned in A.
+ * SVD2_KOG_THREE_STEP (step, sweep and solve, alone): the same with three
+ * steps per pass (each 2x2 block after step t+2 depends on an 8x8
+ * neighbourhood before step t; the pivots of step t+2 are formed from it with
+ * the rotations of steps t and t+1), so the matrix is read and written once
+ * per three steps; a sweep's N-1 steps end with a two-step pass or a single
+ * step where three do not divide them.  Workspace of
+ * kog_workspace_bytes_flags(N, dtype, SVD2_KOG_THREE_STEP).  Bitwise the
+ * result of single steps, returned in A.  Not accepted by the SVD, sigma and
+ * batch entry points.
  * ------------------------------------------------------------------------- */
-enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2, SVD2_KOG_TWO_STEP = 4 };
+enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2, SVD2_KOG_TWO_STEP = 4, SVD2_KOG_THREE_STEP = 8 };
 enum { SVD2_KOG_F64 = 0, SVD2_KOG_C128 = 1, SVD2_KOG_F32 = 2, SVD2_KOG_C64 = 3 };
 
 size_t kog_workspace_bytes(int N, int dtype);
-/* the same for the given flags (SVD2_KOG_TWO_STEP adds N^2 elements) */
+/* the same for the given flags (SVD2_KOG_TWO_STEP adds N^2 elements,
+   SVD2_KOG_THREE_STEP those and a third set of rotations) */
 size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags);
 
 /* one step t (0 <= t < N-1); flags 0 (fused kernel) or SVD2_KOG_UNFUSED.
    With SVD2_KOG_TWO_STEP (alone): steps t and t+1 (0 <= t, t+1 < N-1) in one
    two-step pass into the workspace matrix, which is then copied back into A
-   (workspace of kog_workspace_bytes_flags(N, dtype, SVD2_KOG_TWO_STEP)). */
+   (workspace of kog_workspace_bytes_flags(N, dtype, SVD2_KOG_TWO_STEP)).
+   With SVD2_KOG_THREE_STEP (alone): steps t, t+1, t+2 (t + 2 < N-1) in one
+   three-step pass, copied back the same way. */
 svd2_status dkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
                       hipStream_t stream);
 svd2_status zkog_step(int N, double *A, int lda, int t, void *ws, size_t ws_bytes, unsigned flags,
@@ -463,6 +475,8 @@ svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *w
  * SVD2_ERR_FLAGS.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
  * SVD2_NOT_CONVERGED (outputs as above for the last iterate); synchronises
  * `stream` like *_solve.
+ * kog_svd_workspace_bytes returns 0 for an order, element type or flags
+ * these entry points do not accept.
  * ------------------------------------------------------------------------- */
 size_t kog_svd_workspace_bytes(int N, int dtype, unsigned flags);
 svd2_status dkog_svd(int N, double *A, int lda, double *U, int ldu, double *V, int ldv, double *sigma,
@@ -514,6 +528,14 @@ svd2_status kog_set_tile_rules(int count, const int *max_order, const int *kc, c
  * (4, 8).  Host arrays, copied; safe to call while other threads launch
  * (the tables are guarded); affects later calls. */
 svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *wpg, const int *lc);
+
+/* Workgroup shapes of the three-step kernel (SVD2_KOG_THREE_STEP), by order:
+ * the first rule with N <= max_order[i] applies.  wpg[i] in {1, 2, 4}
+ * wavefronts per workgroup, each on its own block of 60 row pairs; lc[i] in
+ * [2, 128] output column pairs per workgroup, shared by its wavefronts.
+ * count = 0 restores the default (1, 24).  Host arrays, copied; safe to call
+ * while other threads launch; affects later calls. */
+svd2_status kog_set_three_step_tiles(int count, const int *max_order, const int *wpg, const int *lc);
 
 #ifdef __cplusplus
 }

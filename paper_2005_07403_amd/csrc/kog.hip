@@ -59,6 +59,18 @@ TileRule rule2_for(int N) {
   return default_rule2();
 }
 
+// three-step kernel shapes: kc = wavefronts (row blocks) per workgroup, lc =
+// output column pairs per tile
+TileRule default_rule3() { return TileRule{0x7fffffff, 1, 24}; }
+TileRule g_rules3[kMaxRules] = {default_rule3()};
+int g_nrules3 = 1;
+TileRule rule3_for(int N) {
+  std::lock_guard<std::mutex> lock(g_rules_mu);
+  for (int i = 0; i < g_nrules3; ++i)
+    if (N <= g_rules3[i].max_order) return g_rules3[i];
+  return default_rule3();
+}
+
 svd2_status hip_st(hipError_t e) {
   if (e == hipSuccess) return SVD2_OK;
   g_kog_hip = (int)e;
@@ -117,6 +129,22 @@ __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> M
   extern __shared__ __align__(16) char kog_smem[];
   const int tile = xcd_tile((int)blockIdx.x, ntiles);
   two_step_tile<T, CPLX>(kog_smem, N, Mc, Mn, t, B0, B1, wpg, span, lc, tile % gx, tile / gx);
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_pivots3_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
+                                                          Bufs<T, CPLX> B1, Bufs<T, CPLX> B2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N / 2) pivots3_one<T, CPLX>(N, M, t, B0, B1, B2, k);
+}
+
+template <class T, bool CPLX>
+__global__ __launch_bounds__(256) void kog_three_step_kernel(int N, Mat<T, CPLX> Mc, Mat<T, CPLX> Mn, int t,
+                                                             Bufs<T, CPLX> B0, Bufs<T, CPLX> B1, Bufs<T, CPLX> B2,
+                                                             int wpg, int lc, int gx, int ntiles) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int tile = xcd_tile((int)blockIdx.x, ntiles);
+  three_step_tile<T, CPLX>(kog_smem, N, Mc.A, Mc.lda, Mn.A, Mn.lda, t, B0, B1, B2, wpg, lc, tile % gx, tile / gx);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,19 +417,24 @@ template <class T, bool CPLX> struct Ctx {
   bool acc = false;
   Mat<T, CPLX> U{}, V{}, U2{}, V2{};
   Bufs<T, CPLX> B2{}, B3{};  // two steps per pass: the rotations of every second pass
+  Bufs<T, CPLX> Bt{};        // three steps per pass: the rotations of the third step
 };
 
 template <class T, bool CPLX>
 svd2_status validate(int N, T *A, int lda, void *ws, size_t ws_bytes, unsigned flags, Ctx<T, CPLX> &c) {
   if (!A || !ws) return SVD2_ERR_NULL;
   if (N < 2 || N % 2 || lda < N || N > (1 << 19)) return SVD2_ERR_SIZE;
-  if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;
+  if (flags & ~(unsigned)(SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP | SVD2_KOG_THREE_STEP))
+    return SVD2_ERR_FLAGS;
   if ((flags & SVD2_KOG_GRAPH) && !(flags & SVD2_KOG_UNFUSED)) return SVD2_ERR_FLAGS;
   if ((flags & SVD2_KOG_TWO_STEP) && (flags & (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))) return SVD2_ERR_FLAGS;
+  if ((flags & SVD2_KOG_THREE_STEP) && (flags & (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)))
+    return SVD2_ERR_FLAGS;
   if ((uintptr_t)A % (CPLX ? 2 * sizeof(T) : sizeof(T))) return SVD2_ERR_ALIGN;
   if ((uintptr_t)ws % 256) return SVD2_ERR_ALIGN;
   c.L = layout(N, sizeof(T), CPLX);
-  const size_t need = (flags & SVD2_KOG_TWO_STEP) ? c.L.total2 : c.L.total;
+  const size_t need = (flags & SVD2_KOG_THREE_STEP) ? c.L.total3 : (flags & SVD2_KOG_TWO_STEP) ? c.L.total2
+                                                                                              : c.L.total;
   if (ws_bytes < need) return SVD2_ERR_SIZE;
   size_t abytes = ((size_t)lda * (N - 1) + N) * sizeof(T) * (CPLX ? 2 : 1);
   uintptr_t a0 = (uintptr_t)A, a1 = a0 + abytes, w0 = (uintptr_t)ws, w1 = w0 + need;
@@ -410,6 +443,7 @@ svd2_status validate(int N, T *A, int lda, void *ws, size_t ws_bytes, unsigned f
   c.M = Mat<T, CPLX>{A, (size_t)lda};
   c.B = make_bufs<T, CPLX>(ws, N, 0);
   c.B1 = make_bufs<T, CPLX>(ws, N, 1);
+  if (flags & SVD2_KOG_THREE_STEP) c.Bt = make_bufs<T, CPLX>(ws, N, 2);
   c.W = Mat<T, CPLX>{(T *)((char *)ws + c.L.mat), (size_t)N};
   c.ws = (char *)ws;
   c.flags = flags;
@@ -597,6 +631,41 @@ svd2_status two_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<
   return hip_st(hipGetLastError());
 }
 
+struct ThreeStepShape {
+  int wpg, lc, gx, ntiles;
+  size_t lds;
+};
+template <class T, bool CPLX> ThreeStepShape three_step_shape(int N) {
+  const TileRule r = rule3_for(N);
+  const int n = N / 2;
+  ThreeStepShape sh;
+  sh.wpg = r.kc;
+  sh.lc = r.lc < n ? r.lc : n;
+  const int nb = (n + kShift3Out - 1) / kShift3Out;
+  sh.gx = (nb + sh.wpg - 1) / sh.wpg;
+  sh.ntiles = sh.gx * ((n + sh.lc - 1) / sh.lc);
+  sh.lds = three_step_lds<T, CPLX>(sh.lc);
+  return sh;
+}
+
+// three steps t, t+1, t+2 from `cur` into `nxt` (rotations into B0, B1, B2)
+template <class T, bool CPLX>
+svd2_status three_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t,
+                        const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2) {
+  const int n = c.N / 2;
+  hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1);
+  svd2_status s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  hipLaunchKernelGGL((kog_pivots3_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1,
+                     B2);
+  s = hip_st(hipGetLastError());
+  if (s != SVD2_OK) return s;
+  const ThreeStepShape sh = three_step_shape<T, CPLX>(c.N);
+  hipLaunchKernelGGL((kog_three_step_kernel<T, CPLX>), dim3(sh.ntiles), dim3(64 * sh.wpg), sh.lds, c.st, c.N, cur,
+                     nxt, t, B0, B1, B2, sh.wpg, sh.lc, sh.gx, sh.ntiles);
+  return hip_st(hipGetLastError());
+}
+
 // one step t in place on `cur` (gather + SVD in one kernel, then the update)
 template <class T, bool CPLX>
 svd2_status one_step_on(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, int t, bool in_w = false) {
@@ -642,6 +711,25 @@ template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, 
   return s;
 }
 
+// a sweep of the three-step mode (iterate only): passes of three steps, then
+// what is left of the N-1 steps as one two-step pass or one single step; *in_w
+// as in sweep_two_step
+template <class T, bool CPLX> svd2_status sweep_three_step(const Ctx<T, CPLX> &c, bool *in_w) {
+  svd2_status s = SVD2_OK;
+  int t = 0;
+  for (; c.N - 1 - t >= 3 && s == SVD2_OK; t += 3) {
+    s = three_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, c.B, c.B1, c.Bt);
+    *in_w = !*in_w;
+  }
+  if (s == SVD2_OK && c.N - 1 - t == 2) {
+    s = two_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, c.B, c.B1);
+    *in_w = !*in_w;
+    t += 2;
+  }
+  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t);
+  return s;
+}
+
 template <class T, bool CPLX> svd2_status copy_back(const Ctx<T, CPLX> &c) {
   int grid = c.N < 4096 ? c.N : 4096;
   hipLaunchKernelGGL((kog_copy_kernel<T, CPLX>), dim3(grid), dim3(256), 0, c.st, c.N, c.W, c.M);
@@ -649,6 +737,12 @@ template <class T, bool CPLX> svd2_status copy_back(const Ctx<T, CPLX> &c) {
 }
 
 template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
+  if (c.flags & SVD2_KOG_THREE_STEP) {
+    bool in_w = false;
+    svd2_status s = sweep_three_step<T, CPLX>(c, &in_w);
+    if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
+    return s;
+  }
   if (c.flags & SVD2_KOG_TWO_STEP) {
     bool in_w = false, uv_in = false;
     svd2_status s = sweep_two_step<T, CPLX>(c, &in_w, &uv_in);
@@ -709,7 +803,7 @@ template <class T, bool CPLX> svd2_status scale_by(const Ctx<T, CPLX> &c, int e)
 }
 
 template <class T, bool CPLX> svd2_status check_abort(const Ctx<T, CPLX> &c) {
-  if (c.flags & (SVD2_KOG_UNFUSED | SVD2_KOG_TWO_STEP)) return SVD2_OK;
+  if (c.flags & (SVD2_KOG_UNFUSED | SVD2_KOG_TWO_STEP | SVD2_KOG_THREE_STEP)) return SVD2_OK;
   Bar h;
   svd2_status s = hip_st(hipMemcpyAsync(&h, c.ws + c.L.bar, sizeof h, hipMemcpyDeviceToHost, c.st));
   if (s != SVD2_OK) return s;
@@ -747,7 +841,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
   hipGraphExec_t exec = nullptr;
   svd2_status s = SVD2_OK;
   if (c.flags & SVD2_KOG_GRAPH) s = graph_build<T, CPLX>(c, &exec);
-  const bool two = c.flags & SVD2_KOG_TWO_STEP;
+  const bool two = c.flags & SVD2_KOG_TWO_STEP, three = c.flags & SVD2_KOG_THREE_STEP;
   bool in_w = false, uv_in = false;
   double off2 = 0, tot2 = 0, nrm0 = 0;
   int sw = 0, E = 0;
@@ -766,6 +860,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     }
     if (sw == max_sweeps) break;
     if (exec) s = hip_st(hipGraphLaunch(exec, c.st));
+    else if (three) s = sweep_three_step<T, CPLX>(c, &in_w);
     else if (two) s = sweep_two_step<T, CPLX>(c, &in_w, &uv_in);
     else s = sweep<T, CPLX>(c);
     if (s == SVD2_OK) s = norms_async<T, CPLX>(c, in_w);
@@ -789,6 +884,12 @@ svd2_status api_step(int N, T *A, int lda, int t, void *ws, size_t wsb, unsigned
   svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
   if (s != SVD2_OK) return s;
   c.st = st;
+  if (c.flags & SVD2_KOG_THREE_STEP) {
+    // steps t, t+1 and t+2 in one pass into the workspace matrix, then copied back
+    if (t < 0 || t + 2 >= N - 1) return SVD2_ERR_SIZE;
+    s = three_steps<T, CPLX>(c, c.M, c.W, t, c.B, c.B1, c.Bt);
+    return s != SVD2_OK ? s : copy_back<T, CPLX>(c);
+  }
   if (c.flags & SVD2_KOG_TWO_STEP) {
     // steps t and t+1 in one pass into the workspace matrix, then copied back
     if (t < 0 || t + 1 >= N - 1) return SVD2_ERR_SIZE;
@@ -989,14 +1090,16 @@ size_t kog_workspace_bytes_flags(int N, int dtype, unsigned flags) {
     case SVD2_KOG_C64: L = layout(N, 4, true); break;
     default: return 0;
   }
-  return (flags & SVD2_KOG_TWO_STEP) ? L.total2 : L.total;
+  return (flags & SVD2_KOG_THREE_STEP) ? L.total3 : (flags & SVD2_KOG_TWO_STEP) ? L.total2 : L.total;
 }
 
 size_t kog_workspace_bytes(int N, int dtype) { return kog_workspace_bytes_flags(N, dtype, 0); }
 
 size_t kog_svd_workspace_bytes(int N, int dtype, unsigned flags) {
   if (N < 2 || N % 2 || N > (1 << 19)) return 0;
-  const bool two = (svd_flags(flags) & SVD2_KOG_TWO_STEP) != 0;
+  const unsigned f = svd_flags(flags);
+  if (f != SVD2_KOG_TWO_STEP && f != SVD2_KOG_UNFUSED && f != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH)) return 0;
+  const bool two = (f & SVD2_KOG_TWO_STEP) != 0;
   switch (dtype) {
     case SVD2_KOG_F64: return svd_layout(N, 8, false, two).total;
     case SVD2_KOG_C128: return svd_layout(N, 8, true, two).total;
@@ -1148,6 +1251,24 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
   if (count == 0) {
     g_rules2[0] = default_rule2();
     g_nrules2 = 1;
+  }
+  return SVD2_OK;
+}
+
+svd2_status kog_set_three_step_tiles(int count, const int *max_order, const int *wpg, const int *lc) {
+  if (count < 0 || count > kMaxRules) return SVD2_ERR_SIZE;
+  if (count > 0 && (!max_order || !wpg || !lc)) return SVD2_ERR_NULL;
+  for (int i = 0; i < count; ++i) {
+    if (wpg[i] != 1 && wpg[i] != 2 && wpg[i] != 4) return SVD2_ERR_SIZE;
+    if (lc[i] < 2 || lc[i] > 128 || max_order[i] < 2) return SVD2_ERR_SIZE;
+    if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
+  }
+  std::lock_guard<std::mutex> lock(g_rules_mu);
+  for (int i = 0; i < count; ++i) g_rules3[i] = TileRule{max_order[i], wpg[i], lc[i]};
+  g_nrules3 = count;
+  if (count == 0) {
+    g_rules3[0] = default_rule3();
+    g_nrules3 = 1;
   }
   return SVD2_OK;
 }

@@ -76,6 +76,7 @@ struct Bar {
 struct Layout {
   size_t piv, out, red, res, bar, flags, total;
   size_t piv1, out1, mat, total2;  // two-step mode: second rotation set and a matrix buffer
+  size_t piv2, out2, total3;       // three-step mode: a third rotation set
 };
 constexpr int kMaxFusedBlocks = 4096;  // barrier slots (64 bytes each)
 
@@ -96,6 +97,9 @@ inline Layout layout(int N, size_t esz, bool cplx) {
   L.out1 = L.piv1 + nin * arr;
   L.mat = L.out1 + nout * arr;
   L.total2 = L.mat + up((size_t)N * N * esz * (cplx ? 2 : 1));
+  L.piv2 = L.total2;
+  L.out2 = L.piv2 + nin * arr;
+  L.total3 = L.out2 + nout * arr;
   return L;
 }
 
@@ -105,7 +109,7 @@ template <class T, bool CPLX> Bufs<T, CPLX> make_bufs(void *ws, int N, int set =
   size_t arr = up((size_t)(N / 2) * sizeof(T));
   Bufs<T, CPLX> b;
   char *base = (char *)ws;
-  size_t piv = set ? L.piv1 : L.piv, out = set ? L.out1 : L.out;
+  size_t piv = set == 2 ? L.piv2 : set ? L.piv1 : L.piv, out = set == 2 ? L.out2 : set ? L.out1 : L.out;
   for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(base + piv + i * arr);
   for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(base + out + i * arr);
   return b;
@@ -451,6 +455,78 @@ __device__ __forceinline__ void pivots2_one(int N, const Mat<T, CPLX> &M, int t,
 }
 
 
+// pivots of step t+2, after the pivots of steps t (B0) and t+1 (B1) are
+// known: lane k forms pair k's pivot block of step t+2 from the matrix before
+// step t.  Its rows and columns {p, q} belong to two pairs of step t+1, whose
+// four indices x belong to four pairs of step t; each entry after step t+1 is
+// one rotated entry of a step-(t+1) block of entries after step t, each of
+// those one rotated entry of a step-t block of the matrix (64 loads), with
+// the rotations as stored in B0 and B1, so with exactly the operations of two
+// single steps.  Then its SVD goes into B2.
+template <class T, bool CPLX>
+__device__ __forceinline__ void pivots3_one(int N, const Mat<T, CPLX> &M, int t, const Bufs<T, CPLX> &B0,
+                                            const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2, int k) {
+  constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
+  constexpr int NI = Bufs<T, CPLX>::NIN, NO = Bufs<T, CPLX>::NOUT;
+  const int n = N / 2, Mo = N - 1;
+  int a, b;
+  pair_ab(t + 2, k, Mo, a, b);
+  // X1: p, its step-(t+1) partner, q, its step-(t+1) partner
+  const Side S1[2] = {side_at(t + 1, a < b ? a : b, Mo, n), side_at(t + 1, a < b ? b : a, Mo, n)};
+  const int X1[4] = {S1[0].x, S1[0].partner, S1[1].x, S1[1].partner};
+  Side S0[4];
+  RotU<T> U0[4];
+  RotV<T> V0[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    S0[i] = side_at(t, X1[i], Mo, n);
+    const Rot<T> r = load_rot<T, CPLX>(B0, S0[i].k);
+    U0[i] = RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
+    V0[i] = RotV<T>{r.v11, r.v21, r.v12, r.v22};
+  }
+  RotU<T> U1[2];
+  RotV<T> V1[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const Rot<T> r = load_rot<T, CPLX>(B1, S1[i].k);
+    U1[i] = RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
+    V1[i] = RotV<T>{r.v11, r.v21, r.v12, r.v22};
+  }
+  // entries after step t on X1 x X1
+  Cx<T> A1[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      A1[i][j] = after_step<T, CPLX>(S0[i], U0[i], S0[j], V0[j], M.ld(X1[i], X1[j]), M.ld(X1[i], S0[j].partner),
+                                     M.ld(S0[i].partner, X1[j]), M.ld(S0[i].partner, S0[j].partner));
+  // entries after step t+1 on {p, q} x {p, q}: row 2i of X1 with its partner 2i+1
+  Cx<T> e[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      e[i][j] = after_step<T, CPLX>(S1[i], U1[i], S1[j], V1[j], A1[2 * i][2 * j], A1[2 * i][2 * j + 1],
+                                    A1[2 * i + 1][2 * j], A1[2 * i + 1][2 * j + 1]);
+  const Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
+  T x[NI], y[NO];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (CPLX) {
+      x[2 * i] = rec[i].re;
+      x[2 * i + 1] = rec[i].im;
+    } else {
+      x[i] = rec[i].re;
+    }
+  }
+  one_matrix<T, CPLX, RESC>(x, y, 2);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) B2.piv[i][k] = x[i];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) B2.out[i][k] = y[i];
+}
+
+
 // The two-step update proper ("lane-shift" form).  Lane j of a wavefront
 // holds the rows of pair j of step t (P_j = t + j and Q_j = t - j mod N-1;
 // pair 0 is rows t and N-1) and walks column pairs j' of step t in increasing
@@ -724,6 +800,221 @@ __device__ __forceinline__ void two_step_tile(char *kog_smem, int N, const Mat<T
                                               const Mat<T, CPLX> &Mn, int t, const Bufs<T, CPLX> &B0,
                                               const Bufs<T, CPLX> &B1, int wpg, int span, int lc, int bx, int by) {
   two_step_tile_r<T, CPLX>(kog_smem, N, Mc.A, Mc.lda, Mn.A, Mn.lda, t, B0, B1, wpg, span, lc, bx, by);
+}
+
+// ---------------------------------------------------------------------------
+// Three steps per pass: the lane-shift walk with one more level.  Lane j of a
+// wavefront holds the rows of pair j of step t; after the step-t rotation and
+// the row exchange it holds the rows of pair j of step t+1 (valid on lanes
+// 1..62), after the step-(t+1) rotation and a second exchange those of pair j
+// of step t+2 (lanes 2..61), which it rotates and writes: 60 row pairs per
+// wavefront.  The columns pass through two delay windows the same way: the
+// walk over the column pairs of step t feeds the step-(t+1) column pairs one
+// behind, and those feed the step-(t+2) column pairs one further behind.
+// The wavefronts of a workgroup take consecutive blocks of 60 row pairs and
+// the same run of lc output column pairs, whose rotations of all three steps
+// are staged in LDS; each walks two column pairs beyond the run on either
+// side (they only fill the windows), so nothing crosses between wavefronts.
+// Every entry is computed with the operations of the single-step update.
+// ---------------------------------------------------------------------------
+constexpr int kShift3Out = 60;
+
+template <class T, bool CPLX> constexpr size_t three_step_lds(int lc) {
+  return (size_t)(3 * lc + 6) * sizeof(VPack<T, CPLX>);
+}
+
+// the entries of a block in (smaller row, larger row) x (smaller column,
+// larger column) order, relabelled by roles: row P or Q of the lane's pair,
+// column P or Q of the column pair (rflip: P is the larger row index, cflip:
+// P is the larger column index)
+template <class T> struct Lab {
+  Cx<T> PP, QP, PQ, QQ;
+};
+template <class T>
+__device__ __forceinline__ Lab<T> labelled(bool rflip, bool cflip, Cx<T> b11, Cx<T> b21, Cx<T> b12, Cx<T> b22) {
+  return Lab<T>{sel(rflip, sel(cflip, b22, b21), sel(cflip, b12, b11)),
+                sel(rflip, sel(cflip, b12, b11), sel(cflip, b22, b21)),
+                sel(rflip, sel(cflip, b21, b22), sel(cflip, b11, b12)),
+                sel(rflip, sel(cflip, b11, b12), sel(cflip, b21, b22))};
+}
+
+// the row exchange from the pairs of one step to those of the next (all
+// lanes call it): the next pair j takes the P row of lane j+1 and the Q row
+// of lane j-1 (P for j-1 = 0), or its own Q row at the two ends; lo and hi
+// are its smaller and larger row, cP and cQ the columns P and Q
+template <class T, bool CPLX>
+__device__ __forceinline__ void exchange_rows(bool j0, bool kflip, bool lo_own, bool hi_own, const Lab<T> &e,
+                                              ColPair<T> &cP, ColPair<T> &cQ) {
+  Cx<T> dn = shfl_dn1<T, CPLX>(e.PP), up = shfl_up1<T, CPLX>(sel(j0, e.PP, e.QP));
+  cP.lo = sel(lo_own, e.QP, sel(kflip, up, dn));
+  cP.hi = sel(hi_own, e.QP, sel(kflip, dn, up));
+  dn = shfl_dn1<T, CPLX>(e.PQ);
+  up = shfl_up1<T, CPLX>(sel(j0, e.PQ, e.QQ));
+  cQ.lo = sel(lo_own, e.QQ, sel(kflip, up, dn));
+  cQ.hi = sel(hi_own, e.QQ, sel(kflip, dn, up));
+}
+
+// one tile: wavefront w of the workgroup takes row block bxg * wpg + w, the
+// workgroup the output column pairs [by * lc, by * lc + lc); all threads of
+// the workgroup call it
+template <class T, bool CPLX>
+__device__ __forceinline__ void three_step_tile(char *smem, int N, T *__restrict__ mc, size_t ldc,
+                                                T *__restrict__ mn, size_t ldn, int t, const Bufs<T, CPLX> &B0,
+                                                const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2, int wpg, int lc,
+                                                int bxg, int by) {
+  const Mat<T, CPLX> Mc{mc, ldc}, Mn{mn, ldn};
+  const int n = N / 2, Mo = N - 1, t1 = t + 1, t2 = t + 2;
+  const int lane = (int)threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wavefront-uniform
+  const int bx = bxg * wpg + w;
+  const int m0 = by * lc;                                  // output column pairs [m0, mend)
+  const int mend = m0 + lc < n ? m0 + lc : n;
+  const int aw = m0 >= 2 ? m0 - 2 : 0;                     // walk [aw, bw]
+  const int bw = m0 + lc + 1 < n - 1 ? m0 + lc + 1 : n - 1;
+  const int l1lo = m0 >= 1 ? m0 - 1 : 0;                   // step-(t+1) column pairs [l1lo, l1hi]
+  const int l1hi = m0 + lc < n - 1 ? m0 + lc : n - 1;
+  VPack<T, CPLX> *sv0 = (VPack<T, CPLX> *)smem;            // index jj - aw (at most lc + 4)
+  VPack<T, CPLX> *sv1 = sv0 + (lc + 4);                    // index l - l1lo (at most lc + 2)
+  VPack<T, CPLX> *sv2 = sv1 + (lc + 2);                    // index m - m0 (at most lc)
+  for (int i = threadIdx.x; i <= bw - aw; i += blockDim.x) sv0[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B0, aw + i));
+  for (int i = threadIdx.x; i <= l1hi - l1lo; i += blockDim.x)
+    sv1[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B1, l1lo + i));
+  for (int i = threadIdx.x; i < mend - m0; i += blockDim.x) sv2[i] = pack_v<T, CPLX>(load_rot<T, CPLX>(B2, m0 + i));
+  __syncthreads();
+
+  const int j = bx * kShift3Out - 2 + lane;
+  const bool act = j >= 0 && j < n;
+  const bool mid = act && lane >= 1 && lane <= 62;
+  const bool out = act && lane >= 2 && lane <= kShift3Out + 1;
+  int P = 0, Q = 1, a1 = 0, b1 = 0, a2 = 0, b2 = 0;
+  RotU<T> u0{}, u1{}, u2{};
+  if (act) {
+    rows_at(t, j, Mo, P, Q);
+    u0 = load_u<T, CPLX>(B0, j);
+  }
+  if (mid) {
+    pair_ab(t1, j, Mo, a1, b1);
+    u1 = load_u<T, CPLX>(B1, j);
+  }
+  if (out) {
+    pair_ab(t2, j, Mo, a2, b2);
+    u2 = load_u<T, CPLX>(B2, j);
+  }
+  const bool rflip = P > Q;
+  const int rp = rflip ? Q : P, rq = rflip ? P : Q;        // rows of step t's pair j in (p, q) order
+  const bool kflip1 = a1 > b1, kflip2 = a2 > b2;
+  const int op2 = kflip2 ? b2 : a2, oq2 = kflip2 ? a2 : b2; // rows written
+  const bool lo1 = kflip1 ? j == 0 : j == n - 1, hi1 = kflip1 ? j == n - 1 : j == 0;
+  const bool lo2 = kflip2 ? j == 0 : j == n - 1, hi2 = kflip2 ? j == n - 1 : j == 0;
+  const Cx<T> zero{T(0), T(0)};
+
+  // column pair m of step t+2 from its columns ca(m) (cplus) and cb(m) (cminus), written
+  auto level2 = [&](int m, const ColPair<T> &cplus, const ColPair<T> &cminus) {
+    int ca, cb;
+    pair_ab(t2, m, Mo, ca, cb);
+    const bool mflip = ca > cb;
+    const int cp = mflip ? cb : ca, cq = mflip ? ca : cb;
+    Cx<T> c11 = sel(mflip, cminus.lo, cplus.lo), c21 = sel(mflip, cminus.hi, cplus.hi);
+    Cx<T> c12 = sel(mflip, cplus.lo, cminus.lo), c22 = sel(mflip, cplus.hi, cminus.hi);
+    if (m == j) {
+      c11 = Cx<T>{u2.sp, T(0)};
+      c22 = Cx<T>{u2.sq, T(0)};
+      c12 = c21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u2, sv2[m - m0]);
+      rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+    }
+    if (out) {
+      Mn.st(op2, cp, c11);
+      Mn.st(oq2, cp, c21);
+      Mn.st(op2, cq, c12);
+      Mn.st(oq2, cq, c22);
+    }
+  };
+
+  // the window over the step-(t+1) column pairs, in increasing order
+  ColPair<T> q1P{zero, zero}, q1Q{zero, zero}, q2m{zero, zero};
+  int lfirst = -1;
+  auto feed2 = [&](int l, const Lab<T> &e) {
+    ColPair<T> cP, cQ;
+    exchange_rows<T, CPLX>(j == 0, kflip2, lo2, hi2, e, cP, cQ);
+    if (lfirst < 0) lfirst = l;
+    const int m = l - 1;
+    if (m >= m0 && m < mend && (m == 0 ? lfirst == 0 : m - 1 >= lfirst)) level2(m, cP, selp(m == 0, q1Q, q2m));
+    if (l == n - 1 && n - 1 >= m0 && n - 1 < mend && n - 2 >= lfirst)
+      level2(n - 1, cQ, selp(n - 1 == 1, q1P, q1Q));
+    q2m = selp(l - 1 == 0, q1P, q1Q);
+    q1P = cP;
+    q1Q = cQ;
+  };
+
+  // column pair l of step t+1 from its columns ca(l) (cplus) and cb(l) (cminus), rotated, into the window
+  auto level1 = [&](int l, const ColPair<T> &cplus, const ColPair<T> &cminus) {
+    int ca, cb;
+    pair_ab(t1, l, Mo, ca, cb);
+    const bool lflip = ca > cb;
+    Cx<T> c11 = sel(lflip, cminus.lo, cplus.lo), c21 = sel(lflip, cminus.hi, cplus.hi);
+    Cx<T> c12 = sel(lflip, cplus.lo, cminus.lo), c22 = sel(lflip, cplus.hi, cminus.hi);
+    if (l == j) {
+      c11 = Cx<T>{u1.sp, T(0)};
+      c22 = Cx<T>{u1.sq, T(0)};
+      c12 = c21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u1, sv1[l - l1lo]);
+      rotate_block<T, CPLX>(r, r, c11, c21, c12, c22);
+    }
+    feed2(l, labelled<T>(kflip1, lflip, c11, c21, c12, c22));
+  };
+
+  struct Blk {
+    Cx<T> b11, b21, b12, b22;
+  };
+  auto load_blk = [&](int jj) -> Blk {
+    int Pc, Qc;
+    rows_at(t, jj, Mo, Pc, Qc);
+    const int cp = Pc < Qc ? Pc : Qc, cq = Pc < Qc ? Qc : Pc;
+    Blk d{zero, zero, zero, zero};
+    if (act) {
+      d.b11 = Mc.ld(rp, cp);
+      d.b21 = Mc.ld(rq, cp);
+      d.b12 = Mc.ld(rp, cq);
+      d.b22 = Mc.ld(rq, cq);
+    }
+    return d;
+  };
+  if (bx * kShift3Out >= n) return;  // no rows here (after the only barrier)
+  ColPair<T> p1P{zero, zero}, p1Q{zero, zero}, p2m{zero, zero};
+  constexpr int D = two_step_depth<T, CPLX>();
+  Blk q[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) q[d] = aw + d <= bw ? load_blk(aw + d) : Blk{zero, zero, zero, zero};
+  for (int jj = aw; jj <= bw; ++jj) {
+    const Blk a = q[0];
+#pragma unroll
+    for (int d = 0; d + 1 < D; ++d) q[d] = q[d + 1];
+    if (jj + D <= bw) q[D - 1] = load_blk(jj + D);
+    // step t on the block (j, jj), in (p, q) order
+    int Pc, Qc;
+    rows_at(t, jj, Mo, Pc, Qc);
+    Cx<T> b11 = a.b11, b21 = a.b21, b12 = a.b12, b22 = a.b22;
+    if (j == jj) {
+      b11 = Cx<T>{u0.sp, T(0)};
+      b22 = Cx<T>{u0.sq, T(0)};
+      b12 = b21 = zero;
+    } else {
+      Rot<T> r = with_v<T, CPLX>(u0, sv0[jj - aw]);
+      rotate_block<T, CPLX>(r, r, b11, b21, b12, b22);
+    }
+    ColPair<T> curP, curQ;
+    exchange_rows<T, CPLX>(j == 0, kflip1, lo1, hi1, labelled<T>(rflip, Pc > Qc, b11, b21, b12, b22), curP, curQ);
+    const int l = jj - 1;
+    if (l >= l1lo && l <= l1hi && (l == 0 || l - 1 >= aw)) level1(l, curP, selp(l == 0, p1Q, p2m));
+    if (jj == n - 1 && n - 1 >= l1lo && n - 1 <= l1hi && n - 2 >= aw)
+      level1(n - 1, curQ, selp(n - 1 == 1, p1P, p1Q));
+    p2m = selp(jj - 1 == 0, p1P, p1Q);
+    p1P = curP;
+    p1Q = curQ;
+  }
 }
 
 

@@ -77,7 +77,7 @@ EXPORTS = ["dsvd2_batch", "zsvd2_batch", "ssvd2_batch", "csvd2_batch", "svd2_wor
            "kog_workspace_bytes", "dkog_step", "zkog_step", "skog_step", "ckog_step", "dkog_sweep",
            "zkog_sweep", "skog_sweep", "ckog_sweep", "dkog_solve", "zkog_solve", "skog_solve",
            "ckog_solve", "dkog_norms", "zkog_norms", "skog_norms", "ckog_norms", "kog_last_hip_error",
-           "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_batch_workspace_bytes",
+           "kog_set_fused_blocks_per_cu", "kog_set_tile_rules", "kog_set_three_step_tiles", "kog_batch_workspace_bytes",
            "kog_batch_solve", "kog_workspace_bytes_flags", "kog_set_two_step_tiles",
            "kog_batch_workspace_bytes_flags", "kog_sigma_workspace_bytes", "dkog_sigma", "zkog_sigma",
            "skog_sigma", "ckog_sigma", "kog_svd_workspace_bytes", "dkog_svd", "zkog_svd", "skog_svd",
@@ -358,6 +358,7 @@ def svd2(trains, flags: int = 0, out=None, ws=None, nrescued=None, stream=None, 
 SVD2_KOG_UNFUSED = 1
 SVD2_KOG_GRAPH = 2
 SVD2_KOG_TWO_STEP = 4
+SVD2_KOG_THREE_STEP = 8
 KOG_DTYPE = {"d": 0, "z": 1, "s": 2, "c": 3}
 _kog_ready = False
 
@@ -438,7 +439,7 @@ def kog_workspace(A, flags: int = 0):
 def kog_step(A, t: int, ws=None, flags: int = 0, stream=None) -> None:
     k = kog_kind(A)
     N, lda, ptr = _kog_args(A)
-    ws = kog_workspace(A) if ws is None else ws
+    ws = kog_workspace(A, flags) if ws is None else ws
     _kog_check(f"{k}kog_step", getattr(_kog(), f"{k}kog_step")(N, ptr, lda, t, ws.data_ptr(),
                                                               _nbytes(ws), flags, _stream(stream)))
 
@@ -582,6 +583,8 @@ def _batch():
         L.kog_set_tile_rules.restype = ctypes.c_int
         L.kog_set_two_step_tiles.argtypes = L.kog_set_tile_rules.argtypes
         L.kog_set_two_step_tiles.restype = ctypes.c_int
+        L.kog_set_three_step_tiles.argtypes = L.kog_set_tile_rules.argtypes
+        L.kog_set_three_step_tiles.restype = ctypes.c_int
         _batch_ready = True
     return L
 
@@ -599,6 +602,14 @@ def kog_set_two_step_tiles(rules) -> None:
     n = len(rules)
     arr = lambda i: (ctypes.c_int * max(n, 1))(*[r[i] for r in rules])
     _kog_check("kog_set_two_step_tiles", _batch().kog_set_two_step_tiles(n, arr(0), arr(1), arr(2)))
+
+
+def kog_set_three_step_tiles(rules) -> None:
+    """rules: list of (max_order, wavefronts per workgroup, lc) with increasing
+    max_order, for the three-step kernel; [] = default."""
+    n = len(rules)
+    arr = lambda i: (ctypes.c_int * max(n, 1))(*[r[i] for r in rules])
+    _kog_check("kog_set_three_step_tiles", _batch().kog_set_three_step_tiles(n, arr(0), arr(1), arr(2)))
 
 
 def kog_batch_solve(mats, tols, max_sweeps=40, flags: int = 0, ws=None, stream=None) -> list:

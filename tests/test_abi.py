@@ -220,7 +220,7 @@ def test_kog_argument_errors():
     assert call(64, A + 4, 64, 0, ws, wsb, 0) == 2      # misaligned matrix
     assert call(64, A, 64, 0, ws + 8, wsb, 0) == 2      # misaligned workspace
     assert call(64, A, 64, 0, A + 256, wsb, 0) == 3     # workspace overlaps A
-    assert call(64, A, 64, 0, ws, wsb, 8) == 4          # unknown flag
+    assert call(64, A, 64, 0, ws, wsb, 16) == 4         # unknown flag
     assert call(64, A, 64, 0, ws, wsb, 2) == 4          # GRAPH without UNFUSED
     assert call(64, A, 64, 0, ws, wsb, 3) == 4          # GRAPH is solve-only
     assert L.dkog_sweep(64, A, 64, ws, wsb, 3, None) == 4
@@ -235,6 +235,18 @@ def test_kog_argument_errors():
     assert call(64, A, 64, 62, ws, ws2, 4) == 6         # two steps from t = N-2 run past the sweep
     assert call(64, A, 64, -1, ws, ws2, 4) == 6
     assert call(64, A, 64, 63, ws, wsb, 0) == 6         # step out of range
+    # three steps per pass: alone, a third rotation set beyond the two-step workspace
+    ws3 = S.kog_workspace_bytes(64, "d", S.SVD2_KOG_THREE_STEP)
+    assert ws3 > ws2
+    assert S.kog_workspace_bytes(64, "c", S.SVD2_KOG_THREE_STEP) > S.kog_workspace_bytes(64, "c", 4)
+    assert call(64, A, 64, 0, ws, ws3, 8 | 4) == 4      # THREE_STEP with TWO_STEP
+    assert call(64, A, 64, 0, ws, ws3, 8 | 1) == 4      # THREE_STEP with UNFUSED
+    assert L.dkog_sweep(64, A, 64, ws, ws3, 8 | 3, None) == 4
+    assert call(64, A, 64, 0, ws, ws2, 8) == 6          # too small for the third rotation set
+    assert L.dkog_sweep(64, A, 64, ws, ws3 - 8, 8, None) == 6
+    assert call(64, A, 64, 61, ws, ws3, 8) == 6         # three steps from t = N-3 run past the sweep
+    assert call(64, A, 64, -1, ws, ws3, 8) == 6
+    assert L.dkog_sweep(64, A, 64, A + 512, ws3, 8, None) == 3  # overlap
     sw, off = ctypes.c_int(), ctypes.c_double()
     assert L.dkog_solve(64, A, 64, 1e-14, -1, ctypes.byref(sw), ctypes.byref(off), ws, wsb, 0,
                         None) == 6                      # negative max_sweeps
@@ -347,6 +359,24 @@ def test_kog_two_step_tile_rules():
                                     (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
     assert L.kog_set_two_step_tiles(1, None, None, None) == 1
     assert L.kog_set_two_step_tiles(0, None, None, None) == 0      # back to the default
+
+
+def test_kog_three_step_tile_rules():
+    """Shape table of the three-step kernel: wavefronts per workgroup in {1,
+    2, 4}; lc in [2, 128]; the SVD, sigma and batch entry points refuse the
+    three-step flag."""
+    import ctypes
+    L = S.lib()
+    one = lambda x: (ctypes.c_int * 1)(x)
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(3), one(8)) == 6
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(4), one(1)) == 6
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(4), one(129)) == 6
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(1), one(2)) == 0
+    assert L.kog_set_three_step_tiles(2, (ctypes.c_int * 2)(64, 32), (ctypes.c_int * 2)(4, 4),
+                                      (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
+    assert L.kog_set_three_step_tiles(1, None, None, None) == 1
+    assert L.kog_set_three_step_tiles(0, None, None, None) == 0      # back to the default
+    assert S.kog_svd_workspace_bytes(64, "d", S.SVD2_KOG_THREE_STEP) == 0
 
 
 def test_kog_sigma_argument_errors():
