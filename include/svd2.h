@@ -532,9 +532,11 @@ svd2_status kog_set_two_step_tiles(int count, const int *max_order, const int *w
 /* Workgroup shapes of the three-step kernel (SVD2_KOG_THREE_STEP), by order:
  * the first rule with N <= max_order[i] applies.  wpg[i] in {1, 2, 4}
  * wavefronts per workgroup, each on its own block of 60 row pairs; lc[i] in
- * [2, 128] output column pairs per workgroup, shared by its wavefronts.
- * count = 0 restores the default (1, 24).  Host arrays, copied; safe to call
- * while other threads launch; affects later calls. */
+ * [2, 128] output column pairs per workgroup, shared by its wavefronts, or
+ * lc[i] in [-3, 0]: as many as make the grid fill 1 - lc[i] whole rounds of
+ * the workgroups the GPU holds at once.  count = 0 restores the default
+ * (1, 0).  Host arrays, copied; safe to call while other threads launch;
+ * affects later calls. */
 svd2_status kog_set_three_step_tiles(int count, const int *max_order, const int *wpg, const int *lc);
 
 #ifdef __cplusplus

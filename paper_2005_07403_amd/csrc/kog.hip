@@ -61,7 +61,7 @@ TileRule rule2_for(int N) {
 
 // three-step kernel shapes: kc = wavefronts (row blocks) per workgroup, lc =
 // output column pairs per tile
-TileRule default_rule3() { return TileRule{0x7fffffff, 1, 24}; }
+TileRule default_rule3() { return TileRule{0x7fffffff, 1, 0}; }
 TileRule g_rules3[kMaxRules] = {default_rule3()};
 int g_nrules3 = 1;
 TileRule rule3_for(int N) {
@@ -134,8 +134,9 @@ __global__ __launch_bounds__(256) void kog_two_step_kernel(int N, Mat<T, CPLX> M
 template <class T, bool CPLX>
 __global__ __launch_bounds__(256) void kog_pivots3_kernel(int N, Mat<T, CPLX> M, int t, Bufs<T, CPLX> B0,
                                                           Bufs<T, CPLX> B1, Bufs<T, CPLX> B2) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < N / 2) pivots3_one<T, CPLX>(N, M, t, B0, B1, B2, k);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = g >> 2;
+  pivots3_quad<T, CPLX>(N, M, t, B0, B1, B2, k, g & 3, k < N / 2);
 }
 
 template <class T, bool CPLX>
@@ -635,16 +636,52 @@ struct ThreeStepShape {
   int wpg, lc, gx, ntiles;
   size_t lds;
 };
+// the launch shape of the three-step kernel for order N: wpg row blocks per
+// workgroup; lc output column pairs per tile as the rule fixes it, or (rule
+// lc in [-3, 0]) sized so that the grid fills 1 - lc whole rounds of the
+// workgroups the GPU holds at once (a partial last round costs a whole one)
 template <class T, bool CPLX> ThreeStepShape three_step_shape(int N) {
+  // per host thread: concurrent solves on other threads do not share it
+  thread_local int cached_N = 0, cached_wpg = 0, cached_lc = 0;
+  thread_local ThreeStepShape cached{};
   const TileRule r = rule3_for(N);
+  if (N == cached_N && r.kc == cached_wpg && r.lc == cached_lc) return cached;
   const int n = N / 2;
-  ThreeStepShape sh;
+  ThreeStepShape sh{};
   sh.wpg = r.kc;
-  sh.lc = r.lc < n ? r.lc : n;
   const int nb = (n + kShift3Out - 1) / kShift3Out;
   sh.gx = (nb + sh.wpg - 1) / sh.wpg;
-  sh.ntiles = sh.gx * ((n + sh.lc - 1) / sh.lc);
-  sh.lds = three_step_lds<T, CPLX>(sh.lc);
+  auto fix = [&](int lc) {
+    const int hi = n < 128 ? n : 128;
+    lc = lc > hi ? hi : lc;
+    lc = lc < 2 ? 2 : lc;
+    sh.lc = lc;
+    sh.ntiles = sh.gx * ((n + lc - 1) / lc);
+    sh.lds = three_step_lds<T, CPLX>(lc);
+  };
+  if (r.lc > 0) {
+    fix(r.lc);
+  } else {
+    const int rounds = 1 - r.lc;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return ThreeStepShape{};
+    fix(128);  // the widest tile first, then refine with the occupancy it allows
+    for (int it = 0; it < 3; ++it) {
+      int per = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kog_three_step_kernel<T, CPLX>,
+                                                       64 * sh.wpg, sh.lds) != hipSuccess || per < 1)
+        return ThreeStepShape{};
+      long tc = (long)per * cus * rounds / sh.gx;
+      if (tc < 1) tc = 1;
+      fix((int)((n + tc - 1) / tc));
+    }
+  }
+  cached_N = N;
+  cached_wpg = r.kc;
+  cached_lc = r.lc;
+  cached = sh;
   return sh;
 }
 
@@ -656,11 +693,12 @@ svd2_status three_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Ma
   hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
-  hipLaunchKernelGGL((kog_pivots3_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1,
+  hipLaunchKernelGGL((kog_pivots3_kernel<T, CPLX>), dim3((4 * n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1,
                      B2);
   s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   const ThreeStepShape sh = three_step_shape<T, CPLX>(c.N);
+  if (sh.ntiles <= 0) return SVD2_ERR_HIP;
   hipLaunchKernelGGL((kog_three_step_kernel<T, CPLX>), dim3(sh.ntiles), dim3(64 * sh.wpg), sh.lds, c.st, c.N, cur,
                      nxt, t, B0, B1, B2, sh.wpg, sh.lc, sh.gx, sh.ntiles);
   return hip_st(hipGetLastError());
@@ -1260,7 +1298,7 @@ svd2_status kog_set_three_step_tiles(int count, const int *max_order, const int 
   if (count > 0 && (!max_order || !wpg || !lc)) return SVD2_ERR_NULL;
   for (int i = 0; i < count; ++i) {
     if (wpg[i] != 1 && wpg[i] != 2 && wpg[i] != 4) return SVD2_ERR_SIZE;
-    if (lc[i] < 2 || lc[i] > 128 || max_order[i] < 2) return SVD2_ERR_SIZE;
+    if (lc[i] < -3 || lc[i] == 1 || lc[i] > 128 || max_order[i] < 2) return SVD2_ERR_SIZE;
     if (i > 0 && max_order[i] <= max_order[i - 1]) return SVD2_ERR_SIZE;
   }
   std::lock_guard<std::mutex> lock(g_rules_mu);

@@ -456,59 +456,65 @@ __device__ __forceinline__ void pivots2_one(int N, const Mat<T, CPLX> &M, int t,
 
 
 // pivots of step t+2, after the pivots of steps t (B0) and t+1 (B1) are
-// known: lane k forms pair k's pivot block of step t+2 from the matrix before
-// step t.  Its rows and columns {p, q} belong to two pairs of step t+1, whose
-// four indices x belong to four pairs of step t; each entry after step t+1 is
-// one rotated entry of a step-(t+1) block of entries after step t, each of
-// those one rotated entry of a step-t block of the matrix (64 loads), with
-// the rotations as stored in B0 and B1, so with exactly the operations of two
-// single steps.  Then its SVD goes into B2.
+// known, on four lanes per pair: lane sub = 2 a + b of pair k forms entry
+// (a, b) of the pair's step-(t+2) pivot block (rows and columns p < q) from
+// the matrix before step t.  Its row belongs to a pair of step t+1 and its
+// column to another, each of whose two indices belongs to a pair of step t:
+// the entry after step t+1 is one rotated entry of a step-(t+1) block of
+// entries after step t, each of those one rotated entry of a step-t block of
+// the matrix (16 loads per lane), with the rotations as stored in B0 and B1,
+// so with exactly the operations of two single steps.  Lane 0 of the four
+// gathers the block and puts its SVD into B2.  All four lanes call it.
 template <class T, bool CPLX>
-__device__ __forceinline__ void pivots3_one(int N, const Mat<T, CPLX> &M, int t, const Bufs<T, CPLX> &B0,
-                                            const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2, int k) {
+__device__ __forceinline__ void pivots3_quad(int N, const Mat<T, CPLX> &M, int t, const Bufs<T, CPLX> &B0,
+                                             const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2, int k, int sub,
+                                             bool valid) {
   constexpr int RESC = sizeof(T) == 4 ? 1 : 0;
   constexpr int NI = Bufs<T, CPLX>::NIN, NO = Bufs<T, CPLX>::NOUT;
   const int n = N / 2, Mo = N - 1;
-  int a, b;
-  pair_ab(t + 2, k, Mo, a, b);
-  // X1: p, its step-(t+1) partner, q, its step-(t+1) partner
-  const Side S1[2] = {side_at(t + 1, a < b ? a : b, Mo, n), side_at(t + 1, a < b ? b : a, Mo, n)};
-  const int X1[4] = {S1[0].x, S1[0].partner, S1[1].x, S1[1].partner};
-  Side S0[4];
-  RotU<T> U0[4];
-  RotV<T> V0[4];
+  const int ia = sub >> 1, ib = sub & 1;
+  Cx<T> ent{T(0), T(0)};
+  if (valid) {
+    int a, b;
+    pair_ab(t + 2, k, Mo, a, b);
+    const int xr = ia == 0 ? (a < b ? a : b) : (a < b ? b : a);
+    const int xc = ib == 0 ? (a < b ? a : b) : (a < b ? b : a);
+    const Side R1 = side_at(t + 1, xr, Mo, n), C1 = side_at(t + 1, xc, Mo, n);
+    const int rr[2] = {R1.x, R1.partner}, cc[2] = {C1.x, C1.partner};
+    Side R0[2], C0[2];
+    RotU<T> U0[2];
+    RotV<T> V0[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      R0[i] = side_at(t, rr[i], Mo, n);
+      C0[i] = side_at(t, cc[i], Mo, n);
+      const Rot<T> ru = load_rot<T, CPLX>(B0, R0[i].k), rv = load_rot<T, CPLX>(B0, C0[i].k);
+      U0[i] = RotU<T>{ru.u11, ru.u21, ru.u12, ru.u22, ru.sp, ru.sq};
+      V0[i] = RotV<T>{rv.v11, rv.v21, rv.v12, rv.v22};
+    }
+    const Rot<T> r1 = load_rot<T, CPLX>(B1, R1.k), c1 = load_rot<T, CPLX>(B1, C1.k);
+    const RotU<T> U1{r1.u11, r1.u21, r1.u12, r1.u22, r1.sp, r1.sq};
+    const RotV<T> V1{c1.v11, c1.v21, c1.v12, c1.v22};
+    Cx<T> A1[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        A1[i][j] = after_step<T, CPLX>(R0[i], U0[i], C0[j], V0[j], M.ld(rr[i], cc[j]), M.ld(rr[i], C0[j].partner),
+                                       M.ld(R0[i].partner, cc[j]), M.ld(R0[i].partner, C0[j].partner));
+    ent = after_step<T, CPLX>(R1, U1, C1, V1, A1[0][0], A1[0][1], A1[1][0], A1[1][1]);
+  }
+  // gather the block on lane 0 of the four: record order 11, 21, 12, 22 = sub 0, 2, 1, 3
+  const int base = (int)(threadIdx.x & 63) & ~3;
+  Cx<T> rec[4];
+  const int src[4] = {0, 2, 1, 3};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    S0[i] = side_at(t, X1[i], Mo, n);
-    const Rot<T> r = load_rot<T, CPLX>(B0, S0[i].k);
-    U0[i] = RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
-    V0[i] = RotV<T>{r.v11, r.v21, r.v12, r.v22};
+    rec[i].re = __shfl(ent.re, base + src[i], 64);
+    if constexpr (CPLX) rec[i].im = __shfl(ent.im, base + src[i], 64);
+    else rec[i].im = T(0);
   }
-  RotU<T> U1[2];
-  RotV<T> V1[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const Rot<T> r = load_rot<T, CPLX>(B1, S1[i].k);
-    U1[i] = RotU<T>{r.u11, r.u21, r.u12, r.u22, r.sp, r.sq};
-    V1[i] = RotV<T>{r.v11, r.v21, r.v12, r.v22};
-  }
-  // entries after step t on X1 x X1
-  Cx<T> A1[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      A1[i][j] = after_step<T, CPLX>(S0[i], U0[i], S0[j], V0[j], M.ld(X1[i], X1[j]), M.ld(X1[i], S0[j].partner),
-                                     M.ld(S0[i].partner, X1[j]), M.ld(S0[i].partner, S0[j].partner));
-  // entries after step t+1 on {p, q} x {p, q}: row 2i of X1 with its partner 2i+1
-  Cx<T> e[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      e[i][j] = after_step<T, CPLX>(S1[i], U1[i], S1[j], V1[j], A1[2 * i][2 * j], A1[2 * i][2 * j + 1],
-                                    A1[2 * i + 1][2 * j], A1[2 * i + 1][2 * j + 1]);
-  const Cx<T> rec[4] = {e[0][0], e[1][0], e[0][1], e[1][1]};
+  if (!valid || sub != 0) return;
   T x[NI], y[NO];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {

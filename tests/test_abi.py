@@ -363,8 +363,8 @@ def test_kog_two_step_tile_rules():
 
 def test_kog_three_step_tile_rules():
     """Shape table of the three-step kernel: wavefronts per workgroup in {1,
-    2, 4}; lc in [2, 128]; the SVD, sigma and batch entry points refuse the
-    three-step flag."""
+    2, 4}; lc in [2, 128] (fixed) or [-3, 0] (fill whole rounds); the SVD
+    entry points refuse the three-step flag."""
     import ctypes
     L = S.lib()
     one = lambda x: (ctypes.c_int * 1)(x)
@@ -372,6 +372,8 @@ def test_kog_three_step_tile_rules():
     assert L.kog_set_three_step_tiles(1, one(1 << 20), one(4), one(1)) == 6
     assert L.kog_set_three_step_tiles(1, one(1 << 20), one(4), one(129)) == 6
     assert L.kog_set_three_step_tiles(1, one(1 << 20), one(1), one(2)) == 0
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(1), one(-4)) == 6
+    assert L.kog_set_three_step_tiles(1, one(1 << 20), one(2), one(-1)) == 0
     assert L.kog_set_three_step_tiles(2, (ctypes.c_int * 2)(64, 32), (ctypes.c_int * 2)(4, 4),
                                       (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
     assert L.kog_set_three_step_tiles(1, None, None, None) == 1
