@@ -604,17 +604,33 @@ __device__ __forceinline__ void rows_at(int t, int j, int Mo, int &P, int &Q) {
   }
 }
 
+// lane l takes the value of lane l+1 (dn) or l-1 (up): the wavefront
+// shifts of the data-parallel primitives (wave_shl:1 / wave_shr:1), a VALU
+// operand modifier instead of a round trip through the LDS crossbar; the end
+// lanes keep their own value (no lane reads it)
+template <int CTRL> __device__ __forceinline__ float wshift(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, x),
+                                                               __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double wshift(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)rhi << 32) | (long long)(unsigned)rlo);
+}
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
 template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_dn1(Cx<T> x) {
   Cx<T> r;
-  r.re = __shfl_down(x.re, 1, 64);
-  if constexpr (CPLX) r.im = __shfl_down(x.im, 1, 64);
+  r.re = wshift<kWaveShl1>(x.re);
+  if constexpr (CPLX) r.im = wshift<kWaveShl1>(x.im);
   else r.im = T(0);
   return r;
 }
 template <class T, bool CPLX> __device__ __forceinline__ Cx<T> shfl_up1(Cx<T> x) {
   Cx<T> r;
-  r.re = __shfl_up(x.re, 1, 64);
-  if constexpr (CPLX) r.im = __shfl_up(x.im, 1, 64);
+  r.re = wshift<kWaveShr1>(x.re);
+  if constexpr (CPLX) r.im = wshift<kWaveShr1>(x.im);
   else r.im = T(0);
   return r;
 }
