@@ -437,21 +437,23 @@ def barrier_bench():
 
 
 def kog_svd_bench(A, s, G0, mat, steps, passes, full: bool = True):
-    """The full SVD A_0 = U diag(sigma) V^* (transformations accumulated, two
-    steps per pass) on the one-problem workload: one sweep and a full solve,
-    sigma against the known singular values, and the residuals
+    """The full SVD A_0 = U diag(sigma) V^* (transformations accumulated,
+    three steps per pass) on the one-problem workload: one sweep and a full
+    solve, sigma against the known singular values, and the residuals
     ||A_0 - U S V^T||_F / ||A_0||_F and ||U^T U - I||_F computed on the GPU."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     N = A.shape[0]
-    fl = S.SVD2_KOG_TWO_STEP
+    fl = S.SVD2_KOG_THREE_STEP
     ws = torch.empty(S.kog_svd_workspace_bytes(N, "d", fl), dtype=torch.uint8, device="cuda")
-    # per sweep: the iterate read and written once per pass of two steps (and
-    # for the odd last step); U and V once per four steps (pairs of passes),
-    # once for an unpaired last pass and once for the last step
-    single = steps - 2 * passes
-    hbm = 2 * mat * (passes + single) + 2 * 2 * mat * (passes // 2 + passes % 2 + single)
-    res = {"mode": "two_step", "algorithmic_bytes_per_sweep": hbm}
+    # per sweep: the iterate read and written once per pass of three steps
+    # (and once for the two-step pass or single step that ends a sweep when 3
+    # does not divide its steps); U and V once per six steps (pairs of passes),
+    # once for an unpaired last pass and once for that end
+    p3 = steps // 3
+    rest = 1 if steps % 3 else 0
+    hbm = 2 * mat * (p3 + rest) + 2 * 2 * mat * (p3 // 2 + p3 % 2 + rest)
+    res = {"mode": "three_step", "algorithmic_bytes_per_sweep": hbm}
     G = G0.clone(memory_format=torch.preserve_format)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

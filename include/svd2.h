@@ -315,8 +315,8 @@ svd2_status svd2_probe_f32(int op, size_t n, const float *x, const float *y,
  * per three steps; a sweep's N-1 steps end with a two-step pass or a single
  * step where three do not divide them.  Workspace of
  * kog_workspace_bytes_flags(N, dtype, SVD2_KOG_THREE_STEP).  Bitwise the
- * result of single steps, returned in A.  Not accepted by the SVD, sigma and
- * batch entry points.
+ * result of single steps, returned in A.  Also accepted by the SVD entry
+ * points (U and V six steps per walk); not by the batch entry point.
  * ------------------------------------------------------------------------- */
 enum { SVD2_KOG_UNFUSED = 1, SVD2_KOG_GRAPH = 2, SVD2_KOG_TWO_STEP = 4, SVD2_KOG_THREE_STEP = 8 };
 enum { SVD2_KOG_F64 = 0, SVD2_KOG_C128 = 1, SVD2_KOG_F32 = 2, SVD2_KOG_C64 = 3 };
@@ -465,14 +465,16 @@ svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *w
  *     interleaved), columns permuted alike, so A_0 ~ U diag(sigma) V^*;
  *   A: the final iterate (unsorted).
  * ws: kog_svd_workspace_bytes(N, dtype, flags) bytes, 256-byte aligned (the
- * solve's workspace plus two N x N matrices, the sort keys and, two steps per
- * pass, two more rotation sets).  A, U, V,
+ * solve's workspace plus two N x N matrices, the sort keys and, two or three
+ * steps per pass, two or three more rotation sets).  A, U, V,
  * sigma and ws must be pairwise disjoint (SVD2_ERR_ALIAS).  flags: 0 or
  * SVD2_KOG_TWO_STEP (two steps per pass over A; U and V are taken four steps
  * further per pass after every second pass, alternating with workspace
- * copies), SVD2_KOG_UNFUSED (one step per pass, U and V
- * rotated in place) or SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH; anything else is
- * SVD2_ERR_FLAGS.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
+ * copies), SVD2_KOG_THREE_STEP (three steps per pass over A; U and V six
+ * steps further after every second pass), SVD2_KOG_UNFUSED (one step per
+ * pass, U and V rotated in place) or SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH;
+ * anything else is SVD2_ERR_FLAGS.  Every mode gives bitwise the same
+ * results.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
  * SVD2_NOT_CONVERGED (outputs as above for the last iterate); synchronises
  * `stream` like *_solve.
  * kog_svd_workspace_bytes returns 0 for an order, element type or flags

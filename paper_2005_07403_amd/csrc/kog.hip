@@ -419,6 +419,7 @@ template <class T, bool CPLX> struct Ctx {
   Mat<T, CPLX> U{}, V{}, U2{}, V2{};
   Bufs<T, CPLX> B2{}, B3{};  // two steps per pass: the rotations of every second pass
   Bufs<T, CPLX> Bt{};        // three steps per pass: the rotations of the third step
+  Bufs<T, CPLX> B4{};        // SVD entry points, three steps per pass: with B2, B3 the odd passes' rotations
 };
 
 template <class T, bool CPLX>
@@ -749,22 +750,43 @@ template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, 
   return s;
 }
 
-// a sweep of the three-step mode (iterate only): passes of three steps, then
-// what is left of the N-1 steps as one two-step pass or one single step; *in_w
-// as in sweep_two_step
-template <class T, bool CPLX> svd2_status sweep_three_step(const Ctx<T, CPLX> &c, bool *in_w) {
+// a sweep of the three-step mode: passes of three steps, then what is left
+// of the N-1 steps as one two-step pass or one single step; *in_w and *uv_in
+// as in sweep_two_step.  With accumulation the passes alternate between the
+// rotation sets (B, B1, Bt) and (B2, B3, B4), after every second pass one
+// kernel takes U and V six steps further, an unpaired last pass gets a
+// three-step accumulation, the two-step rest a two-step one and a last single
+// step an in-place one.
+template <class T, bool CPLX> svd2_status sweep_three_step(const Ctx<T, CPLX> &c, bool *in_w, bool *uv_in) {
   svd2_status s = SVD2_OK;
   int t = 0;
-  for (; c.N - 1 - t >= 3 && s == SVD2_OK; t += 3) {
-    s = three_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, c.B, c.B1, c.Bt);
+  for (int p = 0; c.N - 1 - t >= 3 && s == SVD2_OK; t += 3, ++p) {
+    const bool odd = c.acc && (p & 1);
+    s = three_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, odd ? c.B2 : c.B, odd ? c.B3 : c.B1,
+                             odd ? c.B4 : c.Bt);
     *in_w = !*in_w;
+    if (s != SVD2_OK || !c.acc) continue;
+    if (odd) {
+      const Bufs<T, CPLX> sets[6] = {c.B, c.B1, c.Bt, c.B2, c.B3, c.B4};
+      s = accum_s<T, CPLX, 6>(c, *uv_in, t - 3, sets);
+      *uv_in = !*uv_in;
+    } else if (c.N - 1 - (t + 3) < 3) {
+      const Bufs<T, CPLX> sets[3] = {c.B, c.B1, c.Bt};
+      s = accum_s<T, CPLX, 3>(c, *uv_in, t, sets);
+      *uv_in = !*uv_in;
+    }
   }
   if (s == SVD2_OK && c.N - 1 - t == 2) {
     s = two_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, c.B, c.B1);
     *in_w = !*in_w;
+    if (s == SVD2_OK && c.acc) {
+      const Bufs<T, CPLX> sets[2] = {c.B, c.B1};
+      s = accum_s<T, CPLX, 2>(c, *uv_in, t, sets);
+      *uv_in = !*uv_in;
+    }
     t += 2;
   }
-  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t);
+  if (s == SVD2_OK && t < c.N - 1) s = one_step_on<T, CPLX>(c, *in_w ? c.W : c.M, t, *uv_in);
   return s;
 }
 
@@ -776,8 +798,8 @@ template <class T, bool CPLX> svd2_status copy_back(const Ctx<T, CPLX> &c) {
 
 template <class T, bool CPLX> svd2_status sweep(const Ctx<T, CPLX> &c) {
   if (c.flags & SVD2_KOG_THREE_STEP) {
-    bool in_w = false;
-    svd2_status s = sweep_three_step<T, CPLX>(c, &in_w);
+    bool in_w = false, uv_in = false;
+    svd2_status s = sweep_three_step<T, CPLX>(c, &in_w, &uv_in);
     if (s == SVD2_OK && in_w) s = copy_back<T, CPLX>(c);
     return s;
   }
@@ -898,7 +920,7 @@ svd2_status solve(Ctx<T, CPLX> &c, double tol, int max_sweeps, int *sweeps, doub
     }
     if (sw == max_sweeps) break;
     if (exec) s = hip_st(hipGraphLaunch(exec, c.st));
-    else if (three) s = sweep_three_step<T, CPLX>(c, &in_w);
+    else if (three) s = sweep_three_step<T, CPLX>(c, &in_w, &uv_in);
     else if (two) s = sweep_two_step<T, CPLX>(c, &in_w, &uv_in);
     else s = sweep<T, CPLX>(c);
     if (s == SVD2_OK) s = norms_async<T, CPLX>(c, in_w);
@@ -976,10 +998,11 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
 // buffers (N x N, lda N), the sort keys and indices (next power of two) and,
 // two steps per pass, two more rotation sets
 struct SvdLayout {
-  size_t u2, v2, keys, idx, b2, b3, total;
+  size_t u2, v2, keys, idx, b2, b3, b4, total;
   int P;
 };
-inline SvdLayout svd_layout(int N, size_t esz, bool cplx, bool two) {
+// passes: 1 (one step per pass), 2 or 3 steps per pass
+inline SvdLayout svd_layout(int N, size_t esz, bool cplx, int passes) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const Layout L = layout(N, esz, cplx);
   const size_t mat = up((size_t)N * N * esz * (cplx ? 2 : 1));
@@ -987,14 +1010,18 @@ inline SvdLayout svd_layout(int N, size_t esz, bool cplx, bool two) {
   SvdLayout S;
   S.P = 1;
   while (S.P < N) S.P <<= 1;
-  S.u2 = two ? L.total2 : L.total;
+  S.u2 = passes == 3 ? L.total3 : passes == 2 ? L.total2 : L.total;
   S.v2 = S.u2 + mat;
   S.keys = S.v2 + mat;
   S.idx = S.keys + up((size_t)S.P * esz);
   S.b2 = S.idx + up((size_t)S.P * sizeof(int));
-  S.b3 = S.b2 + (two ? set : 0);
-  S.total = S.b3 + (two ? set : 0);
+  S.b3 = S.b2 + (passes > 1 ? set : 0);
+  S.b4 = S.b3 + (passes > 1 ? set : 0);
+  S.total = S.b4 + (passes == 3 ? set : 0);
   return S;
+}
+inline int svd_passes(unsigned flags) {
+  return (flags & SVD2_KOG_THREE_STEP) ? 3 : (flags & SVD2_KOG_TWO_STEP) ? 2 : 1;
 }
 
 // a rotation set (pivot and SVD arrays, as make_bufs lays them out) at base
@@ -1013,7 +1040,8 @@ template <class T, bool CPLX>
 svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma, double tol, int max_sweeps,
                     int *sweeps, double *off_rel, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
   flags = svd_flags(flags);
-  if (flags != SVD2_KOG_TWO_STEP && flags != SVD2_KOG_UNFUSED && flags != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))
+  if (flags != SVD2_KOG_TWO_STEP && flags != SVD2_KOG_THREE_STEP && flags != SVD2_KOG_UNFUSED &&
+      flags != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))
     return SVD2_ERR_FLAGS;
   Ctx<T, CPLX> c;
   svd2_status s = validate<T, CPLX>(N, A, lda, ws, wsb, flags, c);
@@ -1022,7 +1050,7 @@ svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma
   if (ldu < N || ldv < N || max_sweeps < 1) return SVD2_ERR_SIZE;
   const size_t esz = sizeof(T) * (CPLX ? 2 : 1);
   if ((uintptr_t)U % esz || (uintptr_t)V % esz || (uintptr_t)sigma % sizeof(T)) return SVD2_ERR_ALIGN;
-  const SvdLayout S = svd_layout(N, sizeof(T), CPLX, (flags & SVD2_KOG_TWO_STEP) != 0);
+  const SvdLayout S = svd_layout(N, sizeof(T), CPLX, svd_passes(flags));
   if (wsb < S.total) return SVD2_ERR_SIZE;
   const uintptr_t r[5][2] = {{(uintptr_t)A, (uintptr_t)A + ((size_t)lda * (N - 1) + N) * esz},
                              {(uintptr_t)U, (uintptr_t)U + ((size_t)ldu * (N - 1) + N) * esz},
@@ -1040,6 +1068,7 @@ svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma
   c.V2 = Mat<T, CPLX>{(T *)(c.ws + S.v2), (size_t)N};
   c.B2 = bufs_at<T, CPLX>(c.ws + S.b2, N);
   c.B3 = bufs_at<T, CPLX>(c.ws + S.b3, N);
+  c.B4 = bufs_at<T, CPLX>(c.ws + S.b4, N);
   const int grid = N < 4096 ? N : 4096;
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.U);
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.V);
@@ -1136,13 +1165,15 @@ size_t kog_workspace_bytes(int N, int dtype) { return kog_workspace_bytes_flags(
 size_t kog_svd_workspace_bytes(int N, int dtype, unsigned flags) {
   if (N < 2 || N % 2 || N > (1 << 19)) return 0;
   const unsigned f = svd_flags(flags);
-  if (f != SVD2_KOG_TWO_STEP && f != SVD2_KOG_UNFUSED && f != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH)) return 0;
-  const bool two = (f & SVD2_KOG_TWO_STEP) != 0;
+  if (f != SVD2_KOG_TWO_STEP && f != SVD2_KOG_THREE_STEP && f != SVD2_KOG_UNFUSED &&
+      f != (SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH))
+    return 0;
+  const int passes = svd_passes(f);
   switch (dtype) {
-    case SVD2_KOG_F64: return svd_layout(N, 8, false, two).total;
-    case SVD2_KOG_C128: return svd_layout(N, 8, true, two).total;
-    case SVD2_KOG_F32: return svd_layout(N, 4, false, two).total;
-    case SVD2_KOG_C64: return svd_layout(N, 4, true, two).total;
+    case SVD2_KOG_F64: return svd_layout(N, 8, false, passes).total;
+    case SVD2_KOG_C128: return svd_layout(N, 8, true, passes).total;
+    case SVD2_KOG_F32: return svd_layout(N, 4, false, passes).total;
+    case SVD2_KOG_C64: return svd_layout(N, 4, true, passes).total;
   }
   return 0;
 }

@@ -1126,8 +1126,9 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // one chunk ahead (the loads cannot move past the previous chunk's stores
 // otherwise).  Segment and chunk lengths as measured best at N = 4096 with
 // four levels: 64 and 2 for real, 32 and 2 for complex data (the complex
-// kernel holds twice the registers per value).
-constexpr int kAccMaxS = 4;
+// kernel holds twice the registers per value).  S = 2 and 4 serve two steps
+// per pass (a pair of passes), S = 3 and 6 three steps per pass.
+constexpr int kAccMaxS = 6;
 template <bool CPLX> struct AccShape {
   static constexpr int seg = CPLX ? 32 : 64, chunk = 2;
 };

@@ -313,7 +313,10 @@ def test_kog_svd_argument_errors():
     assert call(u=ws + wsb - 64) == 3                    # U overlaps the workspace
     assert call(f=S.SVD2_KOG_GRAPH) == 4                 # GRAPH without UNFUSED
     assert call(f=S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_UNFUSED) == 4
-    assert call(f=8) == 4
+    assert call(f=16) == 4                               # unknown flag
+    assert call(f=8) == 6                                # three steps per pass: a larger workspace
+    assert call(f=8, b=S.kog_svd_workspace_bytes(N, "z", 8), u=0) == 1  # accepted: on to the pointer checks
+    assert call(f=8 | 4) == 4
 
 
 def test_kog_batch_argument_errors():
@@ -364,7 +367,7 @@ def test_kog_two_step_tile_rules():
 def test_kog_three_step_tile_rules():
     """Shape table of the three-step kernel: wavefronts per workgroup in {1,
     2, 4}; lc in [2, 128] (fixed) or [-3, 0] (fill whole rounds); the SVD
-    entry points refuse the three-step flag."""
+    workspace query takes the three-step flag alone."""
     import ctypes
     L = S.lib()
     one = lambda x: (ctypes.c_int * 1)(x)
@@ -378,7 +381,8 @@ def test_kog_three_step_tile_rules():
                                       (ctypes.c_int * 2)(8, 8)) == 6   # max_order must increase
     assert L.kog_set_three_step_tiles(1, None, None, None) == 1
     assert L.kog_set_three_step_tiles(0, None, None, None) == 0      # back to the default
-    assert S.kog_svd_workspace_bytes(64, "d", S.SVD2_KOG_THREE_STEP) == 0
+    assert S.kog_svd_workspace_bytes(64, "d", S.SVD2_KOG_THREE_STEP) > S.kog_svd_workspace_bytes(64, "d", 4)
+    assert S.kog_svd_workspace_bytes(64, "d", S.SVD2_KOG_THREE_STEP | S.SVD2_KOG_TWO_STEP) == 0
 
 
 def test_kog_sigma_argument_errors():
