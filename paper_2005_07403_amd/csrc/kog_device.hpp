@@ -1113,154 +1113,189 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // x_j = (tau + j) mod (N-1) and y_j = (tau - j) mod (N-1) (x_0 = tau,
 // y_0 = N-1); pair k of step tau+1 is made of the rotated columns f_k and g_k
 // of step tau, where f_k = x_{k+1} (k < n-1) or y_{n-1} (k = n-1), and
-// g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one row.
-// Level L of a cascade receives the pairs of step t+L in increasing order,
-// rotates each, keeps the y columns of the last three in registers and hands pair k of step
-// t+L+1 to level L+1 as soon as its second input is there (at j = min(k+1,
-// n-1)); the last level rotates and writes.  Level L only takes the pairs in
-// its range [lo_L, hi_L]: the last level's is the workgroup's segment of
-// output pairs, and each level's range is what the next one needs.
-// Grid (row blocks of 256 x segments, 2): segments re-walk a few pairs at
-// their edges, so the output is out of place.  The rotations of every level
-// are staged in LDS first, and the level-0 column loads go in chunks issued
-// one chunk ahead (the loads cannot move past the previous chunk's stores
-// otherwise).  Segment and chunk lengths as measured best at N = 4096 with
-// four levels: 64 and 2 for real, 32 and 2 for complex data (the complex
-// kernel holds twice the registers per value).  S = 2 and 4 serve two steps
-// per pass (a pair of passes), S = 3 and 6 three steps per pass.
+// g_k = y_0 (k = 0), x_0 (k = 1) or y_{k-1} (k >= 2).  A lane owns one row
+// and walks iterations j: level L takes pair j - L of step t+L, whose x
+// column (t + j) mod (N-1) is the same at every level, so the x column
+// rotated by level L goes straight on to level L+1 in the same iteration,
+// while the y columns wait in a delay line of three entries per level (pair
+// 0 enters it as y_0 then x_0, so the second input of the next step's pair
+// is always the entry two iterations back).  Pair n of a level past the last
+// one stands for f_{n-1}: it hands on the y column of pair n-1, one
+// iteration late, which is when the next level takes pair n-1.  Iterations
+// where a level's pair is outside its range compute values that never reach
+// a written one (their rotation is zero and their delay-line entries are
+// shifted out before they are read); only the last level writes, its pairs
+// in the workgroup's segment.  Apart from the iterations that meet pair 0 or
+// pair n, no level tests anything but the orientation of its rotation (the
+// same for the whole wavefront, taken by a branch).  Grid (row blocks of 256
+// x segments, 2): segments re-walk a few pairs at their edges, so the output
+// is out of place.  The rotations of every level are staged in LDS first,
+// and the level-0 columns are loaded three iterations ahead.  Segment
+// lengths: 64 pairs for real, 32 for complex data.  S = 2 and 4 serve two
+// steps per pass (a pair of passes), S = 3 and 6 three steps per pass.
 constexpr int kAccMaxS = 6;
 template <bool CPLX> struct AccShape {
-  static constexpr int seg = CPLX ? 32 : 64, chunk = 2;
+  static constexpr int seg = CPLX ? 32 : 64;
 };
 template <class T, bool CPLX> struct AccSets {
   Bufs<T, CPLX> b[kAccMaxS];  // the rotations of steps t, t+1, ...
 };
-// a level's delay line of rotated y columns (see AccWalk::feed)
-template <class T> struct AccWin {
-  Cx<T> y0, y1, y2;
-};
 
-template <class T, bool CPLX, int S> struct AccWalk {
-  int n, Mo, t, i;
+template <class T, bool CPLX, int S> struct AccRun {
+  static constexpr int NIT = AccShape<CPLX>::seg + 2 * S - 2;  // iterations of a segment, at most
+  static constexpr int D = 3;                                   // load distance (iterations)
+  Mat<T, CPLX> X, Y;
+  const W4<T> *ws;  // [level][iteration - jlo]
+  int n, M, t, i, jlo, jend, jst, jld, dm;
   bool live;
-  Mat<T, CPLX> Y;
-  int lo[S], hi[S];
-  const W4<T> *w[S];
-  AccWin<T> win[S > 1 ? S - 1 : 1];
+  int twoL[S];                     // 2L mod M
+  Cx<T> ring[S > 1 ? S - 1 : 1][3];  // the y delay lines, indexed by iteration mod 3
+  Cx<T> inx[D], iny[D];            // level-0 columns of the next D iterations
 
-  template <int L> __device__ __forceinline__ void feed(int j, Cx<T> x, Cx<T> y) {
-    if (j < lo[L] || j > hi[L]) return;
-    int a, b;
-    pair_ab(t + L, j, Mo, a, b);  // a holds x, b holds y
-    // the orientation is uniform over the wavefront: a branch, whose two
-    // sides write rx and ry directly, costs less than selecting the operands
-    // and the results (8 v_cndmask per real rotation)
+  __device__ __forceinline__ void load(int slot, int ca, int cb) {
+    if (live) {
+      inx[slot] = X.ld(i, ca);
+      iny[slot] = X.ld(i, cb);
+    }
+  }
+
+  // level L of iteration j (phase PH = (j - jlo) mod 3), x column a, y column b
+  template <int L, int PH, bool FAST>
+  __device__ __forceinline__ void level(int j, int a, int b0, Cx<T> x, Cx<T> y) {
+    int b = b0 + twoL[L];
+    if (b >= M) b -= M;
     Cx<T> rx, ry;
-    const W4<T> &wl = w[L][j - lo[L]];
-    if (a > b) {
-      Cx<T> c1 = y, c2 = x;
-      rot_cols<T, CPLX>(wl, c1, c2);
-      ry = c1;
-      rx = c2;
+    bool virt = false;
+    if constexpr (!FAST && L < S - 1) virt = j - L == n;
+    if (virt) {
+      if constexpr (L < S - 1) rx = ry = ring[L][(PH + 2) % 3];
     } else {
-      Cx<T> c1 = x, c2 = y;
-      rot_cols<T, CPLX>(wl, c1, c2);
-      rx = c1;
-      ry = c2;
+      const W4<T> &w = ws[L * NIT + (j - jlo)];
+      if (a > b) {
+        Cx<T> c1 = y, c2 = x;
+        rot_cols<T, CPLX>(w, c1, c2);
+        ry = c1;
+        rx = c2;
+      } else {
+        Cx<T> c1 = x, c2 = y;
+        rot_cols<T, CPLX>(w, c1, c2);
+        rx = c1;
+        ry = c2;
+      }
     }
     if constexpr (L == S - 1) {
-      if (live) {
+      if (j >= jst && live) {
+        if constexpr (!FAST) b = j - L == 0 ? M : b;
         Y.st(i, a, rx);
         Y.st(i, b, ry);
       }
     } else {
-      // Pair k of the next step takes f_k = x_{k+1} (the x just rotated, at
-      // j = k+1) and g_k = y_{k-1} for k >= 2, y_0 for k = 0, x_0 for k = 1.
-      // Pair 0 enters the delay line as y_0 then x_0, so g_k is always the
-      // entry two pairs back, and g_{n-1} of the last pair one back.
-      AccWin<T> &W = win[L];
-      W.y2 = W.y1;
-      W.y1 = sel(j == 0, ry, W.y0);
-      W.y0 = sel(j == 0, rx, ry);
-      if (j >= 1) feed<L + 1>(j - 1, rx, W.y2);
-      if (j == n - 1) feed<L + 1>(n - 1, ry, W.y1);
+      bool first = false;
+      if constexpr (!FAST) first = j - L == 0;
+      if (first) {
+        ring[L][PH] = rx;
+        ring[L][(PH + 2) % 3] = ry;
+      } else {
+        ring[L][PH] = ry;
+      }
+      level<L + 1, PH, FAST>(j, a, b0, rx, ring[L][(PH + 1) % 3]);
+    }
+  }
+
+  // iteration j: its level-0 columns from the load slots, then the loads of
+  // iteration j + D; a and b0 are (t + j) mod M and (t - j) mod M
+  template <int PH> __device__ __forceinline__ void iter(int j, int &a, int &b0) {
+    constexpr int SL = PH % D;
+    const Cx<T> x = inx[SL], y = iny[SL];
+    if (j + D <= jld) {
+      int ca = a + dm, cb = b0 - dm;
+      if (ca >= M) ca -= M;
+      if (cb < 0) cb += M;
+      load(SL, ca, cb);
+    }
+    if (j >= S && j < n)
+      level<0, PH, true>(j, a, b0, x, y);
+    else
+      level<0, PH, false>(j, a, b0, x, y);
+    a = a + 1 < M ? a + 1 : 0;
+    b0 = b0 >= 1 ? b0 - 1 : M - 1;
+  }
+
+  __device__ __forceinline__ void walk() {
+    const Cx<T> zero{T(0), T(0)};
+#pragma unroll
+    for (int L = 0; L < S - 1; ++L) ring[L][0] = ring[L][1] = ring[L][2] = zero;
+#pragma unroll
+    for (int L = 0; L < S; ++L) twoL[L] = (2 * L) % M;
+    dm = D % M;
+    int a = t + jlo, b0 = t - jlo;
+    if (a >= M) a -= M;
+    if (b0 < 0) b0 += M;
+    // the loads of the first D iterations (pair 0's y column is N-1)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      inx[d] = iny[d] = zero;
+      const int j = jlo + d;
+      if (j <= jld) {
+        int ca = a + d % M, cb = b0 - d % M;
+        if (ca >= M) ca -= M;
+        if (cb < 0) cb += M;
+        load(d, ca, j == 0 ? M : cb);
+      }
+    }
+    for (int j = jlo; j <= jend; j += 3) {
+      iter<0>(j, a, b0);
+      if (j + 1 > jend) break;
+      iter<1>(j + 1, a, b0);
+      if (j + 2 > jend) break;
+      iter<2>(j + 2, a, b0);
     }
   }
 };
 
-// The register cap of 4 waves per SIMD (128 VGPRs) binds only the complex
-// FP64 walk (133 VGPRs uncapped, 4 spilled when capped), which then holds a
-// third more waves and runs a sweep 4 % faster at N = 4096.
+// The register cap of 4 waves per SIMD (128 VGPRs) keeps the complex FP64
+// walk at the occupancy the grid needs (one round of 4 waves per SIMD).
 template <class T, bool CPLX, int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
                                                           Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
                                                           AccSets<T, CPLX> R) {
   static_assert(S >= 2 && S <= kAccMaxS, "levels");
-  constexpr int SEG = AccShape<CPLX>::seg, C = AccShape<CPLX>::chunk, WMAX = S * SEG + 2 * S * S;
-  __shared__ W4<T> ws[WMAX];
+  constexpr int SEG = AccShape<CPLX>::seg, NIT = AccRun<T, CPLX, S>::NIT;
+  __shared__ W4<T> ws[S * NIT];
   const int n = N / 2;
   const int rb = (N + 255) / 256, nseg = (n + SEG - 1) / SEG;
   const int blk = (int)blockIdx.x % rb, sg = (int)blockIdx.x / rb;
   if (sg >= nseg) return;
   const int tid = (int)threadIdx.x;
   const bool isv = blockIdx.y != 0;
-  const Mat<T, CPLX> X = isv ? V : U;
-  AccWalk<T, CPLX, S> A;
+  AccRun<T, CPLX, S> A;
+  A.X = isv ? V : U;
+  A.Y = isv ? V2 : U2;
   A.n = n;
-  A.Mo = N - 1;
+  A.M = N - 1;
   A.t = t;
   A.i = blk * 256 + tid;
   A.live = A.i < N;
-  A.Y = isv ? V2 : U2;
-  const int k0 = sg * SEG, k1 = k0 + SEG < n ? k0 + SEG : n;
-  A.lo[S - 1] = k0;
-  A.hi[S - 1] = k1 - 1;
-#pragma unroll
-  for (int L = S - 2; L >= 0; --L) {
-    A.lo[L] = A.lo[L + 1] <= 1 ? 0 : A.lo[L + 1] - 1;
-    A.hi[L] = A.hi[L + 1] + 1 < n - 1 ? A.hi[L + 1] + 1 : n - 1;
-  }
-  int base[S + 1];
-  base[0] = 0;
-#pragma unroll
-  for (int L = 0; L < S; ++L) base[L + 1] = base[L] + (A.hi[L] - A.lo[L] + 1);
+  const int k0 = sg * SEG, k1 = k0 + SEG < n ? k0 + SEG : n;  // output pairs [k0, k1)
+  A.jlo = k0 >= S - 1 ? k0 - (S - 1) : 0;
+  A.jend = k1 + S - 2;
+  A.jst = k0 + S - 1;                              // the last level's pairs from k0 on are written
+  A.jld = A.jend < n - 1 ? A.jend : n - 1;         // iterations with level-0 columns to load
+  const int nit = A.jend - A.jlo + 1;
+  const W4<T> wz{{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
 #pragma unroll
   for (int L = 0; L < S; ++L) {
-    for (int q = tid; q < A.hi[L] - A.lo[L] + 1; q += 256)
-      ws[base[L] + q] = w_of(load_rot<T, CPLX>(R.b[L], A.lo[L] + q), isv);
-    A.w[L] = ws + base[L];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int L = 0; L < S - 1; ++L) A.win[L] = AccWin<T>{};
-  const int jlo = A.lo[0], jhi = A.hi[0];
-  auto load = [&](int jb, Cx<T> (&la)[C], Cx<T> (&lb)[C]) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int j = jb + c;
-      if (j <= jhi && A.live) {
-        int a, b;
-        pair_ab(t, j, A.Mo, a, b);
-        la[c] = X.ld(A.i, a);
-        lb[c] = X.ld(A.i, b);
-      }
+    // level L takes the pairs [lo, hi] of step t+L
+    const int lo = k0 >= S - 1 - L ? k0 - (S - 1 - L) : 0;
+    const int hi = k1 - 1 + (S - 1 - L) < n - 1 ? k1 - 1 + (S - 1 - L) : n - 1;
+    for (int q = tid; q < nit; q += 256) {
+      const int p = A.jlo + q - L;
+      ws[L * NIT + q] = (p >= lo && p <= hi) ? w_of(load_rot<T, CPLX>(R.b[L], p), isv) : wz;
     }
-  };
-  auto walk = [&](int jb, const Cx<T> (&la)[C], const Cx<T> (&lb)[C]) {
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (jb + c <= jhi) A.template feed<0>(jb + c, la[c], lb[c]);
-  };
-  Cx<T> pa[C], pb[C], qa[C], qb[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) pa[c] = pb[c] = qa[c] = qb[c] = Cx<T>{T(0), T(0)};
-  load(jlo, pa, pb);
-  for (int jb = jlo; jb <= jhi; jb += 2 * C) {
-    load(jb + C, qa, qb);
-    walk(jb, pa, pb);
-    load(jb + 2 * C, pa, pb);
-    walk(jb + C, qa, qb);
   }
+  A.ws = ws;
+  __syncthreads();
+  A.walk();
 }
 
 template <class T, bool CPLX>
