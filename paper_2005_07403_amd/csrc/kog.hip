@@ -496,7 +496,7 @@ svd2_status accum_step(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &U, const Mat<T
 // that holds U and V (in_w: the workspace pair) into the other one
 template <class T, bool CPLX, int S>
 svd2_status accum_s(const Ctx<T, CPLX> &c, bool in_w, int t, const Bufs<T, CPLX> *sets) {
-  constexpr int SEG = AccShape<CPLX>::seg;
+  constexpr int SEG = AccShape<T, CPLX>::seg;
   const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + SEG - 1) / SEG;
   const Mat<T, CPLX> &U = in_w ? c.U2 : c.U, &V = in_w ? c.V2 : c.V;
   const Mat<T, CPLX> &U2 = in_w ? c.U : c.U2, &V2 = in_w ? c.V : c.V2;

@@ -1131,19 +1131,21 @@ __global__ __launch_bounds__(256) void kog_accum_kernel(int N, Mat<T, CPLX> U, M
 // x segments, 2): segments re-walk a few pairs at their edges, so the output
 // is out of place.  The rotations of every level are staged in LDS first,
 // and the level-0 columns are loaded three iterations ahead.  Segment
-// lengths: 64 pairs for real, 32 for complex data.  S = 2 and 4 serve two
-// steps per pass (a pair of passes), S = 3 and 6 three steps per pass.
+// lengths as measured best at N = 4096: 64 pairs, 32 for complex FP64
+// (whose walk holds the most registers).  S = 2 and 4 serve two steps per
+// pass (a pair of passes), S = 3 and 6 three steps per pass.
 constexpr int kAccMaxS = 6;
-template <bool CPLX> struct AccShape {
-  static constexpr int seg = CPLX ? 32 : 64;
+// segment length (output pairs per workgroup)
+template <class T, bool CPLX> struct AccShape {
+  static constexpr int seg = CPLX && sizeof(T) == 8 ? 32 : 64;
 };
 template <class T, bool CPLX> struct AccSets {
   Bufs<T, CPLX> b[kAccMaxS];  // the rotations of steps t, t+1, ...
 };
 
 template <class T, bool CPLX, int S> struct AccRun {
-  static constexpr int NIT = AccShape<CPLX>::seg + 2 * S - 2;  // iterations of a segment, at most
-  static constexpr int D = 3;                                   // load distance (iterations)
+  static constexpr int NIT = AccShape<T, CPLX>::seg + 2 * S - 2;  // iterations of a segment, at most
+  static constexpr int D = 3;  // load distance (iterations): one delay-line period
   Mat<T, CPLX> X, Y;
   const W4<T> *ws;  // [level][iteration - jlo]
   int n, M, t, i, jlo, jend, jst, jld, dm;
@@ -1159,7 +1161,7 @@ template <class T, bool CPLX, int S> struct AccRun {
     }
   }
 
-  // level L of iteration j (phase PH = (j - jlo) mod 3), x column a, y column b
+  // level L of iteration j (PH = (j - jlo) mod 3), x column a, y column b
   template <int L, int PH, bool FAST>
   __device__ __forceinline__ void level(int j, int a, int b0, Cx<T> x, Cx<T> y) {
     int b = b0 + twoL[L];
@@ -1205,7 +1207,7 @@ template <class T, bool CPLX, int S> struct AccRun {
   // iteration j: its level-0 columns from the load slots, then the loads of
   // iteration j + D; a and b0 are (t + j) mod M and (t - j) mod M
   template <int PH> __device__ __forceinline__ void iter(int j, int &a, int &b0) {
-    constexpr int SL = PH % D;
+    constexpr int SL = PH;
     const Cx<T> x = inx[SL], y = iny[SL];
     if (j + D <= jld) {
       int ca = a + dm, cb = b0 - dm;
@@ -1243,6 +1245,8 @@ template <class T, bool CPLX, int S> struct AccRun {
         load(d, ca, j == 0 ? M : cb);
       }
     }
+    // three iterations per trip: one period of the delay lines and of the
+    // load slots
     for (int j = jlo; j <= jend; j += 3) {
       iter<0>(j, a, b0);
       if (j + 1 > jend) break;
@@ -1253,14 +1257,17 @@ template <class T, bool CPLX, int S> struct AccRun {
   }
 };
 
-// The register cap of 4 waves per SIMD (128 VGPRs) keeps the complex FP64
-// walk at the occupancy the grid needs (one round of 4 waves per SIMD).
+// Waves per SIMD at least: 3 for the six-level complex FP64 walk (capped at
+// the 128 VGPRs of 4 it spills 212 bytes per lane and its SVD sweep at
+// N = 4096 takes 80 % longer than with 168 and 44 bytes spilled), 4 for the
+// others (the four-level complex FP64 walk: 128 VGPRs, 12 bytes spilled).
+template <class T, bool CPLX> constexpr int acc_min_waves(int S) { return CPLX && sizeof(T) == 8 && S > 4 ? 3 : 4; }
 template <class T, bool CPLX, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(acc_min_waves<T, CPLX>(S), 8))) void kog_accum_s_kernel(int N, Mat<T, CPLX> U, Mat<T, CPLX> V,
                                                           Mat<T, CPLX> U2, Mat<T, CPLX> V2, int t,
                                                           AccSets<T, CPLX> R) {
   static_assert(S >= 2 && S <= kAccMaxS, "levels");
-  constexpr int SEG = AccShape<CPLX>::seg, NIT = AccRun<T, CPLX, S>::NIT;
+  constexpr int SEG = AccShape<T, CPLX>::seg, NIT = AccRun<T, CPLX, S>::NIT;
   __shared__ W4<T> ws[S * NIT];
   const int n = N / 2;
   const int rb = (N + 255) / 256, nseg = (n + SEG - 1) / SEG;
