@@ -401,7 +401,12 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
  * steps, then one out-of-place pass over the matrix), except the last step
  * of each sweep, which stays a single in-place step; every problem gets a
  * second matrix in the workspace, and results end in the caller's matrices,
- * bitwise equal to single steps.  Synchronises the stream; returns SVD2_OK if
+ * bitwise equal to single steps.  With SVD2_KOG_THREE_STEP a pass takes a
+ * running problem three steps further (the single-problem three-step mode)
+ * while at least three steps remain before the last step of its sweep, and
+ * one in-place step otherwise, so that every sweep ends with the in-place
+ * step that tests convergence; three rotation sets and a second matrix per
+ * problem.  Synchronises the stream; returns SVD2_OK if
  * every problem converged, SVD2_NOT_CONVERGED otherwise (see each problem's
  * status).
  * ------------------------------------------------------------------------- */
@@ -421,11 +426,13 @@ typedef struct {
    invalid descriptors). */
 size_t kog_batch_workspace_bytes(int nprob, const kog_problem *probs);
 /* the same for the given flags (SVD2_KOG_TWO_STEP adds a second rotation set
-   and an N^2 matrix per problem) */
+   and an N^2 matrix per problem, SVD2_KOG_THREE_STEP two more sets and the
+   matrix; 0 for flags kog_batch_solve refuses) */
 size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsigned flags);
 /* probs: host array, read and updated.  Matrices must not overlap each other
-   or the workspace (the latter is checked).  flags: SVD2_KOG_GRAPH and/or
-   SVD2_KOG_TWO_STEP. */
+   or the workspace (the latter is checked).  flags: SVD2_KOG_GRAPH, with at
+   most one of SVD2_KOG_TWO_STEP and SVD2_KOG_THREE_STEP (both:
+   SVD2_ERR_FLAGS). */
 svd2_status kog_batch_solve(int nprob, kog_problem *probs, void *ws, size_t ws_bytes, unsigned flags,
                             hipStream_t stream);
 

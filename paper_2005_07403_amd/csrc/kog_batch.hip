@@ -1,6 +1,6 @@
 // kog_batch.hip -- many Kogbetliantz problems of uneven order and mixed
 // element type solved together (device-side convergence, hipGraph replay,
-// work-list compaction; one or two steps per pass).  The shared device code is
+// work-list compaction; one, two or three steps per pass).  The shared device code is
 // in kog_device.hpp.
 #include <stdint.h>
 #include <string.h>
@@ -29,23 +29,32 @@ using namespace kog;
 // in-place step with the convergence test as above.  The work list holds the
 // tiles of both kinds; a tile of the kind a problem does not need in this
 // pass returns at once.
+//
+// In the three-step mode a pass takes a running problem three steps further
+// while at least three steps remain before the last step of its sweep
+// (pivots of the three steps, then the three-step tiles, out of place), and
+// one step (in place, as in the one-step mode) otherwise: the last one or
+// three steps of a sweep, so that every sweep still ends with the in-place
+// step that tests convergence.
 // ---------------------------------------------------------------------------
 struct DevProb {
   void *A;
   long long lda, piv_off, out_off;  // buffer offsets in bytes from the workspace base
-  long long piv1_off, out1_off;     // second rotation set (two-step mode)
-  long long w_off;                  // second matrix (two-step mode), lda = N
+  long long piv1_off, out1_off;     // second rotation set (two- and three-step modes)
+  long long piv2_off, out2_off;     // third rotation set (three-step mode)
+  long long w_off;                  // second matrix (two- and three-step modes), lda = N
   int N, kind, kc, lc;
   int part_off, ntiles, max_sweeps, in_w;  // in_w: the iterate is in the second matrix
   int gx2, ny2, lc2;                // two-step tiles: row blocks, column tiles, pairs per wavefront
   int e;                            // the solve works on 2^-e A (kog_scale_kernel)
+  int gx3, ny3, lc3, pad0;          // three-step tiles: row blocks, column tiles, output pairs per tile
   double tol, tot0;                 // tot0 = ||A_0||_F
   int t, sweeps, status, pad1;      // status: 0 running, 1 converged, 2 max_sweeps reached
   double off_rel;
 };
 struct BatchHdr {
   int nA, nB, nprob, active;
-  int c0[5];  // two-step tiles of element type k: items [c0[k], c0[k+1])
+  int c0[5];  // multi-step tiles of element type k: items [c0[k], c0[k+1])
   int pad[3];
 };
 
@@ -57,7 +66,8 @@ template <class T, bool CPLX>
 __device__ __forceinline__ Bufs<T, CPLX> bufs_of(char *ws, const DevProb &P, int set = 0) {
   Bufs<T, CPLX> b;
   size_t arr = arr_bytes(P.N, sizeof(T));
-  const long long po = set ? P.piv1_off : P.piv_off, oo = set ? P.out1_off : P.out_off;
+  const long long po = set == 2 ? P.piv2_off : set ? P.piv1_off : P.piv_off;
+  const long long oo = set == 2 ? P.out2_off : set ? P.out1_off : P.out_off;
   for (int i = 0; i < Bufs<T, CPLX>::NIN; ++i) b.piv[i] = (T *)(ws + po + i * arr);
   for (int i = 0; i < Bufs<T, CPLX>::NOUT; ++i) b.out[i] = (T *)(ws + oo + i * arr);
   return b;
@@ -99,8 +109,28 @@ __device__ __forceinline__ void batch_two_step(char *smem, char *ws, const DevPr
                          (kUpdBlock / 64) * P.lc2, P.lc2, bx, by);
 }
 
-// this pass takes problem P two steps further
-__device__ __forceinline__ bool two_this_pass(int two, const DevProb &P) { return two && P.t + 1 < P.N - 1; }
+// the steps this pass takes problem P further (mode: steps per pass asked
+// for): the last step of a sweep (t = N-2) is always a single one, and in the
+// three-step mode so are those that leave fewer than three before it
+__device__ __forceinline__ int pass_steps(int mode, const DevProb &P) {
+  if (mode == 2) return P.t + 1 < P.N - 1 ? 2 : 1;
+  if (mode == 3) return P.N - 2 - P.t >= 3 ? 3 : 1;
+  return 1;
+}
+
+// pivots of step t+2 of a three-step pass: four lanes per pair, 64 pairs per
+// pass of the loop; all threads of the block call it
+template <class T, bool CPLX> __device__ __forceinline__ void batch_pivots3(char *ws, const DevProb &P, int k, int sub) {
+  pivots3_quad<T, CPLX>(P.N, mat_of<T, CPLX>(ws, P), P.t, bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1),
+                        bufs_of<T, CPLX>(ws, P, 2), k, sub, k < P.N / 2);
+}
+
+template <class T, bool CPLX>
+__device__ __forceinline__ void batch_three_step(char *smem, char *ws, const DevProb &P, int bx, int by) {
+  const Mat<T, CPLX> cur = mat_of<T, CPLX>(ws, P), nxt = mat_of<T, CPLX>(ws, P, true);
+  three_step_tile<T, CPLX>(smem, P.N, cur.A, cur.lda, nxt.A, nxt.lda, P.t, bufs_of<T, CPLX>(ws, P, 0),
+                           bufs_of<T, CPLX>(ws, P, 1), bufs_of<T, CPLX>(ws, P, 2), 1, P.lc3, bx, by);
+}
 
 // the largest binary exponent among the finite nonzero components of this
 // thread's share of A
@@ -196,12 +226,12 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_init_kernel(BatchHdr *hdr
 
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, const BatchHdr *hdr,
                                                                     const int2 *items, const DevProb *probs,
-                                                                    int two) {
+                                                                    int mode) {
   const int nA = hdr->nA;
   for (int it = blockIdx.x; it < nA; it += gridDim.x) {
     const int2 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.status != 0 || two_this_pass(two, P)) continue;
+    if (P.status != 0 || pass_steps(mode, P) != 1) continue;
     const int k = item.y * kUpdBlock + (int)threadIdx.x;
     if (k >= P.N / 2) continue;
     switch (P.kind) {
@@ -213,18 +243,37 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivot_kernel(char *ws, co
   }
 }
 
-// the pivots of both steps of the problems of one element type in a
-// two-step pass
+// the pivots of steps t and t+1 of the problems of one element type in a
+// two- or three-step pass
 template <class T, bool CPLX, int KIND>
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots2_kernel(char *ws, const BatchHdr *hdr,
+                                                                      const int2 *items, const DevProb *probs,
+                                                                      int mode) {
+  const int nA = hdr->nA;
+  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
+    const int2 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.kind != KIND || P.status != 0 || pass_steps(mode, P) < 2) continue;
+    const int k = item.y * kUpdBlock + (int)threadIdx.x;
+    if (k < P.N / 2) batch_pivots2<T, CPLX>(ws, P, k);
+  }
+}
+
+// the pivots of step t+2 of the problems of one element type in a
+// three-step pass (an item's kUpdBlock pairs in four rounds of 64)
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots3_kernel(char *ws, const BatchHdr *hdr,
                                                                       const int2 *items, const DevProb *probs) {
   const int nA = hdr->nA;
   for (int it = blockIdx.x; it < nA; it += gridDim.x) {
     const int2 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.kind != KIND || P.status != 0 || !two_this_pass(1, P)) continue;
-    const int k = item.y * kUpdBlock + (int)threadIdx.x;
-    if (k < P.N / 2) batch_pivots2<T, CPLX>(ws, P, k);
+    if (P.kind != KIND || P.status != 0 || pass_steps(3, P) != 3) continue;
+    for (int r = 0; r < kUpdBlock / 64; ++r) {
+      const int k = item.y * kUpdBlock + r * 64 + ((int)threadIdx.x >> 2);
+      if (item.y * kUpdBlock + r * 64 >= P.N / 2) break;  // uniform over the block
+      batch_pivots3<T, CPLX>(ws, P, k, (int)threadIdx.x & 3);
+    }
   }
 }
 
@@ -240,8 +289,24 @@ __global__ __launch_bounds__(kUpdBlock, 3) void kog_batch_two_step_kernel(char *
   for (int it = c0 + (int)blockIdx.x; it < c1; it += gridDim.x) {
     const int4 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.status != 0 || !two_this_pass(1, P)) continue;
+    if (P.status != 0 || pass_steps(2, P) != 2) continue;
     batch_two_step<T, CPLX>(kog_smem, ws, P, item.y, item.z);
+    __syncthreads();  // the next item reuses the LDS
+  }
+}
+
+// the three-step tiles (problem, row block, column tile) of the problems of
+// one element type in a three-step pass, one wavefront per tile
+template <class T, bool CPLX, int KIND>
+__global__ __launch_bounds__(64) void kog_batch_three_step_kernel(char *ws, const BatchHdr *hdr, const int4 *items,
+                                                                  const DevProb *probs) {
+  extern __shared__ __align__(16) char kog_smem[];
+  const int c0 = hdr->c0[KIND], c1 = hdr->c0[KIND + 1];
+  for (int it = c0 + (int)blockIdx.x; it < c1; it += gridDim.x) {
+    const int4 item = items[it];
+    const DevProb &P = probs[item.x];
+    if (P.status != 0 || pass_steps(3, P) != 3) continue;
+    batch_three_step<T, CPLX>(kog_smem, ws, P, item.y, item.z);
     __syncthreads();  // the next item reuses the LDS
   }
 }
@@ -250,13 +315,13 @@ __global__ __launch_bounds__(kUpdBlock, 3) void kog_batch_two_step_kernel(char *
 // not in a two-step pass
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, const BatchHdr *hdr,
                                                                      const int4 *items, const DevProb *probs,
-                                                                     double *partials, int two) {
+                                                                     double *partials, int mode) {
   __shared__ double red[kUpdBlock];
   const int nB = hdr->nB;
   for (int it = blockIdx.x; it < nB; it += gridDim.x) {
     const int4 item = items[it];
     const DevProb &P = probs[item.x];
-    if (P.status != 0 || two_this_pass(two, P)) continue;
+    if (P.status != 0 || pass_steps(mode, P) != 1) continue;
     const Tile tl{item.y, P.kc, item.z, P.lc};
     double off2;
     switch (P.kind) {
@@ -271,17 +336,17 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_update_kernel(char *ws, c
 }
 
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *hdr, DevProb *probs,
-                                                                     const double *partials, int two) {
+                                                                     const double *partials, int mode) {
   __shared__ double red[kUpdBlock];
   for (int p = blockIdx.x; p < hdr->nprob; p += gridDim.x) {
     DevProb &P = probs[p];
     // every thread reads the state before thread 0 changes it
-    const int status = P.status, t = P.t, N = P.N;
+    const int status = P.status, t = P.t, N = P.N, steps = pass_steps(mode, P);
     __syncthreads();
     if (status != 0) continue;
-    if (two && t + 1 < N - 1) {  // a two-step pass: no sweep ends inside it
+    if (steps > 1) {  // a multi-step pass: no sweep ends inside it
       if (threadIdx.x == 0) {
-        P.t = t + 2;
+        P.t = t + steps;
         P.in_w ^= 1;
       }
       continue;
@@ -312,10 +377,16 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_finish_kernel(BatchHdr *h
 // ---------------------------------------------------------------------------
 struct BatchLayout {
   size_t hdr, probs, itemsA, itemsB, itemsC, parts, bufs, total;
-  size_t lds[4];  // two-step LDS bytes per element type
+  size_t lds[4];  // multi-step tile LDS bytes per element type
   int maxA, maxB, maxC, nparts;
   int maxC_kind[4];
 };
+
+// steps per pass asked for by the flags (0: both multi-step modes, refused)
+int batch_mode(unsigned flags) {
+  const bool two = (flags & SVD2_KOG_TWO_STEP) != 0, three = (flags & SVD2_KOG_THREE_STEP) != 0;
+  return two && three ? 0 : three ? 3 : two ? 2 : 1;
+}
 
 int esz_of(int kind) { return (kind == SVD2_KOG_F64 || kind == SVD2_KOG_C128) ? 8 : 4; }
 bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
@@ -328,6 +399,19 @@ bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
 // single-problem shapes).
 int batch_lc2(int) { return 8; }
 
+// output column pairs per three-step tile in a batch (one wavefront per
+// tile), fixed for the same reason
+int batch_lc3(int) { return 32; }
+
+size_t three_step_lds_of(int kind, int lc) {
+  switch (kind) {
+    case SVD2_KOG_F64: return three_step_lds<double, false>(lc);
+    case SVD2_KOG_C128: return three_step_lds<double, true>(lc);
+    case SVD2_KOG_F32: return three_step_lds<float, false>(lc);
+    default: return three_step_lds<float, true>(lc);
+  }
+}
+
 size_t two_step_lds_of(int kind, int span) {
   const int wpg = kUpdBlock / 64;
   switch (kind) {
@@ -339,7 +423,7 @@ size_t two_step_lds_of(int kind, int span) {
 }
 
 svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::vector<DevProb> *dp,
-                         bool two) {
+                         int mode) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   if (nprob < 0 || nprob > (1 << 20)) return SVD2_ERR_SIZE;
   if (nprob > 0 && !pr) return SVD2_ERR_NULL;
@@ -361,7 +445,9 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
     size_t arr = arr_bytes(q.N, esz_of(q.dtype));
     const int lc2 = batch_lc2(q.N), span = (kUpdBlock / 64) * lc2;
     const int gx2 = (n + kShiftOut - 1) / kShiftOut, ny2 = (n + span - 1) / span;
+    const int lc3 = batch_lc3(q.N), gx3 = (n + kShift3Out - 1) / kShift3Out, ny3 = (n + lc3 - 1) / lc3;
     const size_t set = (nin + nout) * arr;
+    const int nsets = mode;  // rotation sets: one per step of a pass
     const size_t wbytes = up((size_t)q.N * q.N * esz_of(q.dtype) * (cplx_of(q.dtype) ? 2 : 1));
     if (dp) {
       DevProb d = {};
@@ -377,24 +463,34 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
       d.tol = q.tol;
       d.piv_off = (long long)bufs;  // relative to the buffer region; rebased below
       d.out_off = (long long)(bufs + nin * arr);
-      if (two) {
+      if (mode >= 2) {
         d.piv1_off = (long long)(bufs + set);
         d.out1_off = (long long)(bufs + set + nin * arr);
-        d.w_off = (long long)(bufs + 2 * set);
+        d.w_off = (long long)(bufs + nsets * set);
+      }
+      if (mode == 2) {
         d.gx2 = gx2;
         d.ny2 = ny2;
         d.lc2 = lc2;
       }
+      if (mode == 3) {
+        d.piv2_off = (long long)(bufs + 2 * set);
+        d.out2_off = (long long)(bufs + 2 * set + nin * arr);
+        d.gx3 = gx3;
+        d.ny3 = ny3;
+        d.lc3 = lc3;
+      }
       dp->push_back(d);
     }
-    bufs += two ? 2 * set + wbytes : set;
+    bufs += mode >= 2 ? nsets * set + wbytes : set;
+    const int tiles = mode == 3 ? gx3 * ny3 : mode == 2 ? gx2 * ny2 : 0;
     L.maxA += (n + kUpdBlock - 1) / kUpdBlock;
     L.maxB += kt * lt;
-    L.maxC += two ? gx2 * ny2 : 0;
-    L.maxC_kind[q.dtype] += two ? gx2 * ny2 : 0;
+    L.maxC += tiles;
+    L.maxC_kind[q.dtype] += tiles;
     L.nparts += kt * lt;
-    if (two) {
-      size_t l = two_step_lds_of(q.dtype, span);
+    if (mode >= 2) {
+      size_t l = mode == 3 ? three_step_lds_of(q.dtype, lc3) : two_step_lds_of(q.dtype, span);
       if (l > L.lds[q.dtype]) L.lds[q.dtype] = l;
     }
   }
@@ -410,10 +506,14 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
     for (DevProb &d : *dp) {
       d.piv_off += (long long)L.bufs;
       d.out_off += (long long)L.bufs;
-      if (two) {
+      if (mode >= 2) {
         d.piv1_off += (long long)L.bufs;
         d.out1_off += (long long)L.bufs;
         d.w_off += (long long)L.bufs;
+      }
+      if (mode == 3) {
+        d.piv2_off += (long long)L.bufs;
+        d.out2_off += (long long)L.bufs;
       }
     }
   return SVD2_OK;
@@ -421,18 +521,19 @@ svd2_status batch_layout(int nprob, const kog_problem *pr, BatchLayout &L, std::
 
 // work lists of the problems still running
 void build_items(const std::vector<DevProb> &dp, std::vector<int2> &A, std::vector<int4> &B,
-                 std::vector<int4> &C, int *c0, bool two) {
+                 std::vector<int4> &C, int *c0, int mode) {
   A.clear();
   B.clear();
   C.clear();
-  for (int kind = 0; kind < 4; ++kind) {  // two-step tiles, grouped by element type
+  for (int kind = 0; kind < 4; ++kind) {  // multi-step tiles, grouped by element type
     c0[kind] = (int)C.size();
-    if (!two) continue;
+    if (mode < 2) continue;
     for (int p = 0; p < (int)dp.size(); ++p) {
       const DevProb &d = dp[p];
       if (d.status != 0 || d.kind != kind) continue;
-      for (int y = 0; y < d.ny2; ++y)
-        for (int x = 0; x < d.gx2; ++x) C.push_back(int4{p, x, y, 0});
+      const int ny = mode == 3 ? d.ny3 : d.ny2, gx = mode == 3 ? d.gx3 : d.gx2;
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < gx; ++x) C.push_back(int4{p, x, y, 0});
     }
   }
   c0[4] = (int)C.size();
@@ -451,20 +552,33 @@ struct BatchRun {
   char *ws;
   BatchLayout L;
   hipStream_t st;
-  int gA, gB, gF, two;
+  int gA, gB, gF, mode;
 };
 
-template <class T, bool CPLX, int KIND> svd2_status batch_two_step_launch(const BatchRun &r, hipStream_t st) {
+// the multi-step part of a pass for the problems of one element type: the
+// pivots, then the tiles
+template <class T, bool CPLX, int KIND> svd2_status batch_multi_launch(const BatchRun &r, hipStream_t st) {
   if (r.L.maxC_kind[KIND] == 0) return SVD2_OK;
   BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
   DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  const int2 *itemsA = (const int2 *)(r.ws + r.L.itemsA);
+  const int4 *itemsC = (const int4 *)(r.ws + r.L.itemsC);
   hipLaunchKernelGGL((kog_batch_pivots2_kernel<T, CPLX, KIND>), dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
-                     (const int2 *)(r.ws + r.L.itemsA), probs);
+                     itemsA, probs, r.mode);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   const int g = r.L.maxC_kind[KIND] < 16384 ? r.L.maxC_kind[KIND] : 16384;
-  hipLaunchKernelGGL((kog_batch_two_step_kernel<T, CPLX, KIND>), dim3(g), dim3(kUpdBlock), r.L.lds[KIND], st,
-                     r.ws, hdr, (const int4 *)(r.ws + r.L.itemsC), probs);
+  if (r.mode == 3) {
+    hipLaunchKernelGGL((kog_batch_pivots3_kernel<T, CPLX, KIND>), dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+                       itemsA, probs);
+    s = hip_st(hipGetLastError());
+    if (s != SVD2_OK) return s;
+    hipLaunchKernelGGL((kog_batch_three_step_kernel<T, CPLX, KIND>), dim3(g), dim3(64), r.L.lds[KIND], st, r.ws,
+                       hdr, itemsC, probs);
+  } else {
+    hipLaunchKernelGGL((kog_batch_two_step_kernel<T, CPLX, KIND>), dim3(g), dim3(kUpdBlock), r.L.lds[KIND], st,
+                       r.ws, hdr, itemsC, probs);
+  }
   return hip_st(hipGetLastError());
 }
 
@@ -472,19 +586,20 @@ svd2_status batch_step(const BatchRun &r, hipStream_t st) {
   BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
   DevProb *probs = (DevProb *)(r.ws + r.L.probs);
   hipLaunchKernelGGL(kog_batch_pivot_kernel, dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
-                     (const int2 *)(r.ws + r.L.itemsA), probs, r.two);
+                     (const int2 *)(r.ws + r.L.itemsA), probs, r.mode);
   svd2_status s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
-                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.two);
+                     (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.mode);
   s = hip_st(hipGetLastError());
-  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, false, SVD2_KOG_F64>(r, st);
-  if (s == SVD2_OK && r.two) s = batch_two_step_launch<double, true, SVD2_KOG_C128>(r, st);
-  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, false, SVD2_KOG_F32>(r, st);
-  if (s == SVD2_OK && r.two) s = batch_two_step_launch<float, true, SVD2_KOG_C64>(r, st);
+  const bool multi = r.mode >= 2;
+  if (s == SVD2_OK && multi) s = batch_multi_launch<double, false, SVD2_KOG_F64>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<double, true, SVD2_KOG_C128>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<float, false, SVD2_KOG_F32>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<float, true, SVD2_KOG_C64>(r, st);
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_finish_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, hdr, probs,
-                     (const double *)(r.ws + r.L.parts), r.two);
+                     (const double *)(r.ws + r.L.parts), r.mode);
   return hip_st(hipGetLastError());
 }
 
@@ -508,7 +623,7 @@ svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int 
   std::vector<int2> A;
   std::vector<int4> B, C;
   BatchHdr h = {};
-  build_items(dp, A, B, C, h.c0, r.two != 0);
+  build_items(dp, A, B, C, h.c0, r.mode);
   h.nA = (int)A.size();
   h.nB = (int)B.size();
   h.nprob = (int)dp.size();
@@ -525,11 +640,12 @@ svd2_status upload_items(const BatchRun &r, const std::vector<DevProb> &dp, int 
 }
 
 svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsigned flags, hipStream_t st) {
-  if (flags & ~(unsigned)(SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP)) return SVD2_ERR_FLAGS;
+  if (flags & ~(unsigned)(SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP | SVD2_KOG_THREE_STEP)) return SVD2_ERR_FLAGS;
   BatchRun r;
-  r.two = (flags & SVD2_KOG_TWO_STEP) ? 1 : 0;
+  r.mode = batch_mode(flags);
+  if (r.mode == 0) return SVD2_ERR_FLAGS;
   std::vector<DevProb> dp;
-  svd2_status s = batch_layout(nprob, pr, r.L, &dp, r.two != 0);
+  svd2_status s = batch_layout(nprob, pr, r.L, &dp, r.mode);
   if (s != SVD2_OK) return s;
   if (nprob == 0) return SVD2_OK;
   if (!ws) return SVD2_ERR_NULL;
@@ -556,9 +672,9 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
   hipLaunchKernelGGL(kog_batch_init_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, (BatchHdr *)(r.ws + r.L.hdr),
                      (DevProb *)(r.ws + r.L.probs));
   s = hip_st(hipGetLastError());
-  long long max_steps = 0;  // passes: steps, or (N/2 per sweep) two-step passes
+  long long max_steps = 0;  // passes: at most N-1 per sweep (N/2 with two steps per pass)
   for (const DevProb &d : dp) {
-    long long m = (long long)d.max_sweeps * (r.two ? d.N / 2 : d.N - 1);
+    long long m = (long long)d.max_sweeps * (r.mode == 2 ? d.N / 2 : d.N - 1);
     if (m > max_steps) max_steps = m;
   }
   const int K = 64;  // passes per replay / between host checks
@@ -641,7 +757,9 @@ extern "C" {
 
 size_t kog_batch_workspace_bytes_flags(int nprob, const kog_problem *probs, unsigned flags) {
   BatchLayout L;
-  if (batch_layout(nprob, probs, L, nullptr, (flags & SVD2_KOG_TWO_STEP) != 0) != SVD2_OK) return 0;
+  if (flags & ~(unsigned)(SVD2_KOG_GRAPH | SVD2_KOG_TWO_STEP | SVD2_KOG_THREE_STEP)) return 0;
+  const int mode = batch_mode(flags);
+  if (mode == 0 || batch_layout(nprob, probs, L, nullptr, mode) != SVD2_OK) return 0;
   return L.total;
 }
 

@@ -334,6 +334,14 @@ def test_kog_batch_argument_errors():
     assert L.kog_batch_solve(2, P, ws, wsb - 1, 0, None) == 6    # too small
     assert L.kog_batch_solve(2, P, ws + 8, wsb, 0, None) == 2    # misaligned
     assert L.kog_batch_solve(2, P, ws, wsb, 1, None) == 4        # UNFUSED is not a batch flag
+    wf = L.kog_batch_workspace_bytes_flags
+    w2, w3 = wf(2, P, S.SVD2_KOG_TWO_STEP), wf(2, P, S.SVD2_KOG_THREE_STEP)
+    assert wsb < w2 < w3                     # a second matrix; two, then three rotation sets
+    assert wf(2, P, S.SVD2_KOG_GRAPH) == wsb
+    assert wf(2, P, S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_THREE_STEP) == 0
+    assert wf(2, P, 1) == 0
+    assert L.kog_batch_solve(2, P, ws, w3, S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_THREE_STEP, None) == 4
+    assert L.kog_batch_solve(2, P, ws, w3 - 1, S.SVD2_KOG_THREE_STEP, None) == 6
     P[1].N = 63
     assert L.kog_batch_workspace_bytes(2, P) == 0
     assert L.kog_batch_solve(2, P, ws, wsb, 0, None) == 6        # odd order

@@ -1,6 +1,7 @@
 """GPU parity of the uneven multi-problem Kogbetliantz solve: every problem of
 a mixed batch (orders 2..130, real/complex FP64 and FP32) must end bitwise
-equal to the oracle's single-problem solve, with the same sweep count."""
+equal to the oracle's single-problem solve, with the same sweep count, with
+one, two or three steps per pass."""
 import numpy as np
 import pytest
 
@@ -17,6 +18,16 @@ def _bits(a):
     return np.ascontiguousarray(a).view(np.uint8)
 
 
+def _mode_flags(S, mode):
+    """batch flags for one, two or three steps per pass"""
+    return {1: 0, 2: S.SVD2_KOG_TWO_STEP, 3: S.SVD2_KOG_THREE_STEP}[mode]
+
+
+def _single_flags(S, mode):
+    """the single-problem solver's flags for the same steps per pass"""
+    return {1: S.SVD2_KOG_UNFUSED, 2: S.SVD2_KOG_TWO_STEP, 3: S.SVD2_KOG_THREE_STEP}[mode]
+
+
 def _batch(specs, seed):
     mats = []
     for i, (N, kind, cond) in enumerate(specs):
@@ -26,11 +37,11 @@ def _batch(specs, seed):
 
 
 @pytest.mark.parametrize("graph", [False, True])
-@pytest.mark.parametrize("two", [False, True])
-def test_mixed_batch_bitwise(graph, two):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_mixed_batch_bitwise(graph, mode):
     import torch
     from paper_2005_07403_amd import svd2 as S
-    flags = (S.SVD2_KOG_GRAPH if graph else 0) | (S.SVD2_KOG_TWO_STEP if two else 0)
+    flags = (S.SVD2_KOG_GRAPH if graph else 0) | _mode_flags(S, mode)
     specs = [(2, "d", 10.0), (4, "z", 1e3), (6, "s", 1e2), (32, "d", 1e12), (34, "z", 1e8),
              (64, "s", 1e4), (66, "c", 1e3), (128, "d", 1e6), (130, "z", 1e10), (96, "c", 1e2),
              (40, "s", 1e5), (2, "z", 1.0)]
@@ -47,8 +58,8 @@ def test_mixed_batch_bitwise(graph, two):
         assert np.array_equal(_bits(got), _bits(A)), (i, N, kind)
 
 
-@pytest.mark.parametrize("two", [False, True])
-def test_batch_equals_single_problem_solver(two):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_batch_equals_single_problem_solver(mode):
     """A problem solved inside a batch ends bitwise equal to the same problem
     solved alone by the single-problem entry point (tile shape and batching do
     not change the arithmetic)."""
@@ -58,28 +69,27 @@ def test_batch_equals_single_problem_solver(two):
     mats = _batch(specs, SEED_BASE + 410)
     dev = [torch.from_numpy(m).cuda() for m in mats]
     alone = [torch.from_numpy(m).cuda() for m in mats]
-    res = S.kog_batch_solve(dev, [TOL[k] for _, k, _ in specs],
-                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
+    res = S.kog_batch_solve(dev, [TOL[k] for _, k, _ in specs], flags=_mode_flags(S, mode))
     for i, (_, kind, _) in enumerate(specs):
-        r = S.kog_solve(alone[i], tol=TOL[kind], flags=S.SVD2_KOG_TWO_STEP if two else S.SVD2_KOG_UNFUSED)
+        r = S.kog_solve(alone[i], tol=TOL[kind], flags=_single_flags(S, mode))
         assert r["sweeps"] == res[i]["sweeps"]
         a, b = alone[i].cpu().numpy(), dev[i].cpu().numpy()
         assert np.array_equal(_bits(a), _bits(b))
 
 
-@pytest.mark.parametrize("two", [False, True])
-def test_batch_not_converged_and_already_diagonal(two):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_batch_not_converged_and_already_diagonal(mode):
     """A problem stopped by max_sweeps keeps the iterate of its last sweep
     (bitwise the oracle's after that many sweeps; in the two-step mode the
     iterate of order 64 ends a sweep in the second matrix and is copied
-    back); a diagonal input is left untouched."""
+    back, in the three-step mode in the caller's); a diagonal input is left
+    untouched."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     A = np.asfortranarray(kog_matrix(64, SEED_BASE + 420, cond=1e12))
     D = np.asfortranarray(np.diag(np.arange(1.0, 33.0)))
     dev = [torch.from_numpy(A).cuda(), torch.from_numpy(D).cuda()]
-    res = S.kog_batch_solve(dev, [1e-14, 1e-14], max_sweeps=[1, 5],
-                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
+    res = S.kog_batch_solve(dev, [1e-14, 1e-14], max_sweeps=[1, 5], flags=_mode_flags(S, mode))
     assert res[0]["status"] == 7 and res[0]["sweeps"] == 1
     assert res[1]["status"] == 0 and res[1]["sweeps"] == 0
     assert torch.equal(dev[1].cpu(), torch.from_numpy(D))
@@ -88,10 +98,12 @@ def test_batch_not_converged_and_already_diagonal(two):
     assert np.array_equal(_bits(dev[0].cpu().numpy()), _bits(A))
 
 
-def test_two_step_batch_large_orders():
-    """Orders up to 1026 (several two-step tiles per problem in both
-    directions, a partial last column tile) in the two-step batch: each
-    problem bitwise equal to its single-problem two-step solve."""
+@pytest.mark.parametrize("mode", [2, 3])
+def test_multi_step_batch_large_orders(mode):
+    """Orders up to 1026 (several multi-step tiles per problem in both
+    directions, a partial last column tile; orders whose sweeps leave 0, 1
+    and 2 steps after the last three-step pass) in the two- and three-step
+    batch: each problem bitwise equal to its single-problem solve."""
     import torch
     from paper_2005_07403_amd import svd2 as S
     specs = [(1026, "d", 1e10), (514, "z", 1e6), (770, "s", 1e3), (390, "c", 1e3), (258, "d", 1e2)]
@@ -99,21 +111,23 @@ def test_two_step_batch_large_orders():
     dev = [torch.from_numpy(m).cuda() for m in mats]
     alone = [torch.from_numpy(m).cuda() for m in mats]
     tols = [TOL[k] for _, k, _ in specs]
-    res = S.kog_batch_solve(dev, tols, flags=S.SVD2_KOG_TWO_STEP | S.SVD2_KOG_GRAPH)
+    res = S.kog_batch_solve(dev, tols, flags=_mode_flags(S, mode) | S.SVD2_KOG_GRAPH)
     for i, (N, kind, _) in enumerate(specs):
-        r = S.kog_solve(alone[i], tol=tols[i], flags=S.SVD2_KOG_TWO_STEP)
+        r = S.kog_solve(alone[i], tol=tols[i], flags=_single_flags(S, mode))
         assert r["status"] == res[i]["status"] == 0
         assert r["sweeps"] == res[i]["sweeps"], (N, kind)
         assert np.array_equal(_bits(alone[i].cpu().numpy()), _bits(dev[i].cpu().numpy())), (N, kind)
 
 
 @pytest.mark.slow
-def test_full_uneven_batch_two_step():
+@pytest.mark.parametrize("mode", [2, 3])
+def test_full_uneven_batch_multi_step(mode):
     """The 256-problem uneven workload (orders 32..2048, half complex FP64 at
-    tol 1e-14, half FP32 at tol 1e-7), solved two steps per pass with graph
-    replay as the benchmark times it: every problem converges, its singular
-    values match the construction within 8 N eps sigma_max, and the six
-    smallest problems end bitwise equal to the oracle's single-problem solve."""
+    tol 1e-14, half FP32 at tol 1e-7), solved two or three steps per pass with
+    graph replay as the benchmark times it: every problem converges, its
+    singular values match the construction within 8 N eps sigma_max, and the
+    six smallest problems end bitwise equal to the oracle's single-problem
+    solve."""
     from paper_2005_07403_amd import svd2 as S
     from workloads import kog_problem_set_device
     probs = kog_problem_set_device(256, SEED_BASE + 5)
@@ -121,7 +135,7 @@ def test_full_uneven_batch_two_step():
     tols = [1e-14 if p["cplx"] else 1e-7 for p in probs]
     small = sorted(range(len(probs)), key=lambda i: probs[i]["order"])[:6]
     host = {i: np.asfortranarray(mats[i].cpu().numpy()) for i in small}
-    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH | S.SVD2_KOG_TWO_STEP)
+    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH | _mode_flags(S, mode))
     for i, (p, r) in enumerate(zip(probs, res)):
         assert r["status"] == 0 and r["off_rel"] < tols[i], (i, p["order"], r)
         sig = S.kog_sigma(mats[i]).cpu().numpy().astype(np.float64)
@@ -140,8 +154,8 @@ def _scaled(A, k):
     return np.asfortranarray(A * A.dtype.type(2.0 ** k))
 
 
-@pytest.mark.parametrize("two", [False, True])
-def test_batch_tiny_and_huge_matrices(two):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_batch_tiny_and_huge_matrices(mode):
     """Problems scaled far from 1 (2^+-600 and beyond in FP64, 2^100 and 2^-60
     in FP32) each take the sweeps the oracle takes and end bitwise equal to
     its solve; each problem is scaled by its own power of two."""
@@ -151,8 +165,7 @@ def test_batch_tiny_and_huge_matrices(two):
              (64, "s", 1e3, 100), (40, "c", 1e2, -60), (6, "c", 1e2, 100), (130, "d", 1e8, 0)]
     mats = [_scaled(m, k) for m, (_, _, _, k) in zip(_batch([s[:3] for s in specs], SEED_BASE + 430), specs)]
     dev = [torch.from_numpy(m).cuda() for m in mats]
-    res = S.kog_batch_solve(dev, [TOL[s[1]] for s in specs], max_sweeps=40,
-                            flags=S.SVD2_KOG_TWO_STEP if two else 0)
+    res = S.kog_batch_solve(dev, [TOL[s[1]] for s in specs], max_sweeps=40, flags=_mode_flags(S, mode))
     torch.cuda.synchronize()
     for i, ((N, kind, _, k), A) in enumerate(zip(specs, mats)):
         ro = O.kog_solve(A, tol=TOL[kind], max_sweeps=40)
