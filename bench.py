@@ -487,8 +487,8 @@ def kog_svd_bench(A, s, G0, mat, steps, passes, full: bool = True):
 def kog_batch_bench(nprob: int = 256):
     """The uneven batch: nprob problems of order 32..2048 (log-uniform), half
     complex FP64 (tol 1e-14), half real FP32 (tol 1e-7), condition numbers
-    1e2..1e12, solved together by kog_batch_solve with hipGraph replay, two
-    steps per pass (the reported run) and one step per pass (for
+    1e2..1e12, solved together by kog_batch_solve with hipGraph replay, three
+    steps per pass (the reported run), and one and two steps per pass (for
     comparison, from copies of the same matrices)."""
     import torch
     from paper_2005_07403_amd import svd2 as S
@@ -499,21 +499,28 @@ def kog_batch_bench(nprob: int = 256):
     log(f"[bench] kog batch: {nprob} problems built in {time.perf_counter() - t0:.1f} s")
     mats = [p["A"] for p in probs]
     tols = [1e-14 if p["cplx"] else 1e-7 for p in probs]
-    copies = [A.clone(memory_format=torch.preserve_format) for A in mats]
-    torch.cuda.synchronize()
+    def on_copies(flags):
+        copies = [A.clone(memory_format=torch.preserve_format) for A in mats]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = S.kog_batch_solve(copies, tols, max_sweeps=40, flags=flags)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        del copies
+        torch.cuda.empty_cache()
+        return r, el
+
+    res1, el1 = on_copies(S.SVD2_KOG_GRAPH)
+    res2, el2 = on_copies(S.SVD2_KOG_GRAPH | S.SVD2_KOG_TWO_STEP)
     t0 = time.perf_counter()
-    res1 = S.kog_batch_solve(copies, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH)
-    torch.cuda.synchronize()
-    el1 = time.perf_counter() - t0
-    del copies
-    torch.cuda.empty_cache()
-    t0 = time.perf_counter()
-    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH | S.SVD2_KOG_TWO_STEP)
+    res = S.kog_batch_solve(mats, tols, max_sweeps=40, flags=S.SVD2_KOG_GRAPH | S.SVD2_KOG_THREE_STEP)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     single = {"seconds": el1, "problem_sweeps_per_s": sum(r["sweeps"] for r in res1) / el1,
-              "same_sweeps_as_two_step": all(a["sweeps"] == b["sweeps"] for a, b in zip(res, res1))}
-    log(f"[bench] kog batch, one step per pass: {json.dumps(single)}")
+              "same_sweeps_as_three_step": all(a["sweeps"] == b["sweeps"] for a, b in zip(res, res1))}
+    two = {"seconds": el2, "problem_sweeps_per_s": sum(r["sweeps"] for r in res2) / el2,
+           "same_sweeps_as_three_step": all(a["sweeps"] == b["sweeps"] for a, b in zip(res, res2))}
+    log(f"[bench] kog batch, one step per pass: {json.dumps(single)}; two: {json.dumps(two)}")
     per = []
     for p, r in zip(probs, res):
         d = torch.diagonal(p["A"]).real.double().cpu().numpy()
@@ -525,8 +532,8 @@ def kog_batch_bench(nprob: int = 256):
     total_sweeps = sum(r["sweeps"] for r in res)
     bytes_moved = sum(2 * p["order"] ** 2 * (16 if p["cplx"] else 4) * (p["order"] - 1) * r["sweeps"]
                       for p, r in zip(probs, res))
-    out = {"nprob": nprob, "mode": "two_step", "seconds": el, "converged": sum(r["status"] == 0 for r in res),
-           "one_step_per_pass": single,
+    out = {"nprob": nprob, "mode": "three_step", "seconds": el, "converged": sum(r["status"] == 0 for r in res),
+           "one_step_per_pass": single, "two_steps_per_pass": two,
            "problem_sweeps_per_s": total_sweeps / el, "algorithmic_GBs": bytes_moved / el / 1e9,
            "max_sweeps": max(r["sweeps"] for r in res),
            "max_sigma_err_rel_c128": max(q["sigma_err_rel"] for q in per if q["dtype"] == "c128"),
@@ -602,7 +609,19 @@ def headline(full: dict) -> dict:
     line["variants_fields"] = ["SVDs/s", "hbm_frac", "valu_frac"]
     line["variants"] = {k: [r4(v["svds_per_s"]), r4(v["hbm_frac"]), r4(v.get("valu_frac"))]
                         for k, v in full["variants"].items()}
-    resc = {k: r4(v["rescued_frac"]) for k, v in full["variants"].items() if "rescued_frac" in v}
+    # rescued-lane fractions: one entry per base variant (s, c, s26, c26) when
+    # its rescue variants agree, as they should (which lanes are flagged does
+    # not depend on how they are rescued), else one per variant
+    groups = {}
+    for k, v in full["variants"].items():
+        if "rescued_frac" in v:
+            groups.setdefault(k.split("_")[0], {})[k] = r4(v["rescued_frac"])
+    resc = {}
+    for base, d in groups.items():
+        if len(set(d.values())) == 1:
+            resc[base] = next(iter(d.values()))
+        else:
+            resc.update(d)
     if resc:
         line["rescued_frac"] = resc
     kog = full.get("kogbetliantz")
@@ -626,6 +645,7 @@ def headline(full: dict) -> dict:
             "nprob": kb["nprob"], "seconds": r4(kb["seconds"]), "converged": kb["converged"],
             "problem_sweeps_per_s": r4(kb["problem_sweeps_per_s"]),
             "one_step_per_pass_seconds": r4(kb["one_step_per_pass"]["seconds"]),
+            "two_steps_per_pass_seconds": r4(kb["two_steps_per_pass"]["seconds"]),
             "max_sigma_err_rel_c128": r4(kb["max_sigma_err_rel_c128"]),
             "max_sigma_err_rel_f32": r4(kb["max_sigma_err_rel_f32"])}
     line["kernel_source_sha"] = full["kernel_source_sha"]

@@ -400,8 +400,10 @@ bool cplx_of(int kind) { return kind == SVD2_KOG_C128 || kind == SVD2_KOG_C64; }
 int batch_lc2(int) { return 8; }
 
 // output column pairs per three-step tile in a batch (one wavefront per
-// tile), fixed for the same reason
-int batch_lc3(int) { return 32; }
+// tile), fixed for the same reason (256-problem batch: 8.46 s with 8, 7.81
+// with 12, 7.62 with 16, 7.70 with 24, 7.88 with 32, 8.41 with 64; narrow
+// tiles keep the GPU busy once only the largest problems are left)
+int batch_lc3(int) { return 16; }
 
 size_t three_step_lds_of(int kind, int lc) {
   switch (kind) {

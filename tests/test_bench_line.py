@@ -52,8 +52,9 @@ def fake_full():
                            "seconds_per_sweep_extrapolated": 414.567, "sample": "4 steps at order 4096",
                            "full_solve": {"order": 256, "sweeps": 12, "cpu_seconds": 0.9,
                                           "gpu_two_step_seconds": 0.037, "gpu_sweeps": 12}}
-    batch = {"nprob": 256, "mode": "two_step", "seconds": 9.3123456, "converged": 256,
-             "one_step_per_pass": {"seconds": 15.123456, "problem_sweeps_per_s": 250.1, "same_sweeps_as_two_step": True},
+    batch = {"nprob": 256, "mode": "three_step", "seconds": 7.6123456, "converged": 256,
+             "one_step_per_pass": {"seconds": 15.123456, "problem_sweeps_per_s": 250.1, "same_sweeps_as_three_step": True},
+             "two_steps_per_pass": {"seconds": 9.323456, "problem_sweeps_per_s": 398.1, "same_sweeps_as_three_step": True},
              "problem_sweeps_per_s": 398.123, "algorithmic_GBs": 2345.6, "max_sweeps": 14,
              "max_sigma_err_rel_c128": 1.2345e-14, "max_sigma_err_rel_f32": 3.456e-6,
              "max_off_rel_c128": 9.1e-15, "max_off_rel_f32": 8.2e-8, "problems": problems}
@@ -98,9 +99,9 @@ def test_headline_is_compact_and_last_on_stdout(capsys, tmp_path):
     assert set(line["cpu_baseline"]) >= {"value", "unit", "cores", "kind", "sample"}
     assert line["cpu_baseline"]["kind"] == "oracle"
     assert line["cpu_baseline"]["gpu_vs_oracle_sample"]["z"]["s_equal"] is True
-    # one entry per variant, the rescued-lane fraction of each rescue variant
+    # one entry per variant; one rescued-lane fraction per base variant (its rescue variants agree)
     assert len(line["variants"]) == 26 and all(len(v) == 3 for v in line["variants"].values())
-    assert line["rescued_frac"]["c26_sigma"] == 0.83 and "c_norescue" not in line["rescued_frac"]
+    assert line["rescued_frac"] == {"s": 0.83, "c": 0.83, "s26": 0.83, "c26": 0.83}
     assert line["kogbetliantz"]["sweeps_per_s"]["two_step"] > 0
     assert line["kogbetliantz_batch"]["nprob"] == 256 and "problems" not in line["kogbetliantz_batch"]
     # the detail keeps what the headline leaves out
