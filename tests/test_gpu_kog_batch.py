@@ -172,3 +172,34 @@ def test_batch_tiny_and_huge_matrices(mode):
         assert res[i]["status"] == 0 == ro["status"], (i, res[i], ro["status"])
         assert res[i]["sweeps"] == ro["sweeps"] > 0, (i, res[i], ro["sweeps"])
         assert np.array_equal(_bits(dev[i].cpu().numpy()), _bits(A)), (i, N, kind, k)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_batch_padded_leading_dimensions(mode):
+    """Problems stored with lda > N (views into taller matrices) in every
+    mode: each ends bitwise equal to the oracle's solve, with the oracle's
+    sweep count, and the padding rows stay untouched (in the multi-step modes
+    the iterate passes through the workspace's matrix, whose lda is N)."""
+    import torch
+    from paper_2005_07403_amd import svd2 as S
+    specs = [(66, "d", 1e6), (40, "z", 1e4), (70, "s", 1e3), (34, "c", 1e2)]
+    mats = _batch(specs, SEED_BASE + 440)
+    pads = [3, 5, 1, 8]
+    bigs, views = [], []
+    for A, pad, (N, kind, _) in zip(mats, pads, specs):
+        big = np.asfortranarray(np.full((N + pad, N), 7, dtype=DT[kind]))
+        big[:N, :] = A
+        g = torch.from_numpy(big).cuda()
+        bigs.append(g)
+        views.append(g[:N, :])
+        assert views[-1].stride(1) == N + pad
+    res = S.kog_batch_solve(views, [TOL[k] for _, k, _ in specs], max_sweeps=40,
+                            flags=S.SVD2_KOG_GRAPH | _mode_flags(S, mode))
+    torch.cuda.synchronize()
+    for i, ((N, kind, _), A) in enumerate(zip(specs, mats)):
+        ro = O.kog_solve(A, tol=TOL[kind], max_sweeps=40)
+        assert res[i]["status"] == 0 == ro["status"], (i, res[i])
+        assert res[i]["sweeps"] == ro["sweeps"], (i, res[i], ro["sweeps"])
+        out = bigs[i].cpu().numpy()
+        assert np.array_equal(_bits(np.asfortranarray(out[:N, :])), _bits(A)), (i, N, kind)
+        assert np.all(out[N:, :] == 7), (i, N, kind)
