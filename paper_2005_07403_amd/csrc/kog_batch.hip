@@ -260,20 +260,20 @@ __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots2_kernel(char *ws, 
 }
 
 // the pivots of step t+2 of the problems of one element type in a
-// three-step pass (an item's kUpdBlock pairs in four rounds of 64)
+// three-step pass: four lanes per pair, so an item's kUpdBlock pairs are four
+// work units of 64 (unit u: item u / 4, its pairs from (u % 4) 64 on)
 template <class T, bool CPLX, int KIND>
 __global__ __launch_bounds__(kUpdBlock) void kog_batch_pivots3_kernel(char *ws, const BatchHdr *hdr,
                                                                       const int2 *items, const DevProb *probs) {
-  const int nA = hdr->nA;
-  for (int it = blockIdx.x; it < nA; it += gridDim.x) {
-    const int2 item = items[it];
+  constexpr int R = kUpdBlock / 64;
+  const int nU = hdr->nA * R;
+  for (int u = blockIdx.x; u < nU; u += gridDim.x) {
+    const int2 item = items[u / R];
     const DevProb &P = probs[item.x];
     if (P.kind != KIND || P.status != 0 || pass_steps(3, P) != 3) continue;
-    for (int r = 0; r < kUpdBlock / 64; ++r) {
-      const int k = item.y * kUpdBlock + r * 64 + ((int)threadIdx.x >> 2);
-      if (item.y * kUpdBlock + r * 64 >= P.N / 2) break;  // uniform over the block
-      batch_pivots3<T, CPLX>(ws, P, k, (int)threadIdx.x & 3);
-    }
+    const int k0 = item.y * kUpdBlock + (u % R) * 64;
+    if (k0 >= P.N / 2) continue;  // uniform over the block
+    batch_pivots3<T, CPLX>(ws, P, k0 + ((int)threadIdx.x >> 2), (int)threadIdx.x & 3);
   }
 }
 
@@ -571,7 +571,8 @@ template <class T, bool CPLX, int KIND> svd2_status batch_multi_launch(const Bat
   if (s != SVD2_OK) return s;
   const int g = r.L.maxC_kind[KIND] < 16384 ? r.L.maxC_kind[KIND] : 16384;
   if (r.mode == 3) {
-    hipLaunchKernelGGL((kog_batch_pivots3_kernel<T, CPLX, KIND>), dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
+    const int units = (kUpdBlock / 64) * r.L.maxA, g3 = units < 16384 ? units : 16384;
+    hipLaunchKernelGGL((kog_batch_pivots3_kernel<T, CPLX, KIND>), dim3(g3), dim3(kUpdBlock), 0, st, r.ws, hdr,
                        itemsA, probs);
     s = hip_st(hipGetLastError());
     if (s != SVD2_OK) return s;
