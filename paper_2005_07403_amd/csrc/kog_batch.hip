@@ -555,6 +555,12 @@ struct BatchRun {
   BatchLayout L;
   hipStream_t st;
   int gA, gB, gF, mode;
+  // a second stream for the multi-step kernels of complex element types
+  // (forked from and joined back to the pass's stream by events), so that
+  // the problems of two element types advance concurrently: once few
+  // problems are left, each type's kernels fill only part of the GPU
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // the multi-step part of a pass for the problems of one element type: the
@@ -595,11 +601,16 @@ svd2_status batch_step(const BatchRun &r, hipStream_t st) {
   hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
                      (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.mode);
   s = hip_st(hipGetLastError());
-  const bool multi = r.mode >= 2;
+  const bool multi = r.mode >= 2, two_streams = multi && r.side;
+  hipStream_t cs = two_streams ? r.side : st;  // complex element types
+  if (s == SVD2_OK && two_streams) s = hip_st(hipEventRecord(r.fork, st));
+  if (s == SVD2_OK && two_streams) s = hip_st(hipStreamWaitEvent(cs, r.fork, 0));
   if (s == SVD2_OK && multi) s = batch_multi_launch<double, false, SVD2_KOG_F64>(r, st);
-  if (s == SVD2_OK && multi) s = batch_multi_launch<double, true, SVD2_KOG_C128>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<double, true, SVD2_KOG_C128>(r, cs);
   if (s == SVD2_OK && multi) s = batch_multi_launch<float, false, SVD2_KOG_F32>(r, st);
-  if (s == SVD2_OK && multi) s = batch_multi_launch<float, true, SVD2_KOG_C64>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<float, true, SVD2_KOG_C64>(r, cs);
+  if (s == SVD2_OK && two_streams) s = hip_st(hipEventRecord(r.join, cs));
+  if (s == SVD2_OK && two_streams) s = hip_st(hipStreamWaitEvent(st, r.join, 0));
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_finish_kernel, dim3(r.gF), dim3(kUpdBlock), 0, st, hdr, probs,
                      (const double *)(r.ws + r.L.parts), r.mode);
@@ -665,6 +676,23 @@ svd2_status batch_solve(int nprob, kog_problem *pr, void *ws, size_t wsb, unsign
   }
   r.ws = (char *)ws;
   r.st = st;
+  // two streams when both real and complex problems take multi-step passes
+  const bool real_multi = r.L.maxC_kind[SVD2_KOG_F64] + r.L.maxC_kind[SVD2_KOG_F32] > 0;
+  const bool cplx_multi = r.L.maxC_kind[SVD2_KOG_C128] + r.L.maxC_kind[SVD2_KOG_C64] > 0;
+  struct Side {  // released on every return below
+    BatchRun &r;
+    ~Side() {
+      if (r.fork) (void)hipEventDestroy(r.fork);
+      if (r.join) (void)hipEventDestroy(r.join);
+      if (r.side) (void)hipStreamDestroy(r.side);
+    }
+  } side_guard{r};
+  if (r.mode >= 2 && real_multi && cplx_multi) {
+    s = hip_st(hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking));
+    if (s == SVD2_OK) s = hip_st(hipEventCreateWithFlags(&r.fork, hipEventDisableTiming));
+    if (s == SVD2_OK) s = hip_st(hipEventCreateWithFlags(&r.join, hipEventDisableTiming));
+    if (s != SVD2_OK) return s;
+  }
   r.gA = r.L.maxA < 8192 ? r.L.maxA : 8192;
   r.gB = r.L.maxB < 16384 ? r.L.maxB : 16384;
   r.gF = nprob < 1024 ? nprob : 1024;
