@@ -594,21 +594,26 @@ template <class T, bool CPLX, int KIND> svd2_status batch_multi_launch(const Bat
 svd2_status batch_step(const BatchRun &r, hipStream_t st) {
   BatchHdr *hdr = (BatchHdr *)(r.ws + r.L.hdr);
   DevProb *probs = (DevProb *)(r.ws + r.L.probs);
+  // the problems in a single step and those of each stream's element types
+  // in a multi-step pass are disjoint: the two streams fork before the
+  // single steps and join before the finish
+  const bool multi = r.mode >= 2, two_streams = multi && r.side;
+  hipStream_t cs = two_streams ? r.side : st;  // complex element types
+  svd2_status s = SVD2_OK;
+  if (two_streams) s = hip_st(hipEventRecord(r.fork, st));
+  if (s == SVD2_OK && two_streams) s = hip_st(hipStreamWaitEvent(cs, r.fork, 0));
+  if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_pivot_kernel, dim3(r.gA), dim3(kUpdBlock), 0, st, r.ws, hdr,
                      (const int2 *)(r.ws + r.L.itemsA), probs, r.mode);
-  svd2_status s = hip_st(hipGetLastError());
+  s = hip_st(hipGetLastError());
   if (s != SVD2_OK) return s;
   hipLaunchKernelGGL(kog_batch_update_kernel, dim3(r.gB), dim3(kUpdBlock), 0, st, r.ws, hdr,
                      (const int4 *)(r.ws + r.L.itemsB), probs, (double *)(r.ws + r.L.parts), r.mode);
   s = hip_st(hipGetLastError());
-  const bool multi = r.mode >= 2, two_streams = multi && r.side;
-  hipStream_t cs = two_streams ? r.side : st;  // complex element types
-  if (s == SVD2_OK && two_streams) s = hip_st(hipEventRecord(r.fork, st));
-  if (s == SVD2_OK && two_streams) s = hip_st(hipStreamWaitEvent(cs, r.fork, 0));
-  if (s == SVD2_OK && multi) s = batch_multi_launch<double, false, SVD2_KOG_F64>(r, st);
   if (s == SVD2_OK && multi) s = batch_multi_launch<double, true, SVD2_KOG_C128>(r, cs);
-  if (s == SVD2_OK && multi) s = batch_multi_launch<float, false, SVD2_KOG_F32>(r, st);
   if (s == SVD2_OK && multi) s = batch_multi_launch<float, true, SVD2_KOG_C64>(r, cs);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<double, false, SVD2_KOG_F64>(r, st);
+  if (s == SVD2_OK && multi) s = batch_multi_launch<float, false, SVD2_KOG_F32>(r, st);
   if (s == SVD2_OK && two_streams) s = hip_st(hipEventRecord(r.join, cs));
   if (s == SVD2_OK && two_streams) s = hip_st(hipStreamWaitEvent(st, r.join, 0));
   if (s != SVD2_OK) return s;
