@@ -420,6 +420,13 @@ template <class T, bool CPLX> struct Ctx {
   Bufs<T, CPLX> B2{}, B3{};  // two steps per pass: the rotations of every second pass
   Bufs<T, CPLX> Bt{};        // three steps per pass: the rotations of the third step
   Bufs<T, CPLX> B4{};        // SVD entry points, three steps per pass: with B2, B3 the odd passes' rotations
+  // SVD entry points, three steps per pass: two more triples of rotation
+  // sets, and a second stream on which the walks of U and V run beside the
+  // passes over the iterate (piv_ev: a pass's rotations are there; walk_ev:
+  // a walk is done, for the walks of even and odd index)
+  Bufs<T, CPLX> X[6]{};
+  hipStream_t side = nullptr;
+  hipEvent_t piv_ev = nullptr, walk_ev[2] = {nullptr, nullptr};
 };
 
 template <class T, bool CPLX>
@@ -493,17 +500,18 @@ svd2_status accum_step(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &U, const Mat<T
 }
 
 // S steps t .. t+S-1 (rotations in sets[0 .. S-1]), from the buffer pair
-// that holds U and V (in_w: the workspace pair) into the other one
+// that holds U and V (in_w: the workspace pair) into the other one, on
+// stream st (default: the context's)
 template <class T, bool CPLX, int S>
-svd2_status accum_s(const Ctx<T, CPLX> &c, bool in_w, int t, const Bufs<T, CPLX> *sets) {
+svd2_status accum_s(const Ctx<T, CPLX> &c, bool in_w, int t, const Bufs<T, CPLX> *sets, hipStream_t st = nullptr) {
   constexpr int SEG = AccShape<T, CPLX>::seg;
   const int n = c.N / 2, rb = (c.N + 255) / 256, nseg = (n + SEG - 1) / SEG;
   const Mat<T, CPLX> &U = in_w ? c.U2 : c.U, &V = in_w ? c.V2 : c.V;
   const Mat<T, CPLX> &U2 = in_w ? c.U : c.U2, &V2 = in_w ? c.V : c.V2;
   AccSets<T, CPLX> R{};
   for (int L = 0; L < S; ++L) R.b[L] = sets[L];
-  hipLaunchKernelGGL((kog_accum_s_kernel<T, CPLX, S>), dim3(rb * nseg, 2), dim3(256), 0, c.st, c.N, U, V, U2, V2,
-                     t, R);
+  hipLaunchKernelGGL((kog_accum_s_kernel<T, CPLX, S>), dim3(rb * nseg, 2), dim3(256), 0, st ? st : c.st, c.N, U, V,
+                     U2, V2, t, R);
   return hip_st(hipGetLastError());
 }
 
@@ -687,9 +695,12 @@ template <class T, bool CPLX> ThreeStepShape three_step_shape(int N) {
 }
 
 // three steps t, t+1, t+2 from `cur` into `nxt` (rotations into B0, B1, B2)
+// (after_pivots: recorded on the stream once the three rotation sets are
+// written, before the pass over the matrix)
 template <class T, bool CPLX>
 svd2_status three_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Mat<T, CPLX> &nxt, int t,
-                        const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2) {
+                        const Bufs<T, CPLX> &B0, const Bufs<T, CPLX> &B1, const Bufs<T, CPLX> &B2,
+                        hipEvent_t after_pivots = nullptr) {
   const int n = c.N / 2;
   hipLaunchKernelGGL((kog_pivots2_kernel<T, CPLX>), dim3((n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1);
   svd2_status s = hip_st(hipGetLastError());
@@ -697,6 +708,7 @@ svd2_status three_steps(const Ctx<T, CPLX> &c, const Mat<T, CPLX> &cur, const Ma
   hipLaunchKernelGGL((kog_pivots3_kernel<T, CPLX>), dim3((4 * n + 63) / 64), dim3(64), 0, c.st, c.N, cur, t, B0, B1,
                      B2);
   s = hip_st(hipGetLastError());
+  if (s == SVD2_OK && after_pivots) s = hip_st(hipEventRecord(after_pivots, c.st));
   if (s != SVD2_OK) return s;
   const ThreeStepShape sh = three_step_shape<T, CPLX>(c.N);
   if (sh.ntiles <= 0) return SVD2_ERR_HIP;
@@ -752,30 +764,60 @@ template <class T, bool CPLX> svd2_status sweep_two_step(const Ctx<T, CPLX> &c, 
 
 // a sweep of the three-step mode: passes of three steps, then what is left
 // of the N-1 steps as one two-step pass or one single step; *in_w and *uv_in
-// as in sweep_two_step.  With accumulation the passes alternate between the
-// rotation sets (B, B1, Bt) and (B2, B3, B4), after every second pass one
+// as in sweep_two_step.  With accumulation, after every second pass one
 // kernel takes U and V six steps further, an unpaired last pass gets a
 // three-step accumulation, the two-step rest a two-step one and a last single
-// step an in-place one.
+// step an in-place one.  The passes take their rotation sets from two
+// triples in turn ((B, B1, Bt), (B2, B3, B4)), or with the second stream
+// from four (then X[0..2], X[3..5]): each walk of U and V then runs on that
+// stream once its second pass's rotations are written, beside the passes
+// over the iterate, and pass q waits for the walk that read its triple (the
+// walk of passes q-4 and q-3); the stream joins back before the rest of the
+// sweep.
 template <class T, bool CPLX> svd2_status sweep_three_step(const Ctx<T, CPLX> &c, bool *in_w, bool *uv_in) {
   svd2_status s = SVD2_OK;
+  const bool side = c.acc && c.side;
+  const int ntri = side ? 4 : 2;
+  auto set = [&](int tri, int i) -> const Bufs<T, CPLX> & {
+    static_assert(sizeof(c.X) / sizeof(c.X[0]) == 6, "two extra triples");
+    if (tri == 0) return i == 0 ? c.B : i == 1 ? c.B1 : c.Bt;
+    if (tri == 1) return i == 0 ? c.B2 : i == 1 ? c.B3 : c.B4;
+    return c.X[3 * (tri - 2) + i];
+  };
+  int last_walk = -1;
+  auto join = [&]() -> svd2_status {
+    return side && last_walk >= 0 ? hip_st(hipStreamWaitEvent(c.st, c.walk_ev[last_walk & 1], 0)) : SVD2_OK;
+  };
   int t = 0;
   for (int p = 0; c.N - 1 - t >= 3 && s == SVD2_OK; t += 3, ++p) {
     const bool odd = c.acc && (p & 1);
-    s = three_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, odd ? c.B2 : c.B, odd ? c.B3 : c.B1,
-                             odd ? c.B4 : c.Bt);
+    const int tri = c.acc ? p % ntri : 0;
+    if (side && p >= 4 && !(p & 1)) s = hip_st(hipStreamWaitEvent(c.st, c.walk_ev[(p / 2) & 1], 0));
+    if (s != SVD2_OK) break;
+    s = three_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, set(tri, 0), set(tri, 1), set(tri, 2),
+                             side && odd ? c.piv_ev : nullptr);
     *in_w = !*in_w;
     if (s != SVD2_OK || !c.acc) continue;
     if (odd) {
-      const Bufs<T, CPLX> sets[6] = {c.B, c.B1, c.Bt, c.B2, c.B3, c.B4};
-      s = accum_s<T, CPLX, 6>(c, *uv_in, t - 3, sets);
+      const int pt = tri - 1;  // the previous pass's triple
+      const Bufs<T, CPLX> sets[6] = {set(pt, 0), set(pt, 1), set(pt, 2), set(tri, 0), set(tri, 1), set(tri, 2)};
+      if (side) {
+        s = hip_st(hipStreamWaitEvent(c.side, c.piv_ev, 0));
+        if (s == SVD2_OK) s = accum_s<T, CPLX, 6>(c, *uv_in, t - 3, sets, c.side);
+        if (s == SVD2_OK) s = hip_st(hipEventRecord(c.walk_ev[(p / 2) & 1], c.side));
+        last_walk = p / 2;
+      } else {
+        s = accum_s<T, CPLX, 6>(c, *uv_in, t - 3, sets);
+      }
       *uv_in = !*uv_in;
     } else if (c.N - 1 - (t + 3) < 3) {
-      const Bufs<T, CPLX> sets[3] = {c.B, c.B1, c.Bt};
-      s = accum_s<T, CPLX, 3>(c, *uv_in, t, sets);
+      const Bufs<T, CPLX> sets[3] = {set(tri, 0), set(tri, 1), set(tri, 2)};
+      s = join();
+      if (s == SVD2_OK) s = accum_s<T, CPLX, 3>(c, *uv_in, t, sets);
       *uv_in = !*uv_in;
     }
   }
+  if (s == SVD2_OK) s = join();
   if (s == SVD2_OK && c.N - 1 - t == 2) {
     s = two_steps<T, CPLX>(c, *in_w ? c.W : c.M, *in_w ? c.M : c.W, t, c.B, c.B1);
     *in_w = !*in_w;
@@ -998,7 +1040,7 @@ svd2_status api_norms(int N, const T *A, int lda, double *off2, double *tot2, vo
 // buffers (N x N, lda N), the sort keys and indices (next power of two) and,
 // two steps per pass, two more rotation sets
 struct SvdLayout {
-  size_t u2, v2, keys, idx, b2, b3, b4, total;
+  size_t u2, v2, keys, idx, b2, b3, b4, x, total;
   int P;
 };
 // passes: 1 (one step per pass), 2 or 3 steps per pass
@@ -1017,7 +1059,8 @@ inline SvdLayout svd_layout(int N, size_t esz, bool cplx, int passes) {
   S.b2 = S.idx + up((size_t)S.P * sizeof(int));
   S.b3 = S.b2 + (passes > 1 ? set : 0);
   S.b4 = S.b3 + (passes > 1 ? set : 0);
-  S.total = S.b4 + (passes == 3 ? set : 0);
+  S.x = S.b4 + (passes == 3 ? set : 0);  // three steps per pass: six more sets
+  S.total = S.x + (passes == 3 ? 6 * set : 0);
   return S;
 }
 inline int svd_passes(unsigned flags) {
@@ -1069,6 +1112,23 @@ svd2_status api_svd(int N, T *A, int lda, T *U, int ldu, T *V, int ldv, T *sigma
   c.B2 = bufs_at<T, CPLX>(c.ws + S.b2, N);
   c.B3 = bufs_at<T, CPLX>(c.ws + S.b3, N);
   c.B4 = bufs_at<T, CPLX>(c.ws + S.b4, N);
+  // three steps per pass: the walks of U and V on a second stream
+  struct Side {  // released on every return below
+    Ctx<T, CPLX> &c;
+    ~Side() {
+      if (c.piv_ev) (void)hipEventDestroy(c.piv_ev);
+      for (hipEvent_t e : c.walk_ev)
+        if (e) (void)hipEventDestroy(e);
+      if (c.side) (void)hipStreamDestroy(c.side);
+    }
+  } side_guard{c};
+  if (flags == SVD2_KOG_THREE_STEP) {
+    for (int i = 0; i < 6; ++i) c.X[i] = bufs_at<T, CPLX>(c.ws + S.x + i * (S.b3 - S.b2), N);
+    s = hip_st(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    if (s == SVD2_OK) s = hip_st(hipEventCreateWithFlags(&c.piv_ev, hipEventDisableTiming));
+    for (int i = 0; i < 2 && s == SVD2_OK; ++i) s = hip_st(hipEventCreateWithFlags(&c.walk_ev[i], hipEventDisableTiming));
+    if (s != SVD2_OK) return s;
+  }
   const int grid = N < 4096 ? N : 4096;
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.U);
   hipLaunchKernelGGL((kog_eye_kernel<T, CPLX>), dim3(grid), dim3(256), 0, st, N, c.V);
