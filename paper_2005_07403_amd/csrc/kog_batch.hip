@@ -118,8 +118,8 @@ __device__ __forceinline__ int pass_steps(int mode, const DevProb &P) {
   return 1;
 }
 
-// pivots of step t+2 of a three-step pass: four lanes per pair, 64 pairs per
-// pass of the loop; all threads of the block call it
+// pivots of step t+2 of a three-step pass, pair k, on lane sub of its four
+// (all four lanes call it; valid where k is a pair of P)
 template <class T, bool CPLX> __device__ __forceinline__ void batch_pivots3(char *ws, const DevProb &P, int k, int sub) {
   pivots3_quad<T, CPLX>(P.N, mat_of<T, CPLX>(ws, P), P.t, bufs_of<T, CPLX>(ws, P, 0), bufs_of<T, CPLX>(ws, P, 1),
                         bufs_of<T, CPLX>(ws, P, 2), k, sub, k < P.N / 2);
