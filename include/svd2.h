@@ -406,9 +406,12 @@ svd2_status ckog_norms(int N, const float *A, int lda, double *off2, double *tot
  * while at least three steps remain before the last step of its sweep, and
  * one in-place step otherwise, so that every sweep ends with the in-place
  * step that tests convergence; three rotation sets and a second matrix per
- * problem.  Synchronises the stream; returns SVD2_OK if
- * every problem converged, SVD2_NOT_CONVERGED otherwise (see each problem's
- * status).
+ * problem.  In both multi-step modes, when the batch holds real and complex
+ * problems, the complex problems' kernels of a pass run on a second stream,
+ * created for the call, forked from `stream` and joined back to it in every
+ * pass by events (also inside the hipGraphs), and destroyed before the call
+ * returns.  Synchronises the stream; returns SVD2_OK if every problem
+ * converged, SVD2_NOT_CONVERGED otherwise (see each problem's status).
  * ------------------------------------------------------------------------- */
 typedef struct {
   int dtype;      /* in: SVD2_KOG_F64, _C128, _F32 or _C64                       */
@@ -473,12 +476,14 @@ svd2_status ckog_sigma(int N, const float *A, int lda, float *sigma_out, void *w
  *   A: the final iterate (unsorted).
  * ws: kog_svd_workspace_bytes(N, dtype, flags) bytes, 256-byte aligned (the
  * solve's workspace plus two N x N matrices, the sort keys and, two or three
- * steps per pass, two or three more rotation sets).  A, U, V,
+ * steps per pass, two or nine more rotation sets).  A, U, V,
  * sigma and ws must be pairwise disjoint (SVD2_ERR_ALIAS).  flags: 0 or
  * SVD2_KOG_TWO_STEP (two steps per pass over A; U and V are taken four steps
  * further per pass after every second pass, alternating with workspace
  * copies), SVD2_KOG_THREE_STEP (three steps per pass over A; U and V six
- * steps further after every second pass), SVD2_KOG_UNFUSED (one step per
+ * steps further after every second pass, on a second stream that the call
+ * creates, forks from `stream` by events and joins back before it returns,
+ * and destroys), SVD2_KOG_UNFUSED (one step per
  * pass, U and V rotated in place) or SVD2_KOG_UNFUSED | SVD2_KOG_GRAPH;
  * anything else is SVD2_ERR_FLAGS.  Every mode gives bitwise the same
  * results.  max_sweeps >= 1 (SVD2_ERR_SIZE).  Returns SVD2_OK or
